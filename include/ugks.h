@@ -1,0 +1,174 @@
+/*
+ * ugks.h -- C ABI of the MI355X (gfx950) implementation of the 2D unified gas-kinetic
+ * scheme (UGKS) time step.
+ *
+ * The problem follows the paper "Performance Comparison on Parallel CPU and GPU Algorithms
+ * for Unified Gas-Kinetic Scheme" (Liu, Hu & Li):
+ *   - BGK-Boltzmann equation with a Maxwellian equilibrium, Eq. (1); 2D monatomic gas
+ *     without internal degrees of freedom; velocities in units of sqrt(2kT0/m), so the
+ *     Maxwellian is rho (lambda/pi) exp(-lambda |c - U|^2) with lambda = 1/T.
+ *   - Finite volumes over nx*ny uniform Cartesian cells, nu*nv discrete molecular
+ *     velocities per cell (Sec. 2).
+ *   - Interface fluxes from the integral solution of the BGK equation, Eq. (2), built
+ *     through the flux steps S1-S8 (Sec. 2.B); distribution update with a trapezoidal
+ *     collision term, Eq. (3); conservative update, Eq. (4).
+ *   - The pressure-driven channel of Sec. 3.A: fixed inlet/outlet pressure, diffuse walls.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns int: UGKS_OK (0) or a negative UGKS_E_* code.  Results go
+ *     through out-parameters.  ugks_last_error() gives a message for the last failure.
+ *   - Host buffers are always owned by the caller.  Device memory is owned by the handle
+ *     unless the caller passes a workspace in ugks_opts, which then stays the caller's and
+ *     must outlive the handle.
+ *   - Host arrays use the canonical layout: cell (i, j) is at index j*nx + i (x fastest);
+ *     the velocity index is k*nv + m for (u_k, v_m); f[(j*nx + i)*nu*nv + k*nv + m];
+ *     W[(j*nx + i)*4 + q] with W = (rho, rho U, rho V, rho E).
+ *   - Work is enqueued on the stream given in ugks_opts (hipStream_t; NULL = the default
+ *     stream).  Only ugks_moments, ugks_get_state, ugks_set_state, ugks_get_face_flux,
+ *     ugks_get_kernel_timing and ugks_destroy synchronise with it.
+ *   - A handle may be used by one host thread at a time.
+ */
+#ifndef UGKS_H
+#define UGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UGKS_OK 0
+#define UGKS_E_INVAL (-1)  /* invalid argument (NULL pointer, size, range, inconsistent option) */
+#define UGKS_E_NOMEM (-2)  /* device or host allocation failed, or the workspace is too small */
+#define UGKS_E_DEVICE (-3) /* a HIP runtime call or kernel launch failed */
+#define UGKS_E_STATE (-4)  /* the solution holds NaN, rho <= 0 or T <= 0 */
+#define UGKS_E_BUSY (-5)   /* the handle is in use by another call */
+
+typedef struct ugks_handle ugks_handle;
+
+/* Uniform Cartesian mesh of nx*ny cells on [0, lx] x [0, ly] (Sec. 2: I x J cells). */
+typedef struct {
+  int nx, ny;
+  double lx, ly;
+} ugks_mesh;
+
+/* Discrete velocity grid (Sec. 2: K x M points (u_k, v_m)): nu uniform points on
+   [-umax, umax] and nv on [-vmax, vmax], both ends included, trapezoid weights, built
+   exactly mirror-symmetric.  nu, nv >= 2. */
+typedef struct {
+  int nu, nv;
+  double umax, vmax;
+} ugks_vgrid;
+
+#define UGKS_BC_PERIODIC 0 /* periodic in x and y */
+#define UGKS_BC_CHANNEL 1  /* Sec. 3.A: pressure inlet (x = 0), outlet (x = lx), walls at y = 0, ly */
+
+/* Boundary conditions.  For the channel: p_in / p_out = p_ratio with mean pressure
+   p0 = rho0 T0 / 2, so p_in = 2 r p0/(r+1) and p_out = 2 p0/(r+1).  The inlet ghost column
+   holds p_in and T_in with (U, V) copied from the first column (inlet_fixed_u = 0) or with
+   U = U_in (1 + U_noise xi_j), V = 0 (inlet_fixed_u = 1; xi_j seeded, see ugks_opts.seed).
+   The outlet ghost holds p_out with (U, V, T) copied from the last column.  Walls are
+   diffuse and isothermal at T_wall with zero net mass flux.  Ignored when periodic. */
+typedef struct {
+  int kind;
+  int inlet_fixed_u;
+  double p_ratio;
+  double T_in, T_wall;
+  double U_in, U_noise;
+} ugks_bc;
+
+#define UGKS_FP64 0       /* f stored and computed in FP64 */
+#define UGKS_FP32_STORE 1 /* f stored in FP32; moments, W and the scalar flux work in FP64 */
+
+/* Run options.
+   precision        UGKS_FP64 or UGKS_FP32_STORE.
+   cfl              time step dt = cfl / (umax/dx + vmax/dy) unless dt_override > 0.
+   rho0, T0, noise  initial state: rho = rho0 (1 + noise xi_c), U = V = 0, T = T0, and f the
+                    discrete Maxwellian of that state (|noise| < 1).
+   seed             xi_c is output c = j*nx + i of the SplitMix64 generator seeded with
+                    `seed` (output k = mix(seed + (k+1) * 0x9E3779B97F4A7C15)), mapped to
+                    [-1, 1) as 2 (z >> 11) 2^-53 - 1; the inlet noise xi_j uses output
+                    nx*ny + j.
+   stream           hipStream_t for all work of the handle.
+   workspace        optional device buffer of at least ugks_required_bytes() bytes, aligned
+                    to 256 bytes; NULL lets the library allocate. */
+typedef struct {
+  int precision;
+  int reserved; /* must be 0 */
+  double cfl;
+  double rho0, T0, noise;
+  uint64_t seed;
+  double dt_override;
+  void* stream;
+  void* workspace;
+  size_t workspace_bytes;
+} ugks_opts;
+
+typedef struct {
+  int nx, ny, nu, nv;
+  int nv_stride;   /* velocity stride of f in device memory (nu*nv rounded up to 64) */
+  int precision;
+  double dx, dy, dt;
+  double tau_ref;  /* collision time at rho = T = 1; +inf in the collisionless limit */
+  int64_t steps;   /* steps enqueued so far */
+  size_t device_bytes;
+} ugks_info;
+
+/* Device bytes a handle of this shape needs (f twice, ghosts, moment sums, face records,
+   W, velocity tables).  Pure host arithmetic: no HIP call. */
+int ugks_required_bytes(const ugks_mesh* mesh, const ugks_vgrid* vgrid, const ugks_opts* opts,
+                        size_t* out_bytes);
+
+/* Create a solver and initialise its state on the device.  kn is the Knudsen number on the
+   y extent of the domain (Sec. 3.A defines Kn on the channel width); kn = +INFINITY selects
+   the collisionless limit (tau = inf).  The collision time is tau = mu/p with the hard-sphere
+   viscosity mu = (5 sqrt(pi)/16) kn T^(1/2) and p = rho T/2.  On success *out receives the
+   handle; on failure *out is NULL and the message is kept for ugks_last_error(NULL). */
+int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const ugks_bc* bc,
+                const ugks_opts* opts, ugks_handle** out);
+
+/* Enqueue n >= 0 time steps (Eqs. (2)-(4), steps S1-S8 at every interface) on the handle's
+   stream and return without waiting.  Invalid states reached inside a step are flagged on
+   the device and reported by the next ugks_moments / ugks_get_state. */
+int ugks_step(ugks_handle* h, int n);
+
+/* Wait for the stream, then write (rho, U, V, T) for every cell to host_out
+   (4*nx*ny doubles, caller-owned).  Returns UGKS_E_STATE (after writing) if any cell or
+   interface state was invalid since creation. */
+int ugks_moments(ugks_handle* h, double* host_out);
+
+/* Release the handle and the device memory it owns; NULL is accepted and ignored. */
+int ugks_destroy(ugks_handle* h);
+
+/* Message of the last failure on h (or of the last failed ugks_create when h is NULL).
+   The string belongs to the library and stays valid until the next call on h. */
+const char* ugks_last_error(const ugks_handle* h);
+
+/* Shape, step and memory of a handle. */
+int ugks_get_info(const ugks_handle* h, ugks_info* out);
+
+/* Checkpoint / test hooks.  f: nx*ny*nu*nv doubles, W: 4*nx*ny doubles, canonical layout,
+   caller-owned host memory; either may be NULL.  get waits for the stream; set replaces
+   the current state (in FP32-store mode f is rounded to FP32). */
+int ugks_get_state(ugks_handle* h, double* f, double* W);
+int ugks_set_state(ugks_handle* h, const double* f, const double* W);
+
+/* Macroscopic face fluxes of the last step, integrated over the step and multiplied by the
+   face length, global frame: Fx[(j*(nx+1) + i)*4] through the left face of cell i in +x
+   (i = nx is the right face of the last column), Fy[(j*nx + i)*4] through the bottom face of
+   row j in +y (j = ny is the top face).  Host buffers of 4*(nx+1)*ny and 4*nx*(ny+1)
+   doubles; either may be NULL. */
+int ugks_get_face_flux(ugks_handle* h, double* Fx, double* Fy);
+
+/* Per-kernel timing with HIP events recorded on the handle's stream around every launch.
+   kernel: 0 boundary ghosts, 1 velocity moments, 2 interface scalars, 3 cell update.
+   Enabling resets the totals; get waits for the stream and returns the summed milliseconds
+   and the number of launches timed. */
+int ugks_set_kernel_timing(ugks_handle* h, int on);
+int ugks_get_kernel_timing(ugks_handle* h, int kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

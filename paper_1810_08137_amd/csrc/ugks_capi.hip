@@ -1,0 +1,637 @@
+// Host side of the C ABI declared in include/ugks.h: argument checks, the velocity grid and
+// boundary constants, one device workspace carved into all buffers, and the per-step launch
+// sequence on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "ugks_internal.hpp"
+
+using namespace ugks;
+
+struct ugks_handle {
+  KParams P{};
+  int prec = 0;
+  size_t ssize = 8;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool owns_ws = false;
+  Buffers B{};
+  int cur = 0;
+  int64_t steps = 0;
+  double tau_ref = 0.0;
+  std::string err;
+  std::atomic<int> busy{0};
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> pool;
+  struct Pending {
+    int kernel;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  double total_ms[4] = {0, 0, 0, 0};
+  int64_t launches[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t kAlign = 256;
+constexpr double kPiHost = 3.14159265358979323846;
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int fail(ugks_handle* h, int code, const char* fmt, const char* detail = "") {
+  char buf[512];
+  std::snprintf(buf, sizeof buf, fmt, detail);
+  if (h)
+    h->err = buf;
+  else
+    g_create_error = buf;
+  return code;
+}
+
+int hip_fail(ugks_handle* h, hipError_t e, const char* what) {
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+  if (h)
+    h->err = buf;
+  else
+    g_create_error = buf;
+  return UGKS_E_DEVICE;
+}
+
+struct Busy {
+  ugks_handle* h;
+  bool ok;
+  explicit Busy(ugks_handle* hh) : h(hh) {
+    int z = 0;
+    ok = h->busy.compare_exchange_strong(z, 1);
+  }
+  ~Busy() {
+    if (ok) h->busy.store(0);
+  }
+};
+
+// Uniform nodes on [-a, a] with both ends, made exactly mirror-symmetric; trapezoid weights.
+void velocity_nodes(int n, double a, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double h = 2.0 * a / (double)(n - 1);
+  for (int k = 0; k < n; ++k) x[k] = -a + (double)k * h;
+  for (int k = 0; k < n / 2; ++k) x[n - 1 - k] = -x[k];
+  if (n & 1) x[n / 2] = 0.0;
+  for (int k = 0; k < n; ++k) w[k] = (k == 0 || k == n - 1) ? 0.5 * h : h;
+}
+
+// SplitMix64, counter form: output k of the generator seeded with s.
+uint64_t splitmix(uint64_t s, uint64_t k) {
+  uint64_t z = s + (k + 1u) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+double noise_unit(uint64_t s, uint64_t k) {
+  return 2.0 * ((double)(splitmix(s, k) >> 11) * 0x1.0p-53) - 1.0;
+}
+
+struct Shape {
+  int nx, ny, K, M, NV, NVP;
+  size_t nc;
+};
+
+bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string& why) {
+  if (!mesh || !vg) {
+    why = "mesh and vgrid are required";
+    return false;
+  }
+  if (mesh->nx < 1 || mesh->ny < 1) {
+    why = "nx and ny must be >= 1";
+    return false;
+  }
+  if (!(mesh->lx > 0) || !(mesh->ly > 0) || !std::isfinite(mesh->lx) || !std::isfinite(mesh->ly)) {
+    why = "lx and ly must be positive and finite";
+    return false;
+  }
+  if (vg->nu < 2 || vg->nv < 2) {
+    why = "nu and nv must be >= 2";
+    return false;
+  }
+  if (vg->nu + vg->nv > kMaxTable) {
+    why = "nu + nv exceeds the table limit of the update kernel";
+    return false;
+  }
+  if (!(vg->umax > 0) || !(vg->vmax > 0) || !std::isfinite(vg->umax) || !std::isfinite(vg->vmax)) {
+    why = "umax and vmax must be positive and finite";
+    return false;
+  }
+  if ((double)mesh->nx * (double)mesh->ny > 2.0e9) {
+    why = "too many cells";
+    return false;
+  }
+  s.nx = mesh->nx;
+  s.ny = mesh->ny;
+  s.K = vg->nu;
+  s.M = vg->nv;
+  s.NV = vg->nu * vg->nv;
+  s.NVP = (int)round_up((size_t)s.NV, (size_t)kWave);
+  s.nc = (size_t)s.nx * s.ny;
+  return true;
+}
+
+// Offsets of every buffer inside the workspace.
+Layout layout_of(const Shape& s, int prec) {
+  const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
+  const size_t sizes[17] = {
+      s.nc * s.NVP * ss,                        // f0
+      s.nc * s.NVP * ss,                        // f1
+      s.nc * 4 * 8,                             // W
+      2 * (size_t)s.ny * 4 * 8,                 // Wg
+      2 * (size_t)s.ny * s.NVP * ss,            // fg
+      s.nc * kSlots * 8,                        // hs
+      2 * (size_t)s.ny * 16 * 8,                // hsg
+      (size_t)s.ny * (s.nx + 1) * kRec * 8,     // recx
+      (size_t)(s.ny + 1) * s.nx * kRec * 8,     // recy
+      (size_t)s.NVP * 8,                        // U
+      (size_t)s.NVP * 8,                        // V
+      (size_t)s.NVP * 8,                        // Wq
+      (size_t)s.NVP * 4,                        // kidx
+      (size_t)s.NVP * 4,                        // midx
+      (size_t)s.K * 8,                          // uk
+      (size_t)s.M * 8,                          // vm
+      (size_t)s.ny * 8 + 64,                    // xi_in + flag
+  };
+  Layout L{};
+  size_t off = 0;
+  for (int b = 0; b < 17; ++b) {
+    L.off[b] = off;
+    off += round_up(sizes[b], kAlign);
+  }
+  L.total = off;
+  return L;
+}
+
+void carve(ugks_handle* h, const Layout& L, const Shape& s) {
+  char* base = static_cast<char*>(h->ws);
+  Buffers& B = h->B;
+  B.f[0] = base + L.off[0];
+  B.f[1] = base + L.off[1];
+  B.W = reinterpret_cast<double*>(base + L.off[2]);
+  B.Wg = reinterpret_cast<double*>(base + L.off[3]);
+  B.fg = base + L.off[4];
+  B.hs = reinterpret_cast<double*>(base + L.off[5]);
+  B.hsg = reinterpret_cast<double*>(base + L.off[6]);
+  B.recx = reinterpret_cast<double*>(base + L.off[7]);
+  B.recy = reinterpret_cast<double*>(base + L.off[8]);
+  B.U = reinterpret_cast<double*>(base + L.off[9]);
+  B.V = reinterpret_cast<double*>(base + L.off[10]);
+  B.Wq = reinterpret_cast<double*>(base + L.off[11]);
+  B.kidx = reinterpret_cast<int*>(base + L.off[12]);
+  B.midx = reinterpret_cast<int*>(base + L.off[13]);
+  B.uk = reinterpret_cast<double*>(base + L.off[14]);
+  B.vm = reinterpret_cast<double*>(base + L.off[15]);
+  B.xi_in = reinterpret_cast<double*>(base + L.off[16]);
+  B.flag = reinterpret_cast<int*>(base + L.off[16] + round_up((size_t)s.ny * 8, 64));
+}
+
+hipEvent_t pool_get(ugks_handle* h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Launch one kernel, bracketed by timing events when enabled.
+template <typename F>
+hipError_t timed(ugks_handle* h, int kernel, F&& launch) {
+  if (!h->timing) return launch();
+  hipEvent_t a = pool_get(h), b = pool_get(h);
+  if (a) (void)hipEventRecord(a, h->stream);
+  hipError_t e = launch();
+  if (b) (void)hipEventRecord(b, h->stream);
+  if (a && b) h->pending.push_back({kernel, a, b});
+  return e;
+}
+
+int collect_timing(ugks_handle* h) {
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      h->total_ms[p.kernel] += ms;
+      h->launches[p.kernel] += 1;
+    }
+    h->pool.push_back(p.a);
+    h->pool.push_back(p.b);
+  }
+  h->pending.clear();
+  return UGKS_OK;
+}
+
+int enqueue_step(ugks_handle* h) {
+  KParams& P = h->P;
+  Buffers& B = h->B;
+  const int fp32 = h->prec == UGKS_FP32_STORE;
+  hipError_t e;
+  if (P.bc == UGKS_BC_CHANNEL) {
+    e = timed(h, 0, [&] { return launch_ghost(P, fp32, B.W, B.Wg, B.fg, B.hsg, h->stream); });
+    if (e != hipSuccess) return hip_fail(h, e, "ghost kernel launch");
+  }
+  e = timed(h, 1, [&] { return launch_sums(P, fp32, B.f[h->cur], B.fg, B.hs, h->stream); });
+  if (e != hipSuccess) return hip_fail(h, e, "moment kernel launch");
+  e = timed(h, 2, [&] {
+    return launch_faces(P, B.hs, B.hsg, B.W, B.Wg, B.recx, B.recy, h->stream);
+  });
+  if (e != hipSuccess) return hip_fail(h, e, "interface kernel launch");
+  e = timed(h, 3, [&] {
+    return launch_update(P, fp32, B.f[h->cur], B.f[1 - h->cur], B.fg, B.recx, B.recy, B.W,
+                         h->stream);
+  });
+  if (e != hipSuccess) return hip_fail(h, e, "update kernel launch");
+  h->cur = 1 - h->cur;
+  h->steps += 1;
+  return UGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ugks_required_bytes(const ugks_mesh* mesh, const ugks_vgrid* vgrid, const ugks_opts* opts,
+                        size_t* out_bytes) {
+  if (!out_bytes) return fail(nullptr, UGKS_E_INVAL, "out_bytes is NULL%s");
+  Shape s;
+  std::string why;
+  if (!shape_ok(mesh, vgrid, s, why)) return fail(nullptr, UGKS_E_INVAL, "%s", why.c_str());
+  const int prec = opts ? opts->precision : UGKS_FP64;
+  if (prec != UGKS_FP64 && prec != UGKS_FP32_STORE)
+    return fail(nullptr, UGKS_E_INVAL, "unknown precision%s");
+  *out_bytes = layout_of(s, prec).total;
+  return UGKS_OK;
+}
+
+int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const ugks_bc* bc,
+                const ugks_opts* opts, ugks_handle** out) {
+  if (!out) return fail(nullptr, UGKS_E_INVAL, "out is NULL%s");
+  *out = nullptr;
+  Shape s;
+  std::string why;
+  if (!shape_ok(mesh, vgrid, s, why)) return fail(nullptr, UGKS_E_INVAL, "%s", why.c_str());
+  if (!bc || !opts) return fail(nullptr, UGKS_E_INVAL, "bc and opts are required%s");
+  if (!(kn > 0)) return fail(nullptr, UGKS_E_INVAL, "kn must be > 0 (or +inf)%s");
+  if (bc->kind != UGKS_BC_PERIODIC && bc->kind != UGKS_BC_CHANNEL)
+    return fail(nullptr, UGKS_E_INVAL, "unknown boundary kind%s");
+  if (bc->kind == UGKS_BC_CHANNEL &&
+      (!(bc->p_ratio > 0) || !(bc->T_in > 0) || !(bc->T_wall > 0) || !std::isfinite(bc->p_ratio) ||
+       !std::isfinite(bc->T_in) || !std::isfinite(bc->T_wall)))
+    return fail(nullptr, UGKS_E_INVAL, "channel needs p_ratio, T_in, T_wall > 0%s");
+  if (opts->precision != UGKS_FP64 && opts->precision != UGKS_FP32_STORE)
+    return fail(nullptr, UGKS_E_INVAL, "unknown precision%s");
+  if (opts->reserved != 0) return fail(nullptr, UGKS_E_INVAL, "opts.reserved must be 0%s");
+  if (!(opts->rho0 > 0) || !(opts->T0 > 0) || !(std::fabs(opts->noise) < 1.0))
+    return fail(nullptr, UGKS_E_INVAL, "need rho0 > 0, T0 > 0, |noise| < 1%s");
+  if (!(opts->dt_override > 0) && !(opts->cfl > 0 && std::isfinite(opts->cfl)))
+    return fail(nullptr, UGKS_E_INVAL, "need cfl > 0 or dt_override > 0%s");
+
+  const Layout L = layout_of(s, opts->precision);
+  if (opts->workspace && opts->workspace_bytes < L.total)
+    return fail(nullptr, UGKS_E_NOMEM, "workspace smaller than ugks_required_bytes()%s");
+  if (opts->workspace && (reinterpret_cast<uintptr_t>(opts->workspace) % kAlign) != 0)
+    return fail(nullptr, UGKS_E_INVAL, "workspace must be 256-byte aligned%s");
+
+  ugks_handle* h = new (std::nothrow) ugks_handle();
+  if (!h) return fail(nullptr, UGKS_E_NOMEM, "host allocation failed%s");
+  h->prec = opts->precision;
+  h->ssize = h->prec == UGKS_FP32_STORE ? 4 : 8;
+  h->stream = static_cast<hipStream_t>(opts->stream);
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(nullptr, e, "hipGetDevice");
+  }
+  if (opts->workspace) {
+    h->ws = opts->workspace;
+    h->ws_bytes = opts->workspace_bytes;
+  } else {
+    e = hipMalloc(&h->ws, L.total);
+    if (e != hipSuccess) {
+      delete h;
+      (void)hipGetLastError();
+      return fail(nullptr, UGKS_E_NOMEM, "hipMalloc of the workspace failed%s");
+    }
+    h->ws_bytes = L.total;
+    h->owns_ws = true;
+  }
+  carve(h, L, s);
+
+  // ---- constants
+  KParams& P = h->P;
+  P.nx = s.nx;
+  P.ny = s.ny;
+  P.K = s.K;
+  P.M = s.M;
+  P.NV = s.NV;
+  P.NVP = s.NVP;
+  P.bc = bc->kind;
+  P.collisionless = std::isinf(kn) ? 1 : 0;
+  P.inlet_fixed_u = bc->inlet_fixed_u ? 1 : 0;
+  P.dx = mesh->lx / s.nx;
+  P.dy = mesh->ly / s.ny;
+  P.dt = opts->dt_override > 0 ? opts->dt_override
+                               : opts->cfl / (vgrid->umax / P.dx + vgrid->vmax / P.dy);
+  P.inv_dx = 1.0 / P.dx;
+  P.inv_dy = 1.0 / P.dy;
+  P.area = P.dx * P.dy;
+  P.mu_ref = P.collisionless ? 0.0 : 5.0 * std::sqrt(kPiHost) * kn / 16.0;
+  h->tau_ref = P.collisionless ? std::numeric_limits<double>::infinity() : 2.0 * P.mu_ref;
+  const double p0 = 0.5 * opts->rho0 * opts->T0;
+  const double r = bc->kind == UGKS_BC_CHANNEL ? bc->p_ratio : 1.0;
+  P.p_in = 2.0 * r * p0 / (r + 1.0);
+  P.p_out = 2.0 * p0 / (r + 1.0);
+  P.T_in = bc->kind == UGKS_BC_CHANNEL ? bc->T_in : 1.0;
+  const double Tw = bc->kind == UGKS_BC_CHANNEL ? bc->T_wall : 1.0;
+  P.lam_w = 1.0 / Tw;
+  P.U_in = bc->U_in;
+  P.U_noise = bc->U_noise;
+
+  std::vector<double> uk, wk, vm, wm;
+  velocity_nodes(s.K, vgrid->umax, uk, wk);
+  velocity_nodes(s.M, vgrid->vmax, vm, wm);
+  std::vector<double> U(s.NVP, 0.0), V(s.NVP, 0.0), Wq(s.NVP, 0.0);
+  std::vector<int> kidx(s.NVP, 0), midx(s.NVP, 0);
+  for (int k = 0; k < s.K; ++k)
+    for (int m = 0; m < s.M; ++m) {
+      const int v = k * s.M + m;
+      U[v] = uk[k];
+      V[v] = vm[m];
+      Wq[v] = wk[k] * wm[m];
+      kidx[v] = k;
+      midx[v] = m;
+    }
+  // diffuse-wall constants: moments of the unit-density wall Maxwellian over the velocities
+  // that leave each wall, in the wall's local frame (v, u)
+  P.wall_den_bot = P.wall_den_top = 0.0;
+  for (int q = 0; q < 4; ++q) P.wall_G_bot[q] = P.wall_G_top[q] = 0.0;
+  for (int k = 0; k < s.K; ++k)
+    for (int m = 0; m < s.M; ++m) {
+      const double u = uk[k], v = vm[m], w = wk[k] * wm[m];
+      const double gw = P.lam_w / kPiHost * std::exp(-P.lam_w * (u * u + v * v));
+      const double psi[4] = {1.0, v, u, 0.5 * (u * u + v * v)};
+      if (v > 0) {
+        P.wall_den_bot += w * v * gw;
+        for (int q = 0; q < 4; ++q) P.wall_G_bot[q] += w * v * psi[q] * gw;
+      } else if (v < 0) {
+        P.wall_den_top += w * v * gw;
+        for (int q = 0; q < 4; ++q) P.wall_G_top[q] += w * v * psi[q] * gw;
+      }
+    }
+  std::vector<double> W0(4 * s.nc), xi(s.ny);
+  for (int j = 0; j < s.ny; ++j) {
+    xi[j] = noise_unit(opts->seed, s.nc + (uint64_t)j);
+    for (int i = 0; i < s.nx; ++i) {
+      const size_t c = (size_t)j * s.nx + i;
+      const double rho = opts->rho0 * (1.0 + opts->noise * noise_unit(opts->seed, c));
+      W0[4 * c + 0] = rho;
+      W0[4 * c + 1] = 0.0;
+      W0[4 * c + 2] = 0.0;
+      W0[4 * c + 3] = 0.5 * rho * opts->T0;  // rho/(2 lambda)
+    }
+  }
+  Buffers& B = h->B;
+  P.U = B.U;
+  P.V = B.V;
+  P.Wq = B.Wq;
+  P.kidx = B.kidx;
+  P.midx = B.midx;
+  P.uk = B.uk;
+  P.vm = B.vm;
+  P.xi_in = B.xi_in;
+  P.flag = B.flag;
+
+  struct Copy {
+    void* dst;
+    const void* src;
+    size_t n;
+  } copies[] = {
+      {B.U, U.data(), U.size() * 8},        {B.V, V.data(), V.size() * 8},
+      {B.Wq, Wq.data(), Wq.size() * 8},     {B.kidx, kidx.data(), kidx.size() * 4},
+      {B.midx, midx.data(), midx.size() * 4}, {B.uk, uk.data(), uk.size() * 8},
+      {B.vm, vm.data(), vm.size() * 8},     {B.xi_in, xi.data(), xi.size() * 8},
+      {B.W, W0.data(), W0.size() * 8},
+  };
+  int rc = UGKS_OK;
+  for (auto& cp : copies) {
+    e = hipMemcpyAsync(cp.dst, cp.src, cp.n, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) {
+      rc = hip_fail(nullptr, e, "hipMemcpyAsync of the tables");
+      break;
+    }
+  }
+  if (rc == UGKS_OK) {
+    e = hipMemsetAsync(B.flag, 0, sizeof(int), h->stream);
+    if (e != hipSuccess) rc = hip_fail(nullptr, e, "hipMemsetAsync of the state flag");
+  }
+  if (rc == UGKS_OK) {
+    // the ghost columns of a periodic run are never read; keep them defined anyway
+    e = hipMemsetAsync(B.fg, 0, 2 * (size_t)s.ny * s.NVP * h->ssize, h->stream);
+    if (e == hipSuccess) e = launch_init(P, h->prec == UGKS_FP32_STORE, B.f[0], B.W, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) rc = hip_fail(nullptr, e, "initial state");
+  }
+  if (rc != UGKS_OK) {
+    if (h->owns_ws) (void)hipFree(h->ws);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return UGKS_OK;
+}
+
+int ugks_step(ugks_handle* h, int n) {
+  if (!h) return UGKS_E_INVAL;
+  if (n < 0) return fail(h, UGKS_E_INVAL, "n must be >= 0%s");
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  for (int s = 0; s < n; ++s) {
+    const int rc = enqueue_step(h);
+    if (rc != UGKS_OK) return rc;
+  }
+  return UGKS_OK;
+}
+
+int ugks_moments(ugks_handle* h, double* host_out) {
+  if (!h) return UGKS_E_INVAL;
+  if (!host_out) return fail(h, UGKS_E_INVAL, "host_out is NULL%s");
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  const size_t nc = (size_t)h->P.nx * h->P.ny;
+  std::vector<double> W(4 * nc);
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(W.data(), h->B.W, W.size() * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&flag, h->B.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reading W");
+  bool bad = flag != 0;
+  for (size_t c = 0; c < nc; ++c) {
+    const double* w = &W[4 * c];
+    const double rho = w[0], U = w[1] / rho, V = w[2] / rho;
+    const double T = 2.0 * (w[3] - 0.5 * rho * (U * U + V * V)) / rho;
+    host_out[4 * c + 0] = rho;
+    host_out[4 * c + 1] = U;
+    host_out[4 * c + 2] = V;
+    host_out[4 * c + 3] = T;
+    if (!(rho > 0) || !(T > 0) || !std::isfinite(U) || !std::isfinite(V) || !std::isfinite(T))
+      bad = true;
+  }
+  if (bad) return fail(h, UGKS_E_STATE, "invalid state (NaN, rho <= 0 or T <= 0)%s");
+  return UGKS_OK;
+}
+
+int ugks_destroy(ugks_handle* h) {
+  if (!h) return UGKS_OK;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& p : h->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : h->pool) (void)hipEventDestroy(e);
+  if (h->owns_ws) (void)hipFree(h->ws);
+  delete h;
+  return UGKS_OK;
+}
+
+const char* ugks_last_error(const ugks_handle* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int ugks_get_info(const ugks_handle* h, ugks_info* out) {
+  if (!h || !out) return UGKS_E_INVAL;
+  out->nx = h->P.nx;
+  out->ny = h->P.ny;
+  out->nu = h->P.K;
+  out->nv = h->P.M;
+  out->nv_stride = h->P.NVP;
+  out->precision = h->prec;
+  out->dx = h->P.dx;
+  out->dy = h->P.dy;
+  out->dt = h->P.dt;
+  out->tau_ref = h->tau_ref;
+  out->steps = h->steps;
+  out->device_bytes = h->ws_bytes;
+  return UGKS_OK;
+}
+
+int ugks_get_state(ugks_handle* h, double* f, double* W) {
+  if (!h) return UGKS_E_INVAL;
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = h->P.NV, NVP = h->P.NVP;
+  hipError_t e = hipSuccess;
+  std::vector<char> raw;
+  if (f) {
+    raw.resize(nc * NVP * h->ssize);
+    e = hipMemcpyAsync(raw.data(), h->B.f[h->cur], raw.size(), hipMemcpyDeviceToHost, h->stream);
+  }
+  if (e == hipSuccess && W)
+    e = hipMemcpyAsync(W, h->B.W, nc * 4 * 8, hipMemcpyDeviceToHost, h->stream);
+  int flag = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&flag, h->B.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reading the state");
+  if (f) {
+    for (size_t c = 0; c < nc; ++c)
+      for (size_t v = 0; v < NV; ++v)
+        f[c * NV + v] = h->prec == UGKS_FP32_STORE
+                            ? (double)reinterpret_cast<const float*>(raw.data())[c * NVP + v]
+                            : reinterpret_cast<const double*>(raw.data())[c * NVP + v];
+  }
+  if (flag) return fail(h, UGKS_E_STATE, "invalid state flagged on the device%s");
+  return UGKS_OK;
+}
+
+int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
+  if (!h) return UGKS_E_INVAL;
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = h->P.NV, NVP = h->P.NVP;
+  std::vector<char> raw;
+  hipError_t e = hipSuccess;
+  if (f) {
+    raw.assign(nc * NVP * h->ssize, 0);
+    for (size_t c = 0; c < nc; ++c)
+      for (size_t v = 0; v < NV; ++v) {
+        if (h->prec == UGKS_FP32_STORE)
+          reinterpret_cast<float*>(raw.data())[c * NVP + v] = (float)f[c * NV + v];
+        else
+          reinterpret_cast<double*>(raw.data())[c * NVP + v] = f[c * NV + v];
+      }
+    e = hipMemcpyAsync(h->B.f[h->cur], raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream);
+  }
+  if (e == hipSuccess && W)
+    e = hipMemcpyAsync(h->B.W, W, nc * 4 * 8, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "writing the state");
+  return UGKS_OK;
+}
+
+int ugks_get_face_flux(ugks_handle* h, double* Fx, double* Fy) {
+  if (!h) return UGKS_E_INVAL;
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  const size_t nfx = (size_t)h->P.ny * (h->P.nx + 1), nfy = (size_t)(h->P.ny + 1) * h->P.nx;
+  std::vector<double> rx(Fx ? nfx * kRec : 0), ry(Fy ? nfy * kRec : 0);
+  hipError_t e = hipSuccess;
+  if (Fx) e = hipMemcpyAsync(rx.data(), h->B.recx, rx.size() * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && Fy)
+    e = hipMemcpyAsync(ry.data(), h->B.recy, ry.size() * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reading the face records");
+  for (size_t k = 0; Fx && k < nfx; ++k)
+    for (int q = 0; q < 4; ++q) Fx[4 * k + q] = rx[k * kRec + R_FX + q];
+  for (size_t k = 0; Fy && k < nfy; ++k)
+    for (int q = 0; q < 4; ++q) Fy[4 * k + q] = ry[k * kRec + R_FX + q];
+  return UGKS_OK;
+}
+
+int ugks_set_kernel_timing(ugks_handle* h, int on) {
+  if (!h) return UGKS_E_INVAL;
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  (void)hipStreamSynchronize(h->stream);
+  collect_timing(h);
+  for (int k = 0; k < 4; ++k) {
+    h->total_ms[k] = 0.0;
+    h->launches[k] = 0;
+  }
+  h->timing = on != 0;
+  return UGKS_OK;
+}
+
+int ugks_get_kernel_timing(ugks_handle* h, int kernel, double* total_ms, int64_t* launches) {
+  if (!h || kernel < 0 || kernel > 3 || !total_ms || !launches) return UGKS_E_INVAL;
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "synchronising for timing");
+  collect_timing(h);
+  *total_ms = h->total_ms[kernel];
+  *launches = h->launches[kernel];
+  return UGKS_OK;
+}
+
+}  // extern "C"

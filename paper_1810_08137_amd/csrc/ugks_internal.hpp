@@ -1,0 +1,97 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "ugks.h"
+
+namespace ugks {
+
+constexpr int kWave = 64;      // CDNA wavefront
+constexpr int kSlots = 64;     // per-cell outgoing moment sums: 4 faces x 16
+constexpr int kRec = 32;       // doubles per interface record
+constexpr int kMaxTable = 1024;  // nu + nv limit: six separable exp tables of nu+nv doubles in LDS
+
+// Interface record (doubles), written by the interface kernel, read by the cell update.
+// Frame: "normal"/"tangential" velocity of the face; for x-faces (u, v), for y-faces (v, u).
+enum RecField {
+  R_FX = 0,      // [0..3] macroscopic flux, global frame (rho, rho U, rho V, rho E)
+  R_GCOEF = 4,   // rho0 lambda0 / pi of the interface Maxwellian (or of the wall Maxwellian)
+  R_LAM = 5,     // lambda0
+  R_UX = 6,      // equilibrium velocity, global x component
+  R_VY = 7,      // equilibrium velocity, global y component
+  R_MT = 8,      // [8..12] time weights Mt1..Mt5
+  R_AL = 13,     // [13..16] normal slope for u_n > 0
+  R_AR = 17,     // [17..20] normal slope for u_n < 0
+  R_B = 21,      // [21..24] tangential slope
+  R_A = 25,      // [25..28] time slope
+  R_KIND = 29,   // 0 interior, 1 wall, 2 collisionless interior
+  R_LEN = 30,    // face length
+};
+enum FaceKind { K_INTERIOR = 0, K_WALL = 1, K_FREE = 2 };
+
+// Slot layout of the outgoing sums of one cell: face f in {+x, -x, +y, -y} at 16*f, each
+// [W0(4), Wt(4), Q1(4), Q2(4)] in the local frame of that face.
+enum FaceSide { S_XP = 0, S_XM = 1, S_YP = 2, S_YM = 3 };
+
+struct KParams {
+  int nx, ny, K, M, NV, NVP;
+  int bc, collisionless, inlet_fixed_u, pad0;
+  double dx, dy, dt, inv_dx, inv_dy, area, mu_ref;
+  double p_in, p_out, T_in, lam_w;
+  double U_in, U_noise;
+  double wall_den_bot, wall_den_top;  // sum over wall-leaving velocities of w v g_w
+  double wall_G_bot[4], wall_G_top[4];  // sum of w v psi_local g_w over the same velocities
+  const double* U;      // [NVP] u of each velocity slot (0 in pads)
+  const double* V;      // [NVP]
+  const double* Wq;     // [NVP] quadrature weight (0 in pads)
+  const int* kidx;      // [NVP] k of each velocity slot
+  const int* midx;      // [NVP] m of each velocity slot
+  const double* uk;     // [K]
+  const double* vm;     // [M]
+  const double* xi_in;  // [ny] inlet noise
+  int* flag;            // device flag: set to 1 on an invalid state
+};
+
+// Device buffers carved out of one workspace.
+struct Buffers {
+  void* f[2];       // [nx*ny][NVP] storage type
+  double* W;        // [nx*ny][4]
+  double* Wg;       // [2][ny][4]
+  void* fg;         // [2][ny][NVP] storage type
+  double* hs;       // [nx*ny][64]
+  double* hsg;      // [2][ny][16]
+  double* recx;     // [ny][nx+1][32]
+  double* recy;     // [ny+1][nx][32]
+  double* U;        // [NVP]
+  double* V;
+  double* Wq;
+  int* kidx;
+  int* midx;
+  double* uk;       // [K]
+  double* vm;       // [M]
+  double* xi_in;    // [ny]
+  int* flag;
+};
+
+struct Layout {
+  size_t off[17];
+  size_t total;
+};
+
+// Launchers (ugks_kernels.hip).  All enqueue on `s` and return the launch error.
+hipError_t launch_init(const KParams& P, int fp32, void* f, const double* W, hipStream_t s);
+hipError_t launch_ghost(const KParams& P, int fp32, const double* W, double* Wg, void* fg,
+                        double* hsg, hipStream_t s);
+hipError_t launch_sums(const KParams& P, int fp32, const void* f, const void* fg, double* hs,
+                       hipStream_t s);
+hipError_t launch_faces(const KParams& P, const double* hs, const double* hsg, const double* W,
+                        const double* Wg, double* recx, double* recy, hipStream_t s);
+hipError_t launch_update(const KParams& P, int fp32, const void* fin, void* fout, const void* fg,
+                         const double* recx, const double* recy, double* W, hipStream_t s);
+
+}  // namespace ugks

@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI (CPU only, no compute call): the library loads, exports
+every function the header declares, sizes its workspace as documented and rejects invalid
+arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1810_08137_amd import ugks
+from paper_1810_08137_amd import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ugks.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ugks_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_core_calls():
+    names = _declared_functions()
+    for core in ("ugks_create", "ugks_step", "ugks_moments", "ugks_destroy"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(ugks.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+    assert set(_declared_functions()) == set(ugks.SIGNATURES)
+
+
+def _structs(case=WL.C2, **over):
+    c = dict(case)
+    c.update(over)
+    kn = c.pop("kn")
+    return kn, ugks.make_structs(**c)
+
+
+def test_required_bytes_matches_the_documented_layout():
+    kn, (mesh, vgrid, bc, opts) = _structs()
+    n64 = ugks.ugks_required_bytes(mesh, vgrid, opts)
+    nc, nvp = 400 * 100, 1600
+    f_bytes = nc * nvp * 8
+    assert 2 * f_bytes <= n64 <= 2 * f_bytes * 1.1       # two f buffers dominate
+    opts.precision = ugks.UGKS_FP32_STORE
+    n32 = ugks.ugks_required_bytes(mesh, vgrid, opts)
+    assert n32 < n64 and n64 - n32 >= f_bytes        # FP32 storage halves both f buffers
+
+
+def test_velocity_padding_to_wavefront():
+    kn, (mesh, vgrid, bc, opts) = _structs(WL.C3)
+    n = ugks.ugks_required_bytes(mesh, vgrid, opts)
+    assert n >= 2 * 200 * 50 * 10240 * 8
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("ny", -1), ("lx", 0.0), ("nu", 1), ("nv", 0), ("umax", -1.0),
+    ("nu", 2000), ("noise", 1.5), ("rho0", 0.0), ("T0", -1.0), ("p_ratio", 0.0),
+    ("T_wall", 0.0), ("cfl", 0.0), ("precision", 7), ("bc", 5),
+])
+def test_create_rejects_invalid_arguments(field, value):
+    c = dict(WL.C1)
+    c[field] = value
+    kn = c.pop("kn")
+    mesh, vgrid, bc, opts = ugks.make_structs(**c)
+    h = ctypes.c_void_p(None)
+    rc = ugks.lib().ugks_create(ctypes.byref(mesh), ctypes.byref(vgrid), kn, ctypes.byref(bc),
+                                ctypes.byref(opts), ctypes.byref(h))
+    assert rc == ugks.UGKS_E_INVAL
+    assert not h.value
+    assert ugks.ugks_last_error(None)
+
+
+@pytest.mark.parametrize("kn", [0.0, -0.1, float("nan")])
+def test_create_rejects_bad_knudsen(kn):
+    _, (mesh, vgrid, bc, opts) = _structs(WL.C1)
+    h = ctypes.c_void_p(None)
+    rc = ugks.lib().ugks_create(ctypes.byref(mesh), ctypes.byref(vgrid), kn, ctypes.byref(bc),
+                                ctypes.byref(opts), ctypes.byref(h))
+    assert rc == ugks.UGKS_E_INVAL
+
+
+def test_create_rejects_small_or_misaligned_workspace():
+    _, (mesh, vgrid, bc, opts) = _structs(WL.C1)
+    need = ugks.ugks_required_bytes(mesh, vgrid, opts)
+    opts.workspace = ctypes.c_void_p(4096)
+    opts.workspace_bytes = need - 1
+    h = ctypes.c_void_p(None)
+    rc = ugks.lib().ugks_create(ctypes.byref(mesh), ctypes.byref(vgrid), 0.1, ctypes.byref(bc),
+                                ctypes.byref(opts), ctypes.byref(h))
+    assert rc == ugks.UGKS_E_NOMEM
+    opts.workspace = ctypes.c_void_p(4096 + 8)
+    opts.workspace_bytes = need
+    rc = ugks.lib().ugks_create(ctypes.byref(mesh), ctypes.byref(vgrid), 0.1, ctypes.byref(bc),
+                                ctypes.byref(opts), ctypes.byref(h))
+    assert rc == ugks.UGKS_E_INVAL
+
+
+def test_null_handles():
+    L = ugks.lib()
+    assert L.ugks_destroy(None) == ugks.UGKS_OK
+    assert L.ugks_step(None, 1) == ugks.UGKS_E_INVAL
+    assert L.ugks_moments(None, None) == ugks.UGKS_E_INVAL
+    assert L.ugks_get_info(None, None) == ugks.UGKS_E_INVAL
+    assert L.ugks_get_state(None, None, None) == ugks.UGKS_E_INVAL
+    _, (mesh, vgrid, bc, opts) = _structs(WL.C1)
+    assert L.ugks_create(ctypes.byref(mesh), ctypes.byref(vgrid), 0.1, ctypes.byref(bc),
+                         ctypes.byref(opts), None) == ugks.UGKS_E_INVAL
+    assert L.ugks_required_bytes(None, None, None, None) == ugks.UGKS_E_INVAL

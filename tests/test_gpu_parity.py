@@ -1,0 +1,183 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs.
+
+FP64 bar: rho and T relative, U and V absolute, f per-cell max |df| / max f, all <= 1e-12.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1810_08137_amd import ugks
+from paper_1810_08137_amd import workloads as WL
+from tests import parity as PR
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(**kw):
+    c = dict(WL.CHANNEL_DEFAULTS)
+    c.update(kw)
+    return c
+
+
+def test_c1_first_step_face_fluxes():
+    """One step of the parity case: every interface flux and the new state."""
+    PR.oracle_threads()
+    g, o = PR.make_pair(WL.C1)
+    try:
+        g.step(1)
+        assert o.step(1) == 0
+        Fx, Fy = g.face_flux()
+        Rx, Ry = o.face_flux()
+        scale = np.max(np.abs(Rx), axis=(0, 1))
+        ex = np.max(np.abs(Fx - Rx), axis=(0, 1)) / scale
+        ey = np.max(np.abs(Fy - Ry), axis=(0, 1)) / np.maximum(np.max(np.abs(Ry), axis=(0, 1)), scale)
+        print("[parity] C1 step 1 face flux errors", ex, ey, flush=True)
+        assert np.all(ex < 1e-12) and np.all(ey < 1e-12)
+        f_gpu, W_gpu = g.state()
+        f_ref, W_ref = o.state()
+        PR.assert_within(PR.errors(PR.moments_of_W(W_gpu), PR.moments_of_W(W_ref), f_gpu, f_ref),
+                         PR.FP64_TOL, "C1 step 1")
+    finally:
+        g.close()
+        o.close()
+
+
+def test_c1_parity_full_run():
+    PR.run_and_compare(WL.C1, WL.C1_STEPS, label="C1 40x10 24^2 channel")
+
+
+@pytest.mark.parametrize("nx,ny,nu,nv", [(13, 7, 11, 9), (5, 9, 8, 13), (17, 3, 6, 6)])
+def test_ragged_periodic_boxes(nx, ny, nu, nv):
+    """Velocity counts that are not multiples of 64 and odd cell counts, periodic."""
+    case = _case(nx=nx, ny=ny, lx=1.3, ly=0.9, nu=nu, nv=nv, umax=4.5, vmax=5.5, kn=0.07, bc=0,
+                 noise=0.05, seed=11 + nx)
+    PR.run_and_compare(case, 25, label=f"periodic {nx}x{ny} {nu}x{nv}")
+
+
+@pytest.mark.parametrize("nx,ny,nu,nv", [(9, 5, 7, 7), (6, 4, 9, 5)])
+def test_ragged_channels_with_zero_velocities(nx, ny, nu, nv):
+    """Odd velocity counts put u = 0 and v = 0 on the grid (upwind weight 1/2)."""
+    case = _case(nx=nx, ny=ny, lx=2.0, ly=1.0, nu=nu, nv=nv, umax=5.0, vmax=5.0, kn=0.2,
+                 noise=0.02, seed=4)
+    PR.run_and_compare(case, 30, label=f"channel {nx}x{ny} {nu}x{nv}")
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_collisionless_limit(bc):
+    case = _case(nx=12, ny=6, lx=2.0, ly=1.0, nu=10, nv=9, umax=3.0, vmax=3.0, kn=float("inf"),
+                 bc=bc, noise=0.05, seed=8)
+    PR.run_and_compare(case, 20, label=f"collisionless bc={bc}")
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(1, 6, 1), (8, 1, 1), (1, 1, 0), (1, 5, 0), (2, 2, 1)])
+def test_degenerate_meshes(nx, ny, bc):
+    """Single row (both walls on one row), single column (inlet and outlet ghosts on one
+    cell), a 1x1 periodic box (every neighbour is the cell itself)."""
+    case = _case(nx=nx, ny=ny, lx=0.5 * nx, ly=0.5 * ny, nu=8, nv=8, umax=4.0, vmax=4.0, kn=0.3,
+                 bc=bc, noise=0.03, seed=21)
+    PR.run_and_compare(case, 15, label=f"degenerate {nx}x{ny} bc={bc}")
+
+
+def test_wide_velocity_space_inlet_noise():
+    """The wide-grid configuration's boundary treatment (seeded inlet U) on a small mesh."""
+    case = dict(WL.C3, nx=20, ny=6, nu=41, nv=41)
+    PR.run_and_compare(case, 20, label="C3-shaped small")
+
+
+def test_c2_full_size_steps():
+    """The 400x100 x 40^2 configuration the benchmark times, compared in full."""
+    PR.run_and_compare(WL.C2, 3, label="C2 400x100 40^2")
+
+
+def test_c3_full_size_steps():
+    """200x50 x 101^2 (10201 velocities per cell, padded to 10240)."""
+    PR.run_and_compare(WL.C3, 2, label="C3 200x50 101^2")
+
+
+def test_fp32_store_error_c1():
+    e = PR.run_and_compare(WL.C1, WL.C1_STEPS, precision="fp32_store", tol=PR.FP32_STORE_TOL,
+                           label="C1 FP32-store")
+    assert max(e.values()) > 1e-12      # it really is stored in FP32
+
+
+def test_runs_are_bitwise_deterministic():
+    kn, kw = WL.solver_kwargs(WL.C1)
+    a, b = ugks.Solver(kn, **kw), ugks.Solver(kn, **kw)
+    try:
+        a.step(20)
+        b.step(20)
+        fa, Wa = a.state()
+        fb, Wb = b.state()
+        assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb)
+    finally:
+        a.close()
+        b.close()
+
+
+def test_checkpoint_resume_is_bitwise():
+    kn, kw = WL.solver_kwargs(WL.C1)
+    a, b = ugks.Solver(kn, **kw), ugks.Solver(kn, **dict(kw, seed=99))
+    try:
+        a.step(10)
+        f, W = a.state()
+        b.set_state(f, W)
+        a.step(15)
+        b.step(15)
+        fa, Wa = a.state()
+        fb, Wb = b.state()
+        assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb)
+    finally:
+        a.close()
+        b.close()
+
+
+def test_invalid_state_is_reported_by_moments():
+    kn, kw = WL.solver_kwargs(WL.C1)
+    a = ugks.Solver(kn, **kw)
+    try:
+        f, W = a.state()
+        W[3, 7, 3] = -1.0
+        a.set_state(f, W)
+        a.step(1)
+        with pytest.raises(ugks.UgksError) as ex:
+            a.moments()
+        assert ex.value.code == ugks.UGKS_E_STATE
+    finally:
+        a.close()
+
+
+def test_kernel_timing_counts_launches():
+    kn, kw = WL.solver_kwargs(WL.C1)
+    a = ugks.Solver(kn, **kw)
+    try:
+        a.kernel_timing(True)
+        a.step(5)
+        t = a.kernel_timing()
+        assert all(t[k][1] == 5 for k in ugks.KERNELS)
+        assert all(t[k][0] > 0 for k in ugks.KERNELS)
+    finally:
+        a.close()
+
+
+def test_moving_maxwellian_fixed_point_on_gpu():
+    case = _case(nx=10, ny=10, lx=1.0, ly=1.0, nu=40, nv=40, umax=6.0, vmax=6.0, kn=0.05, bc=0,
+                 noise=0.0)
+    kn, kw = WL.solver_kwargs(case)
+    a = ugks.Solver(kn, **kw)
+    try:
+        f, W = a.state()
+        uk, _ = O.nodes(40, 6.0)
+        uu, vv = np.meshgrid(uk, uk, indexing="ij")
+        rho, U, V, T = 1.05, 0.2, -0.1, 0.95
+        g = rho / (math.pi * T) * np.exp(-((uu - U) ** 2 + (vv - V) ** 2) / T)
+        f[...] = g.ravel()
+        W[...] = (rho, rho * U, rho * V, 0.5 * rho * (U * U + V * V) + rho * T / 2)
+        a.set_state(f, W)
+        a.step(10)
+        f1, W1 = a.state()
+        assert np.array_equal(W1, W)
+        assert np.max(np.abs(f1 - f)) < 1e-14 * np.max(f)
+    finally:
+        a.close()
