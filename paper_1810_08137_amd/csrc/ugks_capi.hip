@@ -28,6 +28,7 @@ struct ugks_handle {
   int cur = 0;
   int64_t steps = 0;
   double tau_ref = 0.0;
+  std::vector<int> slot_of;  // device slot of canonical velocity k*nv + m
   std::string err;
   std::atomic<int> busy{0};
   // kernel timing
@@ -152,7 +153,7 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
 // Offsets of every buffer inside the workspace.
 Layout layout_of(const Shape& s, int prec) {
   const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
-  const size_t sizes[17] = {
+  const size_t sizes[18] = {
       s.nc * s.NVP * ss,                        // f0
       s.nc * s.NVP * ss,                        // f1
       s.nc * 4 * 8,                             // W
@@ -167,13 +168,14 @@ Layout layout_of(const Shape& s, int prec) {
       (size_t)s.NVP * 8,                        // Wq
       (size_t)s.NVP * 4,                        // kidx
       (size_t)s.NVP * 4,                        // midx
+      (size_t)(s.NVP / kWave) * 4,              // chunk_sign
       (size_t)s.K * 8,                          // uk
       (size_t)s.M * 8,                          // vm
       (size_t)s.ny * 8 + 64,                    // xi_in + flag
   };
   Layout L{};
   size_t off = 0;
-  for (int b = 0; b < 17; ++b) {
+  for (int b = 0; b < 18; ++b) {
     L.off[b] = off;
     off += round_up(sizes[b], kAlign);
   }
@@ -198,10 +200,11 @@ void carve(ugks_handle* h, const Layout& L, const Shape& s) {
   B.Wq = reinterpret_cast<double*>(base + L.off[11]);
   B.kidx = reinterpret_cast<int*>(base + L.off[12]);
   B.midx = reinterpret_cast<int*>(base + L.off[13]);
-  B.uk = reinterpret_cast<double*>(base + L.off[14]);
-  B.vm = reinterpret_cast<double*>(base + L.off[15]);
-  B.xi_in = reinterpret_cast<double*>(base + L.off[16]);
-  B.flag = reinterpret_cast<int*>(base + L.off[16] + round_up((size_t)s.ny * 8, 64));
+  B.chunk_sign = reinterpret_cast<int*>(base + L.off[14]);
+  B.uk = reinterpret_cast<double*>(base + L.off[15]);
+  B.vm = reinterpret_cast<double*>(base + L.off[16]);
+  B.xi_in = reinterpret_cast<double*>(base + L.off[17]);
+  B.flag = reinterpret_cast<int*>(base + L.off[17] + round_up((size_t)s.ny * 8, 64));
 }
 
 hipEvent_t pool_get(ugks_handle* h) {
@@ -370,17 +373,46 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   std::vector<double> uk, wk, vm, wm;
   velocity_nodes(s.K, vgrid->umax, uk, wk);
   velocity_nodes(s.M, vgrid->vmax, vm, wm);
+  // Velocity slots ordered by quadrant of (u, v), then the velocities with u = 0 or v = 0,
+  // then padding (weight 0) up to a multiple of 64.
   std::vector<double> U(s.NVP, 0.0), V(s.NVP, 0.0), Wq(s.NVP, 0.0);
   std::vector<int> kidx(s.NVP, 0), midx(s.NVP, 0);
-  for (int k = 0; k < s.K; ++k)
-    for (int m = 0; m < s.M; ++m) {
-      const int v = k * s.M + m;
-      U[v] = uk[k];
-      V[v] = vm[m];
-      Wq[v] = wk[k] * wm[m];
-      kidx[v] = k;
-      midx[v] = m;
+  h->slot_of.assign(s.NV, 0);
+  {
+    int slot = 0;
+    auto place = [&](int k, int m) {
+      U[slot] = uk[k];
+      V[slot] = vm[m];
+      Wq[slot] = wk[k] * wm[m];
+      kidx[slot] = k;
+      midx[slot] = m;
+      h->slot_of[k * s.M + m] = slot;
+      ++slot;
+    };
+    const int su[4] = {1, 1, -1, -1}, sv[4] = {1, -1, 1, -1};
+    for (int q = 0; q < 4; ++q)
+      for (int k = 0; k < s.K; ++k)
+        for (int m = 0; m < s.M; ++m)
+          if ((uk[k] > 0 ? 1 : (uk[k] < 0 ? -1 : 0)) == su[q] &&
+              (vm[m] > 0 ? 1 : (vm[m] < 0 ? -1 : 0)) == sv[q])
+            place(k, m);
+    for (int k = 0; k < s.K; ++k)
+      for (int m = 0; m < s.M; ++m)
+        if (uk[k] == 0.0 || vm[m] == 0.0) place(k, m);
+  }
+  std::vector<int> chunk_sign(s.NVP / kWave, 0);
+  for (int ch = 0; ch < s.NVP / kWave; ++ch) {
+    bool upos = true, uneg = true, vpos = true, vneg = true;
+    for (int l = 0; l < kWave; ++l) {
+      const int v = ch * kWave + l;
+      if (v >= s.NV) continue;  // padding carries weight 0 and may take either side
+      upos = upos && U[v] > 0;
+      uneg = uneg && U[v] < 0;
+      vpos = vpos && V[v] > 0;
+      vneg = vneg && V[v] < 0;
     }
+    chunk_sign[ch] = (upos ? 1 : 0) | (uneg ? 2 : 0) | (vpos ? 4 : 0) | (vneg ? 8 : 0);
+  }
   // diffuse-wall constants: moments of the unit-density wall Maxwellian over the velocities
   // that leave each wall, in the wall's local frame (v, u)
   P.wall_den_bot = P.wall_den_top = 0.0;
@@ -416,6 +448,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   P.Wq = B.Wq;
   P.kidx = B.kidx;
   P.midx = B.midx;
+  P.chunk_sign = B.chunk_sign;
   P.uk = B.uk;
   P.vm = B.vm;
   P.xi_in = B.xi_in;
@@ -429,6 +462,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
       {B.U, U.data(), U.size() * 8},        {B.V, V.data(), V.size() * 8},
       {B.Wq, Wq.data(), Wq.size() * 8},     {B.kidx, kidx.data(), kidx.size() * 4},
       {B.midx, midx.data(), midx.size() * 4}, {B.uk, uk.data(), uk.size() * 8},
+      {B.chunk_sign, chunk_sign.data(), chunk_sign.size() * 4},
       {B.vm, vm.data(), vm.size() * 8},     {B.xi_in, xi.data(), xi.size() * 8},
       {B.W, W0.data(), W0.size() * 8},
   };
@@ -555,10 +589,12 @@ int ugks_get_state(ugks_handle* h, double* f, double* W) {
   if (e != hipSuccess) return hip_fail(h, e, "reading the state");
   if (f) {
     for (size_t c = 0; c < nc; ++c)
-      for (size_t v = 0; v < NV; ++v)
+      for (size_t v = 0; v < NV; ++v) {
+        const size_t sl = c * NVP + (size_t)h->slot_of[v];
         f[c * NV + v] = h->prec == UGKS_FP32_STORE
-                            ? (double)reinterpret_cast<const float*>(raw.data())[c * NVP + v]
-                            : reinterpret_cast<const double*>(raw.data())[c * NVP + v];
+                            ? (double)reinterpret_cast<const float*>(raw.data())[sl]
+                            : reinterpret_cast<const double*>(raw.data())[sl];
+      }
   }
   if (flag) return fail(h, UGKS_E_STATE, "invalid state flagged on the device%s");
   return UGKS_OK;
@@ -575,10 +611,11 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
     raw.assign(nc * NVP * h->ssize, 0);
     for (size_t c = 0; c < nc; ++c)
       for (size_t v = 0; v < NV; ++v) {
+        const size_t sl = c * NVP + (size_t)h->slot_of[v];
         if (h->prec == UGKS_FP32_STORE)
-          reinterpret_cast<float*>(raw.data())[c * NVP + v] = (float)f[c * NV + v];
+          reinterpret_cast<float*>(raw.data())[sl] = (float)f[c * NV + v];
         else
-          reinterpret_cast<double*>(raw.data())[c * NVP + v] = f[c * NV + v];
+          reinterpret_cast<double*>(raw.data())[sl] = f[c * NV + v];
       }
     e = hipMemcpyAsync(h->B.f[h->cur], raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream);
   }

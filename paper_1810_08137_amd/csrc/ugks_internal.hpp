@@ -18,19 +18,22 @@ constexpr int kMaxTable = 1024;  // nu + nv limit: six separable exp tables of n
 
 // Interface record (doubles), written by the interface kernel, read by the cell update.
 // Frame: "normal"/"tangential" velocity of the face; for x-faces (u, v), for y-faces (v, u).
+// The time-integrated distribution flux of one velocity is
+//   un * ( GC Ek[k] Em[m] P(un, ut) + M4 fhat - M5 (un sn + ut st) )
+// with P(un, ut) = e0 + e3 c2h + un (e1 + e4 un + e5 ut + e7 c2h) + ut (e2 + e6 ut + e8 c2h),
+// c2h = (un^2 + ut^2)/2: the time weights Mt1..Mt3 and the slopes a, b, A of S4 folded into
+// nine coefficients (e1, e4, e5, e7 depend on the side the particle comes from).
 enum RecField {
-  R_FX = 0,      // [0..3] macroscopic flux, global frame (rho, rho U, rho V, rho E)
-  R_GCOEF = 4,   // rho0 lambda0 / pi of the interface Maxwellian (or of the wall Maxwellian)
-  R_LAM = 5,     // lambda0
-  R_UX = 6,      // equilibrium velocity, global x component
-  R_VY = 7,      // equilibrium velocity, global y component
-  R_MT = 8,      // [8..12] time weights Mt1..Mt5
-  R_AL = 13,     // [13..16] normal slope for u_n > 0
-  R_AR = 17,     // [17..20] normal slope for u_n < 0
-  R_B = 21,      // [21..24] tangential slope
-  R_A = 25,      // [25..28] time slope
-  R_KIND = 29,   // 0 interior, 1 wall, 2 collisionless interior
-  R_LEN = 30,    // face length
+  R_FX = 0,     // [0..3] macroscopic flux, global frame (rho, rho U, rho V, rho E)
+  R_GC = 4,     // len * rho0 lambda0 / pi (interior); len * dt * rho_w lambda_w / pi (wall)
+  R_LAM = 5,    // lambda of the interface (or wall) Maxwellian
+  R_UX = 6,     // its velocity, global x component
+  R_VY = 7,     // its velocity, global y component
+  R_E = 8,      // [8..16] e0..e8 for un > 0 (normal slope aL)
+  R_ER = 17,    // [17..20] e1, e4, e5, e7 for un < 0 (normal slope aR)
+  R_M4 = 21,    // len * Mt4 (wall: len * dt)
+  R_M5 = 22,    // len * Mt5 (wall: 0)
+  R_KIND = 23,  // 0 interior, 1 wall, 2 collisionless interior
 };
 enum FaceKind { K_INTERIOR = 0, K_WALL = 1, K_FREE = 2 };
 
@@ -51,6 +54,7 @@ struct KParams {
   const double* Wq;     // [NVP] quadrature weight (0 in pads)
   const int* kidx;      // [NVP] k of each velocity slot
   const int* midx;      // [NVP] m of each velocity slot
+  const int* chunk_sign;  // [NVP/64] per 64-slot chunk: bit0/1 all u > 0 / < 0, bit2/3 for v
   const double* uk;     // [K]
   const double* vm;     // [M]
   const double* xi_in;  // [ny] inlet noise
@@ -72,6 +76,7 @@ struct Buffers {
   double* Wq;
   int* kidx;
   int* midx;
+  int* chunk_sign;  // [NVP/64]
   double* uk;       // [K]
   double* vm;       // [M]
   double* xi_in;    // [ny]
@@ -79,7 +84,7 @@ struct Buffers {
 };
 
 struct Layout {
-  size_t off[17];
+  size_t off[18];
   size_t total;
 };
 

@@ -7,12 +7,14 @@
 //           wavefront per cell, velocities across lanes, a 64-wide reduce-scatter at the end
 //   faces   per interface: add the two sides' sums, then the scalar part of the flux
 //           (S2-S5: Maxwellian moments, time weights, micro slopes, equilibrium flux) into a
-//           32-double record
+//           record of folded coefficients
 //   update  per cell and velocity: rebuild the upwind f at the four faces, the interface
 //           Maxwellian from separable exp tables (S6), the distribution flux (S8), then
 //           Eq. (4) for W and Eq. (3) for f
-// f is laid out [cell][velocity] with the velocity index contiguous and padded to a multiple
-// of 64, so every wavefront load is coalesced along velocity.
+// f is laid out [cell][velocity slot] with the slot index contiguous and padded to a multiple
+// of 64, so every wavefront load is coalesced.  Slots are ordered by velocity quadrant, so
+// most 64-slot chunks have one sign of u and one of v: their upwind choices and moment slots
+// are then uniform across the wavefront.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -23,22 +25,39 @@ namespace ugks {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kCellsPerBlock = 4;  // one wavefront per cell
 
 // ------------------------------------------------------------------ storage
 template <typename S>
-__device__ __forceinline__ double ld(const S* __restrict__ p, size_t i) {
+__device__ __forceinline__ double ld(const S* __restrict__ p, unsigned i) {
   return static_cast<double>(p[i]);
 }
+// Load at a 32-bit byte offset from a uniform base: one instruction with a scalar base.
+template <typename T>
+__device__ __forceinline__ T ldb(const T* __restrict__ p, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
+}
 template <typename S>
-__device__ __forceinline__ void st(S* __restrict__ p, size_t i, double x) {
+__device__ __forceinline__ void st(S* __restrict__ p, unsigned i, double x) {
   p[i] = static_cast<S>(x);
 }
 
 // ------------------------------------------------------------------ pointwise physics
-// Van Leer limited slope of two one-sided differences (second-order reconstruction, Sec. 2.A).
-__device__ __forceinline__ double limited(double p, double q) {
+// Reciprocal: hardware estimate refined by two Newton steps (relative error ~1 ulp).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Van Leer limited slope of two one-sided differences, times `scale` (second-order
+// reconstruction, Sec. 2.A): 2 p q / (p + q) when p and q agree in sign, else 0.
+__device__ __forceinline__ double limited(double p, double q, double scale) {
   const double pq = p * q;
-  return pq > 0.0 ? 2.0 * pq / (p + q) : 0.0;
+  const double r = (pq * recip(p + q)) * scale;  // evaluated on every lane, then selected
+  return pq > 0.0 ? r : 0.0;
 }
 
 // Upwind weight of the left state for normal velocity un (1/2 when un = 0).
@@ -123,7 +142,9 @@ __device__ __forceinline__ void micro_slope(const Prim& p, const double* s, doub
   a[0] = s[0] / p.rho - p.U * a[1] - p.V * a[2] - 0.5 * a[3] * q2;
 }
 
-// S3 time weights of Eq. (2) integrated over [0, dt] (see the record layout for their use).
+// S3 time weights of Eq. (2) integrated over [0, dt]:
+// Mt1 int(1 - e^{-t/tau}), Mt2 -int(tau(1 - e^{-t/tau}) - t e^{-t/tau}),
+// Mt3 int(t - tau(1 - e^{-t/tau})), Mt4 int e^{-t/tau}, Mt5 int t e^{-t/tau}.
 __device__ __forceinline__ void time_weights(double dt, double tau, double* Mt) {
   const double e = exp(-dt / tau);
   Mt[3] = -tau * expm1(-dt / tau);
@@ -135,6 +156,14 @@ __device__ __forceinline__ void time_weights(double dt, double tau, double* Mt) 
 
 // ------------------------------------------------------------------ addressing
 __device__ __forceinline__ int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+// Workgroups are handed to the 8 XCDs round-robin; renumber them so that each XCD works
+// through one contiguous range of cells (its own L2 then serves the stencil neighbours).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 
 // f slab of column i of row j, i in [-2, nx+1]: a cell, a wrapped cell (periodic) or the
 // inlet/outlet ghost column (channel).
@@ -170,18 +199,35 @@ __device__ __forceinline__ double wave_sum(double x) {
 // (un, ut), reconstructed f and its normal/tangential slopes.
 __device__ __forceinline__ void add_side(double* a, double wt, double un, double ut, double c2h,
                                          double fh, double sn, double st) {
-  const double psi[4] = {1.0, un, ut, c2h};
   const double x0 = wt * fh;
   const double x1 = wt * st;
   const double x2 = x0 * un;
-  const double x3 = wt * un * (un * sn + ut * st);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    a[q] += x0 * psi[q];
-    a[4 + q] += x1 * psi[q];
-    a[8 + q] += x2 * psi[q];
-    a[12 + q] += x3 * psi[q];
-  }
+  const double x3 = (wt * un) * fma(un, sn, ut * st);
+  a[0] += x0;
+  a[1] = fma(x0, un, a[1]);
+  a[2] = fma(x0, ut, a[2]);
+  a[3] = fma(x0, c2h, a[3]);
+  a[4] += x1;
+  a[5] = fma(x1, un, a[5]);
+  a[6] = fma(x1, ut, a[6]);
+  a[7] = fma(x1, c2h, a[7]);
+  a[8] += x2;
+  a[9] = fma(x2, un, a[9]);
+  a[10] = fma(x2, ut, a[10]);
+  a[11] = fma(x2, c2h, a[11]);
+  a[12] += x3;
+  a[13] = fma(x3, un, a[13]);
+  a[14] = fma(x3, ut, a[14]);
+  a[15] = fma(x3, c2h, a[15]);
+}
+
+// Per-chunk sign code of the velocity slots: +1 / -1 when every real slot of the chunk has
+// that sign of the component, 0 when mixed (or zero).
+__device__ __forceinline__ int chunk_sign_u(int code) {
+  return (code & 1) ? 1 : ((code & 2) ? -1 : 0);
+}
+__device__ __forceinline__ int chunk_sign_v(int code) {
+  return (code & 4) ? 1 : ((code & 8) ? -1 : 0);
 }
 
 // ================================================================== kernels
@@ -198,7 +244,7 @@ __global__ __launch_bounds__(kWave) void init_kernel(KParams P, S* __restrict__ 
     double g = 0.0;
     if (v < P.NV) {
       const double du = P.U[v] - p.U, dv = P.V[v] - p.V;
-      g = coef * exp(-p.lam * (du * du + dv * dv));
+      g = P.Wq[v] > 0.0 ? coef * exp(-p.lam * (du * du + dv * dv)) : 0.0;
     }
     st(fc, v, g);
   }
@@ -213,7 +259,7 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(KParams P, const double* _
   const int j = blockIdx.x, side = blockIdx.y, lane = threadIdx.x;
   const int col = side == 0 ? 0 : P.nx - 1;
   Prim pc, pg;
-  bool ok = prim_of(W + 4 * ((size_t)j * P.nx + col), pc);
+  const bool ok = prim_of(W + 4 * ((size_t)j * P.nx + col), pc);
   if (side == 0) {
     const double T = P.T_in;
     pg.lam = 1.0 / T;
@@ -246,16 +292,16 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(KParams P, const double* _
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
   for (int v = lane; v < P.NVP; v += kWave) {
-    const double u = P.U[v], vv = P.V[v];
+    const double u = P.U[v], vv = P.V[v], w = P.Wq[v];
     double g = 0.0;
-    if (v < P.NV) {
+    if (w > 0.0) {
       const double du = u - pg.U, dv = vv - pg.V;
       g = coef * exp(-pg.lam * (du * du + dv * dv));
     }
     st(row, v, g);
     const double gs = ld(row, v);  // the value the cells will read
     const double h = side == 0 ? upwind_left(u) : 1.0 - upwind_left(u);
-    add_side(acc, P.Wq[v] * h, u, vv, 0.5 * (u * u + vv * vv), gs, 0.0, 0.0);
+    add_side(acc, w * h, u, vv, 0.5 * (u * u + vv * vv), gs, 0.0, 0.0);
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -264,15 +310,18 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(KParams P, const double* _
   }
 }
 
-// Per cell: slopes and the outgoing moment sums of all four faces.  One wavefront per cell.
+// Per cell: slopes and the outgoing moment sums of all four faces.  One wavefront per cell,
+// four cells per block.
 template <typename S>
-__global__ __launch_bounds__(kWave) void sums_kernel(KParams P, const S* __restrict__ f,
-                                                     const S* __restrict__ fg,
-                                                     double* __restrict__ hs) {
-  const int c = blockIdx.x, lane = threadIdx.x;
+__global__ __launch_bounds__(kWave* kCellsPerBlock) void sums_kernel(
+    KParams P, const S* __restrict__ f, const S* __restrict__ fg, double* __restrict__ hs) {
+  const int lane = threadIdx.x & (kWave - 1);
+  // the wavefront index is uniform: keep everything derived from it in scalar registers
+  const int c = xcd_block(blockIdx.x, gridDim.x) * kCellsPerBlock +
+                __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (c >= P.nx * P.ny) return;
   const int i = c % P.nx, j = c / P.nx;
-  const bool chan = P.bc == UGKS_BC_CHANNEL;
-  const bool wall_row = chan && (j == 0 || j == P.ny - 1);
+  const bool wall_row = P.bc == UGKS_BC_CHANNEL && (j == 0 || j == P.ny - 1);
   const S* f0 = f + (size_t)c * P.NVP;
   const S* fw = xslab(P, f, fg, i - 1, j);
   const S* fe = xslab(P, f, fg, i + 1, j);
@@ -282,44 +331,86 @@ __global__ __launch_bounds__(kWave) void sums_kernel(KParams P, const S* __restr
   double acc[kSlots];
 #pragma unroll
   for (int q = 0; q < kSlots; ++q) acc[q] = 0.0;
-  for (int v = lane; v < P.NVP; v += kWave) {
-    const double fc = ld(f0, v);
-    const double sx = limited(ld(fe, v) - fc, fc - ld(fw, v)) * P.inv_dx;
-    const double sy = wall_row ? 0.0 : limited(ld(fn, v) - fc, fc - ld(fs, v)) * P.inv_dy;
-    const double u = P.U[v], vv = P.V[v], w = P.Wq[v];
-    const double c2h = 0.5 * (u * u + vv * vv);
-    const double hx = upwind_left(u), hy = upwind_left(vv);
-    add_side(acc + 16 * S_XP, w * hx, u, vv, c2h, fc + hdx * sx, sx, sy);
-    add_side(acc + 16 * S_XM, w * (1.0 - hx), u, vv, c2h, fc - hdx * sx, sx, sy);
-    add_side(acc + 16 * S_YP, w * hy, vv, u, c2h, fc + hdy * sy, sy, sx);
-    add_side(acc + 16 * S_YM, w * (1.0 - hy), vv, u, c2h, fc - hdy * sy, sy, sx);
+  const int nch = P.NVP / kWave;
+  // stencil values are loaded two chunks ahead of the one being summed
+  double b0[5], b1[5];
+  {
+    const unsigned o0 = (unsigned)lane * (unsigned)sizeof(S);
+    b0[0] = (double)ldb(f0, o0);
+    b0[1] = (double)ldb(fw, o0);
+    b0[2] = (double)ldb(fe, o0);
+    b0[3] = (double)ldb(fs, o0);
+    b0[4] = (double)ldb(fn, o0);
+    const unsigned o1 = (unsigned)(nch > 1 ? kWave + lane : lane) * (unsigned)sizeof(S);
+    b1[0] = (double)ldb(f0, o1);
+    b1[1] = (double)ldb(fw, o1);
+    b1[2] = (double)ldb(fe, o1);
+    b1[3] = (double)ldb(fs, o1);
+    b1[4] = (double)ldb(fn, o1);
+  }
+  for (int ch = 0; ch < nch; ++ch) {
+    const int v = ch * kWave + lane;
+    const int code = P.chunk_sign[ch];
+    const int su = chunk_sign_u(code), sv = chunk_sign_v(code);
+    const double fc = b0[0], fwv = b0[1], fev = b0[2], fsv = b0[3], fnv = b0[4];
+    const unsigned on = (unsigned)(ch + 2 < nch ? v + 2 * kWave : v) * (unsigned)sizeof(S);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) b0[q] = b1[q];
+    b1[0] = (double)ldb(f0, on);
+    b1[1] = (double)ldb(fw, on);
+    b1[2] = (double)ldb(fe, on);
+    b1[3] = (double)ldb(fs, on);
+    b1[4] = (double)ldb(fn, on);
+    const double sx = limited(fev - fc, fc - fwv, 2.0 * P.inv_dx);
+    const double syl = limited(fnv - fc, fc - fsv, 2.0 * P.inv_dy);
+    const double sy = wall_row ? 0.0 : syl;
+    const unsigned v8 = (unsigned)v * 8u;
+    const double u = ldb(P.U, v8), vv = ldb(P.V, v8), w = ldb(P.Wq, v8);
+    const double c2h = 0.5 * fma(u, u, vv * vv);
+    if (su > 0) {
+      add_side(acc + 16 * S_XP, w, u, vv, c2h, fma(hdx, sx, fc), sx, sy);
+    } else if (su < 0) {
+      add_side(acc + 16 * S_XM, w, u, vv, c2h, fma(-hdx, sx, fc), sx, sy);
+    } else {
+      const double hx = upwind_left(u);
+      add_side(acc + 16 * S_XP, w * hx, u, vv, c2h, fma(hdx, sx, fc), sx, sy);
+      add_side(acc + 16 * S_XM, w * (1.0 - hx), u, vv, c2h, fma(-hdx, sx, fc), sx, sy);
+    }
+    if (sv > 0) {
+      add_side(acc + 16 * S_YP, w, vv, u, c2h, fma(hdy, sy, fc), sy, sx);
+    } else if (sv < 0) {
+      add_side(acc + 16 * S_YM, w, vv, u, c2h, fma(-hdy, sy, fc), sy, sx);
+    } else {
+      const double hy = upwind_left(vv);
+      add_side(acc + 16 * S_YP, w * hy, vv, u, c2h, fma(hdy, sy, fc), sy, sx);
+      add_side(acc + 16 * S_YM, w * (1.0 - hy), vv, u, c2h, fma(-hdy, sy, fc), sy, sx);
+    }
   }
   reduce_scatter<32>(acc, lane);
   hs[(size_t)c * kSlots + lane] = acc[0];
 }
 
 // S2-S5 at one interior interface, local frame.  S = [W0, Wt, Q1, Q2].  Writes the local
-// macroscopic flux to F and every coefficient the cell update needs to rec.
+// macroscopic flux to F and the folded coefficients of the distribution flux to rec.
 __device__ void interface_scalars(const KParams& P, const double* S, const double* WL,
                                   const double* WR, double dn, double len, double* F,
-                                  double* rec) {
+                                  double* rec, double& U0, double& V0) {
   const double* W0 = S;
   const double* Wt = S + 4;
   const double* Q1 = S + 8;
   const double* Q2 = S + 12;
-  rec[R_LEN] = len;
   if (P.collisionless) {
     const double Mt4 = P.dt, Mt5 = 0.5 * P.dt * P.dt;
 #pragma unroll
     for (int q = 0; q < 4; ++q) F[q] = len * (Mt4 * Q1[q] - Mt5 * Q2[q]);
-    rec[R_MT + 0] = 0.0;
-    rec[R_MT + 1] = 0.0;
-    rec[R_MT + 2] = 0.0;
-    rec[R_MT + 3] = Mt4;
-    rec[R_MT + 4] = Mt5;
-    rec[R_KIND] = K_FREE;
-    rec[R_GCOEF] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 13; ++q) rec[R_E + q] = 0.0;
+    rec[R_GC] = 0.0;
     rec[R_LAM] = 0.0;
+    rec[R_M4] = len * Mt4;
+    rec[R_M5] = len * Mt5;
+    rec[R_KIND] = K_FREE;
+    U0 = V0 = 0.0;
     return;
   }
   Prim p0;
@@ -357,20 +448,27 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
     const double feq = p0.rho * (Mt[0] * e0[q] + Mt[1] * (eL[q] + eR[q] + eb[q]) + Mt[2] * eA[q]);
     F[q] = len * (feq + Mt[3] * Q1[q] - Mt[4] * Q2[q]);
   }
-  rec[R_GCOEF] = p0.rho * p0.lam / kPi;
+  // folded polynomial of the equilibrium part of the distribution flux
+  rec[R_E + 0] = Mt[0] + Mt[2] * A[0];
+  rec[R_E + 1] = Mt[1] * aL[0] + Mt[2] * A[1];
+  rec[R_E + 2] = Mt[1] * b[0] + Mt[2] * A[2];
+  rec[R_E + 3] = Mt[2] * A[3];
+  rec[R_E + 4] = Mt[1] * aL[1];
+  rec[R_E + 5] = Mt[1] * (aL[2] + b[1]);
+  rec[R_E + 6] = Mt[1] * b[2];
+  rec[R_E + 7] = Mt[1] * aL[3];
+  rec[R_E + 8] = Mt[1] * b[3];
+  rec[R_ER + 0] = Mt[1] * aR[0] + Mt[2] * A[1];
+  rec[R_ER + 1] = Mt[1] * aR[1];
+  rec[R_ER + 2] = Mt[1] * (aR[2] + b[1]);
+  rec[R_ER + 3] = Mt[1] * aR[3];
+  rec[R_GC] = len * p0.rho * p0.lam / kPi;
   rec[R_LAM] = p0.lam;
-#pragma unroll
-  for (int q = 0; q < 5; ++q) rec[R_MT + q] = Mt[q];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    rec[R_AL + q] = aL[q];
-    rec[R_AR + q] = aR[q];
-    rec[R_B + q] = b[q];
-    rec[R_A + q] = A[q];
-  }
+  rec[R_M4] = len * Mt[3];
+  rec[R_M5] = len * Mt[4];
   rec[R_KIND] = K_INTERIOR;
-  rec[6] = p0.U;  // local normal / tangential; the caller maps them to the global frame
-  rec[7] = p0.V;
+  U0 = p0.U;
+  V0 = p0.V;
 }
 
 // One thread per interface: x-faces first (ny rows of nx+1), then y-faces (ny+1 rows of nx).
@@ -385,6 +483,7 @@ __global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __r
   const long nfy = (long)(P.ny + 1) * P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
   double S[16], F[4];
+  double U0, V0;
   if (e < nfx) {
     const int j = (int)(e / (P.nx + 1)), i = (int)(e % (P.nx + 1));
     const double *sL, *sR, *WL, *WR;
@@ -413,10 +512,11 @@ __global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __r
       wr[q] = WR[q];
     }
     double* rec = recx + (size_t)e * kRec;
-    interface_scalars(P, S, wl, wr, P.dx, P.dy, F, rec);
+    interface_scalars(P, S, wl, wr, P.dx, P.dy, F, rec, U0, V0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) rec[R_FX + q] = F[q];
-    // local frame = global frame for x-faces (rec[6], rec[7] already hold U, V)
+    rec[R_UX] = U0;
+    rec[R_VY] = V0;
     return;
   }
   if (e >= nfx + nfy) return;
@@ -439,12 +539,13 @@ __global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __r
     rec[R_FX + 1] = Fl[2];
     rec[R_FX + 2] = Fl[1];
     rec[R_FX + 3] = Fl[3];
-    rec[R_GCOEF] = rho_w * P.lam_w / kPi;
+    rec[R_GC] = s * rho_w * P.lam_w / kPi;
     rec[R_LAM] = P.lam_w;
     rec[R_UX] = 0.0;
     rec[R_VY] = 0.0;
+    rec[R_M4] = s;
+    rec[R_M5] = 0.0;
     rec[R_KIND] = K_WALL;
-    rec[R_LEN] = P.dx;
     if (!(rho_w > 0.0) || !isfinite(rho_w)) *P.flag = 1;
     return;
   }
@@ -456,52 +557,185 @@ __global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __r
   for (int q = 0; q < 16; ++q) S[q] = sL[q] + sR[q];
   const double wl[4] = {W[4 * cl], W[4 * cl + 2], W[4 * cl + 1], W[4 * cl + 3]};
   const double wr[4] = {W[4 * cr], W[4 * cr + 2], W[4 * cr + 1], W[4 * cr + 3]};
-  interface_scalars(P, S, wl, wr, P.dy, P.dx, F, rec);
+  interface_scalars(P, S, wl, wr, P.dy, P.dx, F, rec, U0, V0);
   rec[R_FX + 0] = F[0];
   rec[R_FX + 1] = F[2];
   rec[R_FX + 2] = F[1];
   rec[R_FX + 3] = F[3];
-  const double un0 = rec[6], ut0 = rec[7];
-  rec[R_UX] = ut0;
-  rec[R_VY] = un0;
+  rec[R_UX] = V0;  // local (normal, tangential) = global (y, x)
+  rec[R_VY] = U0;
 }
 
-// S6 + S8: time-integrated flux of f through one face for one velocity.  tk/tm: separable
-// exp tables of the face's Maxwellian along u and v; (un, ut) the face-frame velocity.
-__device__ __forceinline__ double face_flux(const double* __restrict__ r,
-                                            const double* __restrict__ tk,
-                                            const double* __restrict__ tm, int k, int m,
-                                            double un, double ut, double fh, double sn,
-                                            double st) {
-  const double free_part = r[R_MT + 3] * fh - r[R_MT + 4] * (un * sn + ut * st);
-  if (r[R_KIND] == (double)K_FREE) return r[R_LEN] * un * free_part;
-  const double c2h = 0.5 * (un * un + ut * ut);
+// ------------------------------------------------------------------ update kernel
+// Each wavefront (one cell) builds in LDS, for each of its four faces, the equilibrium part of
+// the distribution flux in separable form: with un the normal and ut the tangential velocity,
+//   GC En(un) Et(ut) P(un, ut) = TE[t] (TA[n] + ut (TB[n] + ut (TC[n] + ut TD[n])))
+// where P is the folded cubic of the record, n / t index the normal / tangential velocity node
+// and the normal-slope choice (aL for un > 0, aR for un < 0) is made per node n.  The cell's
+// g^n and g^{n+1} are kept as products of two 1D tables with the Eq. (3) weights folded in.
+struct Tab {
+  int xl_p, xr_p, yb_p, yt_p;          // poly tables, 4 doubles per normal node
+  int xl_e, xr_e, yb_e, yt_e;          // tangential exp tables
+  int gn_k, gn_m, g1_k, g1_m;          // g^n, g^{n+1} factors
+  int total;
+};
+
+__device__ __forceinline__ Tab tab_layout(int K, int M) {
+  Tab t;
+  t.xl_p = 0;
+  t.xr_p = 4 * K;
+  t.yb_p = 8 * K;
+  t.yt_p = 8 * K + 4 * M;
+  t.xl_e = 8 * K + 8 * M;
+  t.xr_e = t.xl_e + M;
+  t.yb_e = t.xr_e + M;
+  t.yt_e = t.yb_e + K;
+  t.gn_k = t.yt_e + K;
+  t.gn_m = t.gn_k + K;
+  t.g1_k = t.gn_m + M;
+  t.g1_m = t.g1_k + K;
+  t.total = t.g1_m + M;
+  return t;
+}
+
+// Fill the four-entry polynomial table of one face at normal node with velocity un.
+__device__ __forceinline__ void face_poly(const double* __restrict__ r, double un, double lam,
+                                          double U0, double* out) {
+  const double d = un - U0;
+  const double En = exp(-lam * d * d) * r[R_GC];
   const bool pos = un > 0.0;
-  const double a0 = pos ? r[R_AL + 0] : r[R_AR + 0];
-  const double a1 = pos ? r[R_AL + 1] : r[R_AR + 1];
-  const double a2 = pos ? r[R_AL + 2] : r[R_AR + 2];
-  const double a3 = pos ? r[R_AL + 3] : r[R_AR + 3];
-  const double pa = a0 + a1 * un + a2 * ut + a3 * c2h;
-  const double pb = r[R_B] + r[R_B + 1] * un + r[R_B + 2] * ut + r[R_B + 3] * c2h;
-  const double pA = r[R_A] + r[R_A + 1] * un + r[R_A + 2] * ut + r[R_A + 3] * c2h;
-  const double G = r[R_GCOEF] * tk[k] * tm[m];
-  const double poly = r[R_MT] + r[R_MT + 1] * (un * pa + ut * pb) + r[R_MT + 2] * pA;
-  return r[R_LEN] * un * (G * poly + free_part);
+  const double e1 = pos ? r[R_E + 1] : r[R_ER + 0];
+  const double e4 = pos ? r[R_E + 4] : r[R_ER + 1];
+  const double e5 = pos ? r[R_E + 5] : r[R_ER + 2];
+  const double e7 = pos ? r[R_E + 7] : r[R_ER + 3];
+  const double e0 = r[R_E + 0], e2 = r[R_E + 2], e3 = r[R_E + 3], e6 = r[R_E + 6],
+               e8 = r[R_E + 8];
+  // P(un, ut) = A + ut (B + ut (C + ut D)) with
+  // A = e0 + un (e1 + un (e4 + e3/2 + un e7/2)), B = e2 + un (e5 + un e8/2),
+  // C = e6 + e3/2 + un e7/2, D = e8/2
+  out[0] = En * fma(un, fma(un, fma(un, 0.5 * e7, e4 + 0.5 * e3), e1), e0);
+  out[1] = En * fma(un, fma(un, 0.5 * e8, e5), e2);
+  out[2] = En * fma(un, 0.5 * e7, e6 + 0.5 * e3);
+  out[3] = En * (0.5 * e8);
 }
 
-// Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  One wavefront per cell; six
-// separable exp tables (four faces, g^n, g^{n+1}) of nu + nv doubles each in LDS.
+// Equilibrium part at one velocity from a face's tables (poly at the normal node, E at the
+// tangential node) and the time-integrated flux of the face.
+__device__ __forceinline__ double face_flux(double2 pab, double2 pcd, double E, double un,
+                                            double ut, double fh, double sn, double st,
+                                            double m4, double m5) {
+  const double G = E * fma(ut, fma(ut, fma(ut, pcd.y, pcd.x), pab.y), pab.x);
+  const double free_part = fma(m4, fh, -m5 * fma(un, sn, ut * st));
+  return un * (G + free_part);
+}
+
 template <typename S>
-__global__ __launch_bounds__(kWave) void update_kernel(KParams P, const S* __restrict__ fin,
-                                                       S* __restrict__ fout,
-                                                       const S* __restrict__ fg,
-                                                       const double* __restrict__ recx,
-                                                       const double* __restrict__ recy,
-                                                       double* __restrict__ W) {
-  extern __shared__ double tab[];
-  const int c = blockIdx.x, lane = threadIdx.x;
-  const int i = c % P.nx, j = c / P.nx;
-  const int KM = P.K + P.M;
+struct UpdateCtx {
+  const S* f0;
+  const S* xw;
+  const S* xe;
+  const S* xww;
+  const S* xee;
+  const S* sw;
+  const S* sc;
+  const S* se;
+  const S* nw;
+  const S* nc;
+  const S* ne;
+  const S* scc;
+  const S* ncc;
+};
+
+// Left-minus-right flux difference for one velocity.  SX = +1 / -1: u has that sign across
+// the wavefront; 0: per lane.  All loads are unconditional (every slab pointer is valid);
+// boundaries only switch results.
+template <int SX, typename S>
+__device__ __forceinline__ double x_part(const KParams& P, const UpdateCtx<S>& X, unsigned vb,
+                                         double u, double vv, double fc, double fW, double fE,
+                                         double sx0, double sy0, bool ghost_w, bool ghost_e,
+                                         bool wall_row, const double* lp, const double* rp,
+                                         double le, double re, double m4l, double m5l,
+                                         double m4r, double m5r) {
+  // particles with u > 0 enter through the left face from cell i-1 (the upwind cell X)
+  const bool right = SX > 0 ? true : (SX < 0 ? false : (u > 0.0));
+  const double fXX = (double)ldb(right ? X.xww : X.xee, vb);
+  const double fXn = (double)ldb(right ? X.nw : X.ne, vb);
+  const double fXs = (double)ldb(right ? X.sw : X.se, vb);
+  const double fX = right ? fW : fE;
+  const bool ghostX = right ? ghost_w : ghost_e;
+  const double sxl = right ? limited(fc - fX, fX - fXX, 2.0 * P.inv_dx)
+                           : limited(fXX - fX, fX - fc, 2.0 * P.inv_dx);
+  const double syl = limited(fXn - fX, fX - fXs, 2.0 * P.inv_dy);
+  const double sxX = ghostX ? 0.0 : sxl;
+  const double syX = (ghostX || wall_row) ? 0.0 : syl;
+  const double sgn_hdx = right ? 0.5 * P.dx : -0.5 * P.dx;
+  const double fh_in = fma(sgn_hdx, sxX, fX);
+  const double fh_own = fma(sgn_hdx, sx0, fc);
+  // left face: upwind is X when moving right, the cell itself when moving left
+  const double fl = right ? fh_in : fh_own, snl = right ? sxX : sx0, stl = right ? syX : sy0;
+  const double fr = right ? fh_own : fh_in, snr = right ? sx0 : sxX, str = right ? sy0 : syX;
+  const double2 lab = *reinterpret_cast<const double2*>(lp);
+  const double2 lcd = *reinterpret_cast<const double2*>(lp + 2);
+  const double2 rab = *reinterpret_cast<const double2*>(rp);
+  const double2 rcd = *reinterpret_cast<const double2*>(rp + 2);
+  const double Fl = face_flux(lab, lcd, le, u, vv, fl, snl, stl, m4l, m5l);
+  const double Fr = face_flux(rab, rcd, re, u, vv, fr, snr, str, m4r, m5r);
+  return Fl - Fr;
+}
+
+// Bottom-minus-top flux difference.  Walls: particles leaving a wall follow rho_w times the
+// wall Maxwellian (its tables hold dx dt rho_w g_w), those reaching it carry the wall-row value.
+template <int SY, typename S>
+__device__ __forceinline__ double y_part(const KParams& P, const UpdateCtx<S>& X, unsigned vb,
+                                         double u, double vv, double fc, double fS, double fN,
+                                         double sx0, double sy0, bool wall_b, bool wall_t,
+                                         bool s_wallrow, bool n_wallrow, const double* bp,
+                                         const double* tp, double be, double te, double m4b,
+                                         double m5b, double m4t, double m5t) {
+  const bool up = SY > 0 ? true : (SY < 0 ? false : (vv > 0.0));
+  const double fYY = (double)ldb(up ? X.scc : X.ncc, vb);
+  const double fYe = (double)ldb(up ? X.se : X.ne, vb);
+  const double fYw = (double)ldb(up ? X.sw : X.nw, vb);
+  const double fY = up ? fS : fN;
+  const bool Y_wallrow = up ? s_wallrow : n_wallrow;
+  const double syl = up ? limited(fc - fY, fY - fYY, 2.0 * P.inv_dy)
+                        : limited(fYY - fY, fY - fc, 2.0 * P.inv_dy);
+  const double syY = Y_wallrow ? 0.0 : syl;
+  const double sxY = limited(fYe - fY, fY - fYw, 2.0 * P.inv_dx);
+  const double sgn_hdy = up ? 0.5 * P.dy : -0.5 * P.dy;
+  const double fh_in = fma(sgn_hdy, syY, fY);
+  const double fh_own = fma(sgn_hdy, sy0, fc);
+  // bottom face: upwind is Y when moving up, the cell itself when moving down
+  const double fb = up ? fh_in : fh_own, snb = up ? syY : sy0, stb = up ? sxY : sx0;
+  const double ft = up ? fh_own : fh_in, snt = up ? sy0 : syY, stt = up ? sx0 : sxY;
+  const double2 bab = *reinterpret_cast<const double2*>(bp);
+  const double2 bcd = *reinterpret_cast<const double2*>(bp + 2);
+  const double2 tab2 = *reinterpret_cast<const double2*>(tp);
+  const double2 tcd = *reinterpret_cast<const double2*>(tp + 2);
+  const double Fb_face = face_flux(bab, bcd, be, vv, u, fb, snb, stb, m4b, m5b);
+  const double Ft_face = face_flux(tab2, tcd, te, vv, u, ft, snt, stt, m4t, m5t);
+  const double Fb_wall = up ? vv * (be * bab.x) : vv * (m4b * fc);
+  const double Ft_wall = up ? vv * (m4t * fc) : vv * (te * tab2.x);
+  const double Fb = wall_b ? Fb_wall : Fb_face;
+  const double Ft = wall_t ? Ft_wall : Ft_face;
+  return Fb - Ft;
+}
+
+// Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  One wavefront per cell.
+template <typename S>
+__global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(
+    KParams P, const S* __restrict__ fin, S* __restrict__ fout, const S* __restrict__ fg,
+    const double* __restrict__ recx, const double* __restrict__ recy, double* __restrict__ W) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cpb = (int)(blockDim.x >> 6);
+  const Tab L = tab_layout(P.K, P.M);
+  double* tb = lds + (size_t)wv * L.total;
+  const int c = xcd_block(blockIdx.x, gridDim.x) * cpb + wv;
+  const bool active = c < P.nx * P.ny;
+  const int cc = active ? c : 0;
+  const int i = cc % P.nx, j = cc / P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
   const double* rl = recx + ((size_t)j * (P.nx + 1) + i) * kRec;
   const double* rr = recx + ((size_t)j * (P.nx + 1) + i + 1) * kRec;
@@ -511,150 +745,162 @@ __global__ __launch_bounds__(kWave) void update_kernel(KParams P, const S* __res
   double Wn[4], W1[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    Wn[q] = W[4 * (size_t)c + q];
+    Wn[q] = W[4 * (size_t)cc + q];
     W1[q] = Wn[q] + (rl[q] - rr[q] + rb[q] - rt[q]) / P.area;
   }
   Prim pn{}, p1{};
-  double tn = 0.0, t1 = 0.0;
+  // Eq. (3) solved for f^{n+1}: f1 = Af f + AdF dF + (A1 g^{n+1} + An g^n), the weights of
+  // g folded into its tables
+  double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
   if (!P.collisionless) {
     const bool ok = prim_of(Wn, pn) && prim_of(W1, p1);
-    if (!ok && lane == 0) *P.flag = 1;
-    tn = collision_time(pn, P.mu_ref);
-    t1 = collision_time(p1, P.mu_ref);
+    if (!ok && lane == 0 && active) *P.flag = 1;
+    const double tn = collision_time(pn, P.mu_ref), t1 = collision_time(p1, P.mu_ref);
+    const double hdt = 0.5 * P.dt;
+    const double den = 1.0 / (1.0 + hdt / t1);
+    Af = (1.0 - hdt / tn) * den;
+    AdF = den / P.area;
+    A1 = (p1.rho * p1.lam / kPi) * (hdt / t1) * den;
+    An = (pn.rho * pn.lam / kPi) * (hdt / tn) * den;
   }
-  // tables: 0 left, 1 right, 2 bottom, 3 top face; 4 g^n; 5 g^{n+1}
-  for (int e = lane; e < 6 * KM; e += kWave) {
-    const int s = e / KM, r = e - s * KM;
-    double lam = 0.0, ux = 0.0, vy = 0.0;
-    bool use = true;
-    if (s < 4) {
-      const double* rs = s == 0 ? rl : (s == 1 ? rr : (s == 2 ? rb : rt));
-      use = rs[R_KIND] != (double)K_FREE;
-      lam = rs[R_LAM];
-      ux = rs[R_UX];
-      vy = rs[R_VY];
+  // poly tables of the two x-faces (normal node k) and the two y-faces (normal node m)
+  for (int e = lane; e < 2 * P.K + 2 * P.M; e += kWave) {
+    double* out;
+    const double* rs;
+    double un, lamf, U0;
+    if (e < 2 * P.K) {
+      const int side = e / P.K, k = e - side * P.K;
+      rs = side ? rr : rl;
+      un = P.uk[k];
+      U0 = rs[R_UX];
+      out = tb + (side ? L.xr_p : L.xl_p) + 4 * k;
     } else {
-      use = !P.collisionless;
-      const Prim& p = s == 4 ? pn : p1;
-      lam = p.lam;
-      ux = p.U;
-      vy = p.V;
+      const int e2 = e - 2 * P.K;
+      const int side = e2 / P.M, m = e2 - side * P.M;
+      rs = side ? rt : rb;
+      un = P.vm[m];
+      U0 = rs[R_VY];
+      out = tb + (side ? L.yt_p : L.yb_p) + 4 * m;
     }
-    const double d = r < P.K ? P.uk[r] - ux : P.vm[r - P.K] - vy;
-    tab[e] = use ? exp(-lam * d * d) : 0.0;
+    lamf = rs[R_LAM];
+    if (rs[R_KIND] == (double)K_WALL) {
+      // wall: only the Maxwellian itself (P = 1), scaled by dx dt rho_w lambda_w / pi
+      const double d = un - U0;
+      out[0] = exp(-lamf * d * d) * rs[R_GC];
+      out[1] = out[2] = out[3] = 0.0;
+    } else {
+      double tmp[4];
+      face_poly(rs, un, lamf, U0, tmp);
+      out[0] = tmp[0];
+      out[1] = tmp[1];
+      out[2] = tmp[2];
+      out[3] = tmp[3];
+    }
+  }
+  // tangential tables of the faces and the two factors of g^n and g^{n+1}
+  for (int e = lane; e < 4 * (P.K + P.M); e += kWave) {
+    double lam, vel, c0, coef = 1.0;
+    int dst;
+    if (e < 2 * P.M) {  // x-faces: tangential v
+      const int side = e / P.M, m = e - side * P.M;
+      const double* rs = side ? rr : rl;
+      lam = rs[R_LAM];
+      vel = P.vm[m];
+      c0 = rs[R_VY];
+      dst = (side ? L.xr_e : L.xl_e) + m;
+    } else if (e < 2 * P.M + 2 * P.K) {  // y-faces: tangential u
+      const int e2 = e - 2 * P.M;
+      const int side = e2 / P.K, k = e2 - side * P.K;
+      const double* rs = side ? rt : rb;
+      lam = rs[R_LAM];
+      vel = P.uk[k];
+      c0 = rs[R_UX];
+      dst = (side ? L.yt_e : L.yb_e) + k;
+    } else {  // g^n, g^{n+1}: u factor carries the Eq. (3) weight
+      const int e3 = e - 2 * P.M - 2 * P.K;
+      const int which = e3 / (P.K + P.M), r = e3 - which * (P.K + P.M);
+      lam = which ? p1.lam : pn.lam;
+      if (r < P.K) {
+        vel = P.uk[r];
+        c0 = which ? p1.U : pn.U;
+        coef = which ? A1 : An;
+        dst = (which ? L.g1_k : L.gn_k) + r;
+      } else {
+        vel = P.vm[r - P.K];
+        c0 = which ? p1.V : pn.V;
+        dst = (which ? L.g1_m : L.gn_m) + (r - P.K);
+      }
+    }
+    const double d = vel - c0;
+    tb[dst] = coef * exp(-lam * d * d);
   }
   __syncthreads();
-  const double cn = pn.rho * pn.lam / kPi, c1 = p1.rho * p1.lam / kPi;
+  if (!active) return;
+  const double m4l = rl[R_M4], m5l = rl[R_M5], m4r = rr[R_M4], m5r = rr[R_M5];
+  const double m4b = rb[R_M4], m5b = rb[R_M5], m4t = rt[R_M4], m5t = rt[R_M5];
   const bool wall_b = chan && j == 0, wall_t = chan && j == P.ny - 1;
   const bool wall_row = wall_b || wall_t;
-  const S* f0 = fin + (size_t)c * P.NVP;
-  const S* xw = xslab(P, fin, fg, i - 1, j);
-  const S* xe = xslab(P, fin, fg, i + 1, j);
-  const S* xww = xslab(P, fin, fg, i - 2, j);
-  const S* xee = xslab(P, fin, fg, i + 2, j);
   const bool ghost_w = chan && i == 0, ghost_e = chan && i == P.nx - 1;
-  // rows j-1 and j+1 (absent beyond a wall) at columns i-1, i, i+1; rows j-2, j+2 at i
-  const bool has_s = !wall_b, has_n = !wall_t;
-  const int js = wrap(j - 1, P.ny), jn = wrap(j + 1, P.ny);
-  const S* sw = xslab(P, fin, fg, i - 1, js);
-  const S* sc = xslab(P, fin, fg, i, js);
-  const S* se = xslab(P, fin, fg, i + 1, js);
-  const S* nw = xslab(P, fin, fg, i - 1, jn);
-  const S* nc = xslab(P, fin, fg, i, jn);
-  const S* ne = xslab(P, fin, fg, i + 1, jn);
-  const int jss = wrap(j - 2, P.ny), jnn = wrap(j + 2, P.ny);
-  const S* scc = fin + ((size_t)jss * P.nx + i) * P.NVP;
-  const S* ncc = fin + ((size_t)jnn * P.nx + i) * P.NVP;
-  // y-neighbour rows that sit next to a wall carry no y-slope
   const bool s_wallrow = chan && (j - 1 == 0);
   const bool n_wallrow = chan && (j + 1 == P.ny - 1);
-  const double hdx = 0.5 * P.dx, hdy = 0.5 * P.dy;
-  const double* tl = tab + 0 * KM;
-  const double* trr = tab + 1 * KM;
-  const double* tb = tab + 2 * KM;
-  const double* tt = tab + 3 * KM;
-  const double* tgn = tab + 4 * KM;
-  const double* tg1 = tab + 5 * KM;
-  S* fo = fout + (size_t)c * P.NVP;
-  for (int v = lane; v < P.NVP; v += kWave) {
-    if (v >= P.NV) {
-      st(fo, v, 0.0);
-      continue;
-    }
-    const int k = P.kidx[v], m = P.midx[v];
-    const double u = P.U[v], vv = P.V[v];
-    const double fc = ld(f0, v);
-    const double fW = ld(xw, v), fE = ld(xe, v);
-    const double fS = has_s ? ld(sc, v) : 0.0;
-    const double fN = has_n ? ld(nc, v) : 0.0;
-    const double sx0 = limited(fE - fc, fc - fW) * P.inv_dx;
-    const double sy0 = wall_row ? 0.0 : limited(fN - fc, fc - fS) * P.inv_dy;
-    double dF = 0.0;
-    if (u != 0.0) {
-      const bool right = u > 0.0;  // particles move in +x: the left face is the inflow face
-      const double sgn = right ? 1.0 : -1.0;
-      const bool ghostX = right ? ghost_w : ghost_e;
-      const double fX = right ? fW : fE;
-      double sxX = 0.0, syX = 0.0;
-      if (!ghostX) {
-        const double fXX = ld(right ? xww : xee, v);
-        sxX = (right ? limited(fc - fX, fX - fXX) : limited(fXX - fX, fX - fc)) * P.inv_dx;
-        if (!wall_row) {
-          const double fXn = ld(right ? nw : ne, v), fXs = ld(right ? sw : se, v);
-          syX = limited(fXn - fX, fX - fXs) * P.inv_dy;
-        }
-      }
-      const double fin_h = fX + sgn * hdx * sxX;
-      const double fout_h = fc + sgn * hdx * sx0;
-      const double* rin = right ? rl : rr;
-      const double* rout = right ? rr : rl;
-      const double* tin = right ? tl : trr;
-      const double* tout = right ? trr : tl;
-      const double Fin = face_flux(rin, tin, tin + P.K, k, m, u, vv, fin_h, sxX, syX);
-      const double Fout = face_flux(rout, tout, tout + P.K, k, m, u, vv, fout_h, sx0, sy0);
-      dF += sgn * (Fin - Fout);
-    }
-    if (vv != 0.0) {
-      const bool up = vv > 0.0;  // particles move in +y: the bottom face is the inflow face
-      const double sgn = up ? 1.0 : -1.0;
-      const double* rin = up ? rb : rt;
-      const double* rout = up ? rt : rb;
-      const double* tin = up ? tb : tt;
-      const double* tout = up ? tt : tb;
-      double Fin, Fout;
-      if (up ? wall_b : wall_t) {
-        // particles leaving the wall: rho_w times the wall Maxwellian
-        Fin = rin[R_LEN] * P.dt * vv * (rin[R_GCOEF] * tin[k] * tin[P.K + m]);
-      } else {
-        const double fY = up ? fS : fN;
-        const bool Y_wallrow = up ? s_wallrow : n_wallrow;
-        double syY = 0.0;
-        if (!Y_wallrow) {
-          const double fYY = ld(up ? scc : ncc, v);
-          syY = (up ? limited(fc - fY, fY - fYY) : limited(fYY - fY, fY - fc)) * P.inv_dy;
-        }
-        const double fYe = ld(up ? se : ne, v), fYw = ld(up ? sw : nw, v);
-        const double sxY = limited(fYe - fY, fY - fYw) * P.inv_dx;
-        Fin = face_flux(rin, tin, tin + P.K, k, m, vv, u, fY + sgn * hdy * syY, syY, sxY);
-      }
-      if (up ? wall_t : wall_b) {
-        // particles reaching the wall carry the wall-row value
-        Fout = rout[R_LEN] * P.dt * vv * fc;
-      } else {
-        Fout = face_flux(rout, tout, tout + P.K, k, m, vv, u, fc + sgn * hdy * sy0, sy0, sx0);
-      }
-      dF += sgn * (Fin - Fout);
-    }
-    double f1;
-    if (P.collisionless) {
-      f1 = fc + dF / P.area;
-    } else {
-      const double gn = cn * tgn[k] * tgn[P.K + m];
-      const double g1 = c1 * tg1[k] * tg1[P.K + m];
-      f1 = (fc + dF / P.area + 0.5 * P.dt * (g1 / t1 + (gn - fc) / tn)) /
-           (1.0 + 0.5 * P.dt / t1);
-    }
-    st(fo, v, f1);
+  const int js = wrap(j - 1, P.ny), jn = wrap(j + 1, P.ny);
+  UpdateCtx<S> X;
+  X.f0 = fin + (size_t)cc * P.NVP;
+  X.xw = xslab(P, fin, fg, i - 1, j);
+  X.xe = xslab(P, fin, fg, i + 1, j);
+  X.xww = xslab(P, fin, fg, i - 2, j);
+  X.xee = xslab(P, fin, fg, i + 2, j);
+  X.sw = xslab(P, fin, fg, i - 1, js);
+  X.sc = xslab(P, fin, fg, i, js);
+  X.se = xslab(P, fin, fg, i + 1, js);
+  X.nw = xslab(P, fin, fg, i - 1, jn);
+  X.nc = xslab(P, fin, fg, i, jn);
+  X.ne = xslab(P, fin, fg, i + 1, jn);
+  X.scc = fin + ((size_t)wrap(j - 2, P.ny) * P.nx + i) * P.NVP;
+  X.ncc = fin + ((size_t)wrap(j + 2, P.ny) * P.nx + i) * P.NVP;
+  S* fo = fout + (size_t)cc * P.NVP;
+  const int nch = P.NVP / kWave;
+  for (int ch = 0; ch < nch; ++ch) {
+    const unsigned v = (unsigned)(ch * kWave + lane);
+    const unsigned vb = v * (unsigned)sizeof(S), v4 = v * 4u, v8 = v * 8u;
+    const int code = P.chunk_sign[ch];
+    const int su = chunk_sign_u(code), sv = chunk_sign_v(code);
+    const int k = ldb(P.kidx, v4), m = ldb(P.midx, v4);
+    const double u = ldb(P.U, v8), vv = ldb(P.V, v8);
+    const double fc = (double)ldb(X.f0, vb);
+    const double fW = (double)ldb(X.xw, vb), fE = (double)ldb(X.xe, vb);
+    const double fS = (double)ldb(X.sc, vb), fN = (double)ldb(X.nc, vb);
+    const double sx0 = limited(fE - fc, fc - fW, 2.0 * P.inv_dx);
+    const double syl = limited(fN - fc, fc - fS, 2.0 * P.inv_dy);
+    const double sy0 = wall_row ? 0.0 : syl;
+    const double* lp = tb + L.xl_p + 4 * k;
+    const double* rp = tb + L.xr_p + 4 * k;
+    const double* bp = tb + L.yb_p + 4 * m;
+    const double* tp = tb + L.yt_p + 4 * m;
+    const double le = tb[L.xl_e + m], re = tb[L.xr_e + m];
+    const double be = tb[L.yb_e + k], te = tb[L.yt_e + k];
+    double dFx, dFy;
+    if (su > 0)
+      dFx = x_part<1>(P, X, vb, u, vv, fc, fW, fE, sx0, sy0, ghost_w, ghost_e, wall_row, lp, rp,
+                      le, re, m4l, m5l, m4r, m5r);
+    else if (su < 0)
+      dFx = x_part<-1>(P, X, vb, u, vv, fc, fW, fE, sx0, sy0, ghost_w, ghost_e, wall_row, lp, rp,
+                       le, re, m4l, m5l, m4r, m5r);
+    else
+      dFx = x_part<0>(P, X, vb, u, vv, fc, fW, fE, sx0, sy0, ghost_w, ghost_e, wall_row, lp, rp,
+                      le, re, m4l, m5l, m4r, m5r);
+    if (sv > 0)
+      dFy = y_part<1>(P, X, vb, u, vv, fc, fS, fN, sx0, sy0, wall_b, wall_t, s_wallrow, n_wallrow,
+                      bp, tp, be, te, m4b, m5b, m4t, m5t);
+    else if (sv < 0)
+      dFy = y_part<-1>(P, X, vb, u, vv, fc, fS, fN, sx0, sy0, wall_b, wall_t, s_wallrow,
+                       n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
+    else
+      dFy = y_part<0>(P, X, vb, u, vv, fc, fS, fN, sx0, sy0, wall_b, wall_t, s_wallrow, n_wallrow,
+                      bp, tp, be, te, m4b, m5b, m4t, m5t);
+    const double g = fma(tb[L.g1_k + k], tb[L.g1_m + m], tb[L.gn_k + k] * tb[L.gn_m + m]);
+    const double f1 = fma(Af, fc, fma(AdF, dFx + dFy, g));
+    *reinterpret_cast<S*>(reinterpret_cast<char*>(fo) + vb) = static_cast<S>(v < (unsigned)P.NV ? f1 : 0.0);
   }
   if (lane == 0) {
 #pragma unroll
@@ -687,12 +933,14 @@ hipError_t launch_ghost(const KParams& P, int fp32, const double* W, double* Wg,
 hipError_t launch_sums(const KParams& P, int fp32, const void* f, const void* fg, double* hs,
                        hipStream_t s) {
   const unsigned nc = (unsigned)((size_t)P.nx * P.ny);
+  const unsigned blocks = (nc + kCellsPerBlock - 1) / kCellsPerBlock;
+  const unsigned threads = kWave * kCellsPerBlock;
   if (fp32)
-    sums_kernel<float><<<nc, kWave, 0, s>>>(P, static_cast<const float*>(f),
-                                            static_cast<const float*>(fg), hs);
+    sums_kernel<float><<<blocks, threads, 0, s>>>(P, static_cast<const float*>(f),
+                                                  static_cast<const float*>(fg), hs);
   else
-    sums_kernel<double><<<nc, kWave, 0, s>>>(P, static_cast<const double*>(f),
-                                             static_cast<const double*>(fg), hs);
+    sums_kernel<double><<<blocks, threads, 0, s>>>(P, static_cast<const double*>(f),
+                                                   static_cast<const double*>(fg), hs);
   return hipGetLastError();
 }
 
@@ -707,15 +955,21 @@ hipError_t launch_faces(const KParams& P, const double* hs, const double* hsg, c
 hipError_t launch_update(const KParams& P, int fp32, const void* fin, void* fout, const void* fg,
                          const double* recx, const double* recy, double* W, hipStream_t s) {
   const unsigned nc = (unsigned)((size_t)P.nx * P.ny);
-  const size_t lds = sizeof(double) * 6 * (size_t)(P.K + P.M);
+  // twelve nu + nv doubles of tables per cell; fewer cells per block for wide grids
+  const size_t per_cell = sizeof(double) * 12 * (size_t)(P.K + P.M);
+  unsigned cpb = kCellsPerBlock;
+  while (cpb > 1 && per_cell * cpb > 64 * 1024) cpb /= 2;
+  const unsigned blocks = (nc + cpb - 1) / cpb;
+  const unsigned threads = kWave * cpb;
+  const size_t lds = per_cell * cpb;
   if (fp32)
-    update_kernel<float><<<nc, kWave, lds, s>>>(P, static_cast<const float*>(fin),
-                                                static_cast<float*>(fout),
-                                                static_cast<const float*>(fg), recx, recy, W);
+    update_kernel<float><<<blocks, threads, lds, s>>>(
+        P, static_cast<const float*>(fin), static_cast<float*>(fout),
+        static_cast<const float*>(fg), recx, recy, W);
   else
-    update_kernel<double><<<nc, kWave, lds, s>>>(P, static_cast<const double*>(fin),
-                                                 static_cast<double*>(fout),
-                                                 static_cast<const double*>(fg), recx, recy, W);
+    update_kernel<double><<<blocks, threads, lds, s>>>(
+        P, static_cast<const double*>(fin), static_cast<double*>(fout),
+        static_cast<const double*>(fg), recx, recy, W);
   return hipGetLastError();
 }
 
