@@ -31,6 +31,9 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=48)
+    ap.add_argument("--serving-steps", type=int, default=100)
     return ap.parse_args()
 
 
@@ -71,9 +74,43 @@ def run_form(WL, ugks, precision, steps, warmup):
         m = s.moments()          # also checks the state is still valid
         assert m.shape == (100, 400, 4)
         return dict(ms_per_step=ms / steps, updates_per_s=upd * steps / (ms * 1e-3),
-                    wall_s=wall, kernels=prof)
+                    wall_s=wall, kernels=prof, moments=m, total_steps=s.info.steps)
     finally:
         s.close()
+
+
+def moment_errors(m, ref):
+    """rho and T relative, U and V absolute (units of sqrt(2kT0/m))."""
+    rel = lambda q: float(abs(m[..., q] - ref[..., q]).max() / abs(ref[..., q]).min())
+    ab = lambda q: float(abs(m[..., q] - ref[..., q]).max())
+    return {"rho_rel": rel(0), "U_abs": ab(1), "V_abs": ab(2), "T_rel": rel(3)}
+
+
+def serving(args, fp64_rate):
+    """Continuous batching of independent channel solves: saturation throughput from a burst
+    of requests, then Poisson arrivals at 0.8x that rate for the latency figures."""
+    from paper_1810_08137_amd import serving as SV
+
+    n, steps = args.serving_requests, args.serving_steps
+    out = {"requests": n, "steps_per_request": steps, "precision": "fp32_store",
+           "meshes": SV.MESHES, "velocity_grids": SV.VGRIDS}
+    ex = SV.GpuExecutor(max_slots=n)
+    try:
+        burst = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=steps)
+        sat = burst.run(SV.serving_requests(n, float("inf"), seed=4, steps=steps))
+        rate = 0.8 * sat["done"] / sat["makespan_s"]
+        srv = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=25)
+        st = srv.run(SV.serving_requests(n, rate, seed=4, steps=steps))
+    finally:
+        ex.close()
+    out["saturation"] = {"requests_per_s": sat["done"] / sat["makespan_s"],
+                         "updates_per_s": sat["updates_per_s"], "makespan_s": sat["makespan_s"]}
+    out["poisson"] = {"rate_per_s": rate, "done": st["done"], "failed": st["failed"],
+                      "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+                      "updates_per_s": st["updates_per_s"], "batches": srv.batches,
+                      "max_resident": srv.max_resident}
+    out["speedup_vs_fp64_single"] = sat["updates_per_s"] / fp64_rate
+    return out
 
 
 def cpu_baseline(WL, budget_s):
@@ -152,7 +189,11 @@ def main():
                              "speedup_vs_fp64": fp32["updates_per_s"] / fp64["updates_per_s"],
                              "step_hbm_frac": 8.0 * upd / (fp32["ms_per_step"] * 1e-3) / 1e9
                              / HBM_PEAK_GBS,
+                             "error_vs_fp64": dict(moment_errors(fp32["moments"], fp64["moments"]),
+                                                   steps=fp32["total_steps"]),
                              "kernels": fp32["kernels"]}
+    if not args.no_serving:
+        out["serving"] = serving(args, fp64["updates_per_s"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(WL, args.cpu_seconds)
     out["paper_context"] = ("paper: 118.38x speed-up of a Tesla V100 over one E5-2650 thread "

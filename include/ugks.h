@@ -168,6 +168,28 @@ int ugks_get_face_flux(ugks_handle* h, double* Fx, double* Fy);
 int ugks_set_kernel_timing(ugks_handle* h, int on);
 int ugks_get_kernel_timing(ugks_handle* h, int kernel, double* total_ms, int64_t* launches);
 
+/* ---------------------------------------------------------------------------------------
+ * Serving: many independent solvers (any mix of meshes, velocity grids, Knudsen numbers and
+ * boundary kinds) advanced together.  Callers: request loops that keep many solves resident on
+ * one GPU and want their steps packed into shared launches.
+ *
+ * A batch owns a device launch plan for up to max_instances handles (the kernels find their
+ * instance in it), a pinned staging copy and an event.  ugks_step_batch enqueues n steps of
+ * every handle in hs[0..count) with one launch per phase covering all of them and returns
+ * without waiting.  Requirements: the handles are distinct and share one precision.  A handle
+ * created on another stream is adopted: the batch's stream (the stream argument of
+ * ugks_batch_create) first waits for the work already enqueued for it, and from then on the
+ * handle's work, including ugks_moments and ugks_destroy, runs on the batch's stream.  Each
+ * handle's result is bitwise the one ugks_step would give it alone.  The plan is rebuilt and re-sent only when
+ * the member list changes or a member was stepped outside the batch; a rebuild first waits for
+ * the previous plan upload.  Errors: UGKS_E_INVAL (arguments), UGKS_E_BUSY (a handle in use),
+ * UGKS_E_DEVICE (launch failure; the message is in ugks_batch_last_error). */
+typedef struct ugks_batch ugks_batch;
+int ugks_batch_create(void* stream, int max_instances, ugks_batch** out);
+int ugks_step_batch(ugks_batch* b, ugks_handle* const* hs, int count, int n);
+int ugks_batch_destroy(ugks_batch* b); /* waits for the stream; NULL is accepted */
+const char* ugks_batch_last_error(const ugks_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

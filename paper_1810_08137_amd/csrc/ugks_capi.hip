@@ -15,7 +15,26 @@
 
 using namespace ugks;
 
+struct ugks_batch {
+  hipStream_t stream = nullptr;
+  int cap = 0;
+  int fp32 = 0;
+  void* plan_dev = nullptr;   // device plan of up to cap instances
+  void* plan_host = nullptr;  // pinned staging of the same size
+  hipEvent_t uploaded = nullptr;
+  bool upload_pending = false;
+  std::vector<uint64_t> members;      // ids of the handles of the current plan, in order
+  std::vector<int64_t> base_steps;     // their step counts when the plan was built
+  int64_t counter = 0;                 // steps enqueued with the current plan
+  PlanView pv{};
+  PlanTotals pt{};
+  std::string err;
+};
+
+static std::atomic<uint64_t> g_next_handle_id{1};
+
 struct ugks_handle {
+  uint64_t uid = g_next_handle_id.fetch_add(1);  // never reused, unlike the address
   KParams P{};
   int prec = 0;
   size_t ssize = 8;
@@ -25,7 +44,10 @@ struct ugks_handle {
   size_t ws_bytes = 0;
   bool owns_ws = false;
   Buffers B{};
-  int cur = 0;
+  Inst inst{};       // this solver as the kernels see it (cur = 0: f[steps & 1] is current)
+  void* plan_dev = nullptr;  // its one-instance launch plan, inside the workspace
+  PlanView pv{};
+  PlanTotals pt{};
   int64_t steps = 0;
   double tau_ref = 0.0;
   std::vector<int> slot_of;  // device slot of canonical velocity k*nv + m
@@ -153,7 +175,7 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
 // Offsets of every buffer inside the workspace.
 Layout layout_of(const Shape& s, int prec) {
   const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
-  const size_t sizes[18] = {
+  const size_t sizes[19] = {
       s.nc * s.NVP * ss,                        // f0
       s.nc * s.NVP * ss,                        // f1
       s.nc * 4 * 8,                             // W
@@ -172,10 +194,11 @@ Layout layout_of(const Shape& s, int prec) {
       (size_t)s.K * 8,                          // uk
       (size_t)s.M * 8,                          // vm
       (size_t)s.ny * 8 + 64,                    // xi_in + flag
+      plan_bytes(1),                            // one-instance launch plan
   };
   Layout L{};
   size_t off = 0;
-  for (int b = 0; b < 18; ++b) {
+  for (int b = 0; b < 19; ++b) {
     L.off[b] = off;
     off += round_up(sizes[b], kAlign);
   }
@@ -205,6 +228,7 @@ void carve(ugks_handle* h, const Layout& L, const Shape& s) {
   B.vm = reinterpret_cast<double*>(base + L.off[16]);
   B.xi_in = reinterpret_cast<double*>(base + L.off[17]);
   B.flag = reinterpret_cast<int*>(base + L.off[17] + round_up((size_t)s.ny * 8, 64));
+  h->plan_dev = base + L.off[18];
 }
 
 hipEvent_t pool_get(ugks_handle* h) {
@@ -218,16 +242,27 @@ hipEvent_t pool_get(ugks_handle* h) {
   return e;
 }
 
-// Launch one kernel, bracketed by timing events when enabled.
-template <typename F>
-hipError_t timed(ugks_handle* h, int kernel, F&& launch) {
-  if (!h->timing) return launch();
-  hipEvent_t a = pool_get(h), b = pool_get(h);
-  if (a) (void)hipEventRecord(a, h->stream);
-  hipError_t e = launch();
-  if (b) (void)hipEventRecord(b, h->stream);
-  if (a && b) h->pending.push_back({kernel, a, b});
-  return e;
+// Enqueue one step of a plan: four launches, each bracketed by timing events when enabled.
+int enqueue_plan_step(ugks_handle* h, const PlanView& pv, const PlanTotals& pt, int fp32,
+                      hipStream_t stream) {
+  static const char* names[4] = {"ghost kernel launch", "moment kernel launch",
+                                 "interface kernel launch", "update kernel launch"};
+  for (int phase = 0; phase < 4; ++phase) {
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool timed = h && h->timing && (phase != 0 || pt.ghost > 0);
+    if (timed) {
+      a = pool_get(h);
+      b = pool_get(h);
+      if (a) (void)hipEventRecord(a, stream);
+    }
+    const hipError_t e = launch_phase(pv, pt, fp32, phase, stream);
+    if (timed) {
+      if (b) (void)hipEventRecord(b, stream);
+      if (a && b) h->pending.push_back({phase, a, b});
+    }
+    if (e != hipSuccess) return hip_fail(h, e, names[phase]);
+  }
+  return UGKS_OK;
 }
 
 int collect_timing(ugks_handle* h) {
@@ -241,31 +276,6 @@ int collect_timing(ugks_handle* h) {
     h->pool.push_back(p.b);
   }
   h->pending.clear();
-  return UGKS_OK;
-}
-
-int enqueue_step(ugks_handle* h) {
-  KParams& P = h->P;
-  Buffers& B = h->B;
-  const int fp32 = h->prec == UGKS_FP32_STORE;
-  hipError_t e;
-  if (P.bc == UGKS_BC_CHANNEL) {
-    e = timed(h, 0, [&] { return launch_ghost(P, fp32, B.W, B.Wg, B.fg, B.hsg, h->stream); });
-    if (e != hipSuccess) return hip_fail(h, e, "ghost kernel launch");
-  }
-  e = timed(h, 1, [&] { return launch_sums(P, fp32, B.f[h->cur], B.fg, B.hs, h->stream); });
-  if (e != hipSuccess) return hip_fail(h, e, "moment kernel launch");
-  e = timed(h, 2, [&] {
-    return launch_faces(P, B.hs, B.hsg, B.W, B.Wg, B.recx, B.recy, h->stream);
-  });
-  if (e != hipSuccess) return hip_fail(h, e, "interface kernel launch");
-  e = timed(h, 3, [&] {
-    return launch_update(P, fp32, B.f[h->cur], B.f[1 - h->cur], B.fg, B.recx, B.recy, B.W,
-                         h->stream);
-  });
-  if (e != hipSuccess) return hip_fail(h, e, "update kernel launch");
-  h->cur = 1 - h->cur;
-  h->steps += 1;
   return UGKS_OK;
 }
 
@@ -443,16 +453,31 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     }
   }
   Buffers& B = h->B;
-  P.U = B.U;
-  P.V = B.V;
-  P.Wq = B.Wq;
-  P.kidx = B.kidx;
-  P.midx = B.midx;
-  P.chunk_sign = B.chunk_sign;
-  P.uk = B.uk;
-  P.vm = B.vm;
-  P.xi_in = B.xi_in;
-  P.flag = B.flag;
+  P.U = gp(B.U);
+  P.V = gp(B.V);
+  P.Wq = gp(B.Wq);
+  P.kidx = gp(B.kidx);
+  P.midx = gp(B.midx);
+  P.chunk_sign = gp(B.chunk_sign);
+  P.uk = gp(B.uk);
+  P.vm = gp(B.vm);
+  P.xi_in = gp(B.xi_in);
+  P.flag = gp(B.flag);
+  Inst& I = h->inst;
+  I.P = P;
+  I.f[0] = gp(B.f[0]);
+  I.f[1] = gp(B.f[1]);
+  I.W = gp(B.W);
+  I.Wg = gp(B.Wg);
+  I.fg = gp(B.fg);
+  I.hs = gp(B.hs);
+  I.hsg = gp(B.hsg);
+  I.recx = gp(B.recx);
+  I.recy = gp(B.recy);
+  I.cur = 0;
+  I.fp32 = h->prec == UGKS_FP32_STORE ? 1 : 0;
+  std::vector<char> plan_host(plan_bytes(1));
+  h->pt = build_plan(&I, 1, plan_host.data(), h->plan_dev, &h->pv);
 
   struct Copy {
     void* dst;
@@ -464,7 +489,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
       {B.midx, midx.data(), midx.size() * 4}, {B.uk, uk.data(), uk.size() * 8},
       {B.chunk_sign, chunk_sign.data(), chunk_sign.size() * 4},
       {B.vm, vm.data(), vm.size() * 8},     {B.xi_in, xi.data(), xi.size() * 8},
-      {B.W, W0.data(), W0.size() * 8},
+      {B.W, W0.data(), W0.size() * 8},          {h->plan_dev, plan_host.data(), plan_host.size()},
   };
   int rc = UGKS_OK;
   for (auto& cp : copies) {
@@ -481,7 +506,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   if (rc == UGKS_OK) {
     // the ghost columns of a periodic run are never read; keep them defined anyway
     e = hipMemsetAsync(B.fg, 0, 2 * (size_t)s.ny * s.NVP * h->ssize, h->stream);
-    if (e == hipSuccess) e = launch_init(P, h->prec == UGKS_FP32_STORE, B.f[0], B.W, h->stream);
+    if (e == hipSuccess) e = launch_init(h->pv, I.fp32, (int)s.nc, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = hip_fail(nullptr, e, "initial state");
   }
@@ -500,8 +525,10 @@ int ugks_step(ugks_handle* h, int n) {
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
   for (int s = 0; s < n; ++s) {
-    const int rc = enqueue_step(h);
+    h->pv.step = (int)(h->steps & 1);
+    const int rc = enqueue_plan_step(h, h->pv, h->pt, h->inst.fp32, h->stream);
     if (rc != UGKS_OK) return rc;
+    h->steps += 1;
   }
   return UGKS_OK;
 }
@@ -578,7 +605,8 @@ int ugks_get_state(ugks_handle* h, double* f, double* W) {
   std::vector<char> raw;
   if (f) {
     raw.resize(nc * NVP * h->ssize);
-    e = hipMemcpyAsync(raw.data(), h->B.f[h->cur], raw.size(), hipMemcpyDeviceToHost, h->stream);
+    e = hipMemcpyAsync(raw.data(), h->B.f[h->steps & 1], raw.size(), hipMemcpyDeviceToHost,
+                       h->stream);
   }
   if (e == hipSuccess && W)
     e = hipMemcpyAsync(W, h->B.W, nc * 4 * 8, hipMemcpyDeviceToHost, h->stream);
@@ -617,7 +645,8 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
         else
           reinterpret_cast<double*>(raw.data())[sl] = f[c * NV + v];
       }
-    e = hipMemcpyAsync(h->B.f[h->cur], raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream);
+    e = hipMemcpyAsync(h->B.f[h->steps & 1], raw.data(), raw.size(), hipMemcpyHostToDevice,
+                       h->stream);
   }
   if (e == hipSuccess && W)
     e = hipMemcpyAsync(h->B.W, W, nc * 4 * 8, hipMemcpyHostToDevice, h->stream);
@@ -670,5 +699,147 @@ int ugks_get_kernel_timing(ugks_handle* h, int kernel, double* total_ms, int64_t
   *launches = h->launches[kernel];
   return UGKS_OK;
 }
+
+
+int ugks_batch_create(void* stream, int max_instances, ugks_batch** out) {
+  if (!out) return fail(nullptr, UGKS_E_INVAL, "out is NULL%s");
+  *out = nullptr;
+  if (max_instances < 1 || max_instances > (1 << 20))
+    return fail(nullptr, UGKS_E_INVAL, "max_instances out of range%s");
+  ugks_batch* b = new (std::nothrow) ugks_batch();
+  if (!b) return fail(nullptr, UGKS_E_NOMEM, "host allocation failed%s");
+  b->stream = static_cast<hipStream_t>(stream);
+  b->cap = max_instances;
+  const size_t bytes = plan_bytes(max_instances);
+  hipError_t e = hipMalloc(&b->plan_dev, bytes);
+  if (e == hipSuccess) e = hipHostMalloc(&b->plan_host, bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (b->plan_dev) (void)hipFree(b->plan_dev);
+    if (b->plan_host) (void)hipHostFree(b->plan_host);
+    delete b;
+    (void)hipGetLastError();
+    return fail(nullptr, UGKS_E_NOMEM, "batch plan allocation failed%s");
+  }
+  *out = b;
+  return UGKS_OK;
+}
+
+int ugks_step_batch(ugks_batch* b, ugks_handle* const* hs, int count, int n) {
+  if (!b) return UGKS_E_INVAL;
+  if (!hs || count < 1 || count > b->cap || n < 0) {
+    b->err = "need 1 <= count <= max_instances, n >= 0 and a handle array";
+    return UGKS_E_INVAL;
+  }
+  for (int q = 0; q < count; ++q) {
+    if (!hs[q]) {
+      b->err = "NULL handle in the batch";
+      return UGKS_E_INVAL;
+    }
+    if (hs[q]->inst.fp32 != hs[0]->inst.fp32) {
+      b->err = "a batch holds handles of one precision";
+      return UGKS_E_INVAL;
+    }
+    for (int r = 0; r < q; ++r)
+      if (hs[r] == hs[q]) {
+        b->err = "a handle appears twice in the batch";
+        return UGKS_E_INVAL;
+      }
+  }
+  // claim every handle for the duration of the call
+  int claimed = 0;
+  for (; claimed < count; ++claimed) {
+    int z = 0;
+    if (!hs[claimed]->busy.compare_exchange_strong(z, 1)) break;
+  }
+  auto release = [&] {
+    for (int q = 0; q < claimed; ++q) hs[q]->busy.store(0);
+  };
+  if (claimed < count) {
+    release();
+    b->err = "a handle of the batch is in use";
+    return UGKS_E_BUSY;
+  }
+  // adopt members created on another stream: the batch stream first waits for their work,
+  // then they live on the batch stream
+  for (int q = 0; q < count; ++q) {
+    ugks_handle* h = hs[q];
+    if (h->stream == b->stream) continue;
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
+    if (ev) (void)hipEventDestroy(ev);
+    if (e != hipSuccess) {
+      release();
+      b->err = hipGetErrorString(e);
+      return UGKS_E_DEVICE;
+    }
+    h->stream = b->stream;
+  }
+  // rebuild the plan when the members changed or were stepped outside this batch
+  bool same = (int)b->members.size() == count;
+  for (int q = 0; same && q < count; ++q)
+    same = b->members[q] == hs[q]->uid && hs[q]->steps == b->base_steps[q] + b->counter;
+  if (!same) {
+    if (b->upload_pending) {
+      const hipError_t e = hipEventSynchronize(b->uploaded);
+      if (e != hipSuccess) {
+        release();
+        b->err = hipGetErrorString(e);
+        return UGKS_E_DEVICE;
+      }
+    }
+    std::vector<Inst> insts(count);
+    b->members.resize(count);
+    b->base_steps.resize(count);
+    for (int q = 0; q < count; ++q) {
+      insts[q] = hs[q]->inst;
+      insts[q].cur = (int)(hs[q]->steps & 1);
+      b->members[q] = hs[q]->uid;
+      b->base_steps[q] = hs[q]->steps;
+    }
+    b->counter = 0;
+    b->fp32 = hs[0]->inst.fp32;
+    b->pt = build_plan(insts.data(), count, b->plan_host, b->plan_dev, &b->pv);
+    hipError_t e = hipMemcpyAsync(b->plan_dev, b->plan_host, plan_bytes(count),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->uploaded, b->stream);
+    if (e != hipSuccess) {
+      release();
+      b->members.clear();
+      b->err = hipGetErrorString(e);
+      return UGKS_E_DEVICE;
+    }
+    b->upload_pending = true;
+  }
+  int rc = UGKS_OK;
+  for (int s = 0; s < n && rc == UGKS_OK; ++s) {
+    b->pv.step = (int)((b->counter + s) & 1);
+    rc = enqueue_plan_step(nullptr, b->pv, b->pt, b->fp32, b->stream);
+  }
+  if (rc == UGKS_OK) {
+    b->counter += n;
+    for (int q = 0; q < count; ++q) hs[q]->steps += n;
+  } else {
+    b->err = g_create_error;
+    b->members.clear();
+    rc = UGKS_E_DEVICE;
+  }
+  release();
+  return rc;
+}
+
+int ugks_batch_destroy(ugks_batch* b) {
+  if (!b) return UGKS_OK;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+  if (b->plan_dev) (void)hipFree(b->plan_dev);
+  if (b->plan_host) (void)hipHostFree(b->plan_host);
+  delete b;
+  return UGKS_OK;
+}
+
+const char* ugks_batch_last_error(const ugks_batch* b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"

@@ -11,6 +11,14 @@
 
 namespace ugks {
 
+// Device buffers are declared in the global address space, so that pointers the kernels read
+// from a launch plan still compile to global (scalar-base) loads rather than flat ones.
+#define UGKS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+inline UGKS_GLOBAL T* gp(T* p) {
+  return (UGKS_GLOBAL T*)p;
+}
+
 constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kSlots = 64;     // per-cell outgoing moment sums: 4 faces x 16
 constexpr int kRec = 32;       // doubles per interface record
@@ -49,16 +57,17 @@ struct KParams {
   double U_in, U_noise;
   double wall_den_bot, wall_den_top;  // sum over wall-leaving velocities of w v g_w
   double wall_G_bot[4], wall_G_top[4];  // sum of w v psi_local g_w over the same velocities
-  const double* U;      // [NVP] u of each velocity slot (0 in pads)
-  const double* V;      // [NVP]
-  const double* Wq;     // [NVP] quadrature weight (0 in pads)
-  const int* kidx;      // [NVP] k of each velocity slot
-  const int* midx;      // [NVP] m of each velocity slot
-  const int* chunk_sign;  // [NVP/64] per 64-slot chunk: bit0/1 all u > 0 / < 0, bit2/3 for v
-  const double* uk;     // [K]
-  const double* vm;     // [M]
-  const double* xi_in;  // [ny] inlet noise
-  int* flag;            // device flag: set to 1 on an invalid state
+  const UGKS_GLOBAL double* U;     // [NVP] u of each velocity slot (0 in pads)
+  const UGKS_GLOBAL double* V;     // [NVP]
+  const UGKS_GLOBAL double* Wq;    // [NVP] quadrature weight (0 in pads)
+  const UGKS_GLOBAL int* kidx;     // [NVP] k of each velocity slot
+  const UGKS_GLOBAL int* midx;     // [NVP] m of each velocity slot
+  const UGKS_GLOBAL int* chunk_sign;  // [NVP/64] per 64-slot chunk: bit0/1 all u > 0 / < 0,
+                                      // bit2/3 the same for v
+  const UGKS_GLOBAL double* uk;    // [K]
+  const UGKS_GLOBAL double* vm;    // [M]
+  const UGKS_GLOBAL double* xi_in;  // [ny] inlet noise
+  UGKS_GLOBAL int* flag;           // device flag: set to 1 on an invalid state
 };
 
 // Device buffers carved out of one workspace.
@@ -84,19 +93,58 @@ struct Buffers {
 };
 
 struct Layout {
-  size_t off[18];
+  size_t off[19];
   size_t total;
 };
 
+// One solver instance as the kernels see it: constants, buffers, and which f buffer holds the
+// state when the launch sequence's step counter is 0.
+struct Inst {
+  KParams P;
+  UGKS_GLOBAL void* f[2];
+  UGKS_GLOBAL double* W;
+  UGKS_GLOBAL double* Wg;
+  UGKS_GLOBAL void* fg;
+  UGKS_GLOBAL double* hs;
+  UGKS_GLOBAL double* hsg;
+  UGKS_GLOBAL double* recx;
+  UGKS_GLOBAL double* recy;
+  int cur;   // f[(cur + step) & 1] is read, the other buffer written
+  int fp32;  // storage type of f
+};
+
+// A launch plan: instances plus, per kernel, the prefix sum of the workgroups each instance
+// takes, so that one launch per phase covers every instance (instance search is uniform per
+// workgroup).  Device-resident; the kernels read it through PlanView.
+struct PlanView {
+  const Inst* inst;
+  const int* off_sums;   // kCellsPerBlock cells per workgroup
+  const int* off_upd;    // cpb_upd cells per workgroup
+  const int* off_face;   // 256 faces per workgroup
+  const int* off_ghost;  // 2 ny workgroups for a channel, 0 for a periodic box
+  int ninst;
+  int step;              // steps enqueued since the plan's `cur` values were taken
+  int cpb_upd;
+  int lds_per_cell;      // bytes of update-kernel LDS per cell
+};
+
+struct PlanTotals {
+  int sums, upd, face, ghost;  // workgroups of each launch
+  int cpb_upd;
+  int lds_per_cell;
+};
+
+// Bytes of a device plan with n instances, and its host image (offsets into one buffer).
+size_t plan_bytes(int n);
+// Build the host image of a plan for `n` instances into `buf` (plan_bytes(n) bytes) and return
+// the totals; `dev` is the device address the image will be copied to.
+PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, PlanView* view);
+
 // Launchers (ugks_kernels.hip).  All enqueue on `s` and return the launch error.
-hipError_t launch_init(const KParams& P, int fp32, void* f, const double* W, hipStream_t s);
-hipError_t launch_ghost(const KParams& P, int fp32, const double* W, double* Wg, void* fg,
-                        double* hsg, hipStream_t s);
-hipError_t launch_sums(const KParams& P, int fp32, const void* f, const void* fg, double* hs,
-                       hipStream_t s);
-hipError_t launch_faces(const KParams& P, const double* hs, const double* hsg, const double* W,
-                        const double* Wg, double* recx, double* recy, hipStream_t s);
-hipError_t launch_update(const KParams& P, int fp32, const void* fin, void* fout, const void* fg,
-                         const double* recx, const double* recy, double* W, hipStream_t s);
+hipError_t launch_init(const PlanView& pv, int fp32, int ncells, hipStream_t s);
+hipError_t launch_step(const PlanView& pv, const PlanTotals& t, int fp32, hipStream_t s,
+                       hipEvent_t* ev /* 8 events or NULL */);
+hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int phase,
+                        hipStream_t s);
 
 }  // namespace ugks

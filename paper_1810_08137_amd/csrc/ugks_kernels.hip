@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "ugks_internal.hpp"
 
@@ -29,16 +30,17 @@ constexpr int kCellsPerBlock = 4;  // one wavefront per cell
 
 // ------------------------------------------------------------------ storage
 template <typename S>
-__device__ __forceinline__ double ld(const S* __restrict__ p, unsigned i) {
+__device__ __forceinline__ double ld(const UGKS_GLOBAL S* p, unsigned i) {
   return static_cast<double>(p[i]);
 }
 // Load at a 32-bit byte offset from a uniform base: one instruction with a scalar base.
 template <typename T>
-__device__ __forceinline__ T ldb(const T* __restrict__ p, unsigned byte_off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
+__device__ __forceinline__ T ldb(const UGKS_GLOBAL T* p, unsigned byte_off) {
+  return *reinterpret_cast<const UGKS_GLOBAL T*>(reinterpret_cast<const UGKS_GLOBAL char*>(p) +
+                                                 byte_off);
 }
 template <typename S>
-__device__ __forceinline__ void st(S* __restrict__ p, unsigned i, double x) {
+__device__ __forceinline__ void st(UGKS_GLOBAL S* p, unsigned i, double x) {
   p[i] = static_cast<S>(x);
 }
 
@@ -71,7 +73,8 @@ struct Prim {
 
 // Primitive variables of W = (rho, rho U, rho V, rho E), 2D gas without internal energy
 // modes: rho E = rho (U^2 + V^2)/2 + rho/(2 lambda).  false on an invalid state.
-__device__ __forceinline__ bool prim_of(const double* W, Prim& p) {
+template <typename Ptr>
+__device__ __forceinline__ bool prim_of(Ptr W, Prim& p) {
   const double rho = W[0];
   const double U = W[1] / rho;
   const double V = W[2] / rho;
@@ -168,7 +171,8 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // f slab of column i of row j, i in [-2, nx+1]: a cell, a wrapped cell (periodic) or the
 // inlet/outlet ghost column (channel).
 template <typename S>
-__device__ __forceinline__ const S* xslab(const KParams& P, const S* f, const S* fg, int i, int j) {
+__device__ __forceinline__ const UGKS_GLOBAL S* xslab(const KParams& P, const UGKS_GLOBAL S* f,
+                                                     const UGKS_GLOBAL S* fg, int i, int j) {
   if (i >= 0 && i < P.nx) return f + ((size_t)j * P.nx + i) * P.NVP;
   if (P.bc == UGKS_BC_PERIODIC) return f + ((size_t)j * P.nx + wrap(i, P.nx)) * P.NVP;
   return fg + ((size_t)(i < 0 ? 0 : P.ny) + j) * P.NVP;
@@ -230,16 +234,47 @@ __device__ __forceinline__ int chunk_sign_v(int code) {
   return (code & 4) ? 1 : ((code & 8) ? -1 : 0);
 }
 
+// ------------------------------------------------------------------ launch plans
+typedef const Inst* __restrict__ inst_cptr;
+typedef const int* __restrict__ int_cptr;
+
+// Instance owning workgroup b: the last instance whose first workgroup is <= b (uniform).
+__device__ __forceinline__ int find_inst(const int* off_generic, int n, int b) {
+  const int_cptr off = (int_cptr)off_generic;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int first_block(const int* off_generic, int ii) {
+  return ((int_cptr)off_generic)[ii];
+}
+
+// The plan is read-only for the whole launch.
+__device__ __forceinline__ const Inst* inst_at(const PlanView& pv, int ii) {
+  return pv.inst + ii;
+}
+
+
 // ================================================================== kernels
 // Discrete Maxwellian of each cell's W (initial state).
 template <typename S>
-__global__ __launch_bounds__(kWave) void init_kernel(KParams P, S* __restrict__ f,
-                                                     const double* __restrict__ W) {
+__global__ __launch_bounds__(kWave) void init_kernel(PlanView pv) {
+  const Inst* __restrict__ I = inst_at(pv, 0);
+  const KParams P = I->P;
+  UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[I->cur]);
+  const UGKS_GLOBAL double* W = I->W;
   const int c = blockIdx.x;
   Prim p;
   if (!prim_of(W + 4 * (size_t)c, p) && threadIdx.x == 0) *P.flag = 1;
   const double coef = p.rho * p.lam / kPi;
-  S* fc = f + (size_t)c * P.NVP;
+  UGKS_GLOBAL S* fc = f + (size_t)c * P.NVP;
   for (int v = threadIdx.x; v < P.NVP; v += kWave) {
     double g = 0.0;
     if (v < P.NV) {
@@ -251,12 +286,20 @@ __global__ __launch_bounds__(kWave) void init_kernel(KParams P, S* __restrict__ 
 }
 
 // Inlet/outlet ghost of one row: state, discrete Maxwellian, and the ghost's moment sums
-// towards the domain (its slopes are zero).  grid (ny, 2), one wavefront each.
+// towards the domain (its slopes are zero).  2 ny workgroups per channel instance, one
+// wavefront each.
 template <typename S>
-__global__ __launch_bounds__(kWave) void ghost_kernel(KParams P, const double* __restrict__ W,
-                                                      double* __restrict__ Wg, S* __restrict__ fg,
-                                                      double* __restrict__ hsg) {
-  const int j = blockIdx.x, side = blockIdx.y, lane = threadIdx.x;
+__global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
+  const int b = blockIdx.x;
+  const int ii = find_inst(pv.off_ghost, pv.ninst, b);
+  const Inst* __restrict__ I = inst_at(pv, ii);
+  const KParams P = I->P;
+  const UGKS_GLOBAL double* W = I->W;
+  UGKS_GLOBAL double* Wg = I->Wg;
+  UGKS_GLOBAL S* fg = static_cast<UGKS_GLOBAL S*>(I->fg);
+  UGKS_GLOBAL double* hsg = I->hsg;
+  const int local = b - first_block(pv.off_ghost, ii);
+  const int side = local / P.ny, j = local - side * P.ny, lane = threadIdx.x;
   const int col = side == 0 ? 0 : P.nx - 1;
   Prim pc, pg;
   const bool ok = prim_of(W + 4 * ((size_t)j * P.nx + col), pc);
@@ -279,7 +322,7 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(KParams P, const double* _
     pg.lam = pc.lam;
   }
   if (!ok && lane == 0) *P.flag = 1;
-  double* wg = Wg + 4 * ((size_t)side * P.ny + j);
+  UGKS_GLOBAL double* wg = Wg + 4 * ((size_t)side * P.ny + j);
   if (lane == 0) {
     wg[0] = pg.rho;
     wg[1] = pg.rho * pg.U;
@@ -287,7 +330,7 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(KParams P, const double* _
     wg[3] = 0.5 * pg.rho * (pg.U * pg.U + pg.V * pg.V) + 0.5 * pg.rho / pg.lam;
   }
   const double coef = pg.rho * pg.lam / kPi;
-  S* row = fg + ((size_t)side * P.ny + j) * P.NVP;
+  UGKS_GLOBAL S* row = fg + ((size_t)side * P.ny + j) * P.NVP;
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
@@ -313,20 +356,26 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(KParams P, const double* _
 // Per cell: slopes and the outgoing moment sums of all four faces.  One wavefront per cell,
 // four cells per block.
 template <typename S>
-__global__ __launch_bounds__(kWave* kCellsPerBlock) void sums_kernel(
-    KParams P, const S* __restrict__ f, const S* __restrict__ fg, double* __restrict__ hs) {
+__global__ __launch_bounds__(kWave* kCellsPerBlock) void sums_kernel(PlanView pv) {
   const int lane = threadIdx.x & (kWave - 1);
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int ii = find_inst(pv.off_sums, pv.ninst, b);
+  const Inst* __restrict__ I = inst_at(pv, ii);
+  const KParams P = I->P;
+  const UGKS_GLOBAL S* f = static_cast<const UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
+  const UGKS_GLOBAL S* fg = static_cast<const UGKS_GLOBAL S*>(I->fg);
+  UGKS_GLOBAL double* hs = I->hs;
   // the wavefront index is uniform: keep everything derived from it in scalar registers
-  const int c = xcd_block(blockIdx.x, gridDim.x) * kCellsPerBlock +
+  const int c = (b - first_block(pv.off_sums, ii)) * kCellsPerBlock +
                 __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= P.nx * P.ny) return;
   const int i = c % P.nx, j = c / P.nx;
   const bool wall_row = P.bc == UGKS_BC_CHANNEL && (j == 0 || j == P.ny - 1);
-  const S* f0 = f + (size_t)c * P.NVP;
-  const S* fw = xslab(P, f, fg, i - 1, j);
-  const S* fe = xslab(P, f, fg, i + 1, j);
-  const S* fs = f + ((size_t)wrap(j - 1, P.ny) * P.nx + i) * P.NVP;
-  const S* fn = f + ((size_t)wrap(j + 1, P.ny) * P.nx + i) * P.NVP;
+  const UGKS_GLOBAL S* f0 = f + (size_t)c * P.NVP;
+  const UGKS_GLOBAL S* fw = xslab(P, f, fg, i - 1, j);
+  const UGKS_GLOBAL S* fe = xslab(P, f, fg, i + 1, j);
+  const UGKS_GLOBAL S* fs = f + ((size_t)wrap(j - 1, P.ny) * P.nx + i) * P.NVP;
+  const UGKS_GLOBAL S* fn = f + ((size_t)wrap(j + 1, P.ny) * P.nx + i) * P.NVP;
   const double hdx = 0.5 * P.dx, hdy = 0.5 * P.dy;
   double acc[kSlots];
 #pragma unroll
@@ -394,7 +443,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void sums_kernel(
 // macroscopic flux to F and the folded coefficients of the distribution flux to rec.
 __device__ void interface_scalars(const KParams& P, const double* S, const double* WL,
                                   const double* WR, double dn, double len, double* F,
-                                  double* rec, double& U0, double& V0) {
+                                  UGKS_GLOBAL double* rec, double& U0, double& V0) {
   const double* W0 = S;
   const double* Wt = S + 4;
   const double* Q1 = S + 8;
@@ -472,13 +521,18 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
 }
 
 // One thread per interface: x-faces first (ny rows of nx+1), then y-faces (ny+1 rows of nx).
-__global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __restrict__ hs,
-                                                    const double* __restrict__ hsg,
-                                                    const double* __restrict__ W,
-                                                    const double* __restrict__ Wg,
-                                                    double* __restrict__ recx,
-                                                    double* __restrict__ recy) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
+  const int b = blockIdx.x;
+  const int ii = find_inst(pv.off_face, pv.ninst, b);
+  const Inst* __restrict__ I = inst_at(pv, ii);
+  const KParams P = I->P;
+  const UGKS_GLOBAL double* hs = I->hs;
+  const UGKS_GLOBAL double* hsg = I->hsg;
+  const UGKS_GLOBAL double* W = I->W;
+  const UGKS_GLOBAL double* Wg = I->Wg;
+  UGKS_GLOBAL double* recx = I->recx;
+  UGKS_GLOBAL double* recy = I->recy;
+  const long e = (long)(b - first_block(pv.off_face, ii)) * blockDim.x + threadIdx.x;
   const long nfx = (long)P.ny * (P.nx + 1);
   const long nfy = (long)(P.ny + 1) * P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
@@ -486,7 +540,7 @@ __global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __r
   double U0, V0;
   if (e < nfx) {
     const int j = (int)(e / (P.nx + 1)), i = (int)(e % (P.nx + 1));
-    const double *sL, *sR, *WL, *WR;
+    const UGKS_GLOBAL double *sL, *sR, *WL, *WR;
     if (i > 0 || !chan) {
       const size_t cl = (size_t)j * P.nx + wrap(i - 1, P.nx);
       sL = hs + cl * kSlots + 16 * S_XP;
@@ -511,7 +565,7 @@ __global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __r
       wl[q] = WL[q];
       wr[q] = WR[q];
     }
-    double* rec = recx + (size_t)e * kRec;
+    UGKS_GLOBAL double* rec = recx + (size_t)e * kRec;
     interface_scalars(P, S, wl, wr, P.dx, P.dy, F, rec, U0, V0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) rec[R_FX + q] = F[q];
@@ -522,12 +576,12 @@ __global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __r
   if (e >= nfx + nfy) return;
   const long e2 = e - nfx;
   const int j = (int)(e2 / P.nx), i = (int)(e2 % P.nx);
-  double* rec = recy + (size_t)e2 * kRec;
+  UGKS_GLOBAL double* rec = recy + (size_t)e2 * kRec;
   if (chan && (j == 0 || j == P.ny)) {
     // diffuse wall: sums of the wall-row cell towards the wall; local frame (v, u)
     const bool top = j == P.ny;
     const size_t c = (size_t)(top ? P.ny - 1 : 0) * P.nx + i;
-    const double* Q1 = hs + c * kSlots + 16 * (top ? S_YP : S_YM) + 8;
+    const UGKS_GLOBAL double* Q1 = hs + c * kSlots + 16 * (top ? S_YP : S_YM) + 8;
     const double den = top ? P.wall_den_top : P.wall_den_bot;
     const double* Gw = top ? P.wall_G_top : P.wall_G_bot;
     const double rho_w = -Q1[0] / den;
@@ -551,8 +605,8 @@ __global__ __launch_bounds__(256) void faces_kernel(KParams P, const double* __r
   }
   const size_t cl = (size_t)wrap(j - 1, P.ny) * P.nx + i;
   const size_t cr = (size_t)wrap(j, P.ny) * P.nx + i;
-  const double* sL = hs + cl * kSlots + 16 * S_YP;
-  const double* sR = hs + cr * kSlots + 16 * S_YM;
+  const UGKS_GLOBAL double* sL = hs + cl * kSlots + 16 * S_YP;
+  const UGKS_GLOBAL double* sR = hs + cr * kSlots + 16 * S_YM;
 #pragma unroll
   for (int q = 0; q < 16; ++q) S[q] = sL[q] + sR[q];
   const double wl[4] = {W[4 * cl], W[4 * cl + 2], W[4 * cl + 1], W[4 * cl + 3]};
@@ -599,7 +653,7 @@ __device__ __forceinline__ Tab tab_layout(int K, int M) {
 }
 
 // Fill the four-entry polynomial table of one face at normal node with velocity un.
-__device__ __forceinline__ void face_poly(const double* __restrict__ r, double un, double lam,
+__device__ __forceinline__ void face_poly(const UGKS_GLOBAL double* r, double un, double lam,
                                           double U0, double* out) {
   const double d = un - U0;
   const double En = exp(-lam * d * d) * r[R_GC];
@@ -631,19 +685,19 @@ __device__ __forceinline__ double face_flux(double2 pab, double2 pcd, double E, 
 
 template <typename S>
 struct UpdateCtx {
-  const S* f0;
-  const S* xw;
-  const S* xe;
-  const S* xww;
-  const S* xee;
-  const S* sw;
-  const S* sc;
-  const S* se;
-  const S* nw;
-  const S* nc;
-  const S* ne;
-  const S* scc;
-  const S* ncc;
+  const UGKS_GLOBAL S* f0;
+  const UGKS_GLOBAL S* xw;
+  const UGKS_GLOBAL S* xe;
+  const UGKS_GLOBAL S* xww;
+  const UGKS_GLOBAL S* xee;
+  const UGKS_GLOBAL S* sw;
+  const UGKS_GLOBAL S* sc;
+  const UGKS_GLOBAL S* se;
+  const UGKS_GLOBAL S* nw;
+  const UGKS_GLOBAL S* nc;
+  const UGKS_GLOBAL S* ne;
+  const UGKS_GLOBAL S* scc;
+  const UGKS_GLOBAL S* ncc;
 };
 
 // Left-minus-right flux difference for one velocity.  SX = +1 / -1: u has that sign across
@@ -723,24 +777,33 @@ __device__ __forceinline__ double y_part(const KParams& P, const UpdateCtx<S>& X
 
 // Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  One wavefront per cell.
 template <typename S>
-__global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(
-    KParams P, const S* __restrict__ fin, S* __restrict__ fout, const S* __restrict__ fg,
-    const double* __restrict__ recx, const double* __restrict__ recy, double* __restrict__ W) {
+__global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView pv) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int cpb = (int)(blockDim.x >> 6);
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int ii = find_inst(pv.off_upd, pv.ninst, b);
+  const Inst* __restrict__ I = inst_at(pv, ii);
+  const KParams P = I->P;
+  const int parity = (I->cur + pv.step) & 1;
+  const UGKS_GLOBAL S* fin = static_cast<const UGKS_GLOBAL S*>(I->f[parity]);
+  UGKS_GLOBAL S* fout = static_cast<UGKS_GLOBAL S*>(I->f[parity ^ 1]);
+  const UGKS_GLOBAL S* fg = static_cast<const UGKS_GLOBAL S*>(I->fg);
+  const UGKS_GLOBAL double* recx = I->recx;
+  const UGKS_GLOBAL double* recy = I->recy;
+  UGKS_GLOBAL double* W = I->W;
   const Tab L = tab_layout(P.K, P.M);
-  double* tb = lds + (size_t)wv * L.total;
-  const int c = xcd_block(blockIdx.x, gridDim.x) * cpb + wv;
+  double* tb = lds + (size_t)wv * (size_t)(pv.lds_per_cell / 8);
+  const int c = (b - first_block(pv.off_upd, ii)) * cpb + wv;
   const bool active = c < P.nx * P.ny;
   const int cc = active ? c : 0;
   const int i = cc % P.nx, j = cc / P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
-  const double* rl = recx + ((size_t)j * (P.nx + 1) + i) * kRec;
-  const double* rr = recx + ((size_t)j * (P.nx + 1) + i + 1) * kRec;
-  const double* rb = recy + ((size_t)j * P.nx + i) * kRec;
-  const double* rt = recy + ((size_t)(j + 1) * P.nx + i) * kRec;
+  const UGKS_GLOBAL double* rl = recx + ((size_t)j * (P.nx + 1) + i) * kRec;
+  const UGKS_GLOBAL double* rr = recx + ((size_t)j * (P.nx + 1) + i + 1) * kRec;
+  const UGKS_GLOBAL double* rb = recy + ((size_t)j * P.nx + i) * kRec;
+  const UGKS_GLOBAL double* rt = recy + ((size_t)(j + 1) * P.nx + i) * kRec;
   // Eq. (4)
   double Wn[4], W1[4];
 #pragma unroll
@@ -766,7 +829,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(
   // poly tables of the two x-faces (normal node k) and the two y-faces (normal node m)
   for (int e = lane; e < 2 * P.K + 2 * P.M; e += kWave) {
     double* out;
-    const double* rs;
+    const UGKS_GLOBAL double* rs;
     double un, lamf, U0;
     if (e < 2 * P.K) {
       const int side = e / P.K, k = e - side * P.K;
@@ -803,7 +866,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(
     int dst;
     if (e < 2 * P.M) {  // x-faces: tangential v
       const int side = e / P.M, m = e - side * P.M;
-      const double* rs = side ? rr : rl;
+      const UGKS_GLOBAL double* rs = side ? rr : rl;
       lam = rs[R_LAM];
       vel = P.vm[m];
       c0 = rs[R_VY];
@@ -811,7 +874,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(
     } else if (e < 2 * P.M + 2 * P.K) {  // y-faces: tangential u
       const int e2 = e - 2 * P.M;
       const int side = e2 / P.K, k = e2 - side * P.K;
-      const double* rs = side ? rt : rb;
+      const UGKS_GLOBAL double* rs = side ? rt : rb;
       lam = rs[R_LAM];
       vel = P.uk[k];
       c0 = rs[R_UX];
@@ -858,7 +921,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(
   X.ne = xslab(P, fin, fg, i + 1, jn);
   X.scc = fin + ((size_t)wrap(j - 2, P.ny) * P.nx + i) * P.NVP;
   X.ncc = fin + ((size_t)wrap(j + 2, P.ny) * P.nx + i) * P.NVP;
-  S* fo = fout + (size_t)cc * P.NVP;
+  UGKS_GLOBAL S* fo = fout + (size_t)cc * P.NVP;
   const int nch = P.NVP / kWave;
   for (int ch = 0; ch < nch; ++ch) {
     const unsigned v = (unsigned)(ch * kWave + lane);
@@ -900,7 +963,8 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(
                       bp, tp, be, te, m4b, m5b, m4t, m5t);
     const double g = fma(tb[L.g1_k + k], tb[L.g1_m + m], tb[L.gn_k + k] * tb[L.gn_m + m]);
     const double f1 = fma(Af, fc, fma(AdF, dFx + dFy, g));
-    *reinterpret_cast<S*>(reinterpret_cast<char*>(fo) + vb) = static_cast<S>(v < (unsigned)P.NV ? f1 : 0.0);
+    *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(fo) + vb) =
+        static_cast<S>(v < (unsigned)P.NV ? f1 : 0.0);
   }
   if (lane == 0) {
 #pragma unroll
@@ -911,66 +975,110 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(
 }  // namespace
 
 // ================================================================== launchers
-hipError_t launch_init(const KParams& P, int fp32, void* f, const double* W, hipStream_t s) {
-  const unsigned nc = (unsigned)((size_t)P.nx * P.ny);
+size_t plan_bytes(int n) {
+  const size_t inst = ((sizeof(Inst) * (size_t)n + 255) / 256) * 256;
+  return inst + 5 * (((size_t)(n + 1) * sizeof(int) + 255) / 256) * 256;
+}
+
+PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, PlanView* view) {
+  char* h = static_cast<char*>(buf);
+  const char* d = static_cast<const char*>(dev);
+  const size_t inst_bytes = ((sizeof(Inst) * (size_t)n + 255) / 256) * 256;
+  const size_t off_bytes = (((size_t)(n + 1) * sizeof(int) + 255) / 256) * 256;
+  std::memcpy(h, insts, sizeof(Inst) * (size_t)n);
+  int* off[5];
+  for (int a = 0; a < 5; ++a) off[a] = reinterpret_cast<int*>(h + inst_bytes + a * off_bytes);
+  PlanTotals t{};
+  // update kernel: cells per workgroup limited by twelve nu + nv tables per cell in LDS
+  int max_cell = 0;
+  for (int q = 0; q < n; ++q) {
+    const int km = insts[q].P.K + insts[q].P.M;
+    max_cell = km * 12 * 8 > max_cell ? km * 12 * 8 : max_cell;
+  }
+  int cpb = kCellsPerBlock;
+  while (cpb > 1 && (size_t)max_cell * cpb > 64 * 1024) cpb /= 2;
+  t.cpb_upd = cpb;
+  t.lds_per_cell = max_cell;
+  for (int q = 0; q < n; ++q) {
+    const KParams& P = insts[q].P;
+    const int nc = P.nx * P.ny;
+    const int nf = P.ny * (P.nx + 1) + (P.ny + 1) * P.nx;
+    off[0][q] = t.sums;
+    off[1][q] = t.upd;
+    off[2][q] = t.face;
+    off[3][q] = t.ghost;
+    off[4][q] = 0;
+    t.sums += (nc + kCellsPerBlock - 1) / kCellsPerBlock;
+    t.upd += (nc + cpb - 1) / cpb;
+    t.face += (nf + 255) / 256;
+    t.ghost += P.bc == UGKS_BC_CHANNEL ? 2 * P.ny : 0;
+  }
+  off[0][n] = t.sums;
+  off[1][n] = t.upd;
+  off[2][n] = t.face;
+  off[3][n] = t.ghost;
+  off[4][n] = 0;
+  view->inst = reinterpret_cast<const Inst*>(d);
+  view->off_sums = reinterpret_cast<const int*>(d + inst_bytes + 0 * off_bytes);
+  view->off_upd = reinterpret_cast<const int*>(d + inst_bytes + 1 * off_bytes);
+  view->off_face = reinterpret_cast<const int*>(d + inst_bytes + 2 * off_bytes);
+  view->off_ghost = reinterpret_cast<const int*>(d + inst_bytes + 3 * off_bytes);
+  view->ninst = n;
+  view->step = 0;
+  view->cpb_upd = cpb;
+  view->lds_per_cell = max_cell;
+  return t;
+}
+
+hipError_t launch_init(const PlanView& pv, int fp32, int ncells, hipStream_t s) {
   if (fp32)
-    init_kernel<float><<<nc, kWave, 0, s>>>(P, static_cast<float*>(f), W);
+    init_kernel<float><<<(unsigned)ncells, kWave, 0, s>>>(pv);
   else
-    init_kernel<double><<<nc, kWave, 0, s>>>(P, static_cast<double*>(f), W);
+    init_kernel<double><<<(unsigned)ncells, kWave, 0, s>>>(pv);
   return hipGetLastError();
 }
 
-hipError_t launch_ghost(const KParams& P, int fp32, const double* W, double* Wg, void* fg,
-                        double* hsg, hipStream_t s) {
-  const dim3 grid((unsigned)P.ny, 2);
-  if (fp32)
-    ghost_kernel<float><<<grid, kWave, 0, s>>>(P, W, Wg, static_cast<float*>(fg), hsg);
-  else
-    ghost_kernel<double><<<grid, kWave, 0, s>>>(P, W, Wg, static_cast<double*>(fg), hsg);
+// phase 0 ghosts, 1 moment sums, 2 interface scalars, 3 cell update
+hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int phase,
+                        hipStream_t s) {
+  switch (phase) {
+    case 0:
+      if (t.ghost == 0) return hipSuccess;
+      if (fp32)
+        ghost_kernel<float><<<(unsigned)t.ghost, kWave, 0, s>>>(pv);
+      else
+        ghost_kernel<double><<<(unsigned)t.ghost, kWave, 0, s>>>(pv);
+      break;
+    case 1:
+      if (fp32)
+        sums_kernel<float><<<(unsigned)t.sums, kWave * kCellsPerBlock, 0, s>>>(pv);
+      else
+        sums_kernel<double><<<(unsigned)t.sums, kWave * kCellsPerBlock, 0, s>>>(pv);
+      break;
+    case 2:
+      faces_kernel<<<(unsigned)t.face, 256, 0, s>>>(pv);
+      break;
+    default: {
+      const size_t lds = (size_t)t.lds_per_cell * t.cpb_upd;
+      const unsigned threads = kWave * (unsigned)t.cpb_upd;
+      if (fp32)
+        update_kernel<float><<<(unsigned)t.upd, threads, lds, s>>>(pv);
+      else
+        update_kernel<double><<<(unsigned)t.upd, threads, lds, s>>>(pv);
+    }
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_sums(const KParams& P, int fp32, const void* f, const void* fg, double* hs,
-                       hipStream_t s) {
-  const unsigned nc = (unsigned)((size_t)P.nx * P.ny);
-  const unsigned blocks = (nc + kCellsPerBlock - 1) / kCellsPerBlock;
-  const unsigned threads = kWave * kCellsPerBlock;
-  if (fp32)
-    sums_kernel<float><<<blocks, threads, 0, s>>>(P, static_cast<const float*>(f),
-                                                  static_cast<const float*>(fg), hs);
-  else
-    sums_kernel<double><<<blocks, threads, 0, s>>>(P, static_cast<const double*>(f),
-                                                   static_cast<const double*>(fg), hs);
-  return hipGetLastError();
-}
-
-hipError_t launch_faces(const KParams& P, const double* hs, const double* hsg, const double* W,
-                        const double* Wg, double* recx, double* recy, hipStream_t s) {
-  const long n = (long)P.ny * (P.nx + 1) + (long)(P.ny + 1) * P.nx;
-  const unsigned blocks = (unsigned)((n + 255) / 256);
-  faces_kernel<<<blocks, 256, 0, s>>>(P, hs, hsg, W, Wg, recx, recy);
-  return hipGetLastError();
-}
-
-hipError_t launch_update(const KParams& P, int fp32, const void* fin, void* fout, const void* fg,
-                         const double* recx, const double* recy, double* W, hipStream_t s) {
-  const unsigned nc = (unsigned)((size_t)P.nx * P.ny);
-  // twelve nu + nv doubles of tables per cell; fewer cells per block for wide grids
-  const size_t per_cell = sizeof(double) * 12 * (size_t)(P.K + P.M);
-  unsigned cpb = kCellsPerBlock;
-  while (cpb > 1 && per_cell * cpb > 64 * 1024) cpb /= 2;
-  const unsigned blocks = (nc + cpb - 1) / cpb;
-  const unsigned threads = kWave * cpb;
-  const size_t lds = per_cell * cpb;
-  if (fp32)
-    update_kernel<float><<<blocks, threads, lds, s>>>(
-        P, static_cast<const float*>(fin), static_cast<float*>(fout),
-        static_cast<const float*>(fg), recx, recy, W);
-  else
-    update_kernel<double><<<blocks, threads, lds, s>>>(
-        P, static_cast<const double*>(fin), static_cast<double*>(fout),
-        static_cast<const double*>(fg), recx, recy, W);
-  return hipGetLastError();
+hipError_t launch_step(const PlanView& pv, const PlanTotals& t, int fp32, hipStream_t s,
+                       hipEvent_t* ev) {
+  for (int phase = 0; phase < 4; ++phase) {
+    if (ev) (void)hipEventRecord(ev[2 * phase], s);
+    const hipError_t e = launch_phase(pv, t, fp32, phase, s);
+    if (ev) (void)hipEventRecord(ev[2 * phase + 1], s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ugks

@@ -1,0 +1,214 @@
+"""Serving form: independent channel-flow solves arriving over time, continuously batched.
+
+Requests of different meshes, velocity grids and Knudsen numbers arrive (Poisson).  The
+server admits them in arrival order while its HBM budget and slot count allow, keeps their
+f/W state resident on the GPU, and advances every resident request together: one
+``ugks_step_batch`` call packs all of them into one launch per phase.  A request that arrives
+while a batch is running is admitted (its solver created on a separate stream) before the
+server waits for that batch, so admission overlaps the device work.  A request leaves after
+its step count, with its moments copied to the host; its latency is arrival -> result on the
+host.  A request whose state turns invalid fails alone.
+
+``Server`` is independent of the GPU: it drives any executor with ``footprint``, ``create``,
+``step``, ``wait``, ``finish`` and ``release``.  ``GpuExecutor`` is the one that runs here.
+"""
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import workloads as WL
+
+
+@dataclass
+class Request:
+    rid: int
+    case: dict          # workload fields (mesh, velocity grid, kn, boundary, seed, ...)
+    steps: int
+    arrival: float      # seconds after the start of the run
+    precision: str = "fp32_store"
+    status: str = "queued"   # queued, running, done, failed, rejected
+    admitted: float = None
+    finished: float = None
+    result: np.ndarray = field(default=None, repr=False)
+    error: str = None
+
+    @property
+    def updates(self):
+        return WL.updates(self.case) * self.steps
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+MESHES = [(50, 12), (100, 25), (200, 50), (400, 100)]
+VGRIDS = [24, 32, 48]
+
+
+def serving_requests(n, rate, seed=4, steps=500, precision="fp32_store", meshes=MESHES,
+                     vgrids=VGRIDS):
+    """Seeded request stream shaped like the serving workload: mesh uniform over `meshes`
+    (4 x 1 channel), square velocity grid over `vgrids` on [-6, 6]^2, Kn log-uniform in
+    [0.01, 1], pressure ratio uniform in [1.5, 3], 1% density noise, Poisson arrivals at
+    `rate` per second (rate = inf: all at t = 0)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(n):
+        if math.isfinite(rate):
+            t += rng.exponential(1.0 / rate)
+        nx, ny = meshes[rng.integers(len(meshes))]
+        nv = vgrids[rng.integers(len(vgrids))]
+        kn = float(10.0 ** rng.uniform(-2.0, 0.0))
+        ratio = float(rng.uniform(1.5, 3.0))
+        case = dict(WL.CHANNEL_DEFAULTS, nx=nx, ny=ny, lx=4.0, ly=1.0, nu=nv, nv=nv, umax=6.0,
+                    vmax=6.0, kn=kn, p_ratio=ratio, noise=0.01, seed=1000 + rid)
+        out.append(Request(rid, case, steps, 0.0 if not math.isfinite(rate) else t,
+                           precision))
+    return out
+
+
+class GpuExecutor:
+    """Runs requests as UGKS solvers on the current GPU, stepped together in one batch."""
+
+    def __init__(self, max_slots):
+        import torch
+
+        from . import ugks
+
+        self.torch = torch
+        self.ugks = ugks
+        self.run_stream = torch.cuda.Stream()
+        self.admit_stream = torch.cuda.Stream()
+        self.batch = ugks.Batch(max_slots, stream=self.run_stream)
+        self.done_event = None
+
+    def footprint(self, req):
+        kn, kw = WL.solver_kwargs(req.case, req.precision)
+        mesh, vgrid, bc, opts = self.ugks.make_structs(**kw)
+        return self.ugks.ugks_required_bytes(mesh, vgrid, opts)
+
+    def create(self, req):
+        kn, kw = WL.solver_kwargs(req.case, req.precision)
+        with self.torch.cuda.stream(self.admit_stream):
+            return self.ugks.Solver(kn, stream=self.admit_stream, **kw)
+
+    def step(self, solvers, n):
+        self.batch.step(solvers, n)
+        ev = self.torch.cuda.Event()
+        ev.record(self.run_stream)
+        self.done_event = ev
+
+    def wait(self):
+        if self.done_event is not None:
+            self.done_event.synchronize()
+
+    def finish(self, solver):
+        return solver.moments()
+
+    def release(self, solver):
+        solver.close()
+
+    def close(self):
+        self.batch.close()
+
+
+class Server:
+    """Continuous batching with FIFO admission by memory footprint."""
+
+    def __init__(self, executor, budget_bytes, max_slots=256, quantum=50,
+                 clock=time.perf_counter, sleep=time.sleep):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.quantum = int(quantum)
+        self.clock = clock
+        self.sleep = sleep
+        self.batches = 0
+        self.max_resident = 0
+
+    def run(self, requests):
+        pending = sorted(requests, key=lambda r: r.arrival)
+        queue, active = [], []   # active entries: [request, solver, steps done, bytes]
+        used = 0
+        t0 = self.clock()
+        now = lambda: self.clock() - t0
+
+        def admit():
+            nonlocal used
+            while pending and pending[0].arrival <= now():
+                queue.append(pending.pop(0))
+            while queue and len(active) < self.max_slots:
+                r = queue[0]
+                need = self.ex.footprint(r)
+                if need > self.budget:
+                    r.status, r.error = "rejected", "footprint exceeds the HBM budget"
+                    queue.pop(0)
+                    continue
+                if used + need > self.budget:
+                    break
+                queue.pop(0)
+                try:
+                    s = self.ex.create(r)
+                except Exception as e:  # a request that cannot start fails alone
+                    r.status, r.error = "failed", str(e)
+                    continue
+                used += need
+                r.status, r.admitted = "running", now()
+                active.append([r, s, 0, need])
+            self.max_resident = max(self.max_resident, len(active))
+
+        while pending or queue or active:
+            admit()
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
+                    continue
+                break
+            q = min(self.quantum, min(r.steps - d for r, _, d, _ in active))
+            members = list(active)
+            self.ex.step([s for _, s, _, _ in members], q)
+            self.batches += 1
+            admit()            # requests arriving meanwhile start while the batch runs
+            self.ex.wait()
+            stepped = {id(e) for e in members}
+            still = []
+            for entry in active:
+                if id(entry) not in stepped:   # admitted during the batch: not stepped yet
+                    still.append(entry)
+                    continue
+                r, s, d, need = entry
+                entry[2] = d = d + q
+                if d >= r.steps:
+                    try:
+                        r.result = self.ex.finish(s)
+                        r.status = "done"
+                    except Exception as e:      # an invalid state fails this request alone
+                        r.status, r.error = "failed", str(e)
+                    r.finished = now()
+                    self.ex.release(s)
+                    used -= need
+                else:
+                    still.append(entry)
+            active = still
+        return summarize(requests, now())
+
+
+def summarize(requests, makespan):
+    done = [r for r in requests if r.status == "done"]
+    lat = np.array([r.latency for r in done]) if done else np.zeros(0)
+    upd = float(sum(r.updates for r in done))
+    return {
+        "requests": len(requests),
+        "done": len(done),
+        "failed": sum(r.status == "failed" for r in requests),
+        "rejected": sum(r.status == "rejected" for r in requests),
+        "makespan_s": makespan,
+        "p50_latency_s": float(np.percentile(lat, 50)) if done else None,
+        "p99_latency_s": float(np.percentile(lat, 99)) if done else None,
+        "mean_latency_s": float(lat.mean()) if done else None,
+        "updates": upd,
+        "updates_per_s": upd / makespan if makespan > 0 else None,
+    }

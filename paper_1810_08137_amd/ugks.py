@@ -83,6 +83,12 @@ SIGNATURES = {
     "ugks_get_kernel_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_double),
                                               ctypes.POINTER(ctypes.c_int64)]),
+    "ugks_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "ugks_step_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.c_int, ctypes.c_int]),
+    "ugks_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "ugks_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
 
 
@@ -199,6 +205,31 @@ def ugks_get_kernel_timing(h, kernel):
     return float(ms.value), int(n.value)
 
 
+def ugks_batch_create(stream_ptr, max_instances):
+    b = ctypes.c_void_p(None)
+    _check(lib().ugks_batch_create(ctypes.c_void_p(stream_ptr), int(max_instances),
+                                   ctypes.byref(b)))
+    return b
+
+
+def ugks_step_batch(b, handles, n):
+    arr = (ctypes.c_void_p * len(handles))(*[h.value for h in handles])
+    rc = lib().ugks_step_batch(b, arr, len(handles), int(n))
+    if rc != UGKS_OK:
+        msg = lib().ugks_batch_last_error(b)
+        raise UgksError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def ugks_batch_destroy(b):
+    return _check(lib().ugks_batch_destroy(b))
+
+
+def ugks_batch_last_error(b):
+    msg = lib().ugks_batch_last_error(b)
+    return msg.decode() if msg else ""
+
+
 # ----------------------------------------------------------------------------- structs
 def make_structs(nx, ny, lx, ly, nu, nv, umax, vmax, bc="channel", p_ratio=2.0, T_in=1.0,
                  T_wall=1.0, inlet_fixed_u=0, U_in=0.0, U_noise=0.0, precision="fp64", cfl=0.8,
@@ -230,8 +261,10 @@ class Solver:
         self.case = dict(case, kn=kn)
         self.mesh, self.vgrid, self.bc, self.opts = make_structs(**case)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self._alloc_stream = self._stream
         nbytes = ugks_required_bytes(self.mesh, self.vgrid, self.opts)
-        self._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        with torch.cuda.stream(self._stream):
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.opts.stream = ctypes.c_void_p(self._stream.cuda_stream)
         self.opts.workspace = ctypes.c_void_p(self._ws.data_ptr())
         self.opts.workspace_bytes = nbytes
@@ -241,6 +274,9 @@ class Solver:
         if getattr(self, "h", None) is not None and self.h.value:
             ugks_destroy(self.h)
             self.h = None
+            if self._stream is not self._alloc_stream:
+                # the workspace was last used on another stream (a batch adopted the handle)
+                self._ws.record_stream(self._stream)
 
     def __del__(self):
         try:
@@ -286,5 +322,31 @@ def updates_per_step(info):
     return info.nx * info.ny * info.nu * info.nv
 
 
-__all__ = [n for n in SIGNATURES] + ["Solver", "make_structs", "UgksError", "lib",
+class Batch:
+    """A batch of solvers stepped together (one launch per phase for all of them)."""
+
+    def __init__(self, max_instances, stream=None):
+        import torch
+
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self.b = ugks_batch_create(self._stream.cuda_stream, max_instances)
+
+    def step(self, solvers, n):
+        ugks_step_batch(self.b, [s.h for s in solvers], n)
+        for s in solvers:   # members now live on the batch's stream
+            s._stream = self._stream
+
+    def close(self):
+        if getattr(self, "b", None) is not None and self.b.value:
+            ugks_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = [n for n in SIGNATURES] + ["Solver", "Batch", "make_structs", "UgksError", "lib",
                                      "updates_per_step"]

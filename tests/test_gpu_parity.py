@@ -102,6 +102,13 @@ def test_fp32_store_error_c1():
     assert max(e.values()) > 1e-12      # it really is stored in FP32
 
 
+def test_fp32_store_c4_against_oracle_50_steps():
+    """The FP32-store form of the 400x100 x 40^2 case against the FP64 oracle."""
+    e = PR.run_and_compare(WL.C4, 50, precision="fp32_store", tol=PR.FP32_STORE_TOL,
+                           label="C4 FP32-store 50 steps")
+    assert max(e.values()) > 1e-12
+
+
 def test_runs_are_bitwise_deterministic():
     kn, kw = WL.solver_kwargs(WL.C1)
     a, b = ugks.Solver(kn, **kw), ugks.Solver(kn, **kw)
