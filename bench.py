@@ -21,6 +21,16 @@ sys.path.insert(0, HERE)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 
+# HBM bytes per launch of the update kernel on this workload: rocprofv3 FETCH_SIZE and
+# WRITE_SIZE of that kernel, each scaled by what the same counter reads for a device copy of
+# known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
+KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
+MEASURED_TRAFFIC = {
+    "source_sha256": "c4cc0d0a3a968128664d8e9577e2f2b88f34929eae841115b3c71f3461f962dc",
+    "fp64": 2.6465e9,
+    "fp32_store": 1.3459e9,
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -52,6 +62,43 @@ def time_solver(solver, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return start.elapsed_time(end), wall
+
+
+def kernel_source_hash():
+    import hashlib
+
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(form):
+    if MEASURED_TRAFFIC["source_sha256"] != kernel_source_hash():
+        return None
+    return MEASURED_TRAFFIC[form]
+
+
+def stream_copy(nbytes=1 << 30, reps=20):
+    """Device-to-device copy bandwidth of this GPU: bytes read plus bytes written per second
+    over `reps` copies of an `nbytes` buffer.  The same copy calibrates the byte counters."""
+    import torch
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        b.copy_(a)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    gbs = 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
+    del a, b
+    return {"buffer_bytes": nbytes, "GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS}
 
 
 def kernel_profile(solver, steps):
@@ -113,10 +160,18 @@ def serving(args, fp64_rate):
     return out
 
 
-def cpu_baseline(WL, budget_s):
-    from oracle import oracle as O
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or 10**9)
+
+def time_oracle(O, WL, threads, budget_s, max_steps):
     O.set_threads(threads)
     used = O.get_threads()
     o = O.Oracle(**WL.oracle_kwargs(WL.C2))
@@ -124,17 +179,26 @@ def cpu_baseline(WL, budget_s):
         t0 = time.perf_counter()
         assert o.step(1) == 0
         first = time.perf_counter() - t0
-        n = max(1, min(10, int(budget_s / max(first, 1e-3)) - 1))
+        n = max(1, min(max_steps, int(budget_s / max(first, 1e-3)) - 1))
         t0 = time.perf_counter()
         assert o.step(n) == 0
         dt = time.perf_counter() - t0
     finally:
         o.close()
-    upd = WL.updates(WL.C2)
-    return {"value": upd * n / dt, "unit": "cell-velocity updates/s", "cores": used,
-            "kind": "oracle",
+    return WL.updates(WL.C2) * n / dt, n, dt, used
+
+
+def cpu_baseline(WL, budget_s):
+    from oracle import oracle as O
+
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or 10**9)
+    v, n, dt, used = time_oracle(O, WL, threads, budget_s, 10)
+    v1, n1, dt1, _ = time_oracle(O, WL, 1, budget_s, 3)
+    return {"value": v, "unit": "cell-velocity updates/s", "cores": used, "kind": "oracle",
             "sample": f"400x100 cells x 40^2 velocities, FP64 oracle, {n} timed steps after 1 "
-                      f"untimed step ({dt:.1f} s), OpenMP over rows with {used} threads"}
+                      f"untimed step ({dt:.1f} s), OpenMP over rows with {used} threads "
+                      f"on {os.cpu_count()} logical CPUs ({cpu_model()})",
+            "single_thread": {"value": v1, "steps": n1, "seconds": dt1}}
 
 
 def main():
@@ -154,6 +218,7 @@ def main():
         sys.exit(1)
     ugks.lib()  # fail loudly when the HIP library is missing
 
+    copy = stream_copy()
     fp64 = run_form(WL, ugks, "fp64", args.steps, args.warmup)
     upd = WL.updates(WL.C2)
     kernels = fp64["kernels"]
@@ -178,8 +243,10 @@ def main():
                                "p_in/p_out 2, 1% seeded density noise, FP64",
                    "cells": 40000, "velocities": 1600, "updates_per_step": upd},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("fp64"),
                      "algorithmic_bytes_per_launch": algo_bytes},
+        "stream_copy": copy,
         "step_hbm_frac": algo_bytes / (fp64["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels": kernels,
     }
@@ -191,6 +258,7 @@ def main():
                              / HBM_PEAK_GBS,
                              "error_vs_fp64": dict(moment_errors(fp32["moments"], fp64["moments"]),
                                                    steps=fp32["total_steps"]),
+                             "update_kernel_traffic": measured_traffic("fp32_store"),
                              "kernels": fp32["kernels"]}
     if not args.no_serving:
         out["serving"] = serving(args, fp64["updates_per_s"])
