@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-steps", type=int, default=100)
+    ap.add_argument("--serving-rates", default="0.8",
+                    help="Poisson arrival rates as fractions of the saturation rate")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="also time the paper's meshes M1-M4 at 29^2, 49^2 and 69^2 velocities")
+    ap.add_argument("--sweep-steps", type=int, default=200)
     return ap.parse_args()
 
 
@@ -135,29 +140,64 @@ def moment_errors(m, ref):
 
 def serving(args, fp64_rate):
     """Continuous batching of independent channel solves: saturation throughput from a burst
-    of requests, then Poisson arrivals at 0.8x that rate for the latency figures."""
+    of requests, then Poisson arrivals at fractions of that rate for the latency figures."""
     from paper_1810_08137_amd import serving as SV
 
     n, steps = args.serving_requests, args.serving_steps
     out = {"requests": n, "steps_per_request": steps, "precision": "fp32_store",
            "meshes": SV.MESHES, "velocity_grids": SV.VGRIDS}
     ex = SV.GpuExecutor(max_slots=n)
+    runs = []
     try:
         burst = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=steps)
         sat = burst.run(SV.serving_requests(n, float("inf"), seed=4, steps=steps))
-        rate = 0.8 * sat["done"] / sat["makespan_s"]
-        srv = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=25)
-        st = srv.run(SV.serving_requests(n, rate, seed=4, steps=steps))
+        sat_rate = sat["done"] / sat["makespan_s"]
+        for frac in [float(x) for x in args.serving_rates.split(",") if x]:
+            srv = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=25)
+            st = srv.run(SV.serving_requests(n, frac * sat_rate, seed=4, steps=steps))
+            runs.append({"rate_fraction": frac, "rate_per_s": frac * sat_rate, "done": st["done"],
+                         "failed": st["failed"], "p50_latency_s": st["p50_latency_s"],
+                         "p99_latency_s": st["p99_latency_s"],
+                         "updates_per_s": st["updates_per_s"], "batches": srv.batches,
+                         "max_resident": srv.max_resident, "host_s": srv.host_s})
     finally:
         ex.close()
-    out["saturation"] = {"requests_per_s": sat["done"] / sat["makespan_s"],
-                         "updates_per_s": sat["updates_per_s"], "makespan_s": sat["makespan_s"]}
-    out["poisson"] = {"rate_per_s": rate, "done": st["done"], "failed": st["failed"],
-                      "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
-                      "updates_per_s": st["updates_per_s"], "batches": srv.batches,
-                      "max_resident": srv.max_resident}
+    out["saturation"] = {"requests_per_s": sat_rate, "updates_per_s": sat["updates_per_s"],
+                         "makespan_s": sat["makespan_s"], "host_s": burst.host_s}
+    out["poisson"] = runs
     out["speedup_vs_fp64_single"] = sat["updates_per_s"] / fp64_rate
     return out
+
+
+# Paper, Table 3: wall time of 10,000 steps at 29^2 velocities (context, other hardware)
+PAPER_TABLE3_V100_S = {(40, 20): 46.68, (80, 40): 93.29, (120, 60): 169.99, (160, 80): 287.83}
+PAPER_TABLE3_E5_2650_1T_S = {(40, 20): 1749.13, (80, 40): 8507.09, (120, 60): 19603.08,
+                             (160, 80): 34076.52}
+
+
+def paper_sweep(WL, ugks, steps):
+    """The paper's channel (L/W = 2, Kn 0.1, p_in/p_out 1.5) on its meshes M1-M4 and velocity
+    grids 29^2, 49^2, 69^2, FP64: updates/s and the implied time of its 10,000-step runs."""
+    rows = []
+    for nx, ny in WL.PAPER_MESHES:
+        for nv in WL.PAPER_VGRIDS:
+            case = WL.paper_mesh(nx, ny, nv)
+            kn, kw = WL.solver_kwargs(case, "fp64")
+            s = ugks.Solver(kn, **kw)
+            try:
+                ms, _ = time_solver(s, steps, 5)
+                s.moments()
+            finally:
+                s.close()
+            rate = WL.updates(case) * steps / (ms * 1e-3)
+            row = {"mesh": [nx, ny], "velocities": [nv, nv], "updates_per_s": rate,
+                   "ms_per_step": ms / steps, "s_per_10000_steps": ms / steps * 10.0}
+            if nv == 29:
+                row["paper_v100_s"] = PAPER_TABLE3_V100_S[(nx, ny)]
+                row["speedup_vs_paper_e5_2650_1t"] = (PAPER_TABLE3_E5_2650_1T_S[(nx, ny)]
+                                                      / row["s_per_10000_steps"])
+            rows.append(row)
+    return {"steps": steps, "dtype": "f64", "rows": rows}
 
 
 def cpu_model():
@@ -262,6 +302,8 @@ def main():
                              "kernels": fp32["kernels"]}
     if not args.no_serving:
         out["serving"] = serving(args, fp64["updates_per_s"])
+    if args.paper_sweep:
+        out["paper_sweep"] = paper_sweep(WL, ugks, args.sweep_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(WL, args.cpu_seconds)
     out["paper_context"] = ("paper: 118.38x speed-up of a Tesla V100 over one E5-2650 thread "

@@ -45,20 +45,19 @@ __device__ __forceinline__ void st(UGKS_GLOBAL S* p, unsigned i, double x) {
 }
 
 // ------------------------------------------------------------------ pointwise physics
-// Reciprocal: hardware estimate refined by two Newton steps (relative error ~1 ulp).
+// Reciprocal: the hardware estimate (relative error below 5e-8 on gfx950) refined by one
+// Newton step (below 3e-15).
 __device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
-// Van Leer limited slope of two one-sided differences, times `scale` (second-order
-// reconstruction, Sec. 2.A): 2 p q / (p + q) when p and q agree in sign, else 0.
-__device__ __forceinline__ double limited(double p, double q, double scale) {
+// Van Leer limited slope of two one-sided differences p, q (second-order reconstruction,
+// Sec. 2.A), 2 p q / ((p + q) dx) when p and q agree in sign, else 0, times half a cell: the
+// change of the reconstruction from the cell centre to a face, p q / (p + q).
+__device__ __forceinline__ double half_limited(double p, double q) {
   const double pq = p * q;
-  const double r = (pq * recip(p + q)) * scale;  // evaluated on every lane, then selected
+  const double r = pq * recip(p + q);
   return pq > 0.0 ? r : 0.0;
 }
 
@@ -168,6 +167,20 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 
+// Cell (or tile) order of a launch: bands of kBand rows, column by column inside a band.  The
+// workgroups an XCD runs at one time then cover a compact patch of the mesh, so the stencil
+// neighbours a wavefront reads were read by its neighbours at about the same time and come
+// from that XCD's L2.
+constexpr int kBand = 16;
+__device__ __forceinline__ void band_order(int L, int nx, int ny, int band, int& i, int& j) {
+  const int per = band * nx;
+  const int bnd = L / per;
+  const int r = L - bnd * per;
+  const int rows = ny - bnd * band < band ? ny - bnd * band : band;
+  i = r / rows;
+  j = bnd * band + (r - i * rows);
+}
+
 // f slab of column i of row j, i in [-2, nx+1]: a cell, a wrapped cell (periodic) or the
 // inlet/outlet ghost column (channel).
 template <typename S>
@@ -199,14 +212,41 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// Reduce 16 per-lane partial sums over the wavefront through the wave's LDS block (16 rows
+// of 65 doubles, the pad keeping the transposed reads on distinct banks) and add the totals
+// to `fin`, whose lane 16 face + q holds sum q of that face.  Lane l adds the values of
+// element l & 15 held by lanes 16 (l >> 4) .. 16 (l >> 4) + 15, then two exchanges combine
+// the quarters.  Sums 4..7 (the tangential-slope moments) were accumulated from half-cell
+// changes and take the factor `tscale` (2 / tangential spacing) here.  LDS operations of one
+// wavefront complete in program order.
+constexpr int kRedRow = kWave + 1;
+__device__ __forceinline__ void flush_face(const double* a, int face, double& fin, int lane,
+                                           double* red, double tscale) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q) red[q * kRedRow + lane] = a[q];
+  __builtin_amdgcn_wave_barrier();
+  const int e = lane & 15, r = lane >> 4;
+  const double* row = red + e * kRedRow + r * 16;
+  double t = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) t += row[k];
+  t += __shfl_xor(t, 16, kWave);
+  t += __shfl_xor(t, 32, kWave);
+  if (e >= 4 && e < 8) t *= tscale;
+  if (r == face) fin += t;
+  __builtin_amdgcn_wave_barrier();
+}
+
 // 16 moment sums of one face side (S1 and S7): weight wt, normal/tangential velocity
-// (un, ut), reconstructed f and its normal/tangential slopes.
+// (un, ut), reconstructed f, the tangential half-cell change ht (the tangential slope times
+// half the tangential spacing; its sums are scaled when flushed) and the slope term
+// D = u sigma_x + v sigma_y.
 __device__ __forceinline__ void add_side(double* a, double wt, double un, double ut, double c2h,
-                                         double fh, double sn, double st) {
+                                         double fh, double ht, double D) {
   const double x0 = wt * fh;
-  const double x1 = wt * st;
+  const double x1 = wt * ht;
   const double x2 = x0 * un;
-  const double x3 = (wt * un) * fma(un, sn, ut * st);
+  const double x3 = (wt * un) * D;
   a[0] += x0;
   a[1] = fma(x0, un, a[1]);
   a[2] = fma(x0, ut, a[2]);
@@ -354,9 +394,14 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
 }
 
 // Per cell: slopes and the outgoing moment sums of all four faces.  One wavefront per cell,
-// four cells per block.
+// four cells per block.  Chunks come in velocity-quadrant order: a run of chunks with one
+// sign of u and one of v feeds one x-face and one y-face, whose 16 running sums are flushed
+// into `fin` (lane 16 face + q) at the end of the run; a chunk of mixed signs feeds each
+// face in turn with per-lane upwind weights.
 template <typename S>
-__global__ __launch_bounds__(kWave* kCellsPerBlock) void sums_kernel(PlanView pv) {
+__global__ __launch_bounds__(kWave* kCellsPerBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void sums_kernel(PlanView pv) {
+  __shared__ double red_all[kCellsPerBlock][16 * kRedRow];
   const int lane = threadIdx.x & (kWave - 1);
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int ii = find_inst(pv.off_sums, pv.ninst, b);
@@ -366,77 +411,96 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void sums_kernel(PlanView pv
   const UGKS_GLOBAL S* fg = static_cast<const UGKS_GLOBAL S*>(I->fg);
   UGKS_GLOBAL double* hs = I->hs;
   // the wavefront index is uniform: keep everything derived from it in scalar registers
-  const int c = (b - first_block(pv.off_sums, ii)) * kCellsPerBlock +
-                __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = (b - first_block(pv.off_sums, ii)) * kCellsPerBlock + wv;
   if (c >= P.nx * P.ny) return;
-  const int i = c % P.nx, j = c / P.nx;
+  double* red = red_all[wv];
+  int i, j;
+  band_order(c, P.nx, P.ny, kBand, i, j);
   const bool wall_row = P.bc == UGKS_BC_CHANNEL && (j == 0 || j == P.ny - 1);
-  const UGKS_GLOBAL S* f0 = f + (size_t)c * P.NVP;
+  const size_t cell = (size_t)j * P.nx + i;
+  const UGKS_GLOBAL S* f0 = f + cell * P.NVP;
   const UGKS_GLOBAL S* fw = xslab(P, f, fg, i - 1, j);
   const UGKS_GLOBAL S* fe = xslab(P, f, fg, i + 1, j);
   const UGKS_GLOBAL S* fs = f + ((size_t)wrap(j - 1, P.ny) * P.nx + i) * P.NVP;
   const UGKS_GLOBAL S* fn = f + ((size_t)wrap(j + 1, P.ny) * P.nx + i) * P.NVP;
-  const double hdx = 0.5 * P.dx, hdy = 0.5 * P.dy;
-  double acc[kSlots];
-#pragma unroll
-  for (int q = 0; q < kSlots; ++q) acc[q] = 0.0;
+  double fin = 0.0;
   const int nch = P.NVP / kWave;
-  // stencil values are loaded two chunks ahead of the one being summed
-  double b0[5], b1[5];
+  // the five stencil values of chunk ch, loaded while chunk ch - 1 is summed
+  double buf[5];
   {
     const unsigned o0 = (unsigned)lane * (unsigned)sizeof(S);
-    b0[0] = (double)ldb(f0, o0);
-    b0[1] = (double)ldb(fw, o0);
-    b0[2] = (double)ldb(fe, o0);
-    b0[3] = (double)ldb(fs, o0);
-    b0[4] = (double)ldb(fn, o0);
-    const unsigned o1 = (unsigned)(nch > 1 ? kWave + lane : lane) * (unsigned)sizeof(S);
-    b1[0] = (double)ldb(f0, o1);
-    b1[1] = (double)ldb(fw, o1);
-    b1[2] = (double)ldb(fe, o1);
-    b1[3] = (double)ldb(fs, o1);
-    b1[4] = (double)ldb(fn, o1);
+    buf[0] = (double)ldb(f0, o0);
+    buf[1] = (double)ldb(fw, o0);
+    buf[2] = (double)ldb(fe, o0);
+    buf[3] = (double)ldb(fs, o0);
+    buf[4] = (double)ldb(fn, o0);
   }
-  for (int ch = 0; ch < nch; ++ch) {
+  struct Point {
+    double fc, hx, hy, D, u, vv, w, c2h;
+  };
+  const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
+  // take chunk ch out of the buffer, start loading chunk ch + 1, and form the half-cell
+  // changes hx = sigma_x dx / 2, hy = sigma_y dy / 2 and D = u sigma_x + v sigma_y
+  auto point = [&](int ch) {
+    Point q;
     const int v = ch * kWave + lane;
+    const double fwv = buf[1], fev = buf[2], fsv = buf[3], fnv = buf[4];
+    q.fc = buf[0];
+    const unsigned on = (unsigned)(ch + 1 < nch ? v + kWave : v) * (unsigned)sizeof(S);
+    buf[0] = (double)ldb(f0, on);
+    buf[1] = (double)ldb(fw, on);
+    buf[2] = (double)ldb(fe, on);
+    buf[3] = (double)ldb(fs, on);
+    buf[4] = (double)ldb(fn, on);
+    q.hx = half_limited(fev - q.fc, q.fc - fwv);
+    const double hyl = half_limited(fnv - q.fc, q.fc - fsv);
+    q.hy = wall_row ? 0.0 : hyl;
+    const unsigned v8 = (unsigned)v * 8u;
+    q.u = ldb(P.U, v8);
+    q.vv = ldb(P.V, v8);
+    q.w = ldb(P.Wq, v8);
+    q.c2h = 0.5 * fma(q.u, q.u, q.vv * q.vv);
+    q.D = fma(q.u * two_idx, q.hx, (q.vv * two_idy) * q.hy);
+    return q;
+  };
+  int ch = 0;
+  while (ch < nch) {
     const int code = P.chunk_sign[ch];
     const int su = chunk_sign_u(code), sv = chunk_sign_v(code);
-    const double fc = b0[0], fwv = b0[1], fev = b0[2], fsv = b0[3], fnv = b0[4];
-    const unsigned on = (unsigned)(ch + 2 < nch ? v + 2 * kWave : v) * (unsigned)sizeof(S);
+    if (su != 0 && sv != 0) {
+      double ax[16], ay[16];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) b0[q] = b1[q];
-    b1[0] = (double)ldb(f0, on);
-    b1[1] = (double)ldb(fw, on);
-    b1[2] = (double)ldb(fe, on);
-    b1[3] = (double)ldb(fs, on);
-    b1[4] = (double)ldb(fn, on);
-    const double sx = limited(fev - fc, fc - fwv, 2.0 * P.inv_dx);
-    const double syl = limited(fnv - fc, fc - fsv, 2.0 * P.inv_dy);
-    const double sy = wall_row ? 0.0 : syl;
-    const unsigned v8 = (unsigned)v * 8u;
-    const double u = ldb(P.U, v8), vv = ldb(P.V, v8), w = ldb(P.Wq, v8);
-    const double c2h = 0.5 * fma(u, u, vv * vv);
-    if (su > 0) {
-      add_side(acc + 16 * S_XP, w, u, vv, c2h, fma(hdx, sx, fc), sx, sy);
-    } else if (su < 0) {
-      add_side(acc + 16 * S_XM, w, u, vv, c2h, fma(-hdx, sx, fc), sx, sy);
+      for (int q = 0; q < 16; ++q) ax[q] = ay[q] = 0.0;
+      do {
+        const Point q = point(ch);
+        add_side(ax, q.w, q.u, q.vv, q.c2h, su > 0 ? q.fc + q.hx : q.fc - q.hx, q.hy, q.D);
+        add_side(ay, q.w, q.vv, q.u, q.c2h, sv > 0 ? q.fc + q.hy : q.fc - q.hy, q.hx, q.D);
+        ++ch;
+      } while (ch < nch && P.chunk_sign[ch] == code);
+      flush_face(ax, su > 0 ? S_XP : S_XM, fin, lane, red, two_idy);
+      flush_face(ay, sv > 0 ? S_YP : S_YM, fin, lane, red, two_idx);
     } else {
-      const double hx = upwind_left(u);
-      add_side(acc + 16 * S_XP, w * hx, u, vv, c2h, fma(hdx, sx, fc), sx, sy);
-      add_side(acc + 16 * S_XM, w * (1.0 - hx), u, vv, c2h, fma(-hdx, sx, fc), sx, sy);
-    }
-    if (sv > 0) {
-      add_side(acc + 16 * S_YP, w, vv, u, c2h, fma(hdy, sy, fc), sy, sx);
-    } else if (sv < 0) {
-      add_side(acc + 16 * S_YM, w, vv, u, c2h, fma(-hdy, sy, fc), sy, sx);
-    } else {
-      const double hy = upwind_left(vv);
-      add_side(acc + 16 * S_YP, w * hy, vv, u, c2h, fma(hdy, sy, fc), sy, sx);
-      add_side(acc + 16 * S_YM, w * (1.0 - hy), vv, u, c2h, fma(-hdy, sy, fc), sy, sx);
+      const Point q = point(ch);
+      const double hx = upwind_left(q.u), hy = upwind_left(q.vv);
+      for (int face = 0; face < 4; ++face) {
+        double a[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a[k] = 0.0;
+        if (face == S_XP)
+          add_side(a, q.w * hx, q.u, q.vv, q.c2h, q.fc + q.hx, q.hy, q.D);
+        else if (face == S_XM)
+          add_side(a, q.w * (1.0 - hx), q.u, q.vv, q.c2h, q.fc - q.hx, q.hy, q.D);
+        else if (face == S_YP)
+          add_side(a, q.w * hy, q.vv, q.u, q.c2h, q.fc + q.hy, q.hx, q.D);
+        else
+          add_side(a, q.w * (1.0 - hy), q.vv, q.u, q.c2h, q.fc - q.hy, q.hx, q.D);
+        flush_face(a, face, fin, lane, red, face < 2 ? two_idy : two_idx);
+      }
+      ++ch;
     }
   }
-  reduce_scatter<32>(acc, lane);
-  hs[(size_t)c * kSlots + lane] = acc[0];
+  hs[cell * kSlots + lane] = fin;
 }
 
 // S2-S5 at one interior interface, local frame.  S = [W0, Wt, Q1, Q2].  Writes the local
@@ -675,11 +739,13 @@ __device__ __forceinline__ void face_poly(const UGKS_GLOBAL double* r, double un
 
 // Equilibrium part at one velocity from a face's tables (poly at the normal node, E at the
 // tangential node) and the time-integrated flux of the face.
+// D = u sigma_x + v sigma_y is the slope term of the upwind cell (the same for its x- and
+// y-faces).
 __device__ __forceinline__ double face_flux(double2 pab, double2 pcd, double E, double un,
-                                            double ut, double fh, double sn, double st,
-                                            double m4, double m5) {
+                                            double ut, double fh, double D, double m4,
+                                            double m5) {
   const double G = E * fma(ut, fma(ut, fma(ut, pcd.y, pcd.x), pab.y), pab.x);
-  const double free_part = fma(m4, fh, -m5 * fma(un, sn, ut * st));
+  const double free_part = fma(m4, fh, -m5 * D);
   return un * (G + free_part);
 }
 
@@ -702,14 +768,15 @@ struct UpdateCtx {
 
 // Left-minus-right flux difference for one velocity.  SX = +1 / -1: u has that sign across
 // the wavefront; 0: per lane.  All loads are unconditional (every slab pointer is valid);
-// boundaries only switch results.
+// boundaries only switch results.  Slopes are carried as half-cell changes h = sigma dx / 2
+// (or dy / 2); ucx = 2 u / dx and vcy = 2 v / dy turn them into u sigma_x + v sigma_y.
 template <int SX, typename S>
-__device__ __forceinline__ double x_part(const KParams& P, const UpdateCtx<S>& X, unsigned vb,
-                                         double u, double vv, double fc, double fW, double fE,
-                                         double sx0, double sy0, bool ghost_w, bool ghost_e,
-                                         bool wall_row, const double* lp, const double* rp,
-                                         double le, double re, double m4l, double m5l,
-                                         double m4r, double m5r) {
+__device__ __forceinline__ double x_part(const UpdateCtx<S>& X, unsigned vb, double u, double vv,
+                                         double ucx, double vcy, double fc, double fW,
+                                         double fE, double hx0, double D0, bool ghost_w,
+                                         bool ghost_e, bool wall_row, const double* lp,
+                                         const double* rp, double le, double re, double m4l,
+                                         double m5l, double m4r, double m5r) {
   // particles with u > 0 enter through the left face from cell i-1 (the upwind cell X)
   const bool right = SX > 0 ? true : (SX < 0 ? false : (u > 0.0));
   const double fXX = (double)ldb(right ? X.xww : X.xee, vb);
@@ -717,57 +784,56 @@ __device__ __forceinline__ double x_part(const KParams& P, const UpdateCtx<S>& X
   const double fXs = (double)ldb(right ? X.sw : X.se, vb);
   const double fX = right ? fW : fE;
   const bool ghostX = right ? ghost_w : ghost_e;
-  const double sxl = right ? limited(fc - fX, fX - fXX, 2.0 * P.inv_dx)
-                           : limited(fXX - fX, fX - fc, 2.0 * P.inv_dx);
-  const double syl = limited(fXn - fX, fX - fXs, 2.0 * P.inv_dy);
-  const double sxX = ghostX ? 0.0 : sxl;
-  const double syX = (ghostX || wall_row) ? 0.0 : syl;
-  const double sgn_hdx = right ? 0.5 * P.dx : -0.5 * P.dx;
-  const double fh_in = fma(sgn_hdx, sxX, fX);
-  const double fh_own = fma(sgn_hdx, sx0, fc);
+  const double hxl = right ? half_limited(fc - fX, fX - fXX) : half_limited(fXX - fX, fX - fc);
+  const double hyl = half_limited(fXn - fX, fX - fXs);
+  const double hxX = ghostX ? 0.0 : hxl;
+  const double hyX = (ghostX || wall_row) ? 0.0 : hyl;
+  const double DX = fma(ucx, hxX, vcy * hyX);
+  const double fh_in = right ? fX + hxX : fX - hxX;
+  const double fh_own = right ? fc + hx0 : fc - hx0;
   // left face: upwind is X when moving right, the cell itself when moving left
-  const double fl = right ? fh_in : fh_own, snl = right ? sxX : sx0, stl = right ? syX : sy0;
-  const double fr = right ? fh_own : fh_in, snr = right ? sx0 : sxX, str = right ? sy0 : syX;
+  const double fl = right ? fh_in : fh_own, Dl = right ? DX : D0;
+  const double fr = right ? fh_own : fh_in, Dr = right ? D0 : DX;
   const double2 lab = *reinterpret_cast<const double2*>(lp);
   const double2 lcd = *reinterpret_cast<const double2*>(lp + 2);
   const double2 rab = *reinterpret_cast<const double2*>(rp);
   const double2 rcd = *reinterpret_cast<const double2*>(rp + 2);
-  const double Fl = face_flux(lab, lcd, le, u, vv, fl, snl, stl, m4l, m5l);
-  const double Fr = face_flux(rab, rcd, re, u, vv, fr, snr, str, m4r, m5r);
+  const double Fl = face_flux(lab, lcd, le, u, vv, fl, Dl, m4l, m5l);
+  const double Fr = face_flux(rab, rcd, re, u, vv, fr, Dr, m4r, m5r);
   return Fl - Fr;
 }
 
 // Bottom-minus-top flux difference.  Walls: particles leaving a wall follow rho_w times the
 // wall Maxwellian (its tables hold dx dt rho_w g_w), those reaching it carry the wall-row value.
 template <int SY, typename S>
-__device__ __forceinline__ double y_part(const KParams& P, const UpdateCtx<S>& X, unsigned vb,
-                                         double u, double vv, double fc, double fS, double fN,
-                                         double sx0, double sy0, bool wall_b, bool wall_t,
-                                         bool s_wallrow, bool n_wallrow, const double* bp,
-                                         const double* tp, double be, double te, double m4b,
-                                         double m5b, double m4t, double m5t) {
+__device__ __forceinline__ double y_part(const UpdateCtx<S>& X, unsigned vb, double u, double vv,
+                                         double ucx, double vcy, double fc, double fS,
+                                         double fN, double hy0, double D0, bool wall_b,
+                                         bool wall_t, bool s_wallrow, bool n_wallrow,
+                                         const double* bp, const double* tp, double be,
+                                         double te, double m4b, double m5b, double m4t,
+                                         double m5t) {
   const bool up = SY > 0 ? true : (SY < 0 ? false : (vv > 0.0));
   const double fYY = (double)ldb(up ? X.scc : X.ncc, vb);
   const double fYe = (double)ldb(up ? X.se : X.ne, vb);
   const double fYw = (double)ldb(up ? X.sw : X.nw, vb);
   const double fY = up ? fS : fN;
   const bool Y_wallrow = up ? s_wallrow : n_wallrow;
-  const double syl = up ? limited(fc - fY, fY - fYY, 2.0 * P.inv_dy)
-                        : limited(fYY - fY, fY - fc, 2.0 * P.inv_dy);
-  const double syY = Y_wallrow ? 0.0 : syl;
-  const double sxY = limited(fYe - fY, fY - fYw, 2.0 * P.inv_dx);
-  const double sgn_hdy = up ? 0.5 * P.dy : -0.5 * P.dy;
-  const double fh_in = fma(sgn_hdy, syY, fY);
-  const double fh_own = fma(sgn_hdy, sy0, fc);
+  const double hyl = up ? half_limited(fc - fY, fY - fYY) : half_limited(fYY - fY, fY - fc);
+  const double hyY = Y_wallrow ? 0.0 : hyl;
+  const double hxY = half_limited(fYe - fY, fY - fYw);
+  const double DY = fma(ucx, hxY, vcy * hyY);
+  const double fh_in = up ? fY + hyY : fY - hyY;
+  const double fh_own = up ? fc + hy0 : fc - hy0;
   // bottom face: upwind is Y when moving up, the cell itself when moving down
-  const double fb = up ? fh_in : fh_own, snb = up ? syY : sy0, stb = up ? sxY : sx0;
-  const double ft = up ? fh_own : fh_in, snt = up ? sy0 : syY, stt = up ? sx0 : sxY;
+  const double fb = up ? fh_in : fh_own, Db = up ? DY : D0;
+  const double ft = up ? fh_own : fh_in, Dt = up ? D0 : DY;
   const double2 bab = *reinterpret_cast<const double2*>(bp);
   const double2 bcd = *reinterpret_cast<const double2*>(bp + 2);
   const double2 tab2 = *reinterpret_cast<const double2*>(tp);
   const double2 tcd = *reinterpret_cast<const double2*>(tp + 2);
-  const double Fb_face = face_flux(bab, bcd, be, vv, u, fb, snb, stb, m4b, m5b);
-  const double Ft_face = face_flux(tab2, tcd, te, vv, u, ft, snt, stt, m4t, m5t);
+  const double Fb_face = face_flux(bab, bcd, be, vv, u, fb, Db, m4b, m5b);
+  const double Ft_face = face_flux(tab2, tcd, te, vv, u, ft, Dt, m4t, m5t);
   const double Fb_wall = up ? vv * (be * bab.x) : vv * (m4b * fc);
   const double Ft_wall = up ? vv * (m4t * fc) : vv * (te * tab2.x);
   const double Fb = wall_b ? Fb_wall : Fb_face;
@@ -797,8 +863,9 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
   double* tb = lds + (size_t)wv * (size_t)(pv.lds_per_cell / 8);
   const int c = (b - first_block(pv.off_upd, ii)) * cpb + wv;
   const bool active = c < P.nx * P.ny;
-  const int cc = active ? c : 0;
-  const int i = cc % P.nx, j = cc / P.nx;
+  int i, j;
+  band_order(active ? c : 0, P.nx, P.ny, kBand, i, j);
+  const int cc = j * P.nx + i;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
   const UGKS_GLOBAL double* rl = recx + ((size_t)j * (P.nx + 1) + i) * kRec;
   const UGKS_GLOBAL double* rr = recx + ((size_t)j * (P.nx + 1) + i + 1) * kRec;
@@ -922,6 +989,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
   X.scc = fin + ((size_t)wrap(j - 2, P.ny) * P.nx + i) * P.NVP;
   X.ncc = fin + ((size_t)wrap(j + 2, P.ny) * P.nx + i) * P.NVP;
   UGKS_GLOBAL S* fo = fout + (size_t)cc * P.NVP;
+  const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
   const int nch = P.NVP / kWave;
   for (int ch = 0; ch < nch; ++ch) {
     const unsigned v = (unsigned)(ch * kWave + lane);
@@ -933,9 +1001,11 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
     const double fc = (double)ldb(X.f0, vb);
     const double fW = (double)ldb(X.xw, vb), fE = (double)ldb(X.xe, vb);
     const double fS = (double)ldb(X.sc, vb), fN = (double)ldb(X.nc, vb);
-    const double sx0 = limited(fE - fc, fc - fW, 2.0 * P.inv_dx);
-    const double syl = limited(fN - fc, fc - fS, 2.0 * P.inv_dy);
-    const double sy0 = wall_row ? 0.0 : syl;
+    const double hx0 = half_limited(fE - fc, fc - fW);
+    const double hyl = half_limited(fN - fc, fc - fS);
+    const double hy0 = wall_row ? 0.0 : hyl;
+    const double ucx = u * two_idx, vcy = vv * two_idy;
+    const double D0 = fma(ucx, hx0, vcy * hy0);
     const double* lp = tb + L.xl_p + 4 * k;
     const double* rp = tb + L.xr_p + 4 * k;
     const double* bp = tb + L.yb_p + 4 * m;
@@ -944,23 +1014,23 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
     const double be = tb[L.yb_e + k], te = tb[L.yt_e + k];
     double dFx, dFy;
     if (su > 0)
-      dFx = x_part<1>(P, X, vb, u, vv, fc, fW, fE, sx0, sy0, ghost_w, ghost_e, wall_row, lp, rp,
-                      le, re, m4l, m5l, m4r, m5r);
+      dFx = x_part<1>(X, vb, u, vv, ucx, vcy, fc, fW, fE, hx0, D0, ghost_w, ghost_e, wall_row,
+                      lp, rp, le, re, m4l, m5l, m4r, m5r);
     else if (su < 0)
-      dFx = x_part<-1>(P, X, vb, u, vv, fc, fW, fE, sx0, sy0, ghost_w, ghost_e, wall_row, lp, rp,
-                       le, re, m4l, m5l, m4r, m5r);
+      dFx = x_part<-1>(X, vb, u, vv, ucx, vcy, fc, fW, fE, hx0, D0, ghost_w, ghost_e, wall_row,
+                       lp, rp, le, re, m4l, m5l, m4r, m5r);
     else
-      dFx = x_part<0>(P, X, vb, u, vv, fc, fW, fE, sx0, sy0, ghost_w, ghost_e, wall_row, lp, rp,
-                      le, re, m4l, m5l, m4r, m5r);
+      dFx = x_part<0>(X, vb, u, vv, ucx, vcy, fc, fW, fE, hx0, D0, ghost_w, ghost_e, wall_row,
+                      lp, rp, le, re, m4l, m5l, m4r, m5r);
     if (sv > 0)
-      dFy = y_part<1>(P, X, vb, u, vv, fc, fS, fN, sx0, sy0, wall_b, wall_t, s_wallrow, n_wallrow,
-                      bp, tp, be, te, m4b, m5b, m4t, m5t);
+      dFy = y_part<1>(X, vb, u, vv, ucx, vcy, fc, fS, fN, hy0, D0, wall_b, wall_t, s_wallrow,
+                      n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
     else if (sv < 0)
-      dFy = y_part<-1>(P, X, vb, u, vv, fc, fS, fN, sx0, sy0, wall_b, wall_t, s_wallrow,
+      dFy = y_part<-1>(X, vb, u, vv, ucx, vcy, fc, fS, fN, hy0, D0, wall_b, wall_t, s_wallrow,
                        n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
     else
-      dFy = y_part<0>(P, X, vb, u, vv, fc, fS, fN, sx0, sy0, wall_b, wall_t, s_wallrow, n_wallrow,
-                      bp, tp, be, te, m4b, m5b, m4t, m5t);
+      dFy = y_part<0>(X, vb, u, vv, ucx, vcy, fc, fS, fN, hy0, D0, wall_b, wall_t, s_wallrow,
+                      n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
     const double g = fma(tb[L.g1_k + k], tb[L.g1_m + m], tb[L.gn_k + k] * tb[L.gn_m + m]);
     const double f1 = fma(Af, fc, fma(AdF, dFx + dFy, g));
     *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(fo) + vb) =
@@ -968,7 +1038,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
   }
   if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) W[4 * (size_t)c + q] = W1[q];
+    for (int q = 0; q < 4; ++q) W[4 * (size_t)cc + q] = W1[q];
   }
 }
 

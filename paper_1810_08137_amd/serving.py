@@ -128,6 +128,7 @@ class Server:
         self.sleep = sleep
         self.batches = 0
         self.max_resident = 0
+        self.host_s = {}
 
     def run(self, requests):
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -135,6 +136,15 @@ class Server:
         used = 0
         t0 = self.clock()
         now = lambda: self.clock() - t0
+        host = {"create": 0.0, "step": 0.0, "wait": 0.0, "finish": 0.0}
+        self.host_s = host
+
+        def timed(part, fn, *a):
+            s0 = self.clock()
+            try:
+                return fn(*a)
+            finally:
+                host[part] += self.clock() - s0
 
         def admit():
             nonlocal used
@@ -151,7 +161,7 @@ class Server:
                     break
                 queue.pop(0)
                 try:
-                    s = self.ex.create(r)
+                    s = timed("create", self.ex.create, r)
                 except Exception as e:  # a request that cannot start fails alone
                     r.status, r.error = "failed", str(e)
                     continue
@@ -169,10 +179,10 @@ class Server:
                 break
             q = min(self.quantum, min(r.steps - d for r, _, d, _ in active))
             members = list(active)
-            self.ex.step([s for _, s, _, _ in members], q)
+            timed("step", self.ex.step, [s for _, s, _, _ in members], q)
             self.batches += 1
             admit()            # requests arriving meanwhile start while the batch runs
-            self.ex.wait()
+            timed("wait", self.ex.wait)
             stepped = {id(e) for e in members}
             still = []
             for entry in active:
@@ -183,7 +193,7 @@ class Server:
                 entry[2] = d = d + q
                 if d >= r.steps:
                     try:
-                        r.result = self.ex.finish(s)
+                        r.result = timed("finish", self.ex.finish, s)
                         r.status = "done"
                     except Exception as e:      # an invalid state fails this request alone
                         r.status, r.error = "failed", str(e)

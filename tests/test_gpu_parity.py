@@ -188,3 +188,10 @@ def test_moving_maxwellian_fixed_point_on_gpu():
         assert np.max(np.abs(f1 - f)) < 1e-14 * np.max(f)
     finally:
         a.close()
+
+
+@pytest.mark.parametrize("nvel", [29, 49])
+def test_paper_mesh_m1(nvel):
+    """The paper's channel on its mesh M1 (40x20, L/W = 2, Kn 0.1, p_in/p_out 1.5) at its
+    29^2 and 49^2 velocity grids (odd counts: u = 0 and v = 0 are nodes)."""
+    PR.run_and_compare(WL.paper_mesh(40, 20, nvel), 20, label=f"paper M1 {nvel}^2")
