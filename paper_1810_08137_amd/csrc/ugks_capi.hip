@@ -188,8 +188,8 @@ Layout layout_of(const Shape& s, int prec) {
       (size_t)s.NVP * 8,                        // U
       (size_t)s.NVP * 8,                        // V
       (size_t)s.NVP * 8,                        // Wq
-      (size_t)s.NVP * 4,                        // kidx
-      (size_t)s.NVP * 4,                        // midx
+      (size_t)s.NVP * 4,                        // km
+      (size_t)(s.K + s.M) * 8,                  // wk, wm
       (size_t)(s.NVP / kWave) * 4,              // chunk_sign
       (size_t)s.K * 8,                          // uk
       (size_t)s.M * 8,                          // vm
@@ -221,8 +221,8 @@ void carve(ugks_handle* h, const Layout& L, const Shape& s) {
   B.U = reinterpret_cast<double*>(base + L.off[9]);
   B.V = reinterpret_cast<double*>(base + L.off[10]);
   B.Wq = reinterpret_cast<double*>(base + L.off[11]);
-  B.kidx = reinterpret_cast<int*>(base + L.off[12]);
-  B.midx = reinterpret_cast<int*>(base + L.off[13]);
+  B.km = reinterpret_cast<int*>(base + L.off[12]);
+  B.wk = reinterpret_cast<double*>(base + L.off[13]);
   B.chunk_sign = reinterpret_cast<int*>(base + L.off[14]);
   B.uk = reinterpret_cast<double*>(base + L.off[15]);
   B.vm = reinterpret_cast<double*>(base + L.off[16]);
@@ -386,7 +386,8 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   // Velocity slots ordered by quadrant of (u, v), then the velocities with u = 0 or v = 0,
   // then padding (weight 0) up to a multiple of 64.
   std::vector<double> U(s.NVP, 0.0), V(s.NVP, 0.0), Wq(s.NVP, 0.0);
-  std::vector<int> kidx(s.NVP, 0), midx(s.NVP, 0);
+  // padding slots point at the zero table rows k = K, m = M of the update kernel
+  std::vector<int> km(s.NVP, s.K | (s.M << 16));
   h->slot_of.assign(s.NV, 0);
   {
     int slot = 0;
@@ -394,8 +395,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
       U[slot] = uk[k];
       V[slot] = vm[m];
       Wq[slot] = wk[k] * wm[m];
-      kidx[slot] = k;
-      midx[slot] = m;
+      km[slot] = k | (m << 16);
       h->slot_of[k * s.M + m] = slot;
       ++slot;
     };
@@ -456,8 +456,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   P.U = gp(B.U);
   P.V = gp(B.V);
   P.Wq = gp(B.Wq);
-  P.kidx = gp(B.kidx);
-  P.midx = gp(B.midx);
+  P.km = gp(B.km);
+  P.wk = gp(B.wk);
+  P.wm = gp(B.wk + s.K);
   P.chunk_sign = gp(B.chunk_sign);
   P.uk = gp(B.uk);
   P.vm = gp(B.vm);
@@ -485,8 +486,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     size_t n;
   } copies[] = {
       {B.U, U.data(), U.size() * 8},        {B.V, V.data(), V.size() * 8},
-      {B.Wq, Wq.data(), Wq.size() * 8},     {B.kidx, kidx.data(), kidx.size() * 4},
-      {B.midx, midx.data(), midx.size() * 4}, {B.uk, uk.data(), uk.size() * 8},
+      {B.Wq, Wq.data(), Wq.size() * 8},     {B.km, km.data(), km.size() * 4},
+      {B.wk, wk.data(), wk.size() * 8},     {B.wk + s.K, wm.data(), wm.size() * 8},
+      {B.uk, uk.data(), uk.size() * 8},
       {B.chunk_sign, chunk_sign.data(), chunk_sign.size() * 4},
       {B.vm, vm.data(), vm.size() * 8},     {B.xi_in, xi.data(), xi.size() * 8},
       {B.W, W0.data(), W0.size() * 8},          {h->plan_dev, plan_host.data(), plan_host.size()},

@@ -22,7 +22,9 @@ inline UGKS_GLOBAL T* gp(T* p) {
 constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kSlots = 64;     // per-cell outgoing moment sums: 4 faces x 16
 constexpr int kRec = 32;       // doubles per interface record
-constexpr int kMaxTable = 1024;  // nu + nv limit: six separable exp tables of nu+nv doubles in LDS
+// nu + nv limit: the update kernel keeps 12 (nu + 1) + 12 (nv + 1) doubles of tables per cell
+// in LDS, which must fit one 64 KB workgroup
+constexpr int kMaxTable = 680;
 
 // Interface record (doubles), written by the interface kernel, read by the cell update.
 // Frame: "normal"/"tangential" velocity of the face; for x-faces (u, v), for y-faces (v, u).
@@ -60,12 +62,13 @@ struct KParams {
   const UGKS_GLOBAL double* U;     // [NVP] u of each velocity slot (0 in pads)
   const UGKS_GLOBAL double* V;     // [NVP]
   const UGKS_GLOBAL double* Wq;    // [NVP] quadrature weight (0 in pads)
-  const UGKS_GLOBAL int* kidx;     // [NVP] k of each velocity slot
-  const UGKS_GLOBAL int* midx;     // [NVP] m of each velocity slot
+  const UGKS_GLOBAL int* km;       // [NVP] k | m << 16 of each velocity slot (K | M << 16 in pads)
   const UGKS_GLOBAL int* chunk_sign;  // [NVP/64] per 64-slot chunk: bit0/1 all u > 0 / < 0,
                                       // bit2/3 the same for v
   const UGKS_GLOBAL double* uk;    // [K]
   const UGKS_GLOBAL double* vm;    // [M]
+  const UGKS_GLOBAL double* wk;    // [K] weights of the u nodes
+  const UGKS_GLOBAL double* wm;    // [M] weights of the v nodes
   const UGKS_GLOBAL double* xi_in;  // [ny] inlet noise
   UGKS_GLOBAL int* flag;           // device flag: set to 1 on an invalid state
 };
@@ -83,8 +86,8 @@ struct Buffers {
   double* U;        // [NVP]
   double* V;
   double* Wq;
-  int* kidx;
-  int* midx;
+  int* km;          // [NVP]
+  double* wk;       // [K], followed by wm [M]
   int* chunk_sign;  // [NVP/64]
   double* uk;       // [K]
   double* vm;       // [M]
@@ -132,6 +135,7 @@ struct PlanTotals {
   int sums, upd, face, ghost;  // workgroups of each launch
   int cpb_upd;
   int lds_per_cell;
+  int lds_upd, lds_sums;       // bytes of dynamic LDS per workgroup
 };
 
 // Bytes of a device plan with n instances, and its host image (offsets into one buffer).

@@ -401,7 +401,8 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
 template <typename S>
 __global__ __launch_bounds__(kWave* kCellsPerBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void sums_kernel(PlanView pv) {
-  __shared__ double red_all[kCellsPerBlock][16 * kRedRow];
+  // LDS: per wavefront the 16 x 65 flush block, then the node tables u_k, v_m, w_k, w_m
+  extern __shared__ double lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int ii = find_inst(pv.off_sums, pv.ninst, b);
@@ -410,11 +411,24 @@ void sums_kernel(PlanView pv) {
   const UGKS_GLOBAL S* f = static_cast<const UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
   const UGKS_GLOBAL S* fg = static_cast<const UGKS_GLOBAL S*>(I->fg);
   UGKS_GLOBAL double* hs = I->hs;
+  double* tu = lds + kCellsPerBlock * 16 * kRedRow;
+  double* tv = tu + (P.K + 1);
+  double* twu = tv + (P.M + 1);
+  double* twv = twu + (P.K + 1);
+  for (int e = threadIdx.x; e < 2 * (P.K + 1) + 2 * (P.M + 1); e += blockDim.x) {
+    double x = 0.0;  // entries K and M (padding slots) stay zero
+    if (e < P.K) x = P.uk[e];
+    else if (e >= P.K + 1 && e < P.K + 1 + P.M) x = P.vm[e - (P.K + 1)];
+    else if (e >= P.K + P.M + 2 && e < 2 * P.K + P.M + 2) x = P.wk[e - (P.K + P.M + 2)];
+    else if (e >= 2 * P.K + P.M + 3 && e < 2 * P.K + 2 * P.M + 3) x = P.wm[e - (2 * P.K + P.M + 3)];
+    tu[e] = x;
+  }
+  __syncthreads();
   // the wavefront index is uniform: keep everything derived from it in scalar registers
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int c = (b - first_block(pv.off_sums, ii)) * kCellsPerBlock + wv;
   if (c >= P.nx * P.ny) return;
-  double* red = red_all[wv];
+  double* red = lds + wv * 16 * kRedRow;
   int i, j;
   band_order(c, P.nx, P.ny, kBand, i, j);
   const bool wall_row = P.bc == UGKS_BC_CHANNEL && (j == 0 || j == P.ny - 1);
@@ -426,8 +440,10 @@ void sums_kernel(PlanView pv) {
   const UGKS_GLOBAL S* fn = f + ((size_t)wrap(j + 1, P.ny) * P.nx + i) * P.NVP;
   double fin = 0.0;
   const int nch = P.NVP / kWave;
-  // the five stencil values of chunk ch, loaded while chunk ch - 1 is summed
+  // the five stencil values and the node index of chunk ch, loaded while chunk ch - 1 is
+  // summed
   double buf[5];
+  int kmb;
   {
     const unsigned o0 = (unsigned)lane * (unsigned)sizeof(S);
     buf[0] = (double)ldb(f0, o0);
@@ -435,6 +451,7 @@ void sums_kernel(PlanView pv) {
     buf[2] = (double)ldb(fe, o0);
     buf[3] = (double)ldb(fs, o0);
     buf[4] = (double)ldb(fn, o0);
+    kmb = ldb(P.km, (unsigned)lane * 4u);
   }
   struct Point {
     double fc, hx, hy, D, u, vv, w, c2h;
@@ -447,19 +464,21 @@ void sums_kernel(PlanView pv) {
     const int v = ch * kWave + lane;
     const double fwv = buf[1], fev = buf[2], fsv = buf[3], fnv = buf[4];
     q.fc = buf[0];
-    const unsigned on = (unsigned)(ch + 1 < nch ? v + kWave : v) * (unsigned)sizeof(S);
+    const int k = kmb & 0xffff, m = kmb >> 16;
+    const unsigned vn = (unsigned)(ch + 1 < nch ? v + kWave : v);
+    const unsigned on = vn * (unsigned)sizeof(S);
     buf[0] = (double)ldb(f0, on);
     buf[1] = (double)ldb(fw, on);
     buf[2] = (double)ldb(fe, on);
     buf[3] = (double)ldb(fs, on);
     buf[4] = (double)ldb(fn, on);
+    kmb = ldb(P.km, vn * 4u);
     q.hx = half_limited(fev - q.fc, q.fc - fwv);
     const double hyl = half_limited(fnv - q.fc, q.fc - fsv);
     q.hy = wall_row ? 0.0 : hyl;
-    const unsigned v8 = (unsigned)v * 8u;
-    q.u = ldb(P.U, v8);
-    q.vv = ldb(P.V, v8);
-    q.w = ldb(P.Wq, v8);
+    q.u = tu[k];
+    q.vv = tv[m];
+    q.w = twu[k] * twv[m];
     q.c2h = 0.5 * fma(q.u, q.u, q.vv * q.vv);
     q.D = fma(q.u * two_idx, q.hx, (q.vv * two_idy) * q.hy);
     return q;
@@ -691,29 +710,23 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
 // where P is the folded cubic of the record, n / t index the normal / tangential velocity node
 // and the normal-slope choice (aL for un > 0, aR for un < 0) is made per node n.  The cell's
 // g^n and g^{n+1} are kept as products of two 1D tables with the Eq. (3) weights folded in.
-struct Tab {
-  int xl_p, xr_p, yb_p, yt_p;          // poly tables, 4 doubles per normal node
-  int xl_e, xr_e, yb_e, yt_e;          // tangential exp tables
-  int gn_k, gn_m, g1_k, g1_m;          // g^n, g^{n+1} factors
-  int total;
-};
+// Everything indexed by the u node k sits in one row of 12 doubles, everything indexed by the
+// v node m in another, so a lane reads all its table entries from two rows:
+//   u row k: left and right face polys (4 + 4), bottom and top face exps, g^n and g^{n+1}
+//            u factors;
+//   v row m: bottom and top face polys (4 + 4), left and right face exps, g^n and g^{n+1}
+//            v factors.
+// Row K and row M stay zero: padding slots point there, so their update is exactly zero.
+constexpr int kRow = 12;
+enum RowEntry { RP_LO = 0, RP_HI = 4, RE_LO = 8, RE_HI = 9, RG_N = 10, RG_1 = 11 };
 
-__device__ __forceinline__ Tab tab_layout(int K, int M) {
-  Tab t;
-  t.xl_p = 0;
-  t.xr_p = 4 * K;
-  t.yb_p = 8 * K;
-  t.yt_p = 8 * K + 4 * M;
-  t.xl_e = 8 * K + 8 * M;
-  t.xr_e = t.xl_e + M;
-  t.yb_e = t.xr_e + M;
-  t.yt_e = t.yb_e + K;
-  t.gn_k = t.yt_e + K;
-  t.gn_m = t.gn_k + K;
-  t.g1_k = t.gn_m + M;
-  t.g1_m = t.g1_k + K;
-  t.total = t.g1_m + M;
-  return t;
+__host__ __device__ __forceinline__ int tab_doubles(int K, int M) {
+  return kRow * (K + 1) + kRow * (M + 1);
+}
+
+// Doubles of the block-shared node tables (even, so the per-cell tables stay 16-byte aligned).
+__host__ __device__ __forceinline__ int node_doubles(int K, int M) {
+  return (K + M + 2 + 1) & ~1;
 }
 
 // Fill the four-entry polynomial table of one face at normal node with velocity un.
@@ -767,21 +780,19 @@ struct UpdateCtx {
 };
 
 // Left-minus-right flux difference for one velocity.  SX = +1 / -1: u has that sign across
-// the wavefront; 0: per lane.  All loads are unconditional (every slab pointer is valid);
+// the wavefront; 0: per lane.  Every stencil value is loaded (every slab pointer is valid);
 // boundaries only switch results.  Slopes are carried as half-cell changes h = sigma dx / 2
 // (or dy / 2); ucx = 2 u / dx and vcy = 2 v / dy turn them into u sigma_x + v sigma_y.
-template <int SX, typename S>
-__device__ __forceinline__ double x_part(const UpdateCtx<S>& X, unsigned vb, double u, double vv,
-                                         double ucx, double vcy, double fc, double fW,
-                                         double fE, double hx0, double D0, bool ghost_w,
+template <int SX>
+__device__ __forceinline__ double x_part(double u, double vv, double ucx, double vcy, double fc,
+                                         double fW, double fE, double fXX, double fXn,
+                                         double fXs, double hx0, double D0, bool ghost_w,
                                          bool ghost_e, bool wall_row, const double* lp,
                                          const double* rp, double le, double re, double m4l,
                                          double m5l, double m4r, double m5r) {
-  // particles with u > 0 enter through the left face from cell i-1 (the upwind cell X)
+  // particles with u > 0 enter through the left face from cell i-1 (the upwind cell X); fXX
+  // is X's far x-neighbour (i -+ 2), fXn and fXs its y-neighbours
   const bool right = SX > 0 ? true : (SX < 0 ? false : (u > 0.0));
-  const double fXX = (double)ldb(right ? X.xww : X.xee, vb);
-  const double fXn = (double)ldb(right ? X.nw : X.ne, vb);
-  const double fXs = (double)ldb(right ? X.sw : X.se, vb);
   const double fX = right ? fW : fE;
   const bool ghostX = right ? ghost_w : ghost_e;
   const double hxl = right ? half_limited(fc - fX, fX - fXX) : half_limited(fXX - fX, fX - fc);
@@ -805,18 +816,16 @@ __device__ __forceinline__ double x_part(const UpdateCtx<S>& X, unsigned vb, dou
 
 // Bottom-minus-top flux difference.  Walls: particles leaving a wall follow rho_w times the
 // wall Maxwellian (its tables hold dx dt rho_w g_w), those reaching it carry the wall-row value.
-template <int SY, typename S>
-__device__ __forceinline__ double y_part(const UpdateCtx<S>& X, unsigned vb, double u, double vv,
-                                         double ucx, double vcy, double fc, double fS,
-                                         double fN, double hy0, double D0, bool wall_b,
+template <int SY>
+__device__ __forceinline__ double y_part(double u, double vv, double ucx, double vcy, double fc,
+                                         double fS, double fN, double fYY, double fYe,
+                                         double fYw, double hy0, double D0, bool wall_b,
                                          bool wall_t, bool s_wallrow, bool n_wallrow,
                                          const double* bp, const double* tp, double be,
                                          double te, double m4b, double m5b, double m4t,
                                          double m5t) {
+  // the upwind cell Y is (i, j -+ 1); fYY is its far y-neighbour, fYe and fYw its x-neighbours
   const bool up = SY > 0 ? true : (SY < 0 ? false : (vv > 0.0));
-  const double fYY = (double)ldb(up ? X.scc : X.ncc, vb);
-  const double fYe = (double)ldb(up ? X.se : X.ne, vb);
-  const double fYw = (double)ldb(up ? X.sw : X.nw, vb);
   const double fY = up ? fS : fN;
   const bool Y_wallrow = up ? s_wallrow : n_wallrow;
   const double hyl = up ? half_limited(fc - fY, fY - fYY) : half_limited(fYY - fY, fY - fc);
@@ -859,8 +868,15 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
   const UGKS_GLOBAL double* recx = I->recx;
   const UGKS_GLOBAL double* recy = I->recy;
   UGKS_GLOBAL double* W = I->W;
-  const Tab L = tab_layout(P.K, P.M);
-  double* tb = lds + (size_t)wv * (size_t)(pv.lds_per_cell / 8);
+  // LDS: the block's node tables u_k (K + 1 entries) and v_m (M + 1), zero in the padding
+  // entries, then the per-cell tables
+  double* tuu = lds;
+  double* tvv = lds + (P.K + 1);
+  double* tb = lds + node_doubles(P.K, P.M) + (size_t)wv * (size_t)(pv.lds_per_cell / 8);
+  double* urow = tb;                        // rows k = 0..K
+  double* vrow = tb + kRow * (P.K + 1);     // rows m = 0..M
+  for (int e = threadIdx.x; e < P.K + P.M + 2; e += blockDim.x)
+    tuu[e] = e < P.K ? P.uk[e] : ((e > P.K && e < P.K + 1 + P.M) ? P.vm[e - P.K - 1] : 0.0);
   const int c = (b - first_block(pv.off_upd, ii)) * cpb + wv;
   const bool active = c < P.nx * P.ny;
   int i, j;
@@ -903,14 +919,14 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
       rs = side ? rr : rl;
       un = P.uk[k];
       U0 = rs[R_UX];
-      out = tb + (side ? L.xr_p : L.xl_p) + 4 * k;
+      out = urow + kRow * k + (side ? RP_HI : RP_LO);
     } else {
       const int e2 = e - 2 * P.K;
       const int side = e2 / P.M, m = e2 - side * P.M;
       rs = side ? rt : rb;
       un = P.vm[m];
       U0 = rs[R_VY];
-      out = tb + (side ? L.yt_p : L.yb_p) + 4 * m;
+      out = vrow + kRow * m + (side ? RP_HI : RP_LO);
     }
     lamf = rs[R_LAM];
     if (rs[R_KIND] == (double)K_WALL) {
@@ -930,14 +946,14 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
   // tangential tables of the faces and the two factors of g^n and g^{n+1}
   for (int e = lane; e < 4 * (P.K + P.M); e += kWave) {
     double lam, vel, c0, coef = 1.0;
-    int dst;
+    double* dst;
     if (e < 2 * P.M) {  // x-faces: tangential v
       const int side = e / P.M, m = e - side * P.M;
       const UGKS_GLOBAL double* rs = side ? rr : rl;
       lam = rs[R_LAM];
       vel = P.vm[m];
       c0 = rs[R_VY];
-      dst = (side ? L.xr_e : L.xl_e) + m;
+      dst = vrow + kRow * m + (side ? RE_HI : RE_LO);
     } else if (e < 2 * P.M + 2 * P.K) {  // y-faces: tangential u
       const int e2 = e - 2 * P.M;
       const int side = e2 / P.K, k = e2 - side * P.K;
@@ -945,7 +961,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
       lam = rs[R_LAM];
       vel = P.uk[k];
       c0 = rs[R_UX];
-      dst = (side ? L.yt_e : L.yb_e) + k;
+      dst = urow + kRow * k + (side ? RE_HI : RE_LO);
     } else {  // g^n, g^{n+1}: u factor carries the Eq. (3) weight
       const int e3 = e - 2 * P.M - 2 * P.K;
       const int which = e3 / (P.K + P.M), r = e3 - which * (P.K + P.M);
@@ -954,16 +970,19 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
         vel = P.uk[r];
         c0 = which ? p1.U : pn.U;
         coef = which ? A1 : An;
-        dst = (which ? L.g1_k : L.gn_k) + r;
+        dst = urow + kRow * r + (which ? RG_1 : RG_N);
       } else {
         vel = P.vm[r - P.K];
         c0 = which ? p1.V : pn.V;
-        dst = (which ? L.g1_m : L.gn_m) + (r - P.K);
+        dst = vrow + kRow * (r - P.K) + (which ? RG_1 : RG_N);
       }
     }
     const double d = vel - c0;
-    tb[dst] = coef * exp(-lam * d * d);
+    *dst = coef * exp(-lam * d * d);
   }
+  // the zero rows of the padding slots
+  for (int e = lane; e < 2 * kRow; e += kWave)
+    (e < kRow ? urow + kRow * P.K : vrow + kRow * P.M)[e % kRow] = 0.0;
   __syncthreads();
   if (!active) return;
   const double m4l = rl[R_M4], m5l = rl[R_M5], m4r = rr[R_M4], m5r = rr[R_M5];
@@ -993,48 +1012,82 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
   const int nch = P.NVP / kWave;
   for (int ch = 0; ch < nch; ++ch) {
     const unsigned v = (unsigned)(ch * kWave + lane);
-    const unsigned vb = v * (unsigned)sizeof(S), v4 = v * 4u, v8 = v * 8u;
+    const unsigned vb = v * (unsigned)sizeof(S);
     const int code = P.chunk_sign[ch];
     const int su = chunk_sign_u(code), sv = chunk_sign_v(code);
-    const int k = ldb(P.kidx, v4), m = ldb(P.midx, v4);
-    const double u = ldb(P.U, v8), vv = ldb(P.V, v8);
+    // all stencil values of the chunk are requested before any is used: the cell, its four
+    // neighbours, and the far values of the upwind neighbours in x and y
+    const int kmv = ldb(P.km, v * 4u);
     const double fc = (double)ldb(X.f0, vb);
     const double fW = (double)ldb(X.xw, vb), fE = (double)ldb(X.xe, vb);
     const double fS = (double)ldb(X.sc, vb), fN = (double)ldb(X.nc, vb);
+    double xxx, xxn, xxs, yyy, yye, yyw;
+    if (su > 0) {
+      xxx = (double)ldb(X.xww, vb);
+      xxn = (double)ldb(X.nw, vb);
+      xxs = (double)ldb(X.sw, vb);
+    } else {
+      xxx = (double)ldb(X.xee, vb);
+      xxn = (double)ldb(X.ne, vb);
+      xxs = (double)ldb(X.se, vb);
+    }
+    if (sv > 0) {
+      yyy = (double)ldb(X.scc, vb);
+      yye = (double)ldb(X.se, vb);
+      yyw = (double)ldb(X.sw, vb);
+    } else {
+      yyy = (double)ldb(X.ncc, vb);
+      yye = (double)ldb(X.ne, vb);
+      yyw = (double)ldb(X.nw, vb);
+    }
+    const int k = kmv & 0xffff, m = kmv >> 16;
+    const double u = tuu[k], vv = tvv[m];
+    if (su == 0 && u > 0.0) {  // mixed chunk: lanes moving +x take the other side
+      xxx = (double)ldb(X.xww, vb);
+      xxn = (double)ldb(X.nw, vb);
+      xxs = (double)ldb(X.sw, vb);
+    }
+    if (sv == 0 && vv > 0.0) {
+      yyy = (double)ldb(X.scc, vb);
+      yye = (double)ldb(X.se, vb);
+      yyw = (double)ldb(X.sw, vb);
+    }
     const double hx0 = half_limited(fE - fc, fc - fW);
     const double hyl = half_limited(fN - fc, fc - fS);
     const double hy0 = wall_row ? 0.0 : hyl;
     const double ucx = u * two_idx, vcy = vv * two_idy;
     const double D0 = fma(ucx, hx0, vcy * hy0);
-    const double* lp = tb + L.xl_p + 4 * k;
-    const double* rp = tb + L.xr_p + 4 * k;
-    const double* bp = tb + L.yb_p + 4 * m;
-    const double* tp = tb + L.yt_p + 4 * m;
-    const double le = tb[L.xl_e + m], re = tb[L.xr_e + m];
-    const double be = tb[L.yb_e + k], te = tb[L.yt_e + k];
+    const double* ur = urow + kRow * k;
+    const double* vr = vrow + kRow * m;
+    const double* lp = ur + RP_LO;
+    const double* rp = ur + RP_HI;
+    const double* bp = vr + RP_LO;
+    const double* tp = vr + RP_HI;
+    const double le = vr[RE_LO], re = vr[RE_HI];
+    const double be = ur[RE_LO], te = ur[RE_HI];
     double dFx, dFy;
     if (su > 0)
-      dFx = x_part<1>(X, vb, u, vv, ucx, vcy, fc, fW, fE, hx0, D0, ghost_w, ghost_e, wall_row,
-                      lp, rp, le, re, m4l, m5l, m4r, m5r);
+      dFx = x_part<1>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, ghost_w, ghost_e,
+                      wall_row, lp, rp, le, re, m4l, m5l, m4r, m5r);
     else if (su < 0)
-      dFx = x_part<-1>(X, vb, u, vv, ucx, vcy, fc, fW, fE, hx0, D0, ghost_w, ghost_e, wall_row,
-                       lp, rp, le, re, m4l, m5l, m4r, m5r);
+      dFx = x_part<-1>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, ghost_w, ghost_e,
+                       wall_row, lp, rp, le, re, m4l, m5l, m4r, m5r);
     else
-      dFx = x_part<0>(X, vb, u, vv, ucx, vcy, fc, fW, fE, hx0, D0, ghost_w, ghost_e, wall_row,
-                      lp, rp, le, re, m4l, m5l, m4r, m5r);
+      dFx = x_part<0>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, ghost_w, ghost_e,
+                      wall_row, lp, rp, le, re, m4l, m5l, m4r, m5r);
     if (sv > 0)
-      dFy = y_part<1>(X, vb, u, vv, ucx, vcy, fc, fS, fN, hy0, D0, wall_b, wall_t, s_wallrow,
-                      n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
+      dFy = y_part<1>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wall_b, wall_t,
+                      s_wallrow, n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
     else if (sv < 0)
-      dFy = y_part<-1>(X, vb, u, vv, ucx, vcy, fc, fS, fN, hy0, D0, wall_b, wall_t, s_wallrow,
-                       n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
+      dFy = y_part<-1>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wall_b, wall_t,
+                       s_wallrow, n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
     else
-      dFy = y_part<0>(X, vb, u, vv, ucx, vcy, fc, fS, fN, hy0, D0, wall_b, wall_t, s_wallrow,
-                      n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
-    const double g = fma(tb[L.g1_k + k], tb[L.g1_m + m], tb[L.gn_k + k] * tb[L.gn_m + m]);
+      dFy = y_part<0>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wall_b, wall_t,
+                      s_wallrow, n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
+    const double g = fma(ur[RG_1], vr[RG_1], ur[RG_N] * vr[RG_N]);
     const double f1 = fma(Af, fc, fma(AdF, dFx + dFy, g));
     *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(fo) + vb) =
-        static_cast<S>(v < (unsigned)P.NV ? f1 : 0.0);
+        static_cast<S>(f1);
   }
   if (lane == 0) {
 #pragma unroll
@@ -1059,16 +1112,22 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   int* off[5];
   for (int a = 0; a < 5; ++a) off[a] = reinterpret_cast<int*>(h + inst_bytes + a * off_bytes);
   PlanTotals t{};
-  // update kernel: cells per workgroup limited by twelve nu + nv tables per cell in LDS
-  int max_cell = 0;
+  // update kernel: cells per workgroup limited by the (nu + 1) + (nv + 1) table rows per cell
+  int max_cell = 0, max_nodes = 0, max_sums = 0;
   for (int q = 0; q < n; ++q) {
-    const int km = insts[q].P.K + insts[q].P.M;
-    max_cell = km * 12 * 8 > max_cell ? km * 12 * 8 : max_cell;
+    const int K = insts[q].P.K, M = insts[q].P.M;
+    const int bytes = tab_doubles(K, M) * 8;
+    max_cell = bytes > max_cell ? bytes : max_cell;
+    max_nodes = node_doubles(K, M) * 8 > max_nodes ? node_doubles(K, M) * 8 : max_nodes;
+    const int sums = (kCellsPerBlock * 16 * kRedRow + 2 * (K + 1) + 2 * (M + 1)) * 8;
+    max_sums = sums > max_sums ? sums : max_sums;
   }
   int cpb = kCellsPerBlock;
-  while (cpb > 1 && (size_t)max_cell * cpb > 64 * 1024) cpb /= 2;
+  while (cpb > 1 && (size_t)max_nodes + (size_t)max_cell * cpb > 64 * 1024) cpb /= 2;
   t.cpb_upd = cpb;
   t.lds_per_cell = max_cell;
+  t.lds_upd = max_nodes + max_cell * cpb;
+  t.lds_sums = max_sums;
   for (int q = 0; q < n; ++q) {
     const KParams& P = insts[q].P;
     const int nc = P.nx * P.ny;
@@ -1121,15 +1180,15 @@ hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int p
       break;
     case 1:
       if (fp32)
-        sums_kernel<float><<<(unsigned)t.sums, kWave * kCellsPerBlock, 0, s>>>(pv);
+        sums_kernel<float><<<(unsigned)t.sums, kWave * kCellsPerBlock, t.lds_sums, s>>>(pv);
       else
-        sums_kernel<double><<<(unsigned)t.sums, kWave * kCellsPerBlock, 0, s>>>(pv);
+        sums_kernel<double><<<(unsigned)t.sums, kWave * kCellsPerBlock, t.lds_sums, s>>>(pv);
       break;
     case 2:
       faces_kernel<<<(unsigned)t.face, 256, 0, s>>>(pv);
       break;
     default: {
-      const size_t lds = (size_t)t.lds_per_cell * t.cpb_upd;
+      const size_t lds = (size_t)t.lds_upd;
       const unsigned threads = kWave * (unsigned)t.cpb_upd;
       if (fp32)
         update_kernel<float><<<(unsigned)t.upd, threads, lds, s>>>(pv);
