@@ -19,6 +19,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "ugks_internal.hpp"
 
@@ -717,17 +718,17 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
 //   v row m: bottom and top face polys (4 + 4), left and right face exps, g^n and g^{n+1}
 //            v factors.
 // Row K and row M stay zero: padding slots point there, so their update is exactly zero.
-constexpr int kRow = 12;
+// Rows are 13 doubles apart (one unused): with an odd stride up to 16 different rows a chunk
+// touches sit on distinct LDS banks for 8-byte reads.
+constexpr int kRow = 13;
 enum RowEntry { RP_LO = 0, RP_HI = 4, RE_LO = 8, RE_HI = 9, RG_N = 10, RG_1 = 11 };
 
 __host__ __device__ __forceinline__ int tab_doubles(int K, int M) {
   return kRow * (K + 1) + kRow * (M + 1);
 }
 
-// Doubles of the block-shared node tables (even, so the per-cell tables stay 16-byte aligned).
-__host__ __device__ __forceinline__ int node_doubles(int K, int M) {
-  return (K + M + 2 + 1) & ~1;
-}
+// Doubles of the block-shared node tables.
+__host__ __device__ __forceinline__ int node_doubles(int K, int M) { return K + M + 2; }
 
 // Fill the four-entry polynomial table of one face at normal node with velocity un.
 __device__ __forceinline__ void face_poly(const UGKS_GLOBAL double* r, double un, double lam,
@@ -805,10 +806,10 @@ __device__ __forceinline__ double x_part(double u, double vv, double ucx, double
   // left face: upwind is X when moving right, the cell itself when moving left
   const double fl = right ? fh_in : fh_own, Dl = right ? DX : D0;
   const double fr = right ? fh_own : fh_in, Dr = right ? D0 : DX;
-  const double2 lab = *reinterpret_cast<const double2*>(lp);
-  const double2 lcd = *reinterpret_cast<const double2*>(lp + 2);
-  const double2 rab = *reinterpret_cast<const double2*>(rp);
-  const double2 rcd = *reinterpret_cast<const double2*>(rp + 2);
+  const double2 lab = make_double2(lp[0], lp[1]);
+  const double2 lcd = make_double2(lp[2], lp[3]);
+  const double2 rab = make_double2(rp[0], rp[1]);
+  const double2 rcd = make_double2(rp[2], rp[3]);
   const double Fl = face_flux(lab, lcd, le, u, vv, fl, Dl, m4l, m5l);
   const double Fr = face_flux(rab, rcd, re, u, vv, fr, Dr, m4r, m5r);
   return Fl - Fr;
@@ -837,10 +838,10 @@ __device__ __forceinline__ double y_part(double u, double vv, double ucx, double
   // bottom face: upwind is Y when moving up, the cell itself when moving down
   const double fb = up ? fh_in : fh_own, Db = up ? DY : D0;
   const double ft = up ? fh_own : fh_in, Dt = up ? D0 : DY;
-  const double2 bab = *reinterpret_cast<const double2*>(bp);
-  const double2 bcd = *reinterpret_cast<const double2*>(bp + 2);
-  const double2 tab2 = *reinterpret_cast<const double2*>(tp);
-  const double2 tcd = *reinterpret_cast<const double2*>(tp + 2);
+  const double2 bab = make_double2(bp[0], bp[1]);
+  const double2 bcd = make_double2(bp[2], bp[3]);
+  const double2 tab2 = make_double2(tp[0], tp[1]);
+  const double2 tcd = make_double2(tp[2], tp[3]);
   const double Fb_face = face_flux(bab, bcd, be, vv, u, fb, Db, m4b, m5b);
   const double Ft_face = face_flux(tab2, tcd, te, vv, u, ft, Dt, m4t, m5t);
   const double Fb_wall = up ? vv * (be * bab.x) : vv * (m4b * fc);
@@ -852,7 +853,8 @@ __device__ __forceinline__ double y_part(double u, double vv, double ucx, double
 
 // Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  One wavefront per cell.
 template <typename S>
-__global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView pv) {
+__global__ __launch_bounds__(kWave* kCellsPerBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void update_kernel(PlanView pv) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -869,7 +871,7 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
   const UGKS_GLOBAL double* recy = I->recy;
   UGKS_GLOBAL double* W = I->W;
   // LDS: the block's node tables u_k (K + 1 entries) and v_m (M + 1), zero in the padding
-  // entries, then the per-cell tables
+  // entries, then the per-cell tables (8-byte aligned)
   double* tuu = lds;
   double* tvv = lds + (P.K + 1);
   double* tb = lds + node_doubles(P.K, P.M) + (size_t)wv * (size_t)(pv.lds_per_cell / 8);
@@ -1010,85 +1012,101 @@ __global__ __launch_bounds__(kWave* kCellsPerBlock) void update_kernel(PlanView 
   UGKS_GLOBAL S* fo = fout + (size_t)cc * P.NVP;
   const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
   const int nch = P.NVP / kWave;
-  for (int ch = 0; ch < nch; ++ch) {
-    const unsigned v = (unsigned)(ch * kWave + lane);
-    const unsigned vb = v * (unsigned)sizeof(S);
-    const int code = P.chunk_sign[ch];
-    const int su = chunk_sign_u(code), sv = chunk_sign_v(code);
-    // all stencil values of the chunk are requested before any is used: the cell, its four
-    // neighbours, and the far values of the upwind neighbours in x and y
-    const int kmv = ldb(P.km, v * 4u);
-    const double fc = (double)ldb(X.f0, vb);
-    const double fW = (double)ldb(X.xw, vb), fE = (double)ldb(X.xe, vb);
-    const double fS = (double)ldb(X.sc, vb), fN = (double)ldb(X.nc, vb);
-    double xxx, xxn, xxs, yyy, yye, yyw;
-    if (su > 0) {
-      xxx = (double)ldb(X.xww, vb);
-      xxn = (double)ldb(X.nw, vb);
-      xxs = (double)ldb(X.sw, vb);
-    } else {
-      xxx = (double)ldb(X.xee, vb);
-      xxn = (double)ldb(X.ne, vb);
-      xxs = (double)ldb(X.se, vb);
+  // The chunk loop, compiled twice: for cells next to a ghost column or a wall (EDGE) and for
+  // the interior, where every boundary switch is constant false.
+  auto chunks = [&](auto edge_c) {
+    constexpr bool EDGE = decltype(edge_c)::value;
+    const bool gw = EDGE && ghost_w, ge = EDGE && ghost_e, wr = EDGE && wall_row;
+    const bool wb = EDGE && wall_b, wt = EDGE && wall_t;
+    const bool swr = EDGE && s_wallrow, nwr = EDGE && n_wallrow;
+    // one chunk; MIXED: its lanes have both signs of u or of v, so the upwind neighbours'
+    // far slabs are chosen per lane (otherwise per chunk, in scalar registers)
+    auto chunk = [&](auto mixed_c, int ch, int su, int sv) {
+      constexpr bool MIXED = decltype(mixed_c)::value;
+      const unsigned v = (unsigned)(ch * kWave + lane);
+      const unsigned vb = v * (unsigned)sizeof(S);
+      // all stencil values of the chunk are requested before any is used
+      const int kmv = ldb(P.km, v * 4u);
+      const double fc = (double)ldb(X.f0, vb);
+      const double fW = (double)ldb(X.xw, vb), fE = (double)ldb(X.xe, vb);
+      const double fS = (double)ldb(X.sc, vb), fN = (double)ldb(X.nc, vb);
+      double xxx, xxn, xxs, yyy, yye, yyw;
+      if (!MIXED) {
+        const UGKS_GLOBAL S* pxx = su > 0 ? X.xww : X.xee;
+        const UGKS_GLOBAL S* pxn = su > 0 ? X.nw : X.ne;
+        const UGKS_GLOBAL S* pxs = su > 0 ? X.sw : X.se;
+        const UGKS_GLOBAL S* pyy = sv > 0 ? X.scc : X.ncc;
+        const UGKS_GLOBAL S* pye = sv > 0 ? X.se : X.ne;
+        const UGKS_GLOBAL S* pyw = sv > 0 ? X.sw : X.nw;
+        xxx = (double)ldb(pxx, vb);
+        xxn = (double)ldb(pxn, vb);
+        xxs = (double)ldb(pxs, vb);
+        yyy = (double)ldb(pyy, vb);
+        yye = (double)ldb(pye, vb);
+        yyw = (double)ldb(pyw, vb);
+      }
+      const int k = kmv & 0xffff, m = kmv >> 16;
+      const double u = tuu[k], vv = tvv[m];
+      if (MIXED) {
+        const bool r = su > 0 || (su == 0 && u > 0.0);
+        const bool t = sv > 0 || (sv == 0 && vv > 0.0);
+        xxx = (double)ldb(r ? X.xww : X.xee, vb);
+        xxn = (double)ldb(r ? X.nw : X.ne, vb);
+        xxs = (double)ldb(r ? X.sw : X.se, vb);
+        yyy = (double)ldb(t ? X.scc : X.ncc, vb);
+        yye = (double)ldb(t ? X.se : X.ne, vb);
+        yyw = (double)ldb(t ? X.sw : X.nw, vb);
+      }
+      const double hx0 = half_limited(fE - fc, fc - fW);
+      const double hyl = half_limited(fN - fc, fc - fS);
+      const double hy0 = wr ? 0.0 : hyl;
+      const double ucx = u * two_idx, vcy = vv * two_idy;
+      const double D0 = fma(ucx, hx0, vcy * hy0);
+      const double* ur = urow + kRow * k;
+      const double* vr = vrow + kRow * m;
+      const double* lp = ur + RP_LO;
+      const double* rp = ur + RP_HI;
+      const double* bp = vr + RP_LO;
+      const double* tp = vr + RP_HI;
+      const double le = vr[RE_LO], re = vr[RE_HI];
+      const double be = ur[RE_LO], te = ur[RE_HI];
+      double dFx, dFy;
+      if (su > 0)
+        dFx = x_part<1>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, gw, ge, wr, lp, rp,
+                        le, re, m4l, m5l, m4r, m5r);
+      else if (su < 0)
+        dFx = x_part<-1>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, gw, ge, wr, lp, rp,
+                         le, re, m4l, m5l, m4r, m5r);
+      else
+        dFx = x_part<0>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, gw, ge, wr, lp, rp,
+                        le, re, m4l, m5l, m4r, m5r);
+      if (sv > 0)
+        dFy = y_part<1>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wb, wt, swr, nwr,
+                        bp, tp, be, te, m4b, m5b, m4t, m5t);
+      else if (sv < 0)
+        dFy = y_part<-1>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wb, wt, swr, nwr,
+                         bp, tp, be, te, m4b, m5b, m4t, m5t);
+      else
+        dFy = y_part<0>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wb, wt, swr, nwr,
+                        bp, tp, be, te, m4b, m5b, m4t, m5t);
+      const double g = fma(ur[RG_1], vr[RG_1], ur[RG_N] * vr[RG_N]);
+      const double f1 = fma(Af, fc, fma(AdF, dFx + dFy, g));
+      *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(fo) + vb) =
+          static_cast<S>(f1);
+    };
+    for (int ch = 0; ch < nch; ++ch) {
+      const int code = P.chunk_sign[ch];
+      const int su = chunk_sign_u(code), sv = chunk_sign_v(code);
+      if (su != 0 && sv != 0)
+        chunk(std::false_type{}, ch, su, sv);
+      else
+        chunk(std::true_type{}, ch, su, sv);
     }
-    if (sv > 0) {
-      yyy = (double)ldb(X.scc, vb);
-      yye = (double)ldb(X.se, vb);
-      yyw = (double)ldb(X.sw, vb);
-    } else {
-      yyy = (double)ldb(X.ncc, vb);
-      yye = (double)ldb(X.ne, vb);
-      yyw = (double)ldb(X.nw, vb);
-    }
-    const int k = kmv & 0xffff, m = kmv >> 16;
-    const double u = tuu[k], vv = tvv[m];
-    if (su == 0 && u > 0.0) {  // mixed chunk: lanes moving +x take the other side
-      xxx = (double)ldb(X.xww, vb);
-      xxn = (double)ldb(X.nw, vb);
-      xxs = (double)ldb(X.sw, vb);
-    }
-    if (sv == 0 && vv > 0.0) {
-      yyy = (double)ldb(X.scc, vb);
-      yye = (double)ldb(X.se, vb);
-      yyw = (double)ldb(X.sw, vb);
-    }
-    const double hx0 = half_limited(fE - fc, fc - fW);
-    const double hyl = half_limited(fN - fc, fc - fS);
-    const double hy0 = wall_row ? 0.0 : hyl;
-    const double ucx = u * two_idx, vcy = vv * two_idy;
-    const double D0 = fma(ucx, hx0, vcy * hy0);
-    const double* ur = urow + kRow * k;
-    const double* vr = vrow + kRow * m;
-    const double* lp = ur + RP_LO;
-    const double* rp = ur + RP_HI;
-    const double* bp = vr + RP_LO;
-    const double* tp = vr + RP_HI;
-    const double le = vr[RE_LO], re = vr[RE_HI];
-    const double be = ur[RE_LO], te = ur[RE_HI];
-    double dFx, dFy;
-    if (su > 0)
-      dFx = x_part<1>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, ghost_w, ghost_e,
-                      wall_row, lp, rp, le, re, m4l, m5l, m4r, m5r);
-    else if (su < 0)
-      dFx = x_part<-1>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, ghost_w, ghost_e,
-                       wall_row, lp, rp, le, re, m4l, m5l, m4r, m5r);
-    else
-      dFx = x_part<0>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, ghost_w, ghost_e,
-                      wall_row, lp, rp, le, re, m4l, m5l, m4r, m5r);
-    if (sv > 0)
-      dFy = y_part<1>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wall_b, wall_t,
-                      s_wallrow, n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
-    else if (sv < 0)
-      dFy = y_part<-1>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wall_b, wall_t,
-                       s_wallrow, n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
-    else
-      dFy = y_part<0>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wall_b, wall_t,
-                      s_wallrow, n_wallrow, bp, tp, be, te, m4b, m5b, m4t, m5t);
-    const double g = fma(ur[RG_1], vr[RG_1], ur[RG_N] * vr[RG_N]);
-    const double f1 = fma(Af, fc, fma(AdF, dFx + dFy, g));
-    *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(fo) + vb) =
-        static_cast<S>(f1);
-  }
+  };
+  if (ghost_w || ghost_e || wall_row || s_wallrow || n_wallrow)
+    chunks(std::true_type{});
+  else
+    chunks(std::false_type{});
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) W[4 * (size_t)cc + q] = W1[q];
