@@ -55,7 +55,7 @@ typedef struct {
 
 /* Discrete velocity grid (Sec. 2: K x M points (u_k, v_m)): nu uniform points on
    [-umax, umax] and nv on [-vmax, vmax], both ends included, trapezoid weights, built
-   exactly mirror-symmetric.  nu, nv >= 2 and nu + nv <= 680 (the per-cell velocity tables
+   exactly mirror-symmetric.  nu, nv >= 2 and nu + nv <= 582 (the per-cell velocity tables
    of the update kernel live in 64 KB of LDS); otherwise UGKS_E_INVAL. */
 typedef struct {
   int nu, nv;

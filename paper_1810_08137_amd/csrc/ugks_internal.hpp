@@ -22,9 +22,9 @@ inline UGKS_GLOBAL T* gp(T* p) {
 constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kSlots = 64;     // per-cell outgoing moment sums: 4 faces x 16
 constexpr int kRec = 32;       // doubles per interface record
-// nu + nv limit: the update kernel keeps 12 (nu + 1) + 12 (nv + 1) doubles of tables per cell
-// in LDS, which must fit one 64 KB workgroup
-constexpr int kMaxTable = 680;
+// nu + nv limit: the update kernel keeps 13 (nu + 1) + 13 (nv + 1) doubles of tables per cell
+// and nu + nv + 2 node values in LDS, which must fit one 64 KB workgroup
+constexpr int kMaxTable = 582;
 
 // Interface record (doubles), written by the interface kernel, read by the cell update.
 // Frame: "normal"/"tangential" velocity of the face; for x-faces (u, v), for y-faces (v, u).

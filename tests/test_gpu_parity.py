@@ -195,3 +195,11 @@ def test_paper_mesh_m1(nvel):
     """The paper's channel on its mesh M1 (40x20, L/W = 2, Kn 0.1, p_in/p_out 1.5) at its
     29^2 and 49^2 velocity grids (odd counts: u = 0 and v = 0 are nodes)."""
     PR.run_and_compare(WL.paper_mesh(40, 20, nvel), 20, label=f"paper M1 {nvel}^2")
+
+
+def test_largest_velocity_grid():
+    """nu + nv at the documented limit (582): the update kernel's per-cell tables then take
+    almost all of a workgroup's 64 KB of LDS (one cell per workgroup)."""
+    case = _case(nx=3, ny=2, lx=1.5, ly=1.0, nu=291, nv=291, umax=12.0, vmax=12.0, kn=0.1,
+                 bc=1, noise=0.02, seed=17)
+    PR.run_and_compare(case, 3, label="291x291 velocities")
