@@ -26,9 +26,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "c4cc0d0a3a968128664d8e9577e2f2b88f34929eae841115b3c71f3461f962dc",
-    "fp64": 2.6465e9,
-    "fp32_store": 1.3459e9,
+    "source_sha256": "f4744c197236968d8f9e4de44cd804fdd9c07a9b81cf0b1d8088c08045f0f0db",
+    "fp64": 1.1974e9,
+    "fp32_store": 0.6116e9,
 }
 
 
