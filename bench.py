@@ -29,7 +29,12 @@ MEASURED_TRAFFIC = {
     "source_sha256": "f4744c197236968d8f9e4de44cd804fdd9c07a9b81cf0b1d8088c08045f0f0db",
     "fp64": 1.1974e9,
     "fp32_store": 0.6116e9,
+    # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
+    "valu_fp64": 1.872e8,
 }
+# VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
+# 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def parse():
@@ -80,6 +85,17 @@ def measured_traffic(form):
     if MEASURED_TRAFFIC["source_sha256"] != kernel_source_hash():
         return None
     return MEASURED_TRAFFIC[form]
+
+
+def valu_issue(avg_ms):
+    """VALU instructions of the update kernel (counter value recorded for this kernel source)
+    per second of its measured launch time, against the chip's issue ceiling."""
+    n = measured_traffic("valu_fp64")
+    if n is None:
+        return None
+    rate = n / (avg_ms * 1e-3)
+    return {"instr_per_launch": n, "issue_per_s": rate, "peak_per_s": VALU_ISSUE_PEAK,
+            "frac": rate / VALU_ISSUE_PEAK}
 
 
 def stream_copy(nbytes=1 << 30, reps=20):
@@ -286,6 +302,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("fp64"),
                      "algorithmic_bytes_per_launch": algo_bytes},
+        "valu_issue": valu_issue(kernels["update"]["avg_ms"]),
         "stream_copy": copy,
         "step_hbm_frac": algo_bytes / (fp64["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels": kernels,
