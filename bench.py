@@ -26,7 +26,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "f4744c197236968d8f9e4de44cd804fdd9c07a9b81cf0b1d8088c08045f0f0db",
+    "source_sha256": "9b30b027fdc32ec117992fbdf70877ed80acecc676cd01294219f1b76b5312ac",
     "fp64": 1.1974e9,
     "fp32_store": 0.6116e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source

@@ -4,7 +4,7 @@
 //   ghost   pressure inlet/outlet ghost columns of a channel (Sec. 3.A)
 //   sums    per cell and velocity: limited slopes of f, the upwind reconstruction at each of
 //           the cell's four faces and their velocity moments (S1 and the sums of S7); one
-//           wavefront per cell, velocities across lanes, a 64-wide reduce-scatter at the end
+//           wavefront per cell, velocities across lanes, running sums reduced through LDS
 //   faces   per interface: add the two sides' sums, then the scalar part of the flux
 //           (S2-S5: Maxwellian moments, time weights, micro slopes, equilibrium flux) into a
 //           record of folded coefficients
@@ -14,7 +14,8 @@
 // f is laid out [cell][velocity slot] with the slot index contiguous and padded to a multiple
 // of 64, so every wavefront load is coalesced.  Slots are ordered by velocity quadrant, so
 // most 64-slot chunks have one sign of u and one of v: their upwind choices and moment slots
-// are then uniform across the wavefront.
+// are then uniform across the wavefront.  The cell kernels visit cells in band order (columns
+// of 16-row bands) so that stencil neighbours are read from L2.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -193,20 +194,6 @@ __device__ __forceinline__ const UGKS_GLOBAL S* xslab(const KParams& P, const UG
 }
 
 // ------------------------------------------------------------------ wave reductions
-// Reduce-scatter of 64 per-lane partial sums: afterwards lane l holds the wave total of
-// slot l.  Recursive halving: 32 + 16 + ... + 1 = 63 exchanges, fixed order.
-template <int H>
-__device__ __forceinline__ void reduce_scatter(double* a, int lane) {
-  const bool upper = (lane & H) != 0;
-#pragma unroll
-  for (int q = 0; q < H; ++q) {
-    const double send = upper ? a[q] : a[q + H];
-    const double keep = upper ? a[q + H] : a[q];
-    a[q] = keep + __shfl_xor(send, H, kWave);
-  }
-  if constexpr (H > 1) reduce_scatter<H / 2>(a, lane);
-}
-
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int h = 32; h >= 1; h >>= 1) x += __shfl_xor(x, h, kWave);
