@@ -55,8 +55,7 @@ typedef struct {
 
 /* Discrete velocity grid (Sec. 2: K x M points (u_k, v_m)): nu uniform points on
    [-umax, umax] and nv on [-vmax, vmax], both ends included, trapezoid weights, built
-   exactly mirror-symmetric.  nu, nv >= 2 and nu + nv <= 582 (the per-cell velocity tables
-   of the update kernel live in 64 KB of LDS); otherwise UGKS_E_INVAL. */
+   exactly mirror-symmetric.  2 <= nu, nv <= 1024; otherwise UGKS_E_INVAL. */
 typedef struct {
   int nu, nv;
   double umax, vmax;
@@ -108,7 +107,8 @@ typedef struct {
 
 typedef struct {
   int nx, ny, nu, nv;
-  int nv_stride;   /* velocity stride of f in device memory (nu*nv rounded up to 64) */
+  int plane_stride; /* values between the velocity planes of f in device memory: f is
+                       stored per velocity as (ny+4) x (nx+4) padded planes */
   int precision;
   double dx, dy, dt;
   double tau_ref;  /* collision time at rho = T = 1; +inf in the collisionless limit */

@@ -50,7 +50,6 @@ struct ugks_handle {
   PlanTotals pt{};
   int64_t steps = 0;
   double tau_ref = 0.0;
-  std::vector<int> slot_of;  // device slot of canonical velocity k*nv + m
   std::string err;
   std::atomic<int> busy{0};
   // kernel timing
@@ -82,6 +81,12 @@ int fail(ugks_handle* h, int code, const char* fmt, const char* detail = "") {
   else
     g_create_error = buf;
   return code;
+}
+
+// Position of cell c = j nx + i inside a velocity plane.
+size_t plane_index(const KParams& P, size_t c) {
+  const size_t j = c / (size_t)P.nx, i = c - j * (size_t)P.nx;
+  return (j + kHalo) * (size_t)P.Lx + i + kHalo;
 }
 
 int hip_fail(ugks_handle* h, hipError_t e, const char* what) {
@@ -129,7 +134,9 @@ double noise_unit(uint64_t s, uint64_t k) {
 }
 
 struct Shape {
-  int nx, ny, K, M, NV, NVP;
+  int nx, ny, K, M, NV;
+  int Lx, Ly;
+  size_t PS;  // values per velocity plane
   size_t nc;
 };
 
@@ -150,15 +157,16 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
     why = "nu and nv must be >= 2";
     return false;
   }
-  if (vg->nu + vg->nv > kMaxTable) {
-    why = "nu + nv exceeds the table limit of the update kernel";
+  if (vg->nu > kMaxNodes || vg->nv > kMaxNodes) {
+    why = "nu and nv must be <= 1024";
     return false;
   }
   if (!(vg->umax > 0) || !(vg->vmax > 0) || !std::isfinite(vg->umax) || !std::isfinite(vg->vmax)) {
     why = "umax and vmax must be positive and finite";
     return false;
   }
-  if ((double)mesh->nx * (double)mesh->ny > 2.0e9) {
+  // a plane (cells and halo) is indexed with 32-bit offsets
+  if (((double)mesh->nx + 2 * kHalo) * ((double)mesh->ny + 2 * kHalo) > 2.0e9) {
     why = "too many cells";
     return false;
   }
@@ -167,7 +175,9 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
   s.K = vg->nu;
   s.M = vg->nv;
   s.NV = vg->nu * vg->nv;
-  s.NVP = (int)round_up((size_t)s.NV, (size_t)kWave);
+  s.Lx = s.nx + 2 * kHalo;
+  s.Ly = s.ny + 2 * kHalo;
+  s.PS = round_up((size_t)s.Lx * (size_t)s.Ly, (size_t)kWave);
   s.nc = (size_t)s.nx * s.ny;
   return true;
 }
@@ -175,22 +185,16 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
 // Offsets of every buffer inside the workspace.
 Layout layout_of(const Shape& s, int prec) {
   const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
-  const size_t sizes[19] = {
-      s.nc * s.NVP * ss,                        // f0
-      s.nc * s.NVP * ss,                        // f1
+  const size_t sizes[13] = {
+      (size_t)s.NV * s.PS * ss,                 // f0: NV planes
+      (size_t)s.NV * s.PS * ss,                 // f1
       s.nc * 4 * 8,                             // W
       2 * (size_t)s.ny * 4 * 8,                 // Wg
-      2 * (size_t)s.ny * s.NVP * ss,            // fg
       s.nc * kSlots * 8,                        // hs
       2 * (size_t)s.ny * 16 * 8,                // hsg
       (size_t)s.ny * (s.nx + 1) * kRec * 8,     // recx
       (size_t)(s.ny + 1) * s.nx * kRec * 8,     // recy
-      (size_t)s.NVP * 8,                        // U
-      (size_t)s.NVP * 8,                        // V
-      (size_t)s.NVP * 8,                        // Wq
-      (size_t)s.NVP * 4,                        // km
       (size_t)(s.K + s.M) * 8,                  // wk, wm
-      (size_t)(s.NVP / kWave) * 4,              // chunk_sign
       (size_t)s.K * 8,                          // uk
       (size_t)s.M * 8,                          // vm
       (size_t)s.ny * 8 + 64,                    // xi_in + flag
@@ -198,7 +202,7 @@ Layout layout_of(const Shape& s, int prec) {
   };
   Layout L{};
   size_t off = 0;
-  for (int b = 0; b < 19; ++b) {
+  for (int b = 0; b < 13; ++b) {
     L.off[b] = off;
     off += round_up(sizes[b], kAlign);
   }
@@ -213,22 +217,16 @@ void carve(ugks_handle* h, const Layout& L, const Shape& s) {
   B.f[1] = base + L.off[1];
   B.W = reinterpret_cast<double*>(base + L.off[2]);
   B.Wg = reinterpret_cast<double*>(base + L.off[3]);
-  B.fg = base + L.off[4];
-  B.hs = reinterpret_cast<double*>(base + L.off[5]);
-  B.hsg = reinterpret_cast<double*>(base + L.off[6]);
-  B.recx = reinterpret_cast<double*>(base + L.off[7]);
-  B.recy = reinterpret_cast<double*>(base + L.off[8]);
-  B.U = reinterpret_cast<double*>(base + L.off[9]);
-  B.V = reinterpret_cast<double*>(base + L.off[10]);
-  B.Wq = reinterpret_cast<double*>(base + L.off[11]);
-  B.km = reinterpret_cast<int*>(base + L.off[12]);
-  B.wk = reinterpret_cast<double*>(base + L.off[13]);
-  B.chunk_sign = reinterpret_cast<int*>(base + L.off[14]);
-  B.uk = reinterpret_cast<double*>(base + L.off[15]);
-  B.vm = reinterpret_cast<double*>(base + L.off[16]);
-  B.xi_in = reinterpret_cast<double*>(base + L.off[17]);
-  B.flag = reinterpret_cast<int*>(base + L.off[17] + round_up((size_t)s.ny * 8, 64));
-  h->plan_dev = base + L.off[18];
+  B.hs = reinterpret_cast<double*>(base + L.off[4]);
+  B.hsg = reinterpret_cast<double*>(base + L.off[5]);
+  B.recx = reinterpret_cast<double*>(base + L.off[6]);
+  B.recy = reinterpret_cast<double*>(base + L.off[7]);
+  B.wk = reinterpret_cast<double*>(base + L.off[8]);
+  B.uk = reinterpret_cast<double*>(base + L.off[9]);
+  B.vm = reinterpret_cast<double*>(base + L.off[10]);
+  B.xi_in = reinterpret_cast<double*>(base + L.off[11]);
+  B.flag = reinterpret_cast<int*>(base + L.off[11] + round_up((size_t)s.ny * 8, 64));
+  h->plan_dev = base + L.off[12];
 }
 
 hipEvent_t pool_get(ugks_handle* h) {
@@ -357,7 +355,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   P.K = s.K;
   P.M = s.M;
   P.NV = s.NV;
-  P.NVP = s.NVP;
+  P.Lx = s.Lx;
+  P.Ly = s.Ly;
+  P.PS = (long long)s.PS;
   P.bc = bc->kind;
   P.collisionless = std::isinf(kn) ? 1 : 0;
   P.inlet_fixed_u = bc->inlet_fixed_u ? 1 : 0;
@@ -383,46 +383,8 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   std::vector<double> uk, wk, vm, wm;
   velocity_nodes(s.K, vgrid->umax, uk, wk);
   velocity_nodes(s.M, vgrid->vmax, vm, wm);
-  // Velocity slots ordered by quadrant of (u, v), then the velocities with u = 0 or v = 0,
-  // then padding (weight 0) up to a multiple of 64.
-  std::vector<double> U(s.NVP, 0.0), V(s.NVP, 0.0), Wq(s.NVP, 0.0);
-  // padding slots point at the zero table rows k = K, m = M of the update kernel
-  std::vector<int> km(s.NVP, s.K | (s.M << 16));
-  h->slot_of.assign(s.NV, 0);
-  {
-    int slot = 0;
-    auto place = [&](int k, int m) {
-      U[slot] = uk[k];
-      V[slot] = vm[m];
-      Wq[slot] = wk[k] * wm[m];
-      km[slot] = k | (m << 16);
-      h->slot_of[k * s.M + m] = slot;
-      ++slot;
-    };
-    const int su[4] = {1, 1, -1, -1}, sv[4] = {1, -1, 1, -1};
-    for (int q = 0; q < 4; ++q)
-      for (int k = 0; k < s.K; ++k)
-        for (int m = 0; m < s.M; ++m)
-          if ((uk[k] > 0 ? 1 : (uk[k] < 0 ? -1 : 0)) == su[q] &&
-              (vm[m] > 0 ? 1 : (vm[m] < 0 ? -1 : 0)) == sv[q])
-            place(k, m);
-    for (int k = 0; k < s.K; ++k)
-      for (int m = 0; m < s.M; ++m)
-        if (uk[k] == 0.0 || vm[m] == 0.0) place(k, m);
-  }
-  std::vector<int> chunk_sign(s.NVP / kWave, 0);
-  for (int ch = 0; ch < s.NVP / kWave; ++ch) {
-    bool upos = true, uneg = true, vpos = true, vneg = true;
-    for (int l = 0; l < kWave; ++l) {
-      const int v = ch * kWave + l;
-      if (v >= s.NV) continue;  // padding carries weight 0 and may take either side
-      upos = upos && U[v] > 0;
-      uneg = uneg && U[v] < 0;
-      vpos = vpos && V[v] > 0;
-      vneg = vneg && V[v] < 0;
-    }
-    chunk_sign[ch] = (upos ? 1 : 0) | (uneg ? 2 : 0) | (vpos ? 4 : 0) | (vneg ? 8 : 0);
-  }
+  P.du = 2.0 * vgrid->umax / (double)(s.K - 1);
+  P.dv = 2.0 * vgrid->vmax / (double)(s.M - 1);
   // diffuse-wall constants: moments of the unit-density wall Maxwellian over the velocities
   // that leave each wall, in the wall's local frame (v, u)
   P.wall_den_bot = P.wall_den_top = 0.0;
@@ -453,13 +415,8 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     }
   }
   Buffers& B = h->B;
-  P.U = gp(B.U);
-  P.V = gp(B.V);
-  P.Wq = gp(B.Wq);
-  P.km = gp(B.km);
   P.wk = gp(B.wk);
   P.wm = gp(B.wk + s.K);
-  P.chunk_sign = gp(B.chunk_sign);
   P.uk = gp(B.uk);
   P.vm = gp(B.vm);
   P.xi_in = gp(B.xi_in);
@@ -470,7 +427,6 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   I.f[1] = gp(B.f[1]);
   I.W = gp(B.W);
   I.Wg = gp(B.Wg);
-  I.fg = gp(B.fg);
   I.hs = gp(B.hs);
   I.hsg = gp(B.hsg);
   I.recx = gp(B.recx);
@@ -485,12 +441,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     const void* src;
     size_t n;
   } copies[] = {
-      {B.U, U.data(), U.size() * 8},        {B.V, V.data(), V.size() * 8},
-      {B.Wq, Wq.data(), Wq.size() * 8},     {B.km, km.data(), km.size() * 4},
       {B.wk, wk.data(), wk.size() * 8},     {B.wk + s.K, wm.data(), wm.size() * 8},
-      {B.uk, uk.data(), uk.size() * 8},
-      {B.chunk_sign, chunk_sign.data(), chunk_sign.size() * 4},
-      {B.vm, vm.data(), vm.size() * 8},     {B.xi_in, xi.data(), xi.size() * 8},
+      {B.uk, uk.data(), uk.size() * 8},     {B.vm, vm.data(), vm.size() * 8},
+      {B.xi_in, xi.data(), xi.size() * 8},
       {B.W, W0.data(), W0.size() * 8},          {h->plan_dev, plan_host.data(), plan_host.size()},
   };
   int rc = UGKS_OK;
@@ -506,9 +459,12 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     if (e != hipSuccess) rc = hip_fail(nullptr, e, "hipMemsetAsync of the state flag");
   }
   if (rc == UGKS_OK) {
-    // the ghost columns of a periodic run are never read; keep them defined anyway
-    e = hipMemsetAsync(B.fg, 0, 2 * (size_t)s.ny * s.NVP * h->ssize, h->stream);
-    if (e == hipSuccess) e = launch_init(h->pv, I.fp32, (int)s.nc, h->stream);
+    // the halo rows and columns start at zero; a channel never writes the halo outside its
+    // ghost columns, whose values the kernels then read as zero
+    e = hipMemsetAsync(B.f[0], 0, (size_t)s.NV * s.PS * h->ssize, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(B.f[1], 0, (size_t)s.NV * s.PS * h->ssize, h->stream);
+    if (e == hipSuccess)
+      e = launch_init(h->pv, I.fp32, (long long)s.nc * (long long)s.NV, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = hip_fail(nullptr, e, "initial state");
   }
@@ -587,7 +543,7 @@ int ugks_get_info(const ugks_handle* h, ugks_info* out) {
   out->ny = h->P.ny;
   out->nu = h->P.K;
   out->nv = h->P.M;
-  out->nv_stride = h->P.NVP;
+  out->plane_stride = h->P.PS;
   out->precision = h->prec;
   out->dx = h->P.dx;
   out->dy = h->P.dy;
@@ -602,11 +558,11 @@ int ugks_get_state(ugks_handle* h, double* f, double* W) {
   if (!h) return UGKS_E_INVAL;
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
-  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = h->P.NV, NVP = h->P.NVP;
+  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = h->P.NV, PS = (size_t)h->P.PS;
   hipError_t e = hipSuccess;
   std::vector<char> raw;
   if (f) {
-    raw.resize(nc * NVP * h->ssize);
+    raw.resize(NV * PS * h->ssize);
     e = hipMemcpyAsync(raw.data(), h->B.f[h->steps & 1], raw.size(), hipMemcpyDeviceToHost,
                        h->stream);
   }
@@ -618,13 +574,15 @@ int ugks_get_state(ugks_handle* h, double* f, double* W) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "reading the state");
   if (f) {
-    for (size_t c = 0; c < nc; ++c)
+    for (size_t c = 0; c < nc; ++c) {
+      const size_t at = plane_index(h->P, c);
       for (size_t v = 0; v < NV; ++v) {
-        const size_t sl = c * NVP + (size_t)h->slot_of[v];
+        const size_t sl = v * PS + at;
         f[c * NV + v] = h->prec == UGKS_FP32_STORE
                             ? (double)reinterpret_cast<const float*>(raw.data())[sl]
                             : reinterpret_cast<const double*>(raw.data())[sl];
       }
+    }
   }
   if (flag) return fail(h, UGKS_E_STATE, "invalid state flagged on the device%s");
   return UGKS_OK;
@@ -634,19 +592,21 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
   if (!h) return UGKS_E_INVAL;
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
-  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = h->P.NV, NVP = h->P.NVP;
+  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = h->P.NV, PS = (size_t)h->P.PS;
   std::vector<char> raw;
   hipError_t e = hipSuccess;
   if (f) {
-    raw.assign(nc * NVP * h->ssize, 0);
-    for (size_t c = 0; c < nc; ++c)
+    raw.assign(NV * PS * h->ssize, 0);
+    for (size_t c = 0; c < nc; ++c) {
+      const size_t at = plane_index(h->P, c);
       for (size_t v = 0; v < NV; ++v) {
-        const size_t sl = c * NVP + (size_t)h->slot_of[v];
+        const size_t sl = v * PS + at;
         if (h->prec == UGKS_FP32_STORE)
           reinterpret_cast<float*>(raw.data())[sl] = (float)f[c * NV + v];
         else
           reinterpret_cast<double*>(raw.data())[sl] = f[c * NV + v];
       }
+    }
     e = hipMemcpyAsync(h->B.f[h->steps & 1], raw.data(), raw.size(), hipMemcpyHostToDevice,
                        h->stream);
   }

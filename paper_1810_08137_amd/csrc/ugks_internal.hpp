@@ -22,9 +22,8 @@ inline UGKS_GLOBAL T* gp(T* p) {
 constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kSlots = 64;     // per-cell outgoing moment sums: 4 faces x 16
 constexpr int kRec = 32;       // doubles per interface record
-// nu + nv limit: the update kernel keeps 13 (nu + 1) + 13 (nv + 1) doubles of tables per cell
-// and nu + nv + 2 node values in LDS, which must fit one 64 KB workgroup
-constexpr int kMaxTable = 582;
+constexpr int kHalo = 2;       // halo columns / rows on each side of a velocity plane
+constexpr int kMaxNodes = 1024;  // nodes per velocity axis
 
 // Interface record (doubles), written by the interface kernel, read by the cell update.
 // Frame: "normal"/"tangential" velocity of the face; for x-faces (u, v), for y-faces (v, u).
@@ -51,20 +50,20 @@ enum FaceKind { K_INTERIOR = 0, K_WALL = 1, K_FREE = 2 };
 // [W0(4), Wt(4), Q1(4), Q2(4)] in the local frame of that face.
 enum FaceSide { S_XP = 0, S_XM = 1, S_YP = 2, S_YM = 3 };
 
+// f is stored velocity-major: plane p = k M + m holds f(u_k, v_m) of every cell, laid out as
+// (ny + 4) rows of Lx = nx + 4 values (cell (i, j) at (j + 2) Lx + i + 2), with two halo
+// columns and rows on each side; planes are PS values apart.
 struct KParams {
-  int nx, ny, K, M, NV, NVP;
-  int bc, collisionless, inlet_fixed_u, pad0;
+  int nx, ny, K, M, NV;
+  int Lx, Ly;       // padded row length and row count of a plane
+  int bc, collisionless, inlet_fixed_u;
+  long long PS;     // values per plane
   double dx, dy, dt, inv_dx, inv_dy, area, mu_ref;
+  double du, dv;    // node spacing of the uniform u and v grids
   double p_in, p_out, T_in, lam_w;
   double U_in, U_noise;
   double wall_den_bot, wall_den_top;  // sum over wall-leaving velocities of w v g_w
   double wall_G_bot[4], wall_G_top[4];  // sum of w v psi_local g_w over the same velocities
-  const UGKS_GLOBAL double* U;     // [NVP] u of each velocity slot (0 in pads)
-  const UGKS_GLOBAL double* V;     // [NVP]
-  const UGKS_GLOBAL double* Wq;    // [NVP] quadrature weight (0 in pads)
-  const UGKS_GLOBAL int* km;       // [NVP] k | m << 16 of each velocity slot (K | M << 16 in pads)
-  const UGKS_GLOBAL int* chunk_sign;  // [NVP/64] per 64-slot chunk: bit0/1 all u > 0 / < 0,
-                                      // bit2/3 the same for v
   const UGKS_GLOBAL double* uk;    // [K]
   const UGKS_GLOBAL double* vm;    // [M]
   const UGKS_GLOBAL double* wk;    // [K] weights of the u nodes
@@ -75,20 +74,14 @@ struct KParams {
 
 // Device buffers carved out of one workspace.
 struct Buffers {
-  void* f[2];       // [nx*ny][NVP] storage type
+  void* f[2];       // [NV][PS] storage type
   double* W;        // [nx*ny][4]
   double* Wg;       // [2][ny][4]
-  void* fg;         // [2][ny][NVP] storage type
-  double* hs;       // [nx*ny][64]
+  double* hs;       // [64][nx*ny]: sum q of face side s of cell c at (16 s + q) nx ny + c
   double* hsg;      // [2][ny][16]
   double* recx;     // [ny][nx+1][32]
   double* recy;     // [ny+1][nx][32]
-  double* U;        // [NVP]
-  double* V;
-  double* Wq;
-  int* km;          // [NVP]
   double* wk;       // [K], followed by wm [M]
-  int* chunk_sign;  // [NVP/64]
   double* uk;       // [K]
   double* vm;       // [M]
   double* xi_in;    // [ny]
@@ -96,7 +89,7 @@ struct Buffers {
 };
 
 struct Layout {
-  size_t off[19];
+  size_t off[13];
   size_t total;
 };
 
@@ -107,7 +100,6 @@ struct Inst {
   UGKS_GLOBAL void* f[2];
   UGKS_GLOBAL double* W;
   UGKS_GLOBAL double* Wg;
-  UGKS_GLOBAL void* fg;
   UGKS_GLOBAL double* hs;
   UGKS_GLOBAL double* hsg;
   UGKS_GLOBAL double* recx;
@@ -121,21 +113,17 @@ struct Inst {
 // workgroup).  Device-resident; the kernels read it through PlanView.
 struct PlanView {
   const Inst* inst;
-  const int* off_sums;   // kCellsPerBlock cells per workgroup
-  const int* off_upd;    // cpb_upd cells per workgroup
+  const int* off_sums;   // one workgroup per row segment of the moment kernel
+  const int* off_upd;    // one workgroup per row segment of the update kernel
   const int* off_face;   // 256 faces per workgroup
-  const int* off_ghost;  // 2 ny workgroups for a channel, 0 for a periodic box
+  const int* off_ghost;  // channel: 2 ny workgroups; periodic: the halo frame of every plane
   int ninst;
   int step;              // steps enqueued since the plan's `cur` values were taken
-  int cpb_upd;
-  int lds_per_cell;      // bytes of update-kernel LDS per cell
 };
 
 struct PlanTotals {
   int sums, upd, face, ghost;  // workgroups of each launch
-  int cpb_upd;
-  int lds_per_cell;
-  int lds_upd, lds_sums;       // bytes of dynamic LDS per workgroup
+  int max_m;                   // largest nv of the plan's instances
 };
 
 // Bytes of a device plan with n instances, and its host image (offsets into one buffer).
@@ -145,7 +133,7 @@ size_t plan_bytes(int n);
 PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, PlanView* view);
 
 // Launchers (ugks_kernels.hip).  All enqueue on `s` and return the launch error.
-hipError_t launch_init(const PlanView& pv, int fp32, int ncells, hipStream_t s);
+hipError_t launch_init(const PlanView& pv, int fp32, long long nvalues, hipStream_t s);
 hipError_t launch_step(const PlanView& pv, const PlanTotals& t, int fp32, hipStream_t s,
                        hipEvent_t* ev /* 8 events or NULL */);
 hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int phase,

@@ -1,21 +1,22 @@
 // gfx950 kernels of the 2D UGKS time step.
 //
 // One step is four launches on one stream:
-//   ghost   pressure inlet/outlet ghost columns of a channel (Sec. 3.A)
-//   sums    per cell and velocity: limited slopes of f, the upwind reconstruction at each of
-//           the cell's four faces and their velocity moments (S1 and the sums of S7); one
-//           wavefront per cell, velocities across lanes, running sums reduced through LDS
+//   ghost   the halo of every velocity plane: pressure inlet/outlet ghost columns of a channel
+//           (Sec. 3.A) with their moment sums, or the periodic images of a periodic box
+//   sums    per cell and velocity: limited slopes of f, the upwind reconstruction at the
+//           cell's outgoing faces and their velocity moments (S1 and the sums of S7)
 //   faces   per interface: add the two sides' sums, then the scalar part of the flux
 //           (S2-S5: Maxwellian moments, time weights, micro slopes, equilibrium flux) into a
 //           record of folded coefficients
-//   update  per cell and velocity: rebuild the upwind f at the four faces, the interface
-//           Maxwellian from separable exp tables (S6), the distribution flux (S8), then
-//           Eq. (4) for W and Eq. (3) for f
-// f is laid out [cell][velocity slot] with the slot index contiguous and padded to a multiple
-// of 64, so every wavefront load is coalesced.  Slots are ordered by velocity quadrant, so
-// most 64-slot chunks have one sign of u and one of v: their upwind choices and moment slots
-// are then uniform across the wavefront.  The cell kernels visit cells in band order (columns
-// of 16-row bands) so that stencil neighbours are read from L2.
+//   update  per cell and velocity: the distribution flux at the faces (S6, S8), then Eq. (4)
+//           for W and Eq. (3) for f
+// f is stored velocity-major: one plane per discrete velocity, a padded nx x ny array with
+// two halo columns and rows on each side (KParams).  A wavefront takes 64 consecutive cells
+// of one row at one velocity, so every load is one coalesced row segment and the x
+// neighbours of a cell come from the neighbouring lanes.  The four wavefronts of a workgroup
+// share one row segment and take one velocity quadrant each: within a quadrant the upwind
+// direction of both axes is uniform, so a face flux is evaluated once, by the lane of its
+// upwind cell, and handed to the downwind lane.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -28,23 +29,63 @@ namespace ugks {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr int kCellsPerBlock = 4;  // one wavefront per cell
+constexpr int kQuads = 4;                     // wavefronts per workgroup, one per quadrant
+constexpr int kTileS = kWave - 2;             // cells per moment-kernel wavefront
+constexpr int kTileU = kWave - 2 * kHalo;     // cells per update-kernel wavefront
+constexpr int kStage = 24;                    // record fields the update kernel stages in LDS
+
+// Quadrant q of a workgroup: sign of u and of v.  Around the cycle (+,+) (-,+) (-,-) (+,-)
+// neighbours share one sign, so each face side collects its sums from two adjacent waves.
+__device__ __forceinline__ int quad_su(int q) { return (q == 0 || q == 3) ? 1 : -1; }
+__device__ __forceinline__ int quad_sv(int q) { return q < 2 ? 1 : -1; }
 
 // ------------------------------------------------------------------ storage
-template <typename S>
-__device__ __forceinline__ double ld(const UGKS_GLOBAL S* p, unsigned i) {
-  return static_cast<double>(p[i]);
-}
-// Load at a 32-bit byte offset from a uniform base: one instruction with a scalar base.
 template <typename T>
 __device__ __forceinline__ T ldb(const UGKS_GLOBAL T* p, unsigned byte_off) {
   return *reinterpret_cast<const UGKS_GLOBAL T*>(reinterpret_cast<const UGKS_GLOBAL char*>(p) +
                                                  byte_off);
 }
 template <typename S>
-__device__ __forceinline__ void st(UGKS_GLOBAL S* p, unsigned i, double x) {
-  p[i] = static_cast<S>(x);
+__device__ __forceinline__ double ldv(const UGKS_GLOBAL S* plane, int idx) {
+  return (double)ldb(plane, (unsigned)idx * (unsigned)sizeof(S));
 }
+template <typename S>
+__device__ __forceinline__ void stv(UGKS_GLOBAL S* plane, int idx, double x) {
+  *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(plane) +
+                                    (unsigned)idx * (unsigned)sizeof(S)) = static_cast<S>(x);
+}
+template <typename S>
+__device__ __forceinline__ const UGKS_GLOBAL S* plane_of(const UGKS_GLOBAL S* f, const KParams& P,
+                                                         int p) {
+  return f + (long long)p * P.PS;
+}
+template <typename S>
+__device__ __forceinline__ UGKS_GLOBAL S* plane_of(UGKS_GLOBAL S* f, const KParams& P, int p) {
+  return f + (long long)p * P.PS;
+}
+// index of cell (i, j) in a plane; i and j may lie in the halo
+__device__ __forceinline__ int pidx(const KParams& P, int i, int j) {
+  return (j + kHalo) * P.Lx + i + kHalo;
+}
+
+// ------------------------------------------------------------------ lane exchange
+// Whole-wavefront DPP shifts by one lane: lane l receives the value lane l - 1 holds
+// (from_lower) or lane l + 1 holds (from_upper); the edge lane keeps its own value.
+__device__ __forceinline__ double dpp_shift(double x, int ctrl_lower) {
+  const long long b = __double_as_longlong(x);
+  const int lo = (int)(unsigned)(b & 0xffffffffll), hi = (int)(b >> 32);
+  int rlo, rhi;
+  if (ctrl_lower) {
+    rlo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);  // wave_shr:1
+    rhi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+  } else {
+    rlo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);  // wave_shl:1
+    rhi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+  }
+  return __longlong_as_double(((long long)rhi << 32) | (long long)(unsigned)rlo);
+}
+__device__ __forceinline__ double from_lower(double x) { return dpp_shift(x, 1); }
+__device__ __forceinline__ double from_upper(double x) { return dpp_shift(x, 0); }
 
 // ------------------------------------------------------------------ pointwise physics
 // Reciprocal: the hardware estimate (relative error below 5e-8 on gfx950) refined by one
@@ -63,10 +104,6 @@ __device__ __forceinline__ double half_limited(double p, double q) {
   return pq > 0.0 ? r : 0.0;
 }
 
-// Upwind weight of the left state for normal velocity un (1/2 when un = 0).
-__device__ __forceinline__ double upwind_left(double un) {
-  return un > 0.0 ? 1.0 : (un < 0.0 ? 0.0 : 0.5);
-}
 
 struct Prim {
   double rho, U, V, lam;  // lambda = 1/T
@@ -160,37 +197,13 @@ __device__ __forceinline__ void time_weights(double dt, double tau, double* Mt) 
 
 // ------------------------------------------------------------------ addressing
 __device__ __forceinline__ int wrap(int i, int n) { return ((i % n) + n) % n; }
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 // Workgroups are handed to the 8 XCDs round-robin; renumber them so that each XCD works
-// through one contiguous range of cells (its own L2 then serves the stencil neighbours).
+// through one contiguous range (its own L2 then serves the rows its neighbours also read).
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
-
-// Cell (or tile) order of a launch: bands of kBand rows, column by column inside a band.  The
-// workgroups an XCD runs at one time then cover a compact patch of the mesh, so the stencil
-// neighbours a wavefront reads were read by its neighbours at about the same time and come
-// from that XCD's L2.
-constexpr int kBand = 16;
-__device__ __forceinline__ void band_order(int L, int nx, int ny, int band, int& i, int& j) {
-  const int per = band * nx;
-  const int bnd = L / per;
-  const int r = L - bnd * per;
-  const int rows = ny - bnd * band < band ? ny - bnd * band : band;
-  i = r / rows;
-  j = bnd * band + (r - i * rows);
-}
-
-// f slab of column i of row j, i in [-2, nx+1]: a cell, a wrapped cell (periodic) or the
-// inlet/outlet ghost column (channel).
-template <typename S>
-__device__ __forceinline__ const UGKS_GLOBAL S* xslab(const KParams& P, const UGKS_GLOBAL S* f,
-                                                     const UGKS_GLOBAL S* fg, int i, int j) {
-  if (i >= 0 && i < P.nx) return f + ((size_t)j * P.nx + i) * P.NVP;
-  if (P.bc == UGKS_BC_PERIODIC) return f + ((size_t)j * P.nx + wrap(i, P.nx)) * P.NVP;
-  return fg + ((size_t)(i < 0 ? 0 : P.ny) + j) * P.NVP;
 }
 
 // ------------------------------------------------------------------ wave reductions
@@ -200,34 +213,9 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-// Reduce 16 per-lane partial sums over the wavefront through the wave's LDS block (16 rows
-// of 65 doubles, the pad keeping the transposed reads on distinct banks) and add the totals
-// to `fin`, whose lane 16 face + q holds sum q of that face.  Lane l adds the values of
-// element l & 15 held by lanes 16 (l >> 4) .. 16 (l >> 4) + 15, then two exchanges combine
-// the quarters.  Sums 4..7 (the tangential-slope moments) were accumulated from half-cell
-// changes and take the factor `tscale` (2 / tangential spacing) here.  LDS operations of one
-// wavefront complete in program order.
-constexpr int kRedRow = kWave + 1;
-__device__ __forceinline__ void flush_face(const double* a, int face, double& fin, int lane,
-                                           double* red, double tscale) {
-#pragma unroll
-  for (int q = 0; q < 16; ++q) red[q * kRedRow + lane] = a[q];
-  __builtin_amdgcn_wave_barrier();
-  const int e = lane & 15, r = lane >> 4;
-  const double* row = red + e * kRedRow + r * 16;
-  double t = 0.0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) t += row[k];
-  t += __shfl_xor(t, 16, kWave);
-  t += __shfl_xor(t, 32, kWave);
-  if (e >= 4 && e < 8) t *= tscale;
-  if (r == face) fin += t;
-  __builtin_amdgcn_wave_barrier();
-}
-
 // 16 moment sums of one face side (S1 and S7): weight wt, normal/tangential velocity
 // (un, ut), reconstructed f, the tangential half-cell change ht (the tangential slope times
-// half the tangential spacing; its sums are scaled when flushed) and the slope term
+// half the tangential spacing; its sums are scaled when written) and the slope term
 // D = u sigma_x + v sigma_y.
 __device__ __forceinline__ void add_side(double* a, double wt, double un, double ut, double c2h,
                                          double fh, double ht, double D) {
@@ -253,13 +241,25 @@ __device__ __forceinline__ void add_side(double* a, double wt, double un, double
   a[15] = fma(x3, c2h, a[15]);
 }
 
-// Per-chunk sign code of the velocity slots: +1 / -1 when every real slot of the chunk has
-// that sign of the component, 0 when mixed (or zero).
-__device__ __forceinline__ int chunk_sign_u(int code) {
-  return (code & 1) ? 1 : ((code & 2) ? -1 : 0);
-}
-__device__ __forceinline__ int chunk_sign_v(int code) {
-  return (code & 4) ? 1 : ((code & 8) ? -1 : 0);
+// Node range of one half of a velocity axis.  Half s = +1 takes the nodes with positive
+// velocity, s = -1 the negative ones; a node at exactly zero belongs to both halves when
+// `share_zero` (moment sums, each visit with weight 1/2), else only to the positive half.
+struct Half {
+  int first, count, step;
+};
+__device__ __forceinline__ Half axis_half(int n, int s, bool share_zero) {
+  const int odd = n & 1, mid = n >> 1;  // with n odd, node mid is zero
+  Half h;
+  if (s > 0) {
+    h.first = mid;
+    h.count = n - mid;
+    h.step = 1;
+  } else {
+    h.first = mid - 1 + (share_zero ? odd : 0);
+    h.count = h.first + 1;
+    h.step = -1;
+  }
+  return h;
 }
 
 // ------------------------------------------------------------------ launch plans
@@ -289,45 +289,72 @@ __device__ __forceinline__ const Inst* inst_at(const PlanView& pv, int ii) {
   return pv.inst + ii;
 }
 
-
 // ================================================================== kernels
-// Discrete Maxwellian of each cell's W (initial state).
+// Discrete Maxwellian of each cell's W (initial state), one thread per plane value.
 template <typename S>
-__global__ __launch_bounds__(kWave) void init_kernel(PlanView pv) {
+__global__ __launch_bounds__(256) void init_kernel(PlanView pv) {
   const Inst* __restrict__ I = inst_at(pv, 0);
   const KParams P = I->P;
   UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[I->cur]);
   const UGKS_GLOBAL double* W = I->W;
-  const int c = blockIdx.x;
-  Prim p;
-  if (!prim_of(W + 4 * (size_t)c, p) && threadIdx.x == 0) *P.flag = 1;
-  const double coef = p.rho * p.lam / kPi;
-  UGKS_GLOBAL S* fc = f + (size_t)c * P.NVP;
-  for (int v = threadIdx.x; v < P.NVP; v += kWave) {
-    double g = 0.0;
-    if (v < P.NV) {
-      const double du = P.U[v] - p.U, dv = P.V[v] - p.V;
-      g = P.Wq[v] > 0.0 ? coef * exp(-p.lam * (du * du + dv * dv)) : 0.0;
-    }
-    st(fc, v, g);
-  }
+  const long long nc = (long long)P.nx * P.ny;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc * P.NV) return;
+  const int p = (int)(e / nc);
+  const int c = (int)(e - (long long)p * nc);
+  const int j = c / P.nx, i = c - j * P.nx;
+  Prim pr;
+  if (!prim_of(W + 4 * (size_t)c, pr) && p == 0) *P.flag = 1;
+  const int k = p / P.M, m = p - k * P.M;
+  const double du = P.uk[k] - pr.U, dv = P.vm[m] - pr.V;
+  const double g = pr.rho * pr.lam / kPi * exp(-pr.lam * (du * du + dv * dv));
+  stv(plane_of(f, P, p), pidx(P, i, j), g);
 }
 
-// Inlet/outlet ghost of one row: state, discrete Maxwellian, and the ghost's moment sums
-// towards the domain (its slopes are zero).  2 ny workgroups per channel instance, one
-// wavefront each.
+// Halo of the current f.  Channel: one wavefront per (side, row) writes the inlet (side 0)
+// or outlet (side 1) ghost Maxwellian into that row's ghost column of every plane and sums
+// its moments towards the domain (its slopes are zero); the other halo values stay zero.
+// Periodic: one thread per halo value of every plane copies the periodic image.
 template <typename S>
 __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
   const int b = blockIdx.x;
   const int ii = find_inst(pv.off_ghost, pv.ninst, b);
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
+  UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
+  const int local = b - first_block(pv.off_ghost, ii);
+  const int lane = threadIdx.x;
+  if (P.bc != UGKS_BC_CHANNEL) {
+    const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
+    const long long e = (long long)local * kWave + lane;
+    if (e >= frame * P.NV) return;
+    const int p = (int)(e / frame);
+    int r = (int)(e - (long long)p * frame);
+    // frame order: the 2 halo rows below, then ny rows of 4 halo columns, then 2 rows above
+    int i, j;
+    const int band = kHalo * P.Lx;
+    if (r < band) {
+      j = r / P.Lx - kHalo;
+      i = r % P.Lx - kHalo;
+    } else if (r < band + 2 * kHalo * P.ny) {
+      r -= band;
+      j = r / (2 * kHalo);
+      const int c = r % (2 * kHalo);
+      i = c < kHalo ? c - kHalo : P.nx + (c - kHalo);
+    } else {
+      r -= band + 2 * kHalo * P.ny;
+      j = P.ny + r / P.Lx;
+      i = r % P.Lx - kHalo;
+    }
+    UGKS_GLOBAL S* pl = plane_of(f, P, p);
+    const double x = ldv(pl, pidx(P, wrap(i, P.nx), wrap(j, P.ny)));
+    stv(pl, pidx(P, i, j), x);
+    return;
+  }
   const UGKS_GLOBAL double* W = I->W;
   UGKS_GLOBAL double* Wg = I->Wg;
-  UGKS_GLOBAL S* fg = static_cast<UGKS_GLOBAL S*>(I->fg);
   UGKS_GLOBAL double* hsg = I->hsg;
-  const int local = b - first_block(pv.off_ghost, ii);
-  const int side = local / P.ny, j = local - side * P.ny, lane = threadIdx.x;
+  const int side = local / P.ny, j = local - side * P.ny;
   const int col = side == 0 ? 0 : P.nx - 1;
   Prim pc, pg;
   const bool ok = prim_of(W + 4 * ((size_t)j * P.nx + col), pc);
@@ -358,21 +385,20 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
     wg[3] = 0.5 * pg.rho * (pg.U * pg.U + pg.V * pg.V) + 0.5 * pg.rho / pg.lam;
   }
   const double coef = pg.rho * pg.lam / kPi;
-  UGKS_GLOBAL S* row = fg + ((size_t)side * P.ny + j) * P.NVP;
+  const int at = pidx(P, side == 0 ? -1 : P.nx, j);
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (int v = lane; v < P.NVP; v += kWave) {
-    const double u = P.U[v], vv = P.V[v], w = P.Wq[v];
-    double g = 0.0;
-    if (w > 0.0) {
-      const double du = u - pg.U, dv = vv - pg.V;
-      g = coef * exp(-pg.lam * (du * du + dv * dv));
-    }
-    st(row, v, g);
-    const double gs = ld(row, v);  // the value the cells will read
-    const double h = side == 0 ? upwind_left(u) : 1.0 - upwind_left(u);
-    add_side(acc, w * h, u, vv, 0.5 * (u * u + vv * vv), gs, 0.0, 0.0);
+  for (int p = lane; p < P.NV; p += kWave) {
+    const int k = p / P.M, m = p - k * P.M;
+    const double u = P.uk[k], vv = P.vm[m], w = P.wk[k] * P.wm[m];
+    const double du = u - pg.U, dv = vv - pg.V;
+    const double g = coef * exp(-pg.lam * (du * du + dv * dv));
+    const S gs = static_cast<S>(g);  // the value the cells will read
+    stv(plane_of(f, P, p), at, (double)gs);
+    const double up = u > 0.0 ? 1.0 : (u < 0.0 ? 0.0 : 0.5);
+    const double h = side == 0 ? up : 1.0 - up;
+    add_side(acc, w * h, u, vv, 0.5 * (u * u + vv * vv), (double)gs, 0.0, 0.0);
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -381,133 +407,79 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
   }
 }
 
-// Per cell: slopes and the outgoing moment sums of all four faces.  One wavefront per cell,
-// four cells per block.  Chunks come in velocity-quadrant order: a run of chunks with one
-// sign of u and one of v feeds one x-face and one y-face, whose 16 running sums are flushed
-// into `fin` (lane 16 face + q) at the end of the run; a chunk of mixed signs feeds each
-// face in turn with per-lane upwind weights.
+// Per cell: slopes and the outgoing moment sums of all four faces.  A workgroup takes one
+// segment of kTileS cells of one row (lanes hold the segment and one neighbour on each side);
+// wavefront q sums velocity quadrant q into the x face and the y face its particles leave
+// through.  The two partial sums of each face side meet in LDS at the end.
 template <typename S>
-__global__ __launch_bounds__(kWave* kCellsPerBlock) __attribute__((amdgpu_waves_per_eu(4)))
-void sums_kernel(PlanView pv) {
-  // LDS: per wavefront the 16 x 65 flush block, then the node tables u_k, v_m, w_k, w_m
-  extern __shared__ double lds[];
+__global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
+  __shared__ double red[4][16][kWave];
   const int lane = threadIdx.x & (kWave - 1);
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int ii = find_inst(pv.off_sums, pv.ninst, b);
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
   const UGKS_GLOBAL S* f = static_cast<const UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
-  const UGKS_GLOBAL S* fg = static_cast<const UGKS_GLOBAL S*>(I->fg);
   UGKS_GLOBAL double* hs = I->hs;
-  double* tu = lds + kCellsPerBlock * 16 * kRedRow;
-  double* tv = tu + (P.K + 1);
-  double* twu = tv + (P.M + 1);
-  double* twv = twu + (P.K + 1);
-  for (int e = threadIdx.x; e < 2 * (P.K + 1) + 2 * (P.M + 1); e += blockDim.x) {
-    double x = 0.0;  // entries K and M (padding slots) stay zero
-    if (e < P.K) x = P.uk[e];
-    else if (e >= P.K + 1 && e < P.K + 1 + P.M) x = P.vm[e - (P.K + 1)];
-    else if (e >= P.K + P.M + 2 && e < 2 * P.K + P.M + 2) x = P.wk[e - (P.K + P.M + 2)];
-    else if (e >= 2 * P.K + P.M + 3 && e < 2 * P.K + 2 * P.M + 3) x = P.wm[e - (2 * P.K + P.M + 3)];
-    tu[e] = x;
-  }
-  __syncthreads();
-  // the wavefront index is uniform: keep everything derived from it in scalar registers
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int c = (b - first_block(pv.off_sums, ii)) * kCellsPerBlock + wv;
-  if (c >= P.nx * P.ny) return;
-  double* red = lds + wv * 16 * kRedRow;
-  int i, j;
-  band_order(c, P.nx, P.ny, kBand, i, j);
-  const bool wall_row = P.bc == UGKS_BC_CHANNEL && (j == 0 || j == P.ny - 1);
-  const size_t cell = (size_t)j * P.nx + i;
-  const UGKS_GLOBAL S* f0 = f + cell * P.NVP;
-  const UGKS_GLOBAL S* fw = xslab(P, f, fg, i - 1, j);
-  const UGKS_GLOBAL S* fe = xslab(P, f, fg, i + 1, j);
-  const UGKS_GLOBAL S* fs = f + ((size_t)wrap(j - 1, P.ny) * P.nx + i) * P.NVP;
-  const UGKS_GLOBAL S* fn = f + ((size_t)wrap(j + 1, P.ny) * P.nx + i) * P.NVP;
-  double fin = 0.0;
-  const int nch = P.NVP / kWave;
-  // the five stencil values and the node index of chunk ch, loaded while chunk ch - 1 is
-  // summed
-  double buf[5];
-  int kmb;
-  {
-    const unsigned o0 = (unsigned)lane * (unsigned)sizeof(S);
-    buf[0] = (double)ldb(f0, o0);
-    buf[1] = (double)ldb(fw, o0);
-    buf[2] = (double)ldb(fe, o0);
-    buf[3] = (double)ldb(fs, o0);
-    buf[4] = (double)ldb(fn, o0);
-    kmb = ldb(P.km, (unsigned)lane * 4u);
-  }
-  struct Point {
-    double fc, hx, hy, D, u, vv, w, c2h;
-  };
+  const int L = b - first_block(pv.off_sums, ii);
+  const int t = L / P.ny, j = L - t * P.ny;
+  const int i = t * kTileS - 1 + lane;
+  const bool valid = lane >= 1 && lane <= kTileS && i < P.nx;
+  const int o = pidx(P, i < P.nx + 1 ? i : P.nx + 1, j);
+  const int Lx = P.Lx;
+  const double my = (P.bc == UGKS_BC_CHANNEL && (j == 0 || j == P.ny - 1)) ? 0.0 : 1.0;
+  const int su = quad_su(q), sv = quad_sv(q);
+  const Half hu = axis_half(P.K, su, true), hv = axis_half(P.M, sv, true);
   const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
-  // take chunk ch out of the buffer, start loading chunk ch + 1, and form the half-cell
-  // changes hx = sigma_x dx / 2, hy = sigma_y dy / 2 and D = u sigma_x + v sigma_y
-  auto point = [&](int ch) {
-    Point q;
-    const int v = ch * kWave + lane;
-    const double fwv = buf[1], fev = buf[2], fsv = buf[3], fnv = buf[4];
-    q.fc = buf[0];
-    const int k = kmb & 0xffff, m = kmb >> 16;
-    const unsigned vn = (unsigned)(ch + 1 < nch ? v + kWave : v);
-    const unsigned on = vn * (unsigned)sizeof(S);
-    buf[0] = (double)ldb(f0, on);
-    buf[1] = (double)ldb(fw, on);
-    buf[2] = (double)ldb(fe, on);
-    buf[3] = (double)ldb(fs, on);
-    buf[4] = (double)ldb(fn, on);
-    kmb = ldb(P.km, vn * 4u);
-    q.hx = half_limited(fev - q.fc, q.fc - fwv);
-    const double hyl = half_limited(fnv - q.fc, q.fc - fsv);
-    q.hy = wall_row ? 0.0 : hyl;
-    q.u = tu[k];
-    q.vv = tv[m];
-    q.w = twu[k] * twv[m];
-    q.c2h = 0.5 * fma(q.u, q.u, q.vv * q.vv);
-    q.D = fma(q.u * two_idx, q.hx, (q.vv * two_idy) * q.hy);
-    return q;
-  };
-  int ch = 0;
-  while (ch < nch) {
-    const int code = P.chunk_sign[ch];
-    const int su = chunk_sign_u(code), sv = chunk_sign_v(code);
-    if (su != 0 && sv != 0) {
-      double ax[16], ay[16];
+  double ax[16], ay[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) ax[q] = ay[q] = 0.0;
-      do {
-        const Point q = point(ch);
-        add_side(ax, q.w, q.u, q.vv, q.c2h, su > 0 ? q.fc + q.hx : q.fc - q.hx, q.hy, q.D);
-        add_side(ay, q.w, q.vv, q.u, q.c2h, sv > 0 ? q.fc + q.hy : q.fc - q.hy, q.hx, q.D);
-        ++ch;
-      } while (ch < nch && P.chunk_sign[ch] == code);
-      flush_face(ax, su > 0 ? S_XP : S_XM, fin, lane, red, two_idy);
-      flush_face(ay, sv > 0 ? S_YP : S_YM, fin, lane, red, two_idx);
-    } else {
-      const Point q = point(ch);
-      const double hx = upwind_left(q.u), hy = upwind_left(q.vv);
-      for (int face = 0; face < 4; ++face) {
-        double a[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) a[k] = 0.0;
-        if (face == S_XP)
-          add_side(a, q.w * hx, q.u, q.vv, q.c2h, q.fc + q.hx, q.hy, q.D);
-        else if (face == S_XM)
-          add_side(a, q.w * (1.0 - hx), q.u, q.vv, q.c2h, q.fc - q.hx, q.hy, q.D);
-        else if (face == S_YP)
-          add_side(a, q.w * hy, q.vv, q.u, q.c2h, q.fc + q.hy, q.hx, q.D);
-        else
-          add_side(a, q.w * (1.0 - hy), q.vv, q.u, q.c2h, q.fc - q.hy, q.hx, q.D);
-        flush_face(a, face, fin, lane, red, face < 2 ? two_idy : two_idx);
-      }
-      ++ch;
+  for (int r = 0; r < 16; ++r) ax[r] = ay[r] = 0.0;
+  for (int a = 0; a < hu.count; ++a) {
+    const int k = hu.first + a * hu.step;
+    const double u = P.uk[k];
+    const double wu = P.wk[k] * (u == 0.0 ? 0.5 : 1.0);
+    const double ucx = u * two_idx;
+    const UGKS_GLOBAL S* row = plane_of(f, P, k * P.M);
+    for (int c = 0; c < hv.count; ++c) {
+      const int m = hv.first + c * hv.step;
+      const double vv = P.vm[m];
+      const double w = wu * P.wm[m] * (vv == 0.0 ? 0.5 : 1.0);
+      const UGKS_GLOBAL S* pl = row + (long long)m * P.PS;
+      const double fc = ldv(pl, o);
+      const double fS = ldv(pl, o - Lx);
+      const double fN = ldv(pl, o + Lx);
+      const double fW = from_lower(fc), fE = from_upper(fc);
+      const double hx = half_limited(fE - fc, fc - fW);
+      const double hy = my * half_limited(fN - fc, fc - fS);
+      const double D = fma(ucx, hx, (vv * two_idy) * hy);
+      const double c2h = 0.5 * fma(u, u, vv * vv);
+      add_side(ax, w, u, vv, c2h, su > 0 ? fc + hx : fc - hx, hy, D);
+      add_side(ay, w, vv, u, c2h, sv > 0 ? fc + hy : fc - hy, hx, D);
     }
   }
-  hs[cell * kSlots + lane] = fin;
+  // x faces: (+) from waves 0 and 3, (-) from 1 and 2; y faces: (+) from 0 and 1, (-) from
+  // 2 and 3.  Waves 1 and 3 hand their sums over, waves 0 and 2 add and write.
+  if (q == 1 || q == 3) {
+    const int s = q == 1 ? 0 : 1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      red[s][r][lane] = ay[r];
+      red[2 + s][r][lane] = ax[r];
+    }
+  }
+  __syncthreads();
+  if (!valid || q == 1 || q == 3) return;
+  const size_t nc = (size_t)P.nx * P.ny, cell = (size_t)j * P.nx + i;
+  const int fy = q == 0 ? S_YP : S_YM, fx = q == 0 ? S_XP : S_XM;
+  const int oy = q == 0 ? 0 : 1, ox = q == 0 ? 3 : 2;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const double sx = (ax[r] + red[ox][r][lane]) * (r >= 4 && r < 8 ? two_idy : 1.0);
+    const double sy = (ay[r] + red[oy][r][lane]) * (r >= 4 && r < 8 ? two_idx : 1.0);
+    hs[(size_t)(16 * fx + r) * nc + cell] = sx;
+    hs[(size_t)(16 * fy + r) * nc + cell] = sy;
+  }
 }
 
 // S2-S5 at one interior interface, local frame.  S = [W0, Wt, Q1, Q2].  Writes the local
@@ -607,29 +579,33 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   const long nfx = (long)P.ny * (P.nx + 1);
   const long nfy = (long)(P.ny + 1) * P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
+  const size_t nc = (size_t)P.nx * P.ny;
   double S[16], F[4];
   double U0, V0;
   if (e < nfx) {
     const int j = (int)(e / (P.nx + 1)), i = (int)(e % (P.nx + 1));
     const UGKS_GLOBAL double *sL, *sR, *WL, *WR;
+    size_t stL = nc, stR = nc;
     if (i > 0 || !chan) {
       const size_t cl = (size_t)j * P.nx + wrap(i - 1, P.nx);
-      sL = hs + cl * kSlots + 16 * S_XP;
+      sL = hs + 16 * S_XP * nc + cl;
       WL = W + 4 * cl;
     } else {
       sL = hsg + (size_t)j * 16;
+      stL = 1;
       WL = Wg + 4 * (size_t)j;
     }
     if (i < P.nx || !chan) {
       const size_t cr = (size_t)j * P.nx + wrap(i, P.nx);
-      sR = hs + cr * kSlots + 16 * S_XM;
+      sR = hs + 16 * S_XM * nc + cr;
       WR = W + 4 * cr;
     } else {
       sR = hsg + ((size_t)P.ny + j) * 16;
+      stR = 1;
       WR = Wg + 4 * ((size_t)P.ny + j);
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) S[q] = sL[q] + sR[q];
+    for (int q = 0; q < 16; ++q) S[q] = sL[q * stL] + sR[q * stR];
     double wl[4], wr[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -652,7 +628,8 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
     // diffuse wall: sums of the wall-row cell towards the wall; local frame (v, u)
     const bool top = j == P.ny;
     const size_t c = (size_t)(top ? P.ny - 1 : 0) * P.nx + i;
-    const UGKS_GLOBAL double* Q1 = hs + c * kSlots + 16 * (top ? S_YP : S_YM) + 8;
+    const UGKS_GLOBAL double* Q1s = hs + (16 * (top ? S_YP : S_YM) + 8) * nc + c;
+    const double Q1[4] = {Q1s[0], Q1s[nc], Q1s[2 * nc], Q1s[3 * nc]};
     const double den = top ? P.wall_den_top : P.wall_den_bot;
     const double* Gw = top ? P.wall_G_top : P.wall_G_bot;
     const double rho_w = -Q1[0] / den;
@@ -671,15 +648,17 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
     rec[R_M4] = s;
     rec[R_M5] = 0.0;
     rec[R_KIND] = K_WALL;
+#pragma unroll
+    for (int q = 0; q < 13; ++q) rec[R_E + q] = 0.0;  // a wall carries no polynomial
     if (!(rho_w > 0.0) || !isfinite(rho_w)) *P.flag = 1;
     return;
   }
   const size_t cl = (size_t)wrap(j - 1, P.ny) * P.nx + i;
   const size_t cr = (size_t)wrap(j, P.ny) * P.nx + i;
-  const UGKS_GLOBAL double* sL = hs + cl * kSlots + 16 * S_YP;
-  const UGKS_GLOBAL double* sR = hs + cr * kSlots + 16 * S_YM;
+  const UGKS_GLOBAL double* sL = hs + 16 * S_YP * nc + cl;
+  const UGKS_GLOBAL double* sR = hs + 16 * S_YM * nc + cr;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) S[q] = sL[q] + sR[q];
+  for (int q = 0; q < 16; ++q) S[q] = sL[q * nc] + sR[q * nc];
   const double wl[4] = {W[4 * cl], W[4 * cl + 2], W[4 * cl + 1], W[4 * cl + 3]};
   const double wr[4] = {W[4 * cr], W[4 * cr + 2], W[4 * cr + 1], W[4 * cr + 3]};
   interface_scalars(P, S, wl, wr, P.dy, P.dx, F, rec, U0, V0);
@@ -692,160 +671,262 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
 }
 
 // ------------------------------------------------------------------ update kernel
-// Each wavefront (one cell) builds in LDS, for each of its four faces, the equilibrium part of
-// the distribution flux in separable form: with un the normal and ut the tangential velocity,
-//   GC En(un) Et(ut) P(un, ut) = TE[t] (TA[n] + ut (TB[n] + ut (TC[n] + ut TD[n])))
-// where P is the folded cubic of the record, n / t index the normal / tangential velocity node
-// and the normal-slope choice (aL for un > 0, aR for un < 0) is made per node n.  The cell's
-// g^n and g^{n+1} are kept as products of two 1D tables with the Eq. (3) weights folded in.
-// Everything indexed by the u node k sits in one row of 12 doubles, everything indexed by the
-// v node m in another, so a lane reads all its table entries from two rows:
-//   u row k: left and right face polys (4 + 4), bottom and top face exps, g^n and g^{n+1}
-//            u factors;
-//   v row m: bottom and top face polys (4 + 4), left and right face exps, g^n and g^{n+1}
-//            v factors.
-// Row K and row M stay zero: padding slots point there, so their update is exactly zero.
-// Rows are 13 doubles apart (one unused): with an odd stride up to 16 different rows a chunk
-// touches sit on distinct LDS banks for 8-byte reads.
-constexpr int kRow = 13;
-enum RowEntry { RP_LO = 0, RP_HI = 4, RE_LO = 8, RE_HI = 9, RG_N = 10, RG_1 = 11 };
-
-__host__ __device__ __forceinline__ int tab_doubles(int K, int M) {
-  return kRow * (K + 1) + kRow * (M + 1);
-}
-
-// Doubles of the block-shared node tables.
-__host__ __device__ __forceinline__ int node_doubles(int K, int M) { return K + M + 2; }
-
-// Fill the four-entry polynomial table of one face at normal node with velocity un.
-__device__ __forceinline__ void face_poly(const UGKS_GLOBAL double* r, double un, double lam,
-                                          double U0, double* out) {
-  const double d = un - U0;
-  const double En = exp(-lam * d * d) * r[R_GC];
-  const bool pos = un > 0.0;
-  const double e1 = pos ? r[R_E + 1] : r[R_ER + 0];
-  const double e4 = pos ? r[R_E + 4] : r[R_ER + 1];
-  const double e5 = pos ? r[R_E + 5] : r[R_ER + 2];
-  const double e7 = pos ? r[R_E + 7] : r[R_ER + 3];
-  const double e0 = r[R_E + 0], e2 = r[R_E + 2], e3 = r[R_E + 3], e6 = r[R_E + 6],
-               e8 = r[R_E + 8];
-  // P(un, ut) = A + ut (B + ut (C + ut D)) with
-  // A = e0 + un (e1 + un (e4 + e3/2 + un e7/2)), B = e2 + un (e5 + un e8/2),
-  // C = e6 + e3/2 + un e7/2, D = e8/2
-  out[0] = En * fma(un, fma(un, fma(un, 0.5 * e7, e4 + 0.5 * e3), e1), e0);
-  out[1] = En * fma(un, fma(un, 0.5 * e8, e5), e2);
-  out[2] = En * fma(un, 0.5 * e7, e6 + 0.5 * e3);
-  out[3] = En * (0.5 * e8);
-}
-
-// Equilibrium part at one velocity from a face's tables (poly at the normal node, E at the
-// tangential node) and the time-integrated flux of the face.
-// D = u sigma_x + v sigma_y is the slope term of the upwind cell (the same for its x- and
-// y-faces).
-__device__ __forceinline__ double face_flux(double2 pab, double2 pcd, double E, double un,
-                                            double ut, double fh, double D, double m4,
-                                            double m5) {
-  const double G = E * fma(ut, fma(ut, fma(ut, pcd.y, pcd.x), pab.y), pab.x);
-  const double free_part = fma(m4, fh, -m5 * D);
-  return un * (G + free_part);
-}
-
-template <typename S>
-struct UpdateCtx {
-  const UGKS_GLOBAL S* f0;
-  const UGKS_GLOBAL S* xw;
-  const UGKS_GLOBAL S* xe;
-  const UGKS_GLOBAL S* xww;
-  const UGKS_GLOBAL S* xee;
-  const UGKS_GLOBAL S* sw;
-  const UGKS_GLOBAL S* sc;
-  const UGKS_GLOBAL S* se;
-  const UGKS_GLOBAL S* nw;
-  const UGKS_GLOBAL S* nc;
-  const UGKS_GLOBAL S* ne;
-  const UGKS_GLOBAL S* scc;
-  const UGKS_GLOBAL S* ncc;
+// Staged face records: sx[field][f] holds x face i0 - 2 + f (the left face of lane f),
+// sy[0 / 1][field][l] the bottom / top face of lane l.
+struct Stage {
+  double sx[kStage][kWave + 1];
+  double sy[2][kStage][kWave];
 };
-
-// Left-minus-right flux difference for one velocity.  SX = +1 / -1: u has that sign across
-// the wavefront; 0: per lane.  Every stencil value is loaded (every slab pointer is valid);
-// boundaries only switch results.  Slopes are carried as half-cell changes h = sigma dx / 2
-// (or dy / 2); ucx = 2 u / dx and vcy = 2 v / dy turn them into u sigma_x + v sigma_y.
-template <int SX>
-__device__ __forceinline__ double x_part(double u, double vv, double ucx, double vcy, double fc,
-                                         double fW, double fE, double fXX, double fXn,
-                                         double fXs, double hx0, double D0, bool ghost_w,
-                                         bool ghost_e, bool wall_row, const double* lp,
-                                         const double* rp, double le, double re, double m4l,
-                                         double m5l, double m4r, double m5r) {
-  // particles with u > 0 enter through the left face from cell i-1 (the upwind cell X); fXX
-  // is X's far x-neighbour (i -+ 2), fXn and fXs its y-neighbours
-  const bool right = SX > 0 ? true : (SX < 0 ? false : (u > 0.0));
-  const double fX = right ? fW : fE;
-  const bool ghostX = right ? ghost_w : ghost_e;
-  const double hxl = right ? half_limited(fc - fX, fX - fXX) : half_limited(fXX - fX, fX - fc);
-  const double hyl = half_limited(fXn - fX, fX - fXs);
-  const double hxX = ghostX ? 0.0 : hxl;
-  const double hyX = (ghostX || wall_row) ? 0.0 : hyl;
-  const double DX = fma(ucx, hxX, vcy * hyX);
-  const double fh_in = right ? fX + hxX : fX - hxX;
-  const double fh_own = right ? fc + hx0 : fc - hx0;
-  // left face: upwind is X when moving right, the cell itself when moving left
-  const double fl = right ? fh_in : fh_own, Dl = right ? DX : D0;
-  const double fr = right ? fh_own : fh_in, Dr = right ? D0 : DX;
-  const double2 lab = make_double2(lp[0], lp[1]);
-  const double2 lcd = make_double2(lp[2], lp[3]);
-  const double2 rab = make_double2(rp[0], rp[1]);
-  const double2 rcd = make_double2(rp[2], rp[3]);
-  const double Fl = face_flux(lab, lcd, le, u, vv, fl, Dl, m4l, m5l);
-  const double Fr = face_flux(rab, rcd, re, u, vv, fr, Dr, m4r, m5r);
-  return Fl - Fr;
+// Once Eq. (4) is done the flux fields (R_FX..R_FX+3) are free: they then hold, per lane, the
+// cell's state for Eq. (3) (CellField n in row cell_row(n)).
+enum CellField { C_LAMN, C_UN, C_VN, C_LAM1, C_U1, C_V1, C_AN, C_A1, C_AF, C_ADF, C_COUNT };
+__device__ __forceinline__ double* cell_row(Stage& st, int n) {
+  return n < 4 ? st.sy[0][R_FX + n] : (n < 8 ? st.sy[1][R_FX + n - 4] : st.sx[R_FX + n - 8]);
+}
+__device__ __forceinline__ const double* cell_row(const Stage& st, int n) {
+  return n < 4 ? st.sy[0][R_FX + n] : (n < 8 ? st.sy[1][R_FX + n - 4] : st.sx[R_FX + n - 8]);
 }
 
-// Bottom-minus-top flux difference.  Walls: particles leaving a wall follow rho_w times the
-// wall Maxwellian (its tables hold dx dt rho_w g_w), those reaching it carry the wall-row value.
-template <int SY>
-__device__ __forceinline__ double y_part(double u, double vv, double ucx, double vcy, double fc,
-                                         double fS, double fN, double fYY, double fYe,
-                                         double fYw, double hy0, double D0, bool wall_b,
-                                         bool wall_t, bool s_wallrow, bool n_wallrow,
-                                         const double* bp, const double* tp, double be,
-                                         double te, double m4b, double m5b, double m4t,
-                                         double m5t) {
-  // the upwind cell Y is (i, j -+ 1); fYY is its far y-neighbour, fYe and fYw its x-neighbours
-  const bool up = SY > 0 ? true : (SY < 0 ? false : (vv > 0.0));
-  const double fY = up ? fS : fN;
-  const bool Y_wallrow = up ? s_wallrow : n_wallrow;
-  const double hyl = up ? half_limited(fc - fY, fY - fYY) : half_limited(fYY - fY, fY - fc);
-  const double hyY = Y_wallrow ? 0.0 : hyl;
-  const double hxY = half_limited(fYe - fY, fY - fYw);
-  const double DY = fma(ucx, hxY, vcy * hyY);
-  const double fh_in = up ? fY + hyY : fY - hyY;
-  const double fh_own = up ? fc + hy0 : fc - hy0;
-  // bottom face: upwind is Y when moving up, the cell itself when moving down
-  const double fb = up ? fh_in : fh_own, Db = up ? DY : D0;
-  const double ft = up ? fh_own : fh_in, Dt = up ? D0 : DY;
-  const double2 bab = make_double2(bp[0], bp[1]);
-  const double2 bcd = make_double2(bp[2], bp[3]);
-  const double2 tab2 = make_double2(tp[0], tp[1]);
-  const double2 tcd = make_double2(tp[2], tp[3]);
-  const double Fb_face = face_flux(bab, bcd, be, vv, u, fb, Db, m4b, m5b);
-  const double Ft_face = face_flux(tab2, tcd, te, vv, u, ft, Dt, m4t, m5t);
-  const double Fb_wall = up ? vv * (be * bab.x) : vv * (m4b * fc);
-  const double Ft_wall = up ? vv * (m4t * fc) : vv * (te * tab2.x);
-  const double Fb = wall_b ? Fb_wall : Fb_face;
-  const double Ft = wall_t ? Ft_wall : Ft_face;
-  return Fb - Ft;
+// A Gaussian factor exp(-lam (x - c)^2) along the uniform nodes x0, x0 + h, x0 + 2h, ...:
+// e is its value at the current node and r the ratio to the next one; successive ratios
+// differ by the factor exp(-2 lam h^2), applied as r + r (exp(-2 lam h^2) - 1) with the
+// second factor from expm1, so that it adds one rounding per node and no drift.
+__device__ __forceinline__ void gauss_next(double& e, double& r, double qm1) {
+  e *= r;
+  r = fma(r, qm1, r);
 }
 
-// Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  One wavefront per cell.
+// Cubic of the folded equilibrium polynomial P(un, ut) of a record (interface scalars) in
+// one velocity with the other fixed.  The e1, e4, e5, e7 of the side the particles come from
+// are passed in (pos: un > 0).
+struct Cubic {
+  double c0, c1, c2, c3;
+};
+// P as a cubic in the tangential velocity at fixed normal velocity un.
+__device__ __forceinline__ Cubic cubic_in_ut(const double* e, double un) {
+  Cubic c;
+  c.c0 = fma(un, fma(un, fma(un, 0.5 * e[7], e[4] + 0.5 * e[3]), e[1]), e[0]);
+  c.c1 = fma(un, fma(un, 0.5 * e[8], e[5]), e[2]);
+  c.c2 = fma(un, 0.5 * e[7], e[6] + 0.5 * e[3]);
+  c.c3 = 0.5 * e[8];
+  return c;
+}
+// P as a cubic in the normal velocity at fixed tangential velocity ut.
+__device__ __forceinline__ Cubic cubic_in_un(const double* e, double ut) {
+  Cubic c;
+  c.c0 = fma(ut, fma(ut, fma(ut, 0.5 * e[8], 0.5 * e[3] + e[6]), e[2]), e[0]);
+  c.c1 = fma(ut, fma(ut, 0.5 * e[7], e[5]), e[1]);
+  c.c2 = fma(ut, 0.5 * e[8], 0.5 * e[3] + e[4]);
+  c.c3 = 0.5 * e[7];
+  return c;
+}
+__device__ __forceinline__ double horner(const Cubic& c, double x) {
+  return fma(x, fma(x, fma(x, c.c3, c.c2), c.c1), c.c0);
+}
+// e0..e8 of a staged record for particles with normal velocity of sign s
+__device__ __forceinline__ void load_e(const double (*st)[kWave + 1], int col, int s, double* e) {
+#pragma unroll
+  for (int n = 0; n < 9; ++n) e[n] = st[R_E + n][col];
+  if (s < 0) {
+    e[1] = st[R_ER + 0][col];
+    e[4] = st[R_ER + 1][col];
+    e[5] = st[R_ER + 2][col];
+    e[7] = st[R_ER + 3][col];
+  }
+}
+__device__ __forceinline__ void load_e(const double (*st)[kWave], int col, int s, double* e) {
+#pragma unroll
+  for (int n = 0; n < 9; ++n) e[n] = st[R_E + n][col];
+  if (s < 0) {
+    e[1] = st[R_ER + 0][col];
+    e[4] = st[R_ER + 1][col];
+    e[5] = st[R_ER + 2][col];
+    e[7] = st[R_ER + 3][col];
+  }
+}
+
+// Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  A workgroup takes one segment of
+// kTileU cells of row j; its lanes hold the segment and two cells on each side.  Wavefront q
+// runs velocity quadrant q (signs su, sv): u nodes outer, v nodes inner.  Per velocity a lane
+// (cell i) forms
+//   its upwind reconstruction and slope term at its outgoing x and y faces,
+//   the flux through its outgoing x face, which the downwind lane takes over as its incoming
+//   x flux (x faces of the segment are each evaluated once),
+//   the flux through its outgoing y face, and the incoming y flux from the reconstruction of
+//   the upwind row's cell (i, j - sv), rebuilt from rows j - 2 sv .. j.
+// The equilibrium part of a face flux is GC En(un) Et(ut) P(un, ut): the Gaussian and cubic
+// of the u node are formed once per node, those of the v node follow the node by Gauss
+// recurrences.  Walls fold into the same form: the face leaving a wall carries only its
+// Maxwellian (P = 1, no free-transport part), the face reaching a wall only the first-order
+// free transport of the wall row.
+template <typename S, int SU>
+__device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& st,
+                                                const double* vnode, int lane, int sv, int j,
+                                                bool valid, bool ghost_lane,
+                                                const UGKS_GLOBAL S* fin, UGKS_GLOBAL S* fout,
+                                                int o) {
+  const bool chan = P.bc == UGKS_BC_CHANNEL;
+  const int xo = lane + (SU > 0 ? 1 : 0);        // staged x face the lane's particles leave by
+  const int yo = sv > 0 ? 1 : 0, yi = 1 - yo;    // y faces: outgoing, incoming
+  // own wall row: no y slope; the upwind row (i, j - sv) likewise
+  const double my = (chan && (j == 0 || j == P.ny - 1)) ? 0.0 : 1.0;
+  const int jy = j - sv;
+  const double mY = (chan && (jy == 0 || jy == P.ny - 1)) ? 0.0 : 1.0;
+  const double gm = ghost_lane ? 0.0 : 1.0;      // ghost columns have zero slopes
+  const double gmy = gm * my;
+  const bool wall_o = chan && (sv > 0 ? j == P.ny - 1 : j == 0);
+  const bool wall_i = chan && (sv > 0 ? j == 0 : j == P.ny - 1);
+  // byte offsets of this cell and of rows j - sv, j + sv, j - 2 sv inside a plane
+  const unsigned bs = (unsigned)sizeof(S);
+  const unsigned oc = (unsigned)o * bs;
+  const unsigned oY = (unsigned)(o - sv * P.Lx) * bs;
+  const unsigned oO = (unsigned)(o + sv * P.Lx) * bs;
+  const unsigned oYY = (unsigned)(o - 2 * sv * P.Lx) * bs;
+  const double m4o = st.sy[yo][R_M4][lane], m5o = wall_o ? 0.0 : st.sy[yo][R_M5][lane];
+  const double m4i = wall_i ? 0.0 : st.sy[yi][R_M4][lane];
+  const double m5i = wall_i ? 0.0 : st.sy[yi][R_M5][lane];
+  const double Af = cell_row(st, C_AF)[lane], AdF = cell_row(st, C_ADF)[lane];
+  const Half hu = axis_half(P.K, SU, false), hv = axis_half(P.M, sv, false);
+  const double v0 = vnode[hv.first], hstep = sv * P.dv;
+  const double h2 = -2.0 * hstep * hstep;
+  const double qx = expm1(h2 * st.sx[R_LAM][xo]);
+  const double qo = expm1(h2 * st.sy[yo][R_LAM][lane]);
+  const double qi = expm1(h2 * st.sy[yi][R_LAM][lane]);
+  const double qn = expm1(h2 * cell_row(st, C_LAMN)[lane]);
+  const double q1 = expm1(h2 * cell_row(st, C_LAM1)[lane]);
+  const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
+  const long long PS = P.PS;
+  for (int a = 0; a < hu.count; ++a) {
+    const int k = hu.first + a * hu.step;
+    const double u = P.uk[k];
+    const double au = fabs(u);
+    const double ucx = u * two_idx;
+    const UGKS_GLOBAL S* pl = plane_of(fin, P, k * P.M + hv.first);
+    UGKS_GLOBAL S* wpl = plane_of(fout, P, k * P.M + hv.first);
+    const long long pstep = hv.step * PS;
+    // the first node's stencil values, requested before the node's tables are formed
+    double fc = (double)ldb(pl, oc), fY = (double)ldb(pl, oY);
+    double fO = (double)ldb(pl, oO), fYY = (double)ldb(pl, oYY);
+    // x face: cubic in v times GC En(u), with |u| folded in
+    Cubic cx;
+    {
+      double e[9];
+      load_e(st.sx, xo, u > 0.0 ? 1 : -1, e);
+      const double d = u - st.sx[R_UX][xo];
+      const double En = st.sx[R_GC][xo] * exp(-st.sx[R_LAM][xo] * d * d) * au;
+      cx = cubic_in_ut(e, u);
+      cx.c0 *= En;
+      cx.c1 *= En;
+      cx.c2 *= En;
+      cx.c3 *= En;
+    }
+    const double m4xu = st.sx[R_M4][xo] * au, m5xu = st.sx[R_M5][xo] * au;
+    // the node's exponentials are formed one group at a time: interleaving them all would
+    // need more registers than the v loop leaves free
+    __builtin_amdgcn_sched_barrier(0);
+    // y faces: cubic in v at tangential u, times GC Et(u)
+    Cubic co, ci;
+    {
+      double e[9];
+      load_e(st.sy[yo], lane, sv, e);
+      const double d = u - st.sy[yo][R_UX][lane];
+      const double Et = wall_o ? 0.0 : st.sy[yo][R_GC][lane] * exp(-st.sy[yo][R_LAM][lane] * d * d);
+      co = cubic_in_un(e, u);
+      co.c0 *= Et;
+      co.c1 *= Et;
+      co.c2 *= Et;
+      co.c3 *= Et;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      double e[9];
+      load_e(st.sy[yi], lane, sv, e);
+      const double d = u - st.sy[yi][R_UX][lane];
+      const double Et = st.sy[yi][R_GC][lane] * exp(-st.sy[yi][R_LAM][lane] * d * d);
+      ci = cubic_in_un(e, u);
+      ci.c0 = wall_i ? Et : ci.c0 * Et;
+      ci.c1 = wall_i ? 0.0 : ci.c1 * Et;
+      ci.c2 = wall_i ? 0.0 : ci.c2 * Et;
+      ci.c3 = wall_i ? 0.0 : ci.c3 * Et;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // g^n and g^{n+1}: u factors with the Eq. (3) weights
+    double cun, cu1;
+    {
+      const double dn = u - cell_row(st, C_UN)[lane], d1 = u - cell_row(st, C_U1)[lane];
+      cun = cell_row(st, C_AN)[lane] * exp(-cell_row(st, C_LAMN)[lane] * dn * dn);
+      cu1 = cell_row(st, C_A1)[lane] * exp(-cell_row(st, C_LAM1)[lane] * d1 * d1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // v-direction Gaussians at the first node of the half and their ratios
+    double ex, rx, eo, ro, ei, ri, en, rn, e1, r1;
+    {
+      auto start = [&](double lam, double c, double& e, double& r) {
+        const double d = v0 - c;
+        e = exp(-lam * d * d);
+        r = exp(-lam * hstep * (2.0 * d + hstep));
+        __builtin_amdgcn_sched_barrier(0);
+      };
+      start(st.sx[R_LAM][xo], st.sx[R_VY][xo], ex, rx);
+      start(st.sy[yo][R_LAM][lane], st.sy[yo][R_VY][lane], eo, ro);
+      start(st.sy[yi][R_LAM][lane], st.sy[yi][R_VY][lane], ei, ri);
+      start(cell_row(st, C_LAMN)[lane], cell_row(st, C_VN)[lane], en, rn);
+      start(cell_row(st, C_LAM1)[lane], cell_row(st, C_V1)[lane], e1, r1);
+    }
+    for (int c = 0; c < hv.count; ++c) {
+      const double vv = vnode[hv.first + c * hv.step];
+      // next node's stencil values (the last node reloads its own)
+      const UGKS_GLOBAL S* pn1 = c + 1 < hv.count ? pl + pstep : pl;
+      const double nfc = (double)ldb(pn1, oc), nfY = (double)ldb(pn1, oY);
+      const double nfO = (double)ldb(pn1, oO), nfYY = (double)ldb(pn1, oYY);
+      const double av = fabs(vv);
+      const double avcy = av * two_idy;
+      // this cell: half-cell changes (x: signed; y: times sv)
+      const double fW = from_lower(fc), fE = from_upper(fc);
+      const double Hx = gm * half_limited(fE - fc, fc - fW);
+      const double Hy = gmy * half_limited(fO - fc, fc - fY);
+      const double D0 = fma(ucx, Hx, avcy * Hy);
+      const double fhx = SU > 0 ? fc + Hx : fc - Hx;
+      const double fhy = fc + Hy;
+      // upwind row's cell
+      const double fYw = from_lower(fY), fYe = from_upper(fY);
+      const double hxY = half_limited(fYe - fY, fY - fYw);
+      const double HyY = mY * half_limited(fc - fY, fY - fYY);
+      const double DY = fma(ucx, hxY, avcy * HyY);
+      const double fhY = fY + HyY;
+      // x: outgoing face of this lane, incoming from the upwind lane
+      const double Fxo = fma(ex, horner(cx, vv), fma(m4xu, fhx, -m5xu * D0));
+      const double Fxi = SU > 0 ? from_lower(Fxo) : from_upper(Fxo);
+      // y: outgoing and incoming faces
+      const double Fyo = av * fma(eo, horner(co, vv), fma(m4o, fhy, -m5o * D0));
+      const double Fyi = av * fma(ei, horner(ci, vv), fma(m4i, fhY, -m5i * DY));
+      const double g = fma(cu1, e1, cun * en);
+      const double f1 = fma(Af, fc, fma(AdF, (Fxi - Fxo) + (Fyi - Fyo), g));
+      if (valid)
+        *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(wpl) + oc) =
+            static_cast<S>(f1);
+      gauss_next(ex, rx, qx);
+      gauss_next(eo, ro, qo);
+      gauss_next(ei, ri, qi);
+      gauss_next(en, rn, qn);
+      gauss_next(e1, r1, q1);
+      pl = pn1;
+      wpl += pstep;
+      fc = nfc;
+      fY = nfY;
+      fO = nfO;
+      fYY = nfYY;
+    }
+  }
+}
+
 template <typename S>
-__global__ __launch_bounds__(kWave* kCellsPerBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(3)))
 void update_kernel(PlanView pv) {
-  extern __shared__ double lds[];
+  __shared__ Stage st;
+  extern __shared__ double vnode[];  // the v nodes of the largest instance of the plan
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int cpb = (int)(blockDim.x >> 6);
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int ii = find_inst(pv.off_upd, pv.ninst, b);
   const Inst* __restrict__ I = inst_at(pv, ii);
@@ -853,251 +934,81 @@ void update_kernel(PlanView pv) {
   const int parity = (I->cur + pv.step) & 1;
   const UGKS_GLOBAL S* fin = static_cast<const UGKS_GLOBAL S*>(I->f[parity]);
   UGKS_GLOBAL S* fout = static_cast<UGKS_GLOBAL S*>(I->f[parity ^ 1]);
-  const UGKS_GLOBAL S* fg = static_cast<const UGKS_GLOBAL S*>(I->fg);
   const UGKS_GLOBAL double* recx = I->recx;
   const UGKS_GLOBAL double* recy = I->recy;
   UGKS_GLOBAL double* W = I->W;
-  // LDS: the block's node tables u_k (K + 1 entries) and v_m (M + 1), zero in the padding
-  // entries, then the per-cell tables (8-byte aligned)
-  double* tuu = lds;
-  double* tvv = lds + (P.K + 1);
-  double* tb = lds + node_doubles(P.K, P.M) + (size_t)wv * (size_t)(pv.lds_per_cell / 8);
-  double* urow = tb;                        // rows k = 0..K
-  double* vrow = tb + kRow * (P.K + 1);     // rows m = 0..M
-  for (int e = threadIdx.x; e < P.K + P.M + 2; e += blockDim.x)
-    tuu[e] = e < P.K ? P.uk[e] : ((e > P.K && e < P.K + 1 + P.M) ? P.vm[e - P.K - 1] : 0.0);
-  const int c = (b - first_block(pv.off_upd, ii)) * cpb + wv;
-  const bool active = c < P.nx * P.ny;
-  int i, j;
-  band_order(active ? c : 0, P.nx, P.ny, kBand, i, j);
-  const int cc = j * P.nx + i;
+  const int L = b - first_block(pv.off_upd, ii);
+  const int t = L / P.ny, j = L - t * P.ny;
+  const int i0 = t * kTileU;
+  const int i = i0 - kHalo + lane;
+  const bool valid = lane >= kHalo && lane < kHalo + kTileU && i < P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
-  const UGKS_GLOBAL double* rl = recx + ((size_t)j * (P.nx + 1) + i) * kRec;
-  const UGKS_GLOBAL double* rr = recx + ((size_t)j * (P.nx + 1) + i + 1) * kRec;
-  const UGKS_GLOBAL double* rb = recy + ((size_t)j * P.nx + i) * kRec;
-  const UGKS_GLOBAL double* rt = recy + ((size_t)(j + 1) * P.nx + i) * kRec;
-  // Eq. (4)
-  double Wn[4], W1[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    Wn[q] = W[4 * (size_t)cc + q];
-    W1[q] = Wn[q] + (rl[q] - rr[q] + rb[q] - rt[q]) / P.area;
-  }
-  Prim pn{}, p1{};
-  // Eq. (3) solved for f^{n+1}: f1 = Af f + AdF dF + (A1 g^{n+1} + An g^n), the weights of
-  // g folded into its tables
-  double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
-  if (!P.collisionless) {
-    const bool ok = prim_of(Wn, pn) && prim_of(W1, p1);
-    if (!ok && lane == 0 && active) *P.flag = 1;
-    const double tn = collision_time(pn, P.mu_ref), t1 = collision_time(p1, P.mu_ref);
-    const double hdt = 0.5 * P.dt;
-    const double den = 1.0 / (1.0 + hdt / t1);
-    Af = (1.0 - hdt / tn) * den;
-    AdF = den / P.area;
-    A1 = (p1.rho * p1.lam / kPi) * (hdt / t1) * den;
-    An = (pn.rho * pn.lam / kPi) * (hdt / tn) * den;
-  }
-  // poly tables of the two x-faces (normal node k) and the two y-faces (normal node m)
-  for (int e = lane; e < 2 * P.K + 2 * P.M; e += kWave) {
-    double* out;
-    const UGKS_GLOBAL double* rs;
-    double un, lamf, U0;
-    if (e < 2 * P.K) {
-      const int side = e / P.K, k = e - side * P.K;
-      rs = side ? rr : rl;
-      un = P.uk[k];
-      U0 = rs[R_UX];
-      out = urow + kRow * k + (side ? RP_HI : RP_LO);
-    } else {
-      const int e2 = e - 2 * P.K;
-      const int side = e2 / P.M, m = e2 - side * P.M;
-      rs = side ? rt : rb;
-      un = P.vm[m];
-      U0 = rs[R_VY];
-      out = vrow + kRow * m + (side ? RP_HI : RP_LO);
-    }
-    lamf = rs[R_LAM];
-    if (rs[R_KIND] == (double)K_WALL) {
-      // wall: only the Maxwellian itself (P = 1), scaled by dx dt rho_w lambda_w / pi
-      const double d = un - U0;
-      out[0] = exp(-lamf * d * d) * rs[R_GC];
-      out[1] = out[2] = out[3] = 0.0;
-    } else {
-      double tmp[4];
-      face_poly(rs, un, lamf, U0, tmp);
-      out[0] = tmp[0];
-      out[1] = tmp[1];
-      out[2] = tmp[2];
-      out[3] = tmp[3];
+  const bool ghost_lane = chan && (i == -1 || i == P.nx);
+  const int o = pidx(P, i < P.nx + 1 ? i : P.nx + 1, j);
+  // stage the records of the segment's faces (x faces i0-2 .. i0+62, y faces below / above
+  // lanes 0..63; indices clamped into the mesh for lanes outside it)
+  for (int e = threadIdx.x; e < (kWave + 1) * kRec; e += blockDim.x) {
+    const int fc = e / kRec, fld = e - fc * kRec;
+    if (fld < kStage) {
+      const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
+      st.sx[fld][fc] = recx[((size_t)j * (P.nx + 1) + fi) * kRec + fld];
     }
   }
-  // tangential tables of the faces and the two factors of g^n and g^{n+1}
-  for (int e = lane; e < 4 * (P.K + P.M); e += kWave) {
-    double lam, vel, c0, coef = 1.0;
-    double* dst;
-    if (e < 2 * P.M) {  // x-faces: tangential v
-      const int side = e / P.M, m = e - side * P.M;
-      const UGKS_GLOBAL double* rs = side ? rr : rl;
-      lam = rs[R_LAM];
-      vel = P.vm[m];
-      c0 = rs[R_VY];
-      dst = vrow + kRow * m + (side ? RE_HI : RE_LO);
-    } else if (e < 2 * P.M + 2 * P.K) {  // y-faces: tangential u
-      const int e2 = e - 2 * P.M;
-      const int side = e2 / P.K, k = e2 - side * P.K;
-      const UGKS_GLOBAL double* rs = side ? rt : rb;
-      lam = rs[R_LAM];
-      vel = P.uk[k];
-      c0 = rs[R_UX];
-      dst = urow + kRow * k + (side ? RE_HI : RE_LO);
-    } else {  // g^n, g^{n+1}: u factor carries the Eq. (3) weight
-      const int e3 = e - 2 * P.M - 2 * P.K;
-      const int which = e3 / (P.K + P.M), r = e3 - which * (P.K + P.M);
-      lam = which ? p1.lam : pn.lam;
-      if (r < P.K) {
-        vel = P.uk[r];
-        c0 = which ? p1.U : pn.U;
-        coef = which ? A1 : An;
-        dst = urow + kRow * r + (which ? RG_1 : RG_N);
-      } else {
-        vel = P.vm[r - P.K];
-        c0 = which ? p1.V : pn.V;
-        dst = vrow + kRow * (r - P.K) + (which ? RG_1 : RG_N);
-      }
+  for (int e = threadIdx.x; e < 2 * kWave * kRec; e += blockDim.x) {
+    const int side = e / (kWave * kRec), r = e - side * (kWave * kRec);
+    const int fc = r / kRec, fld = r - fc * kRec;
+    if (fld < kStage) {
+      const int fi = clampi(i0 - kHalo + fc, 0, P.nx - 1);
+      st.sy[side][fld][fc] = recy[((size_t)(j + side) * P.nx + fi) * kRec + fld];
     }
-    const double d = vel - c0;
-    *dst = coef * exp(-lam * d * d);
   }
-  // the zero rows of the padding slots
-  for (int e = lane; e < 2 * kRow; e += kWave)
-    (e < kRow ? urow + kRow * P.K : vrow + kRow * P.M)[e % kRow] = 0.0;
+  for (int e = threadIdx.x; e < P.M; e += blockDim.x) vnode[e] = P.vm[e];
   __syncthreads();
-  if (!active) return;
-  const double m4l = rl[R_M4], m5l = rl[R_M5], m4r = rr[R_M4], m5r = rr[R_M5];
-  const double m4b = rb[R_M4], m5b = rb[R_M5], m4t = rt[R_M4], m5t = rt[R_M5];
-  const bool wall_b = chan && j == 0, wall_t = chan && j == P.ny - 1;
-  const bool wall_row = wall_b || wall_t;
-  const bool ghost_w = chan && i == 0, ghost_e = chan && i == P.nx - 1;
-  const bool s_wallrow = chan && (j - 1 == 0);
-  const bool n_wallrow = chan && (j + 1 == P.ny - 1);
-  const int js = wrap(j - 1, P.ny), jn = wrap(j + 1, P.ny);
-  UpdateCtx<S> X;
-  X.f0 = fin + (size_t)cc * P.NVP;
-  X.xw = xslab(P, fin, fg, i - 1, j);
-  X.xe = xslab(P, fin, fg, i + 1, j);
-  X.xww = xslab(P, fin, fg, i - 2, j);
-  X.xee = xslab(P, fin, fg, i + 2, j);
-  X.sw = xslab(P, fin, fg, i - 1, js);
-  X.sc = xslab(P, fin, fg, i, js);
-  X.se = xslab(P, fin, fg, i + 1, js);
-  X.nw = xslab(P, fin, fg, i - 1, jn);
-  X.nc = xslab(P, fin, fg, i, jn);
-  X.ne = xslab(P, fin, fg, i + 1, jn);
-  X.scc = fin + ((size_t)wrap(j - 2, P.ny) * P.nx + i) * P.NVP;
-  X.ncc = fin + ((size_t)wrap(j + 2, P.ny) * P.nx + i) * P.NVP;
-  UGKS_GLOBAL S* fo = fout + (size_t)cc * P.NVP;
-  const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
-  const int nch = P.NVP / kWave;
-  // The chunk loop, compiled twice: for cells next to a ghost column or a wall (EDGE) and for
-  // the interior, where every boundary switch is constant false.
-  auto chunks = [&](auto edge_c) {
-    constexpr bool EDGE = decltype(edge_c)::value;
-    const bool gw = EDGE && ghost_w, ge = EDGE && ghost_e, wr = EDGE && wall_row;
-    const bool wb = EDGE && wall_b, wt = EDGE && wall_t;
-    const bool swr = EDGE && s_wallrow, nwr = EDGE && n_wallrow;
-    // one chunk; MIXED: its lanes have both signs of u or of v, so the upwind neighbours'
-    // far slabs are chosen per lane (otherwise per chunk, in scalar registers)
-    auto chunk = [&](auto mixed_c, int ch, int su, int sv) {
-      constexpr bool MIXED = decltype(mixed_c)::value;
-      const unsigned v = (unsigned)(ch * kWave + lane);
-      const unsigned vb = v * (unsigned)sizeof(S);
-      // all stencil values of the chunk are requested before any is used
-      const int kmv = ldb(P.km, v * 4u);
-      const double fc = (double)ldb(X.f0, vb);
-      const double fW = (double)ldb(X.xw, vb), fE = (double)ldb(X.xe, vb);
-      const double fS = (double)ldb(X.sc, vb), fN = (double)ldb(X.nc, vb);
-      double xxx, xxn, xxs, yyy, yye, yyw;
-      if (!MIXED) {
-        const UGKS_GLOBAL S* pxx = su > 0 ? X.xww : X.xee;
-        const UGKS_GLOBAL S* pxn = su > 0 ? X.nw : X.ne;
-        const UGKS_GLOBAL S* pxs = su > 0 ? X.sw : X.se;
-        const UGKS_GLOBAL S* pyy = sv > 0 ? X.scc : X.ncc;
-        const UGKS_GLOBAL S* pye = sv > 0 ? X.se : X.ne;
-        const UGKS_GLOBAL S* pyw = sv > 0 ? X.sw : X.nw;
-        xxx = (double)ldb(pxx, vb);
-        xxn = (double)ldb(pxn, vb);
-        xxs = (double)ldb(pxs, vb);
-        yyy = (double)ldb(pyy, vb);
-        yye = (double)ldb(pye, vb);
-        yyw = (double)ldb(pyw, vb);
-      }
-      const int k = kmv & 0xffff, m = kmv >> 16;
-      const double u = tuu[k], vv = tvv[m];
-      if (MIXED) {
-        const bool r = su > 0 || (su == 0 && u > 0.0);
-        const bool t = sv > 0 || (sv == 0 && vv > 0.0);
-        xxx = (double)ldb(r ? X.xww : X.xee, vb);
-        xxn = (double)ldb(r ? X.nw : X.ne, vb);
-        xxs = (double)ldb(r ? X.sw : X.se, vb);
-        yyy = (double)ldb(t ? X.scc : X.ncc, vb);
-        yye = (double)ldb(t ? X.se : X.ne, vb);
-        yyw = (double)ldb(t ? X.sw : X.nw, vb);
-      }
-      const double hx0 = half_limited(fE - fc, fc - fW);
-      const double hyl = half_limited(fN - fc, fc - fS);
-      const double hy0 = wr ? 0.0 : hyl;
-      const double ucx = u * two_idx, vcy = vv * two_idy;
-      const double D0 = fma(ucx, hx0, vcy * hy0);
-      const double* ur = urow + kRow * k;
-      const double* vr = vrow + kRow * m;
-      const double* lp = ur + RP_LO;
-      const double* rp = ur + RP_HI;
-      const double* bp = vr + RP_LO;
-      const double* tp = vr + RP_HI;
-      const double le = vr[RE_LO], re = vr[RE_HI];
-      const double be = ur[RE_LO], te = ur[RE_HI];
-      double dFx, dFy;
-      if (su > 0)
-        dFx = x_part<1>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, gw, ge, wr, lp, rp,
-                        le, re, m4l, m5l, m4r, m5r);
-      else if (su < 0)
-        dFx = x_part<-1>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, gw, ge, wr, lp, rp,
-                         le, re, m4l, m5l, m4r, m5r);
-      else
-        dFx = x_part<0>(u, vv, ucx, vcy, fc, fW, fE, xxx, xxn, xxs, hx0, D0, gw, ge, wr, lp, rp,
-                        le, re, m4l, m5l, m4r, m5r);
-      if (sv > 0)
-        dFy = y_part<1>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wb, wt, swr, nwr,
-                        bp, tp, be, te, m4b, m5b, m4t, m5t);
-      else if (sv < 0)
-        dFy = y_part<-1>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wb, wt, swr, nwr,
-                         bp, tp, be, te, m4b, m5b, m4t, m5t);
-      else
-        dFy = y_part<0>(u, vv, ucx, vcy, fc, fS, fN, yyy, yye, yyw, hy0, D0, wb, wt, swr, nwr,
-                        bp, tp, be, te, m4b, m5b, m4t, m5t);
-      const double g = fma(ur[RG_1], vr[RG_1], ur[RG_N] * vr[RG_N]);
-      const double f1 = fma(Af, fc, fma(AdF, dFx + dFy, g));
-      *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(fo) + vb) =
-          static_cast<S>(f1);
-    };
-    for (int ch = 0; ch < nch; ++ch) {
-      const int code = P.chunk_sign[ch];
-      const int su = chunk_sign_u(code), sv = chunk_sign_v(code);
-      if (su != 0 && sv != 0)
-        chunk(std::false_type{}, ch, su, sv);
-      else
-        chunk(std::true_type{}, ch, su, sv);
-    }
-  };
-  if (ghost_w || ghost_e || wall_row || s_wallrow || n_wallrow)
-    chunks(std::true_type{});
-  else
-    chunks(std::false_type{});
-  if (lane == 0) {
+  if (q == 0) {
+    // Eq. (4), and the cell's Maxwellians of W^n and W^{n+1} with the weights of Eq. (3)
+    // solved for f^{n+1}: f1 = Af f + AdF dF + (A1 g^{n+1} + An g^n)
+    const size_t cc = (size_t)j * P.nx + (valid ? i : 0);
+    double Wn[4] = {1.0, 0.0, 0.0, 1.0}, W1[4];
+    if (valid) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) W[4 * (size_t)cc + q] = W1[q];
+      for (int r = 0; r < 4; ++r) Wn[r] = W[4 * cc + r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double dW = (st.sx[R_FX + r][lane] - st.sx[R_FX + r][lane + 1] +
+                         st.sy[0][R_FX + r][lane] - st.sy[1][R_FX + r][lane]) /
+                        P.area;
+      W1[r] = valid ? Wn[r] + dW : Wn[r];
+    }
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W[4 * cc + r] = W1[r];
+    }
+    Prim pn{}, p1{};
+    double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
+    if (!P.collisionless) {
+      const bool ok = prim_of(Wn, pn) && prim_of(W1, p1);
+      if (!ok && valid) *P.flag = 1;
+      const double tn = collision_time(pn, P.mu_ref), t1 = collision_time(p1, P.mu_ref);
+      const double hdt = 0.5 * P.dt;
+      const double den = 1.0 / (1.0 + hdt / t1);
+      Af = (1.0 - hdt / tn) * den;
+      AdF = den / P.area;
+      A1 = (p1.rho * p1.lam / kPi) * (hdt / t1) * den;
+      An = (pn.rho * pn.lam / kPi) * (hdt / tn) * den;
+    }
+    // every read of the flux fields by this wavefront is complete before they are reused
+    __builtin_amdgcn_wave_barrier();
+    const double cell[C_COUNT] = {pn.lam, pn.U, pn.V, p1.lam, p1.U, p1.V, An, A1, Af, AdF};
+#pragma unroll
+    for (int n = 0; n < C_COUNT; ++n) cell_row(st, n)[lane] = cell[n];
   }
+  __syncthreads();
+  const int sv = quad_sv(q);
+  if (quad_su(q) > 0)
+    update_quadrant<S, 1>(P, st, vnode, lane, sv, j, valid, ghost_lane, fin, fout, o);
+  else
+    update_quadrant<S, -1>(P, st, vnode, lane, sv, j, valid, ghost_lane, fin, fout, o);
 }
 
 }  // namespace
@@ -1117,35 +1028,24 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   int* off[5];
   for (int a = 0; a < 5; ++a) off[a] = reinterpret_cast<int*>(h + inst_bytes + a * off_bytes);
   PlanTotals t{};
-  // update kernel: cells per workgroup limited by the (nu + 1) + (nv + 1) table rows per cell
-  int max_cell = 0, max_nodes = 0, max_sums = 0;
-  for (int q = 0; q < n; ++q) {
-    const int K = insts[q].P.K, M = insts[q].P.M;
-    const int bytes = tab_doubles(K, M) * 8;
-    max_cell = bytes > max_cell ? bytes : max_cell;
-    max_nodes = node_doubles(K, M) * 8 > max_nodes ? node_doubles(K, M) * 8 : max_nodes;
-    const int sums = (kCellsPerBlock * 16 * kRedRow + 2 * (K + 1) + 2 * (M + 1)) * 8;
-    max_sums = sums > max_sums ? sums : max_sums;
-  }
-  int cpb = kCellsPerBlock;
-  while (cpb > 1 && (size_t)max_nodes + (size_t)max_cell * cpb > 64 * 1024) cpb /= 2;
-  t.cpb_upd = cpb;
-  t.lds_per_cell = max_cell;
-  t.lds_upd = max_nodes + max_cell * cpb;
-  t.lds_sums = max_sums;
   for (int q = 0; q < n; ++q) {
     const KParams& P = insts[q].P;
-    const int nc = P.nx * P.ny;
     const int nf = P.ny * (P.nx + 1) + (P.ny + 1) * P.nx;
     off[0][q] = t.sums;
     off[1][q] = t.upd;
     off[2][q] = t.face;
     off[3][q] = t.ghost;
     off[4][q] = 0;
-    t.sums += (nc + kCellsPerBlock - 1) / kCellsPerBlock;
-    t.upd += (nc + cpb - 1) / cpb;
+    t.sums += ((P.nx + kTileS - 1) / kTileS) * P.ny;
+    t.upd += ((P.nx + kTileU - 1) / kTileU) * P.ny;
+    t.max_m = P.M > t.max_m ? P.M : t.max_m;
     t.face += (nf + 255) / 256;
-    t.ghost += P.bc == UGKS_BC_CHANNEL ? 2 * P.ny : 0;
+    if (P.bc == UGKS_BC_CHANNEL) {
+      t.ghost += 2 * P.ny;
+    } else {
+      const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
+      t.ghost += (int)((frame * P.NV + kWave - 1) / kWave);
+    }
   }
   off[0][n] = t.sums;
   off[1][n] = t.upd;
@@ -1159,16 +1059,15 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   view->off_ghost = reinterpret_cast<const int*>(d + inst_bytes + 3 * off_bytes);
   view->ninst = n;
   view->step = 0;
-  view->cpb_upd = cpb;
-  view->lds_per_cell = max_cell;
   return t;
 }
 
-hipError_t launch_init(const PlanView& pv, int fp32, int ncells, hipStream_t s) {
+hipError_t launch_init(const PlanView& pv, int fp32, long long nvalues, hipStream_t s) {
+  const unsigned blocks = (unsigned)((nvalues + 255) / 256);
   if (fp32)
-    init_kernel<float><<<(unsigned)ncells, kWave, 0, s>>>(pv);
+    init_kernel<float><<<blocks, 256, 0, s>>>(pv);
   else
-    init_kernel<double><<<(unsigned)ncells, kWave, 0, s>>>(pv);
+    init_kernel<double><<<blocks, 256, 0, s>>>(pv);
   return hipGetLastError();
 }
 
@@ -1185,21 +1084,18 @@ hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int p
       break;
     case 1:
       if (fp32)
-        sums_kernel<float><<<(unsigned)t.sums, kWave * kCellsPerBlock, t.lds_sums, s>>>(pv);
+        sums_kernel<float><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
       else
-        sums_kernel<double><<<(unsigned)t.sums, kWave * kCellsPerBlock, t.lds_sums, s>>>(pv);
+        sums_kernel<double><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
       break;
     case 2:
       faces_kernel<<<(unsigned)t.face, 256, 0, s>>>(pv);
       break;
-    default: {
-      const size_t lds = (size_t)t.lds_upd;
-      const unsigned threads = kWave * (unsigned)t.cpb_upd;
+    default:
       if (fp32)
-        update_kernel<float><<<(unsigned)t.upd, threads, lds, s>>>(pv);
+        update_kernel<float><<<(unsigned)t.upd, kWave * kQuads, 8 * (size_t)t.max_m, s>>>(pv);
       else
-        update_kernel<double><<<(unsigned)t.upd, threads, lds, s>>>(pv);
-    }
+        update_kernel<double><<<(unsigned)t.upd, kWave * kQuads, 8 * (size_t)t.max_m, s>>>(pv);
   }
   return hipGetLastError();
 }

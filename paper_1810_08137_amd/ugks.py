@@ -54,7 +54,7 @@ class ugks_opts(ctypes.Structure):
 
 class ugks_info(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nu", ctypes.c_int),
-                ("nv", ctypes.c_int), ("nv_stride", ctypes.c_int), ("precision", ctypes.c_int),
+                ("nv", ctypes.c_int), ("plane_stride", ctypes.c_int), ("precision", ctypes.c_int),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
                 ("tau_ref", ctypes.c_double), ("steps", ctypes.c_int64),
                 ("device_bytes", ctypes.c_size_t)]

@@ -198,8 +198,8 @@ def test_paper_mesh_m1(nvel):
 
 
 def test_largest_velocity_grid():
-    """nu + nv at the documented limit (582): the update kernel's per-cell tables then take
-    almost all of a workgroup's 64 KB of LDS (one cell per workgroup)."""
+    """291 x 291 velocities on a 3 x 2 channel: long Gauss recurrences along v (146 nodes per
+    half) and a single row segment per row."""
     case = _case(nx=3, ny=2, lx=1.5, ly=1.0, nu=291, nv=291, umax=12.0, vmax=12.0, kn=0.1,
                  bc=1, noise=0.02, seed=17)
     PR.run_and_compare(case, 3, label="291x291 velocities")
