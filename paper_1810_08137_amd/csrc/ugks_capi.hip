@@ -165,9 +165,9 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
     why = "umax and vmax must be positive and finite";
     return false;
   }
-  // a plane (cells and halo) is indexed with 32-bit offsets
-  if (((double)mesh->nx + 2 * kHalo) * ((double)mesh->ny + 2 * kHalo) > 2.0e9) {
-    why = "too many cells";
+  // the kernels address a plane (cells and halo) with 32-bit byte offsets
+  if (((double)mesh->nx + 2 * kHalo) * ((double)mesh->ny + 2 * kHalo) > (double)(1 << 28)) {
+    why = "too many cells: (nx + 4)(ny + 4) must not exceed 2^28";
     return false;
   }
   s.nx = mesh->nx;

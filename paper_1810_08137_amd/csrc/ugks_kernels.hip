@@ -32,7 +32,7 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kQuads = 4;                     // wavefronts per workgroup, one per quadrant
 constexpr int kTileS = kWave - 2;             // cells per moment-kernel wavefront
 constexpr int kTileU = kWave - 2 * kHalo;     // cells per update-kernel wavefront
-constexpr int kStage = 24;                    // record fields the update kernel stages in LDS
+constexpr int kStage = R_M5 + 1;              // record fields the update kernel stages in LDS
 
 // Quadrant q of a workgroup: sign of u and of v.  Around the cycle (+,+) (-,+) (-,-) (+,-)
 // neighbours share one sign, so each face side collects its sums from two adjacent waves.
@@ -63,6 +63,26 @@ template <typename S>
 __device__ __forceinline__ UGKS_GLOBAL S* plane_of(UGKS_GLOBAL S* f, const KParams& P, int p) {
   return f + (long long)p * P.PS;
 }
+// Buffer resource of one plane (base, size in bytes): loads at a per-lane 32-bit byte offset
+// from a scalar base, range-checked by the hardware.  Word 3 selects 32-bit data for the
+// untyped buffer instructions.
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const UGKS_GLOBAL S* plane,
+                                                             const KParams& P) {
+  return __builtin_amdgcn_make_buffer_rsrc(
+      (void*)plane, (short)0, (int)((unsigned long long)P.PS * sizeof(S)), 0x00020000);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
+  return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <typename S>
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return bload(r, off, S{});
+}
+
 // index of cell (i, j) in a plane; i and j may lie in the halo
 __device__ __forceinline__ int pidx(const KParams& P, int i, int j) {
   return (j + kHalo) * P.Lx + i + kHalo;
@@ -410,7 +430,11 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
 // Per cell: slopes and the outgoing moment sums of all four faces.  A workgroup takes one
 // segment of kTileS cells of one row (lanes hold the segment and one neighbour on each side);
 // wavefront q sums velocity quadrant q into the x face and the y face its particles leave
-// through.  The two partial sums of each face side meet in LDS at the end.
+// through.  Along one v line (u fixed) every sum is a combination of the running v moments
+//   F^n = sum_m w_m v^n f,  X^n = sum_m w_m v^n hx,  Y^n = sum_m w_m v^n hy
+// (hx, hy: half-cell changes; n up to 3, 3 and 4), with f_hat = f + s hx (or s hy) and
+// D = (2u/dx) hx + (2v/dy) hy; the 32 face sums take them in once per line.  The two partial
+// sums of each face side meet in LDS at the end.
 template <typename S>
 __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   __shared__ double red[4][16][kWave];
@@ -427,7 +451,9 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   const int i = t * kTileS - 1 + lane;
   const bool valid = lane >= 1 && lane <= kTileS && i < P.nx;
   const int o = pidx(P, i < P.nx + 1 ? i : P.nx + 1, j);
-  const int Lx = P.Lx;
+  const unsigned bs = (unsigned)sizeof(S);
+  const unsigned oc = (unsigned)o * bs, oS = (unsigned)(o - P.Lx) * bs;
+  const unsigned oN = (unsigned)(o + P.Lx) * bs;
   const double my = (P.bc == UGKS_BC_CHANNEL && (j == 0 || j == P.ny - 1)) ? 0.0 : 1.0;
   const int su = quad_su(q), sv = quad_sv(q);
   const Half hu = axis_half(P.K, su, true), hv = axis_half(P.M, sv, true);
@@ -439,24 +465,96 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     const int k = hu.first + a * hu.step;
     const double u = P.uk[k];
     const double wu = P.wk[k] * (u == 0.0 ? 0.5 : 1.0);
-    const double ucx = u * two_idx;
-    const UGKS_GLOBAL S* row = plane_of(f, P, k * P.M);
-    for (int c = 0; c < hv.count; ++c) {
+    const UGKS_GLOBAL S* line = plane_of(f, P, k * P.M);
+    double F0 = 0, F1 = 0, F2 = 0, F3 = 0, X0 = 0, X1 = 0, X2 = 0, X3 = 0;
+    double Y0 = 0, Y1 = 0, Y2 = 0, Y3 = 0, Y4 = 0;
+    struct Vals {
+      double c, s, n;
+    };
+    auto load = [&](int c) {
+      const __amdgpu_buffer_rsrc_t r =
+          plane_rsrc(line + (long long)(hv.first + c * hv.step) * P.PS, P);
+      return Vals{bload<S>(r, oc), bload<S>(r, oS), bload<S>(r, oN)};
+    };
+    auto node = [&](const Vals& x, int c) {
       const int m = hv.first + c * hv.step;
       const double vv = P.vm[m];
-      const double w = wu * P.wm[m] * (vv == 0.0 ? 0.5 : 1.0);
-      const UGKS_GLOBAL S* pl = row + (long long)m * P.PS;
-      const double fc = ldv(pl, o);
-      const double fS = ldv(pl, o - Lx);
-      const double fN = ldv(pl, o + Lx);
-      const double fW = from_lower(fc), fE = from_upper(fc);
-      const double hx = half_limited(fE - fc, fc - fW);
-      const double hy = my * half_limited(fN - fc, fc - fS);
-      const double D = fma(ucx, hx, (vv * two_idy) * hy);
-      const double c2h = 0.5 * fma(u, u, vv * vv);
-      add_side(ax, w, u, vv, c2h, su > 0 ? fc + hx : fc - hx, hy, D);
-      add_side(ay, w, vv, u, c2h, sv > 0 ? fc + hy : fc - hy, hx, D);
+      const double wv = P.wm[m] * (vv == 0.0 ? 0.5 : 1.0);
+      const double v2 = vv * vv, v3 = v2 * vv, v4 = v2 * v2;
+      const double fW = from_lower(x.c), fE = from_upper(x.c);
+      const double hx = half_limited(fE - x.c, x.c - fW);
+      const double hy = my * half_limited(x.n - x.c, x.c - x.s);
+      const double xf = wv * x.c, xx = wv * hx, xy = wv * hy;
+      F0 += xf;
+      F1 = fma(xf, vv, F1);
+      F2 = fma(xf, v2, F2);
+      F3 = fma(xf, v3, F3);
+      X0 += xx;
+      X1 = fma(xx, vv, X1);
+      X2 = fma(xx, v2, X2);
+      X3 = fma(xx, v3, X3);
+      Y0 += xy;
+      Y1 = fma(xy, vv, Y1);
+      Y2 = fma(xy, v2, Y2);
+      Y3 = fma(xy, v3, Y3);
+      Y4 = fma(xy, v4, Y4);
+    };
+    // two value sets, each node's loads issued one node ahead
+    Vals va = load(0);
+    int c = 0;
+    for (; c + 1 < hv.count; c += 2) {
+      const Vals vb = load(c + 1);
+      node(va, c);
+      va = load(c + 2 < hv.count ? c + 2 : c + 1);
+      node(vb, c + 1);
     }
+    if (c < hv.count) node(va, c);
+    // moments of the x-face reconstruction (S), the y-face one (R) and of D
+    const double ucx = u * two_idx, u2h = 0.5 * u * u, wuu = wu * u;
+    const double S0 = su > 0 ? F0 + X0 : F0 - X0, S1 = su > 0 ? F1 + X1 : F1 - X1;
+    const double S2 = su > 0 ? F2 + X2 : F2 - X2;
+    const double R0 = sv > 0 ? F0 + Y0 : F0 - Y0, R1 = sv > 0 ? F1 + Y1 : F1 - Y1;
+    const double R2 = sv > 0 ? F2 + Y2 : F2 - Y2, R3 = sv > 0 ? F3 + Y3 : F3 - Y3;
+    const double D0 = fma(ucx, X0, two_idy * Y1), D1 = fma(ucx, X1, two_idy * Y2);
+    const double D2 = fma(ucx, X2, two_idy * Y3), D3 = fma(ucx, X3, two_idy * Y4);
+    // x face: psi = (1, u, v, c2h), c2h = (u^2 + v^2)/2
+    const double cS = fma(u2h, S0, 0.5 * S2), cT = fma(u2h, Y0, 0.5 * Y2);
+    const double cD = fma(u2h, D0, 0.5 * D2);
+    ax[0] = fma(wu, S0, ax[0]);
+    ax[1] = fma(wuu, S0, ax[1]);
+    ax[2] = fma(wu, S1, ax[2]);
+    ax[3] = fma(wu, cS, ax[3]);
+    ax[4] = fma(wu, Y0, ax[4]);
+    ax[5] = fma(wuu, Y0, ax[5]);
+    ax[6] = fma(wu, Y1, ax[6]);
+    ax[7] = fma(wu, cT, ax[7]);
+    ax[8] = fma(wuu, S0, ax[8]);
+    ax[9] = fma(wuu * u, S0, ax[9]);
+    ax[10] = fma(wuu, S1, ax[10]);
+    ax[11] = fma(wuu, cS, ax[11]);
+    ax[12] = fma(wuu, D0, ax[12]);
+    ax[13] = fma(wuu * u, D0, ax[13]);
+    ax[14] = fma(wuu, D1, ax[14]);
+    ax[15] = fma(wuu, cD, ax[15]);
+    // y face: psi = (1, v, u, c2h)
+    const double cR = fma(u2h, R0, 0.5 * R2), cX = fma(u2h, X0, 0.5 * X2);
+    const double cR1 = fma(u2h, R1, 0.5 * R3), cD1 = fma(u2h, D1, 0.5 * D3);
+    ay[0] = fma(wu, R0, ay[0]);
+    ay[1] = fma(wu, R1, ay[1]);
+    ay[2] = fma(wuu, R0, ay[2]);
+    ay[3] = fma(wu, cR, ay[3]);
+    ay[4] = fma(wu, X0, ay[4]);
+    ay[5] = fma(wu, X1, ay[5]);
+    ay[6] = fma(wuu, X0, ay[6]);
+    ay[7] = fma(wu, cX, ay[7]);
+    ay[8] = fma(wu, R1, ay[8]);
+    ay[9] = fma(wu, R2, ay[9]);
+    ay[10] = fma(wuu, R1, ay[10]);
+    ay[11] = fma(wu, cR1, ay[11]);
+    ay[12] = fma(wu, D1, ay[12]);
+    ay[13] = fma(wu, D2, ay[13]);
+    ay[14] = fma(wuu, D1, ay[14]);
+    ay[15] = fma(wu, cD1, ay[15]);
   }
   // x faces: (+) from waves 0 and 3, (-) from 1 and 2; y faces: (+) from 0 and 1, (-) from
   // 2 and 3.  Waves 1 and 3 hand their sums over, waves 0 and 2 add and write.
@@ -676,6 +774,11 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
 struct Stage {
   double sx[kStage][kWave + 1];
   double sy[2][kStage][kWave];
+  // v-direction Gaussians (value, ratio) at the first node of each half of the v axis:
+  // g^n and g^{n+1} per half, the bottom and top faces per half, the x face per wavefront
+  double gs[2][4][kWave];
+  double ys[2][4][kWave];
+  double xs[kQuads][2][kWave];
 };
 // Once Eq. (4) is done the flux fields (R_FX..R_FX+3) are free: they then hold, per lane, the
 // cell's state for Eq. (3) (CellField n in row cell_row(n)).
@@ -761,7 +864,8 @@ __device__ __forceinline__ void load_e(const double (*st)[kWave], int col, int s
 // free transport of the wall row.
 template <typename S, int SU>
 __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& st,
-                                                const double* vnode, int lane, int sv, int j,
+                                                const double* vnode, int q, int lane, int sv,
+                                                int j,
                                                 bool valid, bool ghost_lane,
                                                 const UGKS_GLOBAL S* fin, UGKS_GLOBAL S* fout,
                                                 int o) {
@@ -787,7 +891,7 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
   const double m5i = wall_i ? 0.0 : st.sy[yi][R_M5][lane];
   const double Af = cell_row(st, C_AF)[lane], AdF = cell_row(st, C_ADF)[lane];
   const Half hu = axis_half(P.K, SU, false), hv = axis_half(P.M, sv, false);
-  const double v0 = vnode[hv.first], hstep = sv * P.dv;
+  const double hstep = sv * P.dv;
   const double h2 = -2.0 * hstep * hstep;
   const double qx = expm1(h2 * st.sx[R_LAM][xo]);
   const double qo = expm1(h2 * st.sy[yo][R_LAM][lane]);
@@ -795,18 +899,23 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
   const double qn = expm1(h2 * cell_row(st, C_LAMN)[lane]);
   const double q1 = expm1(h2 * cell_row(st, C_LAM1)[lane]);
   const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
-  const long long PS = P.PS;
   for (int a = 0; a < hu.count; ++a) {
     const int k = hu.first + a * hu.step;
     const double u = P.uk[k];
     const double au = fabs(u);
     const double ucx = u * two_idx;
-    const UGKS_GLOBAL S* pl = plane_of(fin, P, k * P.M + hv.first);
-    UGKS_GLOBAL S* wpl = plane_of(fout, P, k * P.M + hv.first);
-    const long long pstep = hv.step * PS;
+    const UGKS_GLOBAL S* line = plane_of(fin, P, k * P.M);
+    UGKS_GLOBAL S* wline = plane_of(fout, P, k * P.M);
+    struct Vals {
+      double c, y, o, yy;
+    };
+    auto load = [&](int c) {
+      const __amdgpu_buffer_rsrc_t r =
+          plane_rsrc(line + (long long)(hv.first + c * hv.step) * P.PS, P);
+      return Vals{bload<S>(r, oc), bload<S>(r, oY), bload<S>(r, oO), bload<S>(r, oYY)};
+    };
     // the first node's stencil values, requested before the node's tables are formed
-    double fc = (double)ldb(pl, oc), fY = (double)ldb(pl, oY);
-    double fO = (double)ldb(pl, oO), fYY = (double)ldb(pl, oYY);
+    Vals va = load(0);
     // x face: cubic in v times GC En(u), with |u| folded in
     Cubic cx;
     {
@@ -859,26 +968,16 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
     }
     __builtin_amdgcn_sched_barrier(0);
     // v-direction Gaussians at the first node of the half and their ratios
-    double ex, rx, eo, ro, ei, ri, en, rn, e1, r1;
-    {
-      auto start = [&](double lam, double c, double& e, double& r) {
-        const double d = v0 - c;
-        e = exp(-lam * d * d);
-        r = exp(-lam * hstep * (2.0 * d + hstep));
-        __builtin_amdgcn_sched_barrier(0);
-      };
-      start(st.sx[R_LAM][xo], st.sx[R_VY][xo], ex, rx);
-      start(st.sy[yo][R_LAM][lane], st.sy[yo][R_VY][lane], eo, ro);
-      start(st.sy[yi][R_LAM][lane], st.sy[yi][R_VY][lane], ei, ri);
-      start(cell_row(st, C_LAMN)[lane], cell_row(st, C_VN)[lane], en, rn);
-      start(cell_row(st, C_LAM1)[lane], cell_row(st, C_V1)[lane], e1, r1);
-    }
-    for (int c = 0; c < hv.count; ++c) {
-      const double vv = vnode[hv.first + c * hv.step];
-      // next node's stencil values (the last node reloads its own)
-      const UGKS_GLOBAL S* pn1 = c + 1 < hv.count ? pl + pstep : pl;
-      const double nfc = (double)ldb(pn1, oc), nfY = (double)ldb(pn1, oY);
-      const double nfO = (double)ldb(pn1, oO), nfYY = (double)ldb(pn1, oYY);
+    const int hf = sv > 0 ? 0 : 1;
+    double ex = st.xs[q][0][lane], rx = st.xs[q][1][lane];
+    double eo = st.ys[hf][2 * yo][lane], ro = st.ys[hf][2 * yo + 1][lane];
+    double ei = st.ys[hf][2 * yi][lane], ri = st.ys[hf][2 * yi + 1][lane];
+    double en = st.gs[hf][0][lane], rn = st.gs[hf][1][lane];
+    double e1 = st.gs[hf][2][lane], r1 = st.gs[hf][3][lane];
+    auto node = [&](const Vals& x, int c) {
+      const int m = hv.first + c * hv.step;
+      const double vv = vnode[m];
+      const double fc = x.c, fY = x.y, fO = x.o, fYY = x.yy;
       const double av = fabs(vv);
       const double avcy = av * two_idy;
       // this cell: half-cell changes (x: signed; y: times sv)
@@ -903,20 +1002,24 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
       const double g = fma(cu1, e1, cun * en);
       const double f1 = fma(Af, fc, fma(AdF, (Fxi - Fxo) + (Fyi - Fyo), g));
       if (valid)
-        *reinterpret_cast<UGKS_GLOBAL S*>(reinterpret_cast<UGKS_GLOBAL char*>(wpl) + oc) =
+        *reinterpret_cast<UGKS_GLOBAL S*>(
+            reinterpret_cast<UGKS_GLOBAL char*>(wline + (long long)m * P.PS) + oc) =
             static_cast<S>(f1);
       gauss_next(ex, rx, qx);
       gauss_next(eo, ro, qo);
       gauss_next(ei, ri, qi);
       gauss_next(en, rn, qn);
       gauss_next(e1, r1, q1);
-      pl = pn1;
-      wpl += pstep;
-      fc = nfc;
-      fY = nfY;
-      fO = nfO;
-      fYY = nfYY;
+    };
+    // two value sets, each node's loads issued one node ahead
+    int c = 0;
+    for (; c + 1 < hv.count; c += 2) {
+      const Vals vb = load(c + 1);
+      node(va, c);
+      va = load(c + 2 < hv.count ? c + 2 : c + 1);
+      node(vb, c + 1);
     }
+    if (c < hv.count) node(va, c);
   }
 }
 
@@ -1005,10 +1108,32 @@ void update_kernel(PlanView pv) {
   }
   __syncthreads();
   const int sv = quad_sv(q);
+  {
+    // Gauss starts: wavefront q takes its x face and, for the half of v its sign selects,
+    // g^n and g^{n+1} (q = 0, 2) or the two y faces (q = 1, 3)
+    const int hf = sv > 0 ? 0 : 1;
+    const double hstep = sv * P.dv;
+    const double v0 = vnode[sv > 0 ? P.M / 2 : P.M / 2 - 1];
+    auto start = [&](double lam, double c, double* e, double* r) {
+      const double d = v0 - c;
+      e[lane] = exp(-lam * d * d);
+      r[lane] = exp(-lam * hstep * (2.0 * d + hstep));
+    };
+    const int xo = lane + (quad_su(q) > 0 ? 1 : 0);
+    start(st.sx[R_LAM][xo], st.sx[R_VY][xo], st.xs[q][0], st.xs[q][1]);
+    if (q == 0 || q == 2) {
+      start(cell_row(st, C_LAMN)[lane], cell_row(st, C_VN)[lane], st.gs[hf][0], st.gs[hf][1]);
+      start(cell_row(st, C_LAM1)[lane], cell_row(st, C_V1)[lane], st.gs[hf][2], st.gs[hf][3]);
+    } else {
+      start(st.sy[0][R_LAM][lane], st.sy[0][R_VY][lane], st.ys[hf][0], st.ys[hf][1]);
+      start(st.sy[1][R_LAM][lane], st.sy[1][R_VY][lane], st.ys[hf][2], st.ys[hf][3]);
+    }
+  }
+  __syncthreads();
   if (quad_su(q) > 0)
-    update_quadrant<S, 1>(P, st, vnode, lane, sv, j, valid, ghost_lane, fin, fout, o);
+    update_quadrant<S, 1>(P, st, vnode, q, lane, sv, j, valid, ghost_lane, fin, fout, o);
   else
-    update_quadrant<S, -1>(P, st, vnode, lane, sv, j, valid, ghost_lane, fin, fout, o);
+    update_quadrant<S, -1>(P, st, vnode, q, lane, sv, j, valid, ghost_lane, fin, fout, o);
 }
 
 }  // namespace
