@@ -42,7 +42,8 @@ extern "C" {
 #define UGKS_E_INVAL (-1)  /* invalid argument (NULL pointer, size, range, inconsistent option) */
 #define UGKS_E_NOMEM (-2)  /* device or host allocation failed, or the workspace is too small */
 #define UGKS_E_DEVICE (-3) /* a HIP runtime call or kernel launch failed */
-#define UGKS_E_STATE (-4)  /* the solution holds NaN, rho <= 0 or T <= 0 */
+#define UGKS_E_STATE (-4)  /* the solution holds NaN, rho <= 0 or T <= 0, or a Maxwellian
+                              whose speed ratio |V| / T^(1/2) along v exceeds about 26 */
 #define UGKS_E_BUSY (-5)   /* the handle is in use by another call */
 
 typedef struct ugks_handle ugks_handle;

@@ -185,16 +185,17 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
 // Offsets of every buffer inside the workspace.
 Layout layout_of(const Shape& s, int prec) {
   const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
-  const size_t sizes[13] = {
+  const size_t sizes[14] = {
       (size_t)s.NV * s.PS * ss,                 // f0: NV planes
       (size_t)s.NV * s.PS * ss,                 // f1
-      s.nc * 4 * 8,                             // W
+      s.nc * 4 * 8,                             // W0
+      s.nc * 4 * 8,                             // W1
       2 * (size_t)s.ny * 4 * 8,                 // Wg
-      s.nc * kSlots * 8,                        // hs
+      (size_t)velocity_chunks(s.nx, s.ny, s.K) * s.nc * kSlots * 8,  // hs: partial sums
       2 * (size_t)s.ny * 16 * 8,                // hsg
       (size_t)s.ny * (s.nx + 1) * kRec * 8,     // recx
       (size_t)(s.ny + 1) * s.nx * kRec * 8,     // recy
-      (size_t)(s.K + s.M) * 8,                  // wk, wm
+      (size_t)(s.K + 6 * s.M) * 8,              // wk, wm, vmom
       (size_t)s.K * 8,                          // uk
       (size_t)s.M * 8,                          // vm
       (size_t)s.ny * 8 + 64,                    // xi_in + flag
@@ -202,7 +203,7 @@ Layout layout_of(const Shape& s, int prec) {
   };
   Layout L{};
   size_t off = 0;
-  for (int b = 0; b < 13; ++b) {
+  for (int b = 0; b < 14; ++b) {
     L.off[b] = off;
     off += round_up(sizes[b], kAlign);
   }
@@ -215,18 +216,19 @@ void carve(ugks_handle* h, const Layout& L, const Shape& s) {
   Buffers& B = h->B;
   B.f[0] = base + L.off[0];
   B.f[1] = base + L.off[1];
-  B.W = reinterpret_cast<double*>(base + L.off[2]);
-  B.Wg = reinterpret_cast<double*>(base + L.off[3]);
-  B.hs = reinterpret_cast<double*>(base + L.off[4]);
-  B.hsg = reinterpret_cast<double*>(base + L.off[5]);
-  B.recx = reinterpret_cast<double*>(base + L.off[6]);
-  B.recy = reinterpret_cast<double*>(base + L.off[7]);
-  B.wk = reinterpret_cast<double*>(base + L.off[8]);
-  B.uk = reinterpret_cast<double*>(base + L.off[9]);
-  B.vm = reinterpret_cast<double*>(base + L.off[10]);
-  B.xi_in = reinterpret_cast<double*>(base + L.off[11]);
-  B.flag = reinterpret_cast<int*>(base + L.off[11] + round_up((size_t)s.ny * 8, 64));
-  h->plan_dev = base + L.off[12];
+  B.W[0] = reinterpret_cast<double*>(base + L.off[2]);
+  B.W[1] = reinterpret_cast<double*>(base + L.off[3]);
+  B.Wg = reinterpret_cast<double*>(base + L.off[4]);
+  B.hs = reinterpret_cast<double*>(base + L.off[5]);
+  B.hsg = reinterpret_cast<double*>(base + L.off[6]);
+  B.recx = reinterpret_cast<double*>(base + L.off[7]);
+  B.recy = reinterpret_cast<double*>(base + L.off[8]);
+  B.wk = reinterpret_cast<double*>(base + L.off[9]);
+  B.uk = reinterpret_cast<double*>(base + L.off[10]);
+  B.vm = reinterpret_cast<double*>(base + L.off[11]);
+  B.xi_in = reinterpret_cast<double*>(base + L.off[12]);
+  B.flag = reinterpret_cast<int*>(base + L.off[12] + round_up((size_t)s.ny * 8, 64));
+  h->plan_dev = base + L.off[13];
 }
 
 hipEvent_t pool_get(ugks_handle* h) {
@@ -357,6 +359,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   P.NV = s.NV;
   P.Lx = s.Lx;
   P.Ly = s.Ly;
+  P.gmax = velocity_chunks(s.nx, s.ny, s.K);
   P.PS = (long long)s.PS;
   P.bc = bc->kind;
   P.collisionless = std::isinf(kn) ? 1 : 0;
@@ -417,6 +420,16 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   Buffers& B = h->B;
   P.wk = gp(B.wk);
   P.wm = gp(B.wk + s.K);
+  P.vmom = gp(B.wk + s.K + s.M);
+  // moment-kernel weights w_m v_m^n; a node at v = 0 is visited by both halves of v
+  std::vector<double> vmom(5 * (size_t)s.M);
+  for (int m = 0; m < s.M; ++m) {
+    double w = wm[m] * (vm[m] == 0.0 ? 0.5 : 1.0);
+    for (int n = 0; n < 5; ++n) {
+      vmom[5 * (size_t)m + n] = w;
+      w *= vm[m];
+    }
+  }
   P.uk = gp(B.uk);
   P.vm = gp(B.vm);
   P.xi_in = gp(B.xi_in);
@@ -425,7 +438,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   I.P = P;
   I.f[0] = gp(B.f[0]);
   I.f[1] = gp(B.f[1]);
-  I.W = gp(B.W);
+  I.W[0] = gp(B.W[0]);
+  I.W[1] = gp(B.W[1]);
+  I.gsplit = 1;
   I.Wg = gp(B.Wg);
   I.hs = gp(B.hs);
   I.hsg = gp(B.hsg);
@@ -442,9 +457,10 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     size_t n;
   } copies[] = {
       {B.wk, wk.data(), wk.size() * 8},     {B.wk + s.K, wm.data(), wm.size() * 8},
+      {B.wk + s.K + s.M, vmom.data(), vmom.size() * 8},
       {B.uk, uk.data(), uk.size() * 8},     {B.vm, vm.data(), vm.size() * 8},
       {B.xi_in, xi.data(), xi.size() * 8},
-      {B.W, W0.data(), W0.size() * 8},          {h->plan_dev, plan_host.data(), plan_host.size()},
+      {B.W[0], W0.data(), W0.size() * 8},          {h->plan_dev, plan_host.data(), plan_host.size()},
   };
   int rc = UGKS_OK;
   for (auto& cp : copies) {
@@ -456,6 +472,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   }
   if (rc == UGKS_OK) {
     e = hipMemsetAsync(B.flag, 0, sizeof(int), h->stream);
+
     if (e != hipSuccess) rc = hip_fail(nullptr, e, "hipMemsetAsync of the state flag");
   }
   if (rc == UGKS_OK) {
@@ -499,7 +516,8 @@ int ugks_moments(ugks_handle* h, double* host_out) {
   const size_t nc = (size_t)h->P.nx * h->P.ny;
   std::vector<double> W(4 * nc);
   int flag = 0;
-  hipError_t e = hipMemcpyAsync(W.data(), h->B.W, W.size() * 8, hipMemcpyDeviceToHost, h->stream);
+  hipError_t e = hipMemcpyAsync(W.data(), h->B.W[h->steps & 1], W.size() * 8,
+                                hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(&flag, h->B.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -567,7 +585,7 @@ int ugks_get_state(ugks_handle* h, double* f, double* W) {
                        h->stream);
   }
   if (e == hipSuccess && W)
-    e = hipMemcpyAsync(W, h->B.W, nc * 4 * 8, hipMemcpyDeviceToHost, h->stream);
+    e = hipMemcpyAsync(W, h->B.W[h->steps & 1], nc * 4 * 8, hipMemcpyDeviceToHost, h->stream);
   int flag = 0;
   if (e == hipSuccess)
     e = hipMemcpyAsync(&flag, h->B.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
@@ -611,7 +629,7 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
                        h->stream);
   }
   if (e == hipSuccess && W)
-    e = hipMemcpyAsync(h->B.W, W, nc * 4 * 8, hipMemcpyHostToDevice, h->stream);
+    e = hipMemcpyAsync(h->B.W[h->steps & 1], W, nc * 4 * 8, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "writing the state");
   return UGKS_OK;

@@ -57,6 +57,7 @@ struct KParams {
   int nx, ny, K, M, NV;
   int Lx, Ly;       // padded row length and row count of a plane
   int bc, collisionless, inlet_fixed_u;
+  int gmax;         // velocity chunks per quadrant the moment-sum buffer has room for
   long long PS;     // values per plane
   double dx, dy, dt, inv_dx, inv_dy, area, mu_ref;
   double du, dv;    // node spacing of the uniform u and v grids
@@ -68,6 +69,7 @@ struct KParams {
   const UGKS_GLOBAL double* vm;    // [M]
   const UGKS_GLOBAL double* wk;    // [K] weights of the u nodes
   const UGKS_GLOBAL double* wm;    // [M] weights of the v nodes
+  const UGKS_GLOBAL double* vmom;  // [M][5] w_m v_m^n (n = 0..4), halved at v_m = 0
   const UGKS_GLOBAL double* xi_in;  // [ny] inlet noise
   UGKS_GLOBAL int* flag;           // device flag: set to 1 on an invalid state
 };
@@ -75,13 +77,14 @@ struct KParams {
 // Device buffers carved out of one workspace.
 struct Buffers {
   void* f[2];       // [NV][PS] storage type
-  double* W;        // [nx*ny][4]
+  double* W[2];     // [nx*ny][4], ping-pong with f
   double* Wg;       // [2][ny][4]
-  double* hs;       // [64][nx*ny]: sum q of face side s of cell c at (16 s + q) nx ny + c
+  double* hs;       // [gmax][64][nx*ny]: partial g of sum q of face side s of cell c at
+                    // ((g 64) + 16 s + q) nx ny + c
   double* hsg;      // [2][ny][16]
   double* recx;     // [ny][nx+1][32]
   double* recy;     // [ny+1][nx][32]
-  double* wk;       // [K], followed by wm [M]
+  double* wk;       // [K], followed by wm [M], then vmom [M][5]
   double* uk;       // [K]
   double* vm;       // [M]
   double* xi_in;    // [ny]
@@ -89,7 +92,7 @@ struct Buffers {
 };
 
 struct Layout {
-  size_t off[13];
+  size_t off[14];
   size_t total;
 };
 
@@ -98,14 +101,15 @@ struct Layout {
 struct Inst {
   KParams P;
   UGKS_GLOBAL void* f[2];
-  UGKS_GLOBAL double* W;
+  UGKS_GLOBAL double* W[2];
   UGKS_GLOBAL double* Wg;
   UGKS_GLOBAL double* hs;
   UGKS_GLOBAL double* hsg;
   UGKS_GLOBAL double* recx;
   UGKS_GLOBAL double* recy;
-  int cur;   // f[(cur + step) & 1] is read, the other buffer written
+  int cur;   // f[(cur + step) & 1] and W[(cur + step) & 1] are read, the others written
   int fp32;  // storage type of f
+  int gsplit;  // velocity chunks per quadrant (P.gmax; set by build_plan)
 };
 
 // A launch plan: instances plus, per kernel, the prefix sum of the workgroups each instance
@@ -113,21 +117,26 @@ struct Inst {
 // workgroup).  Device-resident; the kernels read it through PlanView.
 struct PlanView {
   const Inst* inst;
-  const int* off_sums;   // one workgroup per row segment of the moment kernel
-  const int* off_upd;    // one workgroup per row segment of the update kernel
+  const int* off_sums;   // one workgroup per (row segment, velocity chunk) of the moment kernel
+  const int* off_upd;    // one workgroup per (row segment, velocity chunk) of the update kernel
   const int* off_face;   // 256 faces per workgroup
   const int* off_ghost;  // channel: 2 ny workgroups; periodic: the halo frame of every plane
+  const int* off_red;    // chunk-sum workgroups (instances with more than one chunk)
   int ninst;
   int step;              // steps enqueued since the plan's `cur` values were taken
 };
 
 struct PlanTotals {
   int sums, upd, face, ghost;  // workgroups of each launch
+  int red;                     // workgroups of the chunk-sum launch (0: not launched)
   int max_m;                   // largest nv of the plan's instances
 };
 
 // Bytes of a device plan with n instances, and its host image (offsets into one buffer).
 size_t plan_bytes(int n);
+// Velocity chunks per quadrant of an instance: enough update workgroups to fill the GPU
+// when the instance runs alone, at least one u node per chunk and at most 16 chunks.
+int velocity_chunks(int nx, int ny, int K);
 // Build the host image of a plan for `n` instances into `buf` (plan_bytes(n) bytes) and return
 // the totals; `dev` is the device address the image will be copied to.
 PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, PlanView* view);

@@ -90,17 +90,18 @@ __device__ __forceinline__ int pidx(const KParams& P, int i, int j) {
 
 // ------------------------------------------------------------------ lane exchange
 // Whole-wavefront DPP shifts by one lane: lane l receives the value lane l - 1 holds
-// (from_lower) or lane l + 1 holds (from_upper); the edge lane keeps its own value.
+// (from_lower) or lane l + 1 holds (from_upper); the edge lane, which has no source, reads 0
+// (bound control), so no copy of an "old" value is needed.
 __device__ __forceinline__ double dpp_shift(double x, int ctrl_lower) {
   const long long b = __double_as_longlong(x);
   const int lo = (int)(unsigned)(b & 0xffffffffll), hi = (int)(b >> 32);
   int rlo, rhi;
   if (ctrl_lower) {
-    rlo = __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false);  // wave_shr:1
-    rhi = __builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false);
+    rlo = __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true);  // wave_shr:1
+    rhi = __builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true);
   } else {
-    rlo = __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false);  // wave_shl:1
-    rhi = __builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false);
+    rlo = __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true);  // wave_shl:1
+    rhi = __builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true);
   }
   return __longlong_as_double(((long long)rhi << 32) | (long long)(unsigned)rlo);
 }
@@ -282,6 +283,21 @@ __device__ __forceinline__ Half axis_half(int n, int s, bool share_zero) {
   return h;
 }
 
+// Nodes [a0, a1) of a half's node sequence taken by velocity chunk g of G.
+__device__ __forceinline__ void chunk_range(int count, int g, int G, int& a0, int& a1) {
+  a0 = (int)((long long)g * count / G);
+  a1 = (int)((long long)(g + 1) * count / G);
+}
+
+// Workgroup L of a cell kernel: row segment t, velocity chunk g, row j (rows fastest, so
+// that the workgroups an XCD runs at once are neighbouring rows of one chunk).
+__device__ __forceinline__ void cell_block(int L, int ny, int G, int& t, int& g, int& j) {
+  j = L % ny;
+  const int tg = L / ny;
+  t = tg / G;
+  g = tg - t * G;
+}
+
 // ------------------------------------------------------------------ launch plans
 typedef const Inst* __restrict__ inst_cptr;
 typedef const int* __restrict__ int_cptr;
@@ -316,7 +332,7 @@ __global__ __launch_bounds__(256) void init_kernel(PlanView pv) {
   const Inst* __restrict__ I = inst_at(pv, 0);
   const KParams P = I->P;
   UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[I->cur]);
-  const UGKS_GLOBAL double* W = I->W;
+  const UGKS_GLOBAL double* W = I->W[I->cur];
   const long long nc = (long long)P.nx * P.ny;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nc * P.NV) return;
@@ -331,22 +347,24 @@ __global__ __launch_bounds__(256) void init_kernel(PlanView pv) {
   stv(plane_of(f, P, p), pidx(P, i, j), g);
 }
 
-// Halo of the current f.  Channel: one wavefront per (side, row) writes the inlet (side 0)
+// Halo of the current f.  Channel: one workgroup per (side, row) writes the inlet (side 0)
 // or outlet (side 1) ghost Maxwellian into that row's ghost column of every plane and sums
 // its moments towards the domain (its slopes are zero); the other halo values stay zero.
 // Periodic: one thread per halo value of every plane copies the periodic image.
+constexpr int kGhostThreads = 256;
 template <typename S>
-__global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
+__global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
+  __shared__ double part[kGhostThreads / kWave][16];
   const int b = blockIdx.x;
   const int ii = find_inst(pv.off_ghost, pv.ninst, b);
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
   UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
   const int local = b - first_block(pv.off_ghost, ii);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), tid = threadIdx.x;
   if (P.bc != UGKS_BC_CHANNEL) {
     const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
-    const long long e = (long long)local * kWave + lane;
+    const long long e = (long long)local * kGhostThreads + tid;
     if (e >= frame * P.NV) return;
     const int p = (int)(e / frame);
     int r = (int)(e - (long long)p * frame);
@@ -371,7 +389,7 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
     stv(pl, pidx(P, i, j), x);
     return;
   }
-  const UGKS_GLOBAL double* W = I->W;
+  const UGKS_GLOBAL double* W = I->W[(I->cur + pv.step) & 1];
   UGKS_GLOBAL double* Wg = I->Wg;
   UGKS_GLOBAL double* hsg = I->hsg;
   const int side = local / P.ny, j = local - side * P.ny;
@@ -396,9 +414,9 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
     pg.V = pc.V;
     pg.lam = pc.lam;
   }
-  if (!ok && lane == 0) *P.flag = 1;
+  if (!ok && tid == 0) *P.flag = 1;
   UGKS_GLOBAL double* wg = Wg + 4 * ((size_t)side * P.ny + j);
-  if (lane == 0) {
+  if (tid == 0) {
     wg[0] = pg.rho;
     wg[1] = pg.rho * pg.U;
     wg[2] = pg.rho * pg.V;
@@ -409,7 +427,7 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (int p = lane; p < P.NV; p += kWave) {
+  for (int p = tid; p < P.NV; p += kGhostThreads) {
     const int k = p / P.M, m = p - k * P.M;
     const double u = P.uk[k], vv = P.vm[m], w = P.wk[k] * P.wm[m];
     const double du = u - pg.U, dv = vv - pg.V;
@@ -420,10 +438,18 @@ __global__ __launch_bounds__(kWave) void ghost_kernel(PlanView pv) {
     const double h = side == 0 ? up : 1.0 - up;
     add_side(acc, w * h, u, vv, 0.5 * (u * u + vv * vv), (double)gs, 0.0, 0.0);
   }
+  const int w = tid >> 6;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const double t = wave_sum(acc[q]);
-    if (lane == q) hsg[((size_t)side * P.ny + j) * 16 + q] = t;
+    if (lane == q) part[w][q] = t;
+  }
+  __syncthreads();
+  if (tid < 16) {
+    double t = 0.0;
+#pragma unroll
+    for (int r = 0; r < kGhostThreads / kWave; ++r) t += part[r][tid];
+    hsg[((size_t)side * P.ny + j) * 16 + tid] = t;
   }
 }
 
@@ -445,9 +471,10 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
   const UGKS_GLOBAL S* f = static_cast<const UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
-  UGKS_GLOBAL double* hs = I->hs;
-  const int L = b - first_block(pv.off_sums, ii);
-  const int t = L / P.ny, j = L - t * P.ny;
+  const int G = I->gsplit;
+  int t, g, j;
+  cell_block(b - first_block(pv.off_sums, ii), P.ny, G, t, g, j);
+  UGKS_GLOBAL double* hs = I->hs + (size_t)g * kSlots * ((size_t)P.nx * P.ny);
   const int i = t * kTileS - 1 + lane;
   const bool valid = lane >= 1 && lane <= kTileS && i < P.nx;
   const int o = pidx(P, i < P.nx + 1 ? i : P.nx + 1, j);
@@ -461,7 +488,9 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   double ax[16], ay[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) ax[r] = ay[r] = 0.0;
-  for (int a = 0; a < hu.count; ++a) {
+  int a0, a1;
+  chunk_range(hu.count, g, G, a0, a1);
+  for (int a = a0; a < a1; ++a) {
     const int k = hu.first + a * hu.step;
     const double u = P.uk[k];
     const double wu = P.wk[k] * (u == 0.0 ? 0.5 : 1.0);
@@ -477,27 +506,25 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
       return Vals{bload<S>(r, oc), bload<S>(r, oS), bload<S>(r, oN)};
     };
     auto node = [&](const Vals& x, int c) {
-      const int m = hv.first + c * hv.step;
-      const double vv = P.vm[m];
-      const double wv = P.wm[m] * (vv == 0.0 ? 0.5 : 1.0);
-      const double v2 = vv * vv, v3 = v2 * vv, v4 = v2 * v2;
+      // w_m v_m^n, n = 0..4, with the weight 1/2 of a node at v = 0 (visited by both halves)
+      const UGKS_GLOBAL double* wp = P.vmom + 5 * (hv.first + c * hv.step);
+      const double w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3], w4 = wp[4];
       const double fW = from_lower(x.c), fE = from_upper(x.c);
       const double hx = half_limited(fE - x.c, x.c - fW);
       const double hy = my * half_limited(x.n - x.c, x.c - x.s);
-      const double xf = wv * x.c, xx = wv * hx, xy = wv * hy;
-      F0 += xf;
-      F1 = fma(xf, vv, F1);
-      F2 = fma(xf, v2, F2);
-      F3 = fma(xf, v3, F3);
-      X0 += xx;
-      X1 = fma(xx, vv, X1);
-      X2 = fma(xx, v2, X2);
-      X3 = fma(xx, v3, X3);
-      Y0 += xy;
-      Y1 = fma(xy, vv, Y1);
-      Y2 = fma(xy, v2, Y2);
-      Y3 = fma(xy, v3, Y3);
-      Y4 = fma(xy, v4, Y4);
+      F0 = fma(x.c, w0, F0);
+      F1 = fma(x.c, w1, F1);
+      F2 = fma(x.c, w2, F2);
+      F3 = fma(x.c, w3, F3);
+      X0 = fma(hx, w0, X0);
+      X1 = fma(hx, w1, X1);
+      X2 = fma(hx, w2, X2);
+      X3 = fma(hx, w3, X3);
+      Y0 = fma(hy, w0, Y0);
+      Y1 = fma(hy, w1, Y1);
+      Y2 = fma(hy, w2, Y2);
+      Y3 = fma(hy, w3, Y3);
+      Y4 = fma(hy, w4, Y4);
     };
     // two value sets, each node's loads issued one node ahead
     Vals va = load(0);
@@ -567,17 +594,36 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     }
   }
   __syncthreads();
-  if (!valid || q == 1 || q == 3) return;
-  const size_t nc = (size_t)P.nx * P.ny, cell = (size_t)j * P.nx + i;
-  const int fy = q == 0 ? S_YP : S_YM, fx = q == 0 ? S_XP : S_XM;
-  const int oy = q == 0 ? 0 : 1, ox = q == 0 ? 3 : 2;
+  const size_t nc = (size_t)P.nx * P.ny;
+  if (valid && (q == 0 || q == 2)) {
+    const size_t cell = (size_t)j * P.nx + i;
+    const int fy = q == 0 ? S_YP : S_YM, fx = q == 0 ? S_XP : S_XM;
+    const int oy = q == 0 ? 0 : 1, ox = q == 0 ? 3 : 2;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const double sx = (ax[r] + red[ox][r][lane]) * (r >= 4 && r < 8 ? two_idy : 1.0);
-    const double sy = (ay[r] + red[oy][r][lane]) * (r >= 4 && r < 8 ? two_idx : 1.0);
-    hs[(size_t)(16 * fx + r) * nc + cell] = sx;
-    hs[(size_t)(16 * fy + r) * nc + cell] = sy;
+    for (int r = 0; r < 16; ++r) {
+      const double sx = (ax[r] + red[ox][r][lane]) * (r >= 4 && r < 8 ? two_idy : 1.0);
+      const double sy = (ay[r] + red[oy][r][lane]) * (r >= 4 && r < 8 ? two_idx : 1.0);
+      hs[(size_t)(16 * fx + r) * nc + cell] = sx;
+      hs[(size_t)(16 * fy + r) * nc + cell] = sy;
+    }
   }
+}
+
+// With several velocity chunks per quadrant the moment kernel leaves G partial sums per
+// value; one thread per (sum, cell) adds them, in chunk order, into the first.
+__global__ __launch_bounds__(256) void chunk_sum_kernel(PlanView pv) {
+  const int b = blockIdx.x;
+  const int ii = find_inst(pv.off_red, pv.ninst, b);
+  const Inst* __restrict__ I = inst_at(pv, ii);
+  const KParams P = I->P;
+  const size_t nc = (size_t)P.nx * P.ny;
+  const size_t e = (size_t)(b - first_block(pv.off_red, ii)) * blockDim.x + threadIdx.x;
+  if (e >= kSlots * nc) return;
+  UGKS_GLOBAL double* at = I->hs + e;
+  const size_t gstride = (size_t)kSlots * nc;
+  double x = at[0];
+  for (int g = 1; g < I->gsplit; ++g) x += at[(size_t)g * gstride];
+  at[0] = x;
 }
 
 // S2-S5 at one interior interface, local frame.  S = [W0, Wt, Q1, Q2].  Writes the local
@@ -669,7 +715,7 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   const KParams P = I->P;
   const UGKS_GLOBAL double* hs = I->hs;
   const UGKS_GLOBAL double* hsg = I->hsg;
-  const UGKS_GLOBAL double* W = I->W;
+  const UGKS_GLOBAL double* W = I->W[(I->cur + pv.step) & 1];
   const UGKS_GLOBAL double* Wg = I->Wg;
   UGKS_GLOBAL double* recx = I->recx;
   UGKS_GLOBAL double* recy = I->recy;
@@ -865,7 +911,7 @@ __device__ __forceinline__ void load_e(const double (*st)[kWave], int col, int s
 template <typename S, int SU>
 __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& st,
                                                 const double* vnode, int q, int lane, int sv,
-                                                int j,
+                                                int j, int g, int G,
                                                 bool valid, bool ghost_lane,
                                                 const UGKS_GLOBAL S* fin, UGKS_GLOBAL S* fout,
                                                 int o) {
@@ -899,7 +945,9 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
   const double qn = expm1(h2 * cell_row(st, C_LAMN)[lane]);
   const double q1 = expm1(h2 * cell_row(st, C_LAM1)[lane]);
   const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
-  for (int a = 0; a < hu.count; ++a) {
+  int a0, a1;
+  chunk_range(hu.count, g, G, a0, a1);
+  for (int a = a0; a < a1; ++a) {
     const int k = hu.first + a * hu.step;
     const double u = P.uk[k];
     const double au = fabs(u);
@@ -1039,9 +1087,11 @@ void update_kernel(PlanView pv) {
   UGKS_GLOBAL S* fout = static_cast<UGKS_GLOBAL S*>(I->f[parity ^ 1]);
   const UGKS_GLOBAL double* recx = I->recx;
   const UGKS_GLOBAL double* recy = I->recy;
-  UGKS_GLOBAL double* W = I->W;
-  const int L = b - first_block(pv.off_upd, ii);
-  const int t = L / P.ny, j = L - t * P.ny;
+  const UGKS_GLOBAL double* W = I->W[parity];
+  UGKS_GLOBAL double* Wout = I->W[parity ^ 1];
+  const int G = I->gsplit;
+  int t, g, j;
+  cell_block(b - first_block(pv.off_upd, ii), P.ny, G, t, g, j);
   const int i0 = t * kTileU;
   const int i = i0 - kHalo + lane;
   const bool valid = lane >= kHalo && lane < kHalo + kTileU && i < P.nx;
@@ -1083,9 +1133,10 @@ void update_kernel(PlanView pv) {
                         P.area;
       W1[r] = valid ? Wn[r] + dW : Wn[r];
     }
-    if (valid) {
+    // every velocity chunk of the segment forms the same W^{n+1}; chunk 0 stores it
+    if (valid && g == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) W[4 * cc + r] = W1[r];
+      for (int r = 0; r < 4; ++r) Wout[4 * cc + r] = W1[r];
     }
     Prim pn{}, p1{};
     double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
@@ -1114,10 +1165,15 @@ void update_kernel(PlanView pv) {
     const int hf = sv > 0 ? 0 : 1;
     const double hstep = sv * P.dv;
     const double v0 = vnode[sv > 0 ? P.M / 2 : P.M / 2 - 1];
+    // A start value below the normal range cannot be carried up to a peak that lies inside
+    // the half: such a state (speed ratio |V| lambda^(1/2) above about 26 across v) is flagged.
+    bool lost = false;
     auto start = [&](double lam, double c, double* e, double* r) {
       const double d = v0 - c;
-      e[lane] = exp(-lam * d * d);
+      const double x = lam * d * d;
+      e[lane] = exp(-x);
       r[lane] = exp(-lam * hstep * (2.0 * d + hstep));
+      lost = lost || (x > 700.0 && (sv > 0 ? c > v0 : c < v0));
     };
     const int xo = lane + (quad_su(q) > 0 ? 1 : 0);
     start(st.sx[R_LAM][xo], st.sx[R_VY][xo], st.xs[q][0], st.xs[q][1]);
@@ -1128,20 +1184,34 @@ void update_kernel(PlanView pv) {
       start(st.sy[0][R_LAM][lane], st.sy[0][R_VY][lane], st.ys[hf][0], st.ys[hf][1]);
       start(st.sy[1][R_LAM][lane], st.sy[1][R_VY][lane], st.ys[hf][2], st.ys[hf][3]);
     }
+    if (lost && valid) *P.flag = 1;
   }
   __syncthreads();
   if (quad_su(q) > 0)
-    update_quadrant<S, 1>(P, st, vnode, q, lane, sv, j, valid, ghost_lane, fin, fout, o);
+    update_quadrant<S, 1>(P, st, vnode, q, lane, sv, j, g, G, valid, ghost_lane, fin, fout, o);
   else
-    update_quadrant<S, -1>(P, st, vnode, q, lane, sv, j, valid, ghost_lane, fin, fout, o);
+    update_quadrant<S, -1>(P, st, vnode, q, lane, sv, j, g, G, valid, ghost_lane, fin, fout,
+                           o);
 }
 
 }  // namespace
 
 // ================================================================== launchers
+// Update workgroups that fill the GPU once: 3 per CU (its LDS and registers allow 3).
+constexpr long long kFillWorkgroups = 256 * 3;
+
+int velocity_chunks(int nx, int ny, int K) {
+  const long long base = (long long)((nx + kTileU - 1) / kTileU) * ny;
+  long long G = kFillWorkgroups / base;
+  const int half = K / 2;  // nodes of the smaller half of the u axis
+  if (G > half) G = half;
+  if (G > 16) G = 16;
+  return G < 1 ? 1 : (int)G;
+}
+
 size_t plan_bytes(int n) {
   const size_t inst = ((sizeof(Inst) * (size_t)n + 255) / 256) * 256;
-  return inst + 5 * (((size_t)(n + 1) * sizeof(int) + 255) / 256) * 256;
+  return inst + 6 * (((size_t)(n + 1) * sizeof(int) + 255) / 256) * 256;
 }
 
 PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, PlanView* view) {
@@ -1150,38 +1220,47 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   const size_t inst_bytes = ((sizeof(Inst) * (size_t)n + 255) / 256) * 256;
   const size_t off_bytes = (((size_t)(n + 1) * sizeof(int) + 255) / 256) * 256;
   std::memcpy(h, insts, sizeof(Inst) * (size_t)n);
-  int* off[5];
-  for (int a = 0; a < 5; ++a) off[a] = reinterpret_cast<int*>(h + inst_bytes + a * off_bytes);
+  int* off[6];
+  for (int a = 0; a < 6; ++a) off[a] = reinterpret_cast<int*>(h + inst_bytes + a * off_bytes);
   PlanTotals t{};
+  // each instance keeps the velocity chunks it was created with, in any plan, so that its
+  // sums are added in the same order whether it is stepped alone or in a batch
+  Inst* img = reinterpret_cast<Inst*>(h);
+  for (int q = 0; q < n; ++q) img[q].gsplit = insts[q].P.gmax;
   for (int q = 0; q < n; ++q) {
     const KParams& P = insts[q].P;
+    const int G = img[q].gsplit;
     const int nf = P.ny * (P.nx + 1) + (P.ny + 1) * P.nx;
     off[0][q] = t.sums;
     off[1][q] = t.upd;
     off[2][q] = t.face;
     off[3][q] = t.ghost;
-    off[4][q] = 0;
-    t.sums += ((P.nx + kTileS - 1) / kTileS) * P.ny;
-    t.upd += ((P.nx + kTileU - 1) / kTileU) * P.ny;
+    off[4][q] = t.red;
+    off[5][q] = 0;
+    if (G > 1) t.red += (int)((kSlots * (long long)P.nx * P.ny + 255) / 256);
+    t.sums += ((P.nx + kTileS - 1) / kTileS) * P.ny * G;
+    t.upd += ((P.nx + kTileU - 1) / kTileU) * P.ny * G;
     t.max_m = P.M > t.max_m ? P.M : t.max_m;
     t.face += (nf + 255) / 256;
     if (P.bc == UGKS_BC_CHANNEL) {
       t.ghost += 2 * P.ny;
     } else {
       const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
-      t.ghost += (int)((frame * P.NV + kWave - 1) / kWave);
+      t.ghost += (int)((frame * P.NV + kGhostThreads - 1) / kGhostThreads);
     }
   }
   off[0][n] = t.sums;
   off[1][n] = t.upd;
   off[2][n] = t.face;
   off[3][n] = t.ghost;
-  off[4][n] = 0;
+  off[4][n] = t.red;
+  off[5][n] = 0;
   view->inst = reinterpret_cast<const Inst*>(d);
   view->off_sums = reinterpret_cast<const int*>(d + inst_bytes + 0 * off_bytes);
   view->off_upd = reinterpret_cast<const int*>(d + inst_bytes + 1 * off_bytes);
   view->off_face = reinterpret_cast<const int*>(d + inst_bytes + 2 * off_bytes);
   view->off_ghost = reinterpret_cast<const int*>(d + inst_bytes + 3 * off_bytes);
+  view->off_red = reinterpret_cast<const int*>(d + inst_bytes + 4 * off_bytes);
   view->ninst = n;
   view->step = 0;
   return t;
@@ -1203,15 +1282,20 @@ hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int p
     case 0:
       if (t.ghost == 0) return hipSuccess;
       if (fp32)
-        ghost_kernel<float><<<(unsigned)t.ghost, kWave, 0, s>>>(pv);
+        ghost_kernel<float><<<(unsigned)t.ghost, kGhostThreads, 0, s>>>(pv);
       else
-        ghost_kernel<double><<<(unsigned)t.ghost, kWave, 0, s>>>(pv);
+        ghost_kernel<double><<<(unsigned)t.ghost, kGhostThreads, 0, s>>>(pv);
       break;
     case 1:
       if (fp32)
         sums_kernel<float><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
       else
         sums_kernel<double><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
+      if (t.red > 0) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        chunk_sum_kernel<<<(unsigned)t.red, 256, 0, s>>>(pv);
+      }
       break;
     case 2:
       faces_kernel<<<(unsigned)t.face, 256, 0, s>>>(pv);
