@@ -26,11 +26,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "9b30b027fdc32ec117992fbdf70877ed80acecc676cd01294219f1b76b5312ac",
-    "fp64": 1.1974e9,
-    "fp32_store": 0.6116e9,
+    "source_sha256": "337f34528c7e537983eb64106d715e36aa915d1e4ca1dbfa7da2b75382027947",
+    "fp64": 1.7197e9,
+    "fp32_store": 0.7916e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
-    "valu_fp64": 1.872e8,
+    "valu_fp64": 1.290e8,
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
 # 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)
@@ -168,6 +168,8 @@ def serving(args, fp64_rate):
         burst = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=steps)
         sat = burst.run(SV.serving_requests(n, float("inf"), seed=4, steps=steps))
         sat_rate = sat["done"] / sat["makespan_s"]
+        print(f"serving: saturation {sat['updates_per_s']:.4g} updates/s", file=sys.stderr,
+              flush=True)
         for frac in [float(x) for x in args.serving_rates.split(",") if x]:
             srv = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=25)
             st = srv.run(SV.serving_requests(n, frac * sat_rate, seed=4, steps=steps))
@@ -176,6 +178,7 @@ def serving(args, fp64_rate):
                          "p99_latency_s": st["p99_latency_s"],
                          "updates_per_s": st["updates_per_s"], "batches": srv.batches,
                          "max_resident": srv.max_resident, "host_s": srv.host_s})
+            print(f"serving: {frac} x saturation rate done", file=sys.stderr, flush=True)
     finally:
         ex.close()
     out["saturation"] = {"requests_per_s": sat_rate, "updates_per_s": sat["updates_per_s"],
