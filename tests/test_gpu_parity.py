@@ -203,3 +203,31 @@ def test_largest_velocity_grid():
     case = _case(nx=3, ny=2, lx=1.5, ly=1.0, nu=291, nv=291, umax=12.0, vmax=12.0, kn=0.1,
                  bc=1, noise=0.02, seed=17)
     PR.run_and_compare(case, 3, label="291x291 velocities")
+
+
+@pytest.mark.parametrize("V,flagged", [(20.0, False), (30.0, True)])
+def test_transverse_speed_ratio_limit(V, flagged):
+    """The v-direction Gaussians start at the innermost node of each half of v.  A Maxwellian
+    centred so far out that its start value underflows (speed ratio |V| lambda^(1/2) = 30 here)
+    is reported as an invalid state instead of being updated wrongly; ratio 20 is inside the
+    range and runs normally."""
+    case = _case(nx=4, ny=4, lx=1.0, ly=1.0, nu=16, nv=16, umax=40.0, vmax=40.0, kn=0.1, bc=0,
+                 noise=0.0)
+    kn, kw = WL.solver_kwargs(case)
+    a = ugks.Solver(kn, **kw)
+    try:
+        f, W = a.state()
+        W[..., 1] = 0.0
+        W[..., 2] = V * W[..., 0]
+        W[..., 3] = 0.5 * W[..., 0] * V * V + 0.5 * W[..., 0]  # T = 1
+        a.set_state(f, W)
+        a.step(1)
+        if flagged:
+            with pytest.raises(ugks.UgksError) as ex:
+                a.moments()
+            assert ex.value.code == ugks.UGKS_E_STATE
+        else:
+            m = a.moments()
+            assert np.all(np.isfinite(m))
+    finally:
+        a.close()
