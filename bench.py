@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-steps", type=int, default=100)
+    ap.add_argument("--serving-chunks", type=int, default=4,
+                    help="cap on the velocity chunks of the serving solvers (0: automatic)")
     ap.add_argument("--serving-rates", default="0.8",
                     help="Poisson arrival rates as fractions of the saturation rate")
     ap.add_argument("--paper-sweep", action="store_true",
@@ -161,8 +163,9 @@ def serving(args, fp64_rate):
 
     n, steps = args.serving_requests, args.serving_steps
     out = {"requests": n, "steps_per_request": steps, "precision": "fp32_store",
+           "velocity_chunks_cap": args.serving_chunks or "automatic",
            "meshes": SV.MESHES, "velocity_grids": SV.VGRIDS}
-    ex = SV.GpuExecutor(max_slots=n)
+    ex = SV.GpuExecutor(max_slots=n, velocity_chunks=args.serving_chunks)
     runs = []
     try:
         burst = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=steps)

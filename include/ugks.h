@@ -87,6 +87,11 @@ typedef struct {
    cfl              time step dt = cfl / (umax/dx + vmax/dy) unless dt_override > 0.
    rho0, T0, noise  initial state: rho = rho0 (1 + noise xi_c), U = V = 0, T = T0, and f the
                     discrete Maxwellian of that state (|noise| < 1).
+   velocity_chunks  Each velocity quadrant of a row segment is split over G workgroups.
+                    0: automatic, enough to fill the GPU with this solver alone (at most 16
+                    and nu/2); n in 1..16: at most n (the automatic choice capped at n).
+                    Solvers that are stepped in large batches gain from a small cap.  Results
+                    depend on G only through the order in which velocity sums are added.
    seed             xi_c is output c = j*nx + i of the SplitMix64 generator seeded with
                     `seed` (output k = mix(seed + (k+1) * 0x9E3779B97F4A7C15)), mapped to
                     [-1, 1) as 2 (z >> 11) 2^-53 - 1; the inlet noise xi_j uses output
@@ -96,7 +101,7 @@ typedef struct {
                     to 256 bytes; NULL lets the library allocate. */
 typedef struct {
   int precision;
-  int reserved; /* must be 0 */
+  int velocity_chunks;
   double cfl;
   double rho0, T0, noise;
   uint64_t seed;

@@ -183,7 +183,13 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
 }
 
 // Offsets of every buffer inside the workspace.
-Layout layout_of(const Shape& s, int prec) {
+// Velocity chunks of a solver: the automatic choice, capped at the requested number.
+int chunks_of(const Shape& s, int cap) {
+  const int a = velocity_chunks(s.nx, s.ny, s.K);
+  return cap > 0 && cap < a ? cap : a;
+}
+
+Layout layout_of(const Shape& s, int prec, int chunks) {
   const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
   const size_t sizes[14] = {
       (size_t)s.NV * s.PS * ss,                 // f0: NV planes
@@ -191,7 +197,7 @@ Layout layout_of(const Shape& s, int prec) {
       s.nc * 4 * 8,                             // W0
       s.nc * 4 * 8,                             // W1
       2 * (size_t)s.ny * 4 * 8,                 // Wg
-      (size_t)velocity_chunks(s.nx, s.ny, s.K) * s.nc * kSlots * 8,  // hs: partial sums
+      (size_t)chunks * s.nc * kSlots * 8,      // hs: per-chunk partial sums
       2 * (size_t)s.ny * 16 * 8,                // hsg
       (size_t)s.ny * (s.nx + 1) * kRec * 8,     // recx
       (size_t)(s.ny + 1) * s.nx * kRec * 8,     // recy
@@ -292,7 +298,9 @@ int ugks_required_bytes(const ugks_mesh* mesh, const ugks_vgrid* vgrid, const ug
   const int prec = opts ? opts->precision : UGKS_FP64;
   if (prec != UGKS_FP64 && prec != UGKS_FP32_STORE)
     return fail(nullptr, UGKS_E_INVAL, "unknown precision%s");
-  *out_bytes = layout_of(s, prec).total;
+  if (opts && (opts->velocity_chunks < 0 || opts->velocity_chunks > 16))
+    return fail(nullptr, UGKS_E_INVAL, "velocity_chunks must be in 0..16%s");
+  *out_bytes = layout_of(s, prec, chunks_of(s, opts ? opts->velocity_chunks : 0)).total;
   return UGKS_OK;
 }
 
@@ -313,13 +321,15 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     return fail(nullptr, UGKS_E_INVAL, "channel needs p_ratio, T_in, T_wall > 0%s");
   if (opts->precision != UGKS_FP64 && opts->precision != UGKS_FP32_STORE)
     return fail(nullptr, UGKS_E_INVAL, "unknown precision%s");
-  if (opts->reserved != 0) return fail(nullptr, UGKS_E_INVAL, "opts.reserved must be 0%s");
+  if (opts->velocity_chunks < 0 || opts->velocity_chunks > 16)
+    return fail(nullptr, UGKS_E_INVAL, "velocity_chunks must be in 0..16%s");
   if (!(opts->rho0 > 0) || !(opts->T0 > 0) || !(std::fabs(opts->noise) < 1.0))
     return fail(nullptr, UGKS_E_INVAL, "need rho0 > 0, T0 > 0, |noise| < 1%s");
   if (!(opts->dt_override > 0) && !(opts->cfl > 0 && std::isfinite(opts->cfl)))
     return fail(nullptr, UGKS_E_INVAL, "need cfl > 0 or dt_override > 0%s");
 
-  const Layout L = layout_of(s, opts->precision);
+  const int chunks = chunks_of(s, opts->velocity_chunks);
+  const Layout L = layout_of(s, opts->precision, chunks);
   if (opts->workspace && opts->workspace_bytes < L.total)
     return fail(nullptr, UGKS_E_NOMEM, "workspace smaller than ugks_required_bytes()%s");
   if (opts->workspace && (reinterpret_cast<uintptr_t>(opts->workspace) % kAlign) != 0)
@@ -359,7 +369,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   P.NV = s.NV;
   P.Lx = s.Lx;
   P.Ly = s.Ly;
-  P.gmax = velocity_chunks(s.nx, s.ny, s.K);
+  P.gmax = chunks;
   P.PS = (long long)s.PS;
   P.bc = bc->kind;
   P.collisionless = std::isinf(kn) ? 1 : 0;

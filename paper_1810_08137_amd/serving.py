@@ -71,9 +71,12 @@ def serving_requests(n, rate, seed=4, steps=500, precision="fp32_store", meshes=
 
 
 class GpuExecutor:
-    """Runs requests as UGKS solvers on the current GPU, stepped together in one batch."""
+    """Runs requests as UGKS solvers on the current GPU, stepped together in one batch.
+    ``velocity_chunks`` caps every solver's velocity chunks (0: automatic).  A batch of
+    resident requests fills the GPU by itself, so a small cap saves per-chunk setup; the
+    default 4 keeps the low-load latency of the automatic choice."""
 
-    def __init__(self, max_slots):
+    def __init__(self, max_slots, velocity_chunks=4):
         import torch
 
         from . import ugks
@@ -83,17 +86,19 @@ class GpuExecutor:
         self.run_stream = torch.cuda.Stream()
         self.admit_stream = torch.cuda.Stream()
         self.batch = ugks.Batch(max_slots, stream=self.run_stream)
+        self.velocity_chunks = int(velocity_chunks)
         self.done_event = None
 
     def footprint(self, req):
         kn, kw = WL.solver_kwargs(req.case, req.precision)
-        mesh, vgrid, bc, opts = self.ugks.make_structs(**kw)
+        mesh, vgrid, bc, opts = self.ugks.make_structs(velocity_chunks=self.velocity_chunks, **kw)
         return self.ugks.ugks_required_bytes(mesh, vgrid, opts)
 
     def create(self, req):
         kn, kw = WL.solver_kwargs(req.case, req.precision)
         with self.torch.cuda.stream(self.admit_stream):
-            return self.ugks.Solver(kn, stream=self.admit_stream, **kw)
+            return self.ugks.Solver(kn, stream=self.admit_stream,
+                                    velocity_chunks=self.velocity_chunks, **kw)
 
     def step(self, solvers, n):
         self.batch.step(solvers, n)

@@ -45,7 +45,7 @@ class ugks_bc(ctypes.Structure):
 
 
 class ugks_opts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("reserved", ctypes.c_int),
+    _fields_ = [("precision", ctypes.c_int), ("velocity_chunks", ctypes.c_int),
                 ("cfl", ctypes.c_double), ("rho0", ctypes.c_double), ("T0", ctypes.c_double),
                 ("noise", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("dt_override", ctypes.c_double), ("stream", ctypes.c_void_p),
@@ -233,15 +233,16 @@ def ugks_batch_last_error(b):
 # ----------------------------------------------------------------------------- structs
 def make_structs(nx, ny, lx, ly, nu, nv, umax, vmax, bc="channel", p_ratio=2.0, T_in=1.0,
                  T_wall=1.0, inlet_fixed_u=0, U_in=0.0, U_noise=0.0, precision="fp64", cfl=0.8,
-                 rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, **_):
+                 rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, velocity_chunks=0,
+                 **_):
     mesh = ugks_mesh(int(nx), int(ny), float(lx), float(ly))
     vgrid = ugks_vgrid(int(nu), int(nv), float(umax), float(vmax))
     kind = {"periodic": UGKS_BC_PERIODIC, "channel": UGKS_BC_CHANNEL}[bc] if isinstance(bc, str) else int(bc)
     b = ugks_bc(kind, int(inlet_fixed_u), float(p_ratio), float(T_in), float(T_wall),
                 float(U_in), float(U_noise))
     prec = {"fp64": UGKS_FP64, "fp32_store": UGKS_FP32_STORE}[precision] if isinstance(precision, str) else int(precision)
-    o = ugks_opts(prec, 0, float(cfl), float(rho0), float(T0), float(noise), int(seed),
-                  float(dt_override), None, None, 0)
+    o = ugks_opts(prec, int(velocity_chunks), float(cfl), float(rho0), float(T0), float(noise),
+                  int(seed), float(dt_override), None, None, 0)
     return mesh, vgrid, b, o
 
 

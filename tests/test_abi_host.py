@@ -40,21 +40,36 @@ def _structs(case=WL.C2, **over):
     return kn, ugks.make_structs(**c)
 
 
+def _plane(nx, ny):
+    """Values per velocity plane: (ny + 4) rows of nx + 4, rounded up to 64."""
+    return -(-((nx + 4) * (ny + 4)) // 64) * 64
+
+
 def test_required_bytes_matches_the_documented_layout():
     kn, (mesh, vgrid, bc, opts) = _structs()
     n64 = ugks.ugks_required_bytes(mesh, vgrid, opts)
-    nc, nvp = 400 * 100, 1600
-    f_bytes = nc * nvp * 8
+    f_bytes = 1600 * _plane(400, 100) * 8
     assert 2 * f_bytes <= n64 <= 2 * f_bytes * 1.1       # two f buffers dominate
     opts.precision = ugks.UGKS_FP32_STORE
     n32 = ugks.ugks_required_bytes(mesh, vgrid, opts)
     assert n32 < n64 and n64 - n32 >= f_bytes        # FP32 storage halves both f buffers
 
 
-def test_velocity_padding_to_wavefront():
+def test_planes_include_the_halo():
     kn, (mesh, vgrid, bc, opts) = _structs(WL.C3)
     n = ugks.ugks_required_bytes(mesh, vgrid, opts)
-    assert n >= 2 * 200 * 50 * 10240 * 8
+    assert n >= 2 * 101 * 101 * _plane(200, 50) * 8
+
+
+def test_velocity_chunks_size_the_partial_sums():
+    """Each velocity chunk keeps 64 partial sums per cell; a cap below the automatic choice
+    (14 for this mesh) sets the count."""
+    c = dict(WL.paper_mesh(40, 20, 29))
+    c.pop("kn")
+    m1, v1, _, o1 = ugks.make_structs(velocity_chunks=1, **c)
+    m4, v4, _, o4 = ugks.make_structs(velocity_chunks=4, **c)
+    d = ugks.ugks_required_bytes(m4, v4, o4) - ugks.ugks_required_bytes(m1, v1, o1)
+    assert d >= 3 * 40 * 20 * 64 * 8
 
 
 @pytest.mark.parametrize("field,value", [
@@ -62,6 +77,7 @@ def test_velocity_padding_to_wavefront():
     ("nu", 2000), ("nu", 1025), ("noise", 1.5), ("rho0", 0.0), ("T0", -1.0),
     ("p_ratio", 0.0),
     ("T_wall", 0.0), ("cfl", 0.0), ("precision", 7), ("bc", 5),
+    ("velocity_chunks", -1), ("velocity_chunks", 17),
 ])
 def test_create_rejects_invalid_arguments(field, value):
     c = dict(WL.C1)
