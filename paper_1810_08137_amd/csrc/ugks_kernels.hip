@@ -4,7 +4,9 @@
 //   ghost   the halo of every velocity plane: pressure inlet/outlet ghost columns of a channel
 //           (Sec. 3.A) with their moment sums, or the periodic images of a periodic box
 //   sums    per cell and velocity: limited slopes of f, the upwind reconstruction at the
-//           cell's outgoing faces and their velocity moments (S1 and the sums of S7)
+//           cell's outgoing faces and their velocity moments (S1 and the sums of S7); a
+//           solver that splits its velocities into chunks adds the chunks' partial sums in
+//           a second, small launch
 //   faces   per interface: add the two sides' sums, then the scalar part of the flux
 //           (S2-S5: Maxwellian moments, time weights, micro slopes, equilibrium flux) into a
 //           record of folded coefficients
@@ -15,7 +17,7 @@
 // of one row at one velocity, so every load is one coalesced row segment and the x
 // neighbours of a cell come from the neighbouring lanes.  The four wavefronts of a workgroup
 // share one row segment and take one velocity quadrant each: within a quadrant the upwind
-// direction of both axes is uniform, so a face flux is evaluated once, by the lane of its
+// direction of both axes is uniform, so an x-face flux is evaluated once, by the lane of its
 // upwind cell, and handed to the downwind lane.
 #include <hip/hip_runtime.h>
 
