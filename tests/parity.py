@@ -52,6 +52,21 @@ def make_pair(case, precision="fp64"):
     return g, o
 
 
+def oracle_sensitivity(case, steps):
+    """How far the oracle's own f moves (per-cell max |df| / max f) after `steps` steps when
+    its initial f changes by one rounding: the accuracy any other rounding order can reach."""
+    oracle_threads()
+    a = O.Oracle(**WL.oracle_kwargs(case))
+    b = O.Oracle(**WL.oracle_kwargs(case))
+    f, W = b.state()
+    sign = np.where(np.sin(np.arange(f.size)) >= 0.0, 1.0, -1.0).reshape(f.shape)
+    b.set_state(f * (1.0 + 2.0 ** -53 * sign), W)
+    assert a.step(steps) == 0 and b.step(steps) == 0
+    fa, _ = a.state()
+    fb, _ = b.state()
+    return float(np.max(np.max(np.abs(fa - fb), axis=-1) / np.max(np.abs(fa), axis=-1)))
+
+
 def run_and_compare(case, steps, precision="fp64", tol=FP64_TOL, check_f=True, label=""):
     oracle_threads()
     g, o = make_pair(case, precision)

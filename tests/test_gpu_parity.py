@@ -197,6 +197,37 @@ def test_paper_mesh_m1(nvel):
     PR.run_and_compare(WL.paper_mesh(40, 20, nvel), 20, label=f"paper M1 {nvel}^2")
 
 
+def test_velocity_grid_at_the_limit():
+    """nu = nv = 1024, the documented maximum: 512 v nodes per half for the Gauss
+    recurrences, 16 velocity chunks and an 8 KB v-node table in the update kernel's LDS."""
+    case = _case(nx=3, ny=2, lx=1.5, ly=1.0, nu=1024, nv=1024, umax=12.0, vmax=12.0, kn=0.1,
+                 bc=1, noise=0.02, seed=17)
+    PR.run_and_compare(case, 2, label="1024x1024 velocities")
+
+
+def _tiny_grid(nu, nv):
+    return _case(nx=5, ny=4, lx=1.0, ly=0.8, nu=nu, nv=nv, umax=2.0, vmax=2.0, kn=0.2, bc=0,
+                 noise=0.05, seed=31)
+
+
+@pytest.mark.parametrize("nu,nv", [(2, 3), (3, 2)])
+def test_two_node_velocity_axes(nu, nv):
+    """The smallest velocity axes: one node per half (with three nodes the zero node is
+    shared by the two halves of the moment sums)."""
+    PR.run_and_compare(_tiny_grid(nu, nv), 10, label=f"periodic {nu}x{nv} velocities")
+
+
+def test_two_by_two_velocity_grid_within_its_conditioning():
+    """With u, v in {-2, 2} every velocity has |c|^2 = 8, far from the Maxwellian the cells
+    hold, and the step amplifies a one-rounding change of f about 3e5-fold: no rounding
+    order reaches 1e-12 here.  The bar is ten times the oracle's own spread under such a
+    change (measured in the test, about 5e-11 after 3 steps)."""
+    case = _tiny_grid(2, 2)
+    s = PR.oracle_sensitivity(case, 3)
+    assert s > PR.FP64_TOL  # the case really is that sensitive
+    PR.run_and_compare(case, 3, tol=10 * s, label="periodic 2x2 velocities")
+
+
 def test_largest_velocity_grid():
     """291 x 291 velocities on a 3 x 2 channel: long Gauss recurrences along v (146 nodes per
     half) and a single row segment per row."""
