@@ -26,7 +26,7 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "5399e475db027733d5e8c2bd3d36452fe0a52112304336356982b1383c004a52",
+    "source_sha256": "04d8c04839e32b5036e892e7c01bb920de719d87f0daba3547d4cf69a70a0ea6",
     "fp64": 1.7197e9,
     "fp32_store": 0.7916e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source

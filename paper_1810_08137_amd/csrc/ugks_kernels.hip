@@ -66,13 +66,15 @@ __device__ __forceinline__ UGKS_GLOBAL S* plane_of(UGKS_GLOBAL S* f, const KPara
   return f + (long long)p * P.PS;
 }
 // Buffer resource of one plane (base, size in bytes): loads at a per-lane 32-bit byte offset
-// from a scalar base, range-checked by the hardware.  Word 3 selects 32-bit data for the
-// untyped buffer instructions.
+// from a scalar base, range-checked by the hardware.  The size field is an unsigned 32-bit
+// count (a plane holds at most 2^28 values, so at most 2^31 bytes).  Word 3 selects 32-bit
+// data for the untyped buffer instructions.
 template <typename S>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const UGKS_GLOBAL S* plane,
                                                              const KParams& P) {
-  return __builtin_amdgcn_make_buffer_rsrc(
-      (void*)plane, (short)0, (int)((unsigned long long)P.PS * sizeof(S)), 0x00020000);
+  const unsigned bytes = (unsigned)((unsigned long long)P.PS * sizeof(S));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)plane, (short)0, __builtin_bit_cast(int, bytes),
+                                           0x00020000);
 }
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
