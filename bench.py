@@ -26,11 +26,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "04d8c04839e32b5036e892e7c01bb920de719d87f0daba3547d4cf69a70a0ea6",
-    "fp64": 1.7197e9,
-    "fp32_store": 0.7916e9,
+    "source_sha256": "75cb71f77e852501c6a7e3f473fce893c972f731959068e6cd0dd490bbc65bbf",
+    "fp64": 1.3312e9,
+    "fp32_store": 0.7587e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
-    "valu_fp64": 1.290e8,
+    "valu_fp64": 1.279e8,
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
 # 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)

@@ -35,6 +35,7 @@ constexpr int kQuads = 4;                     // wavefronts per workgroup, one p
 constexpr int kTileS = kWave - 2;             // cells per moment-kernel wavefront
 constexpr int kTileU = kWave - 2 * kHalo;     // cells per update-kernel wavefront
 constexpr int kStage = R_M5 + 1;              // record fields the update kernel stages in LDS
+constexpr unsigned kDropOffset = 0xFFFFFFF0u;  // beyond any plane (at most 2^31 bytes)
 
 // Quadrant q of a workgroup: sign of u and of v.  Around the cycle (+,+) (-,+) (-,-) (+,-)
 // neighbours share one sign, so each face side collects its sums from two adjacent waves.
@@ -81,6 +82,15 @@ __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off, 
 }
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
   return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+// Stores through the same resources; an offset past the plane's range is dropped by the
+// hardware range check, so lanes without a cell to write need no branch.
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, double x, double) {
+  typedef unsigned u2v __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, x), r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, double x, float) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)x), r, off, 0, 0);
 }
 template <typename S>
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
@@ -1053,10 +1063,8 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
       const double Fyi = av * fma(ei, horner(ci, vv), fma(m4i, fhY, -m5i * DY));
       const double g = fma(cu1, e1, cun * en);
       const double f1 = fma(Af, fc, fma(AdF, (Fxi - Fxo) + (Fyi - Fyo), g));
-      if (valid)
-        *reinterpret_cast<UGKS_GLOBAL S*>(
-            reinterpret_cast<UGKS_GLOBAL char*>(wline + (long long)m * P.PS) + oc) =
-            static_cast<S>(f1);
+      // lanes outside the segment store past the plane's range, which the hardware drops
+      bstore(plane_rsrc(wline + (long long)m * P.PS, P), valid ? oc : kDropOffset, f1, S{});
       gauss_next(ex, rx, qx);
       gauss_next(eo, ro, qo);
       gauss_next(ei, ri, qi);
