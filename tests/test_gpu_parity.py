@@ -109,6 +109,20 @@ def test_fp32_store_c4_against_oracle_50_steps():
     assert max(e.values()) > 1e-12
 
 
+def test_fp32_store_with_velocity_chunks():
+    """FP32-store on the paper's M1 mesh at 49^2 (16 velocity chunks per quadrant)."""
+    e = PR.run_and_compare(WL.paper_mesh(40, 20, 49), 20, precision="fp32_store",
+                           tol=PR.FP32_STORE_TOL, label="paper M1 49^2 FP32-store")
+    assert max(e.values()) > 1e-12
+
+
+def test_fp32_store_wide_velocity_grid():
+    """FP32-store on 200x50 x 101^2 (3 velocity chunks, Gaussians over 51 v nodes)."""
+    e = PR.run_and_compare(WL.C3, 2, precision="fp32_store", tol=PR.FP32_STORE_TOL,
+                           label="C3 FP32-store")
+    assert max(e.values()) > 1e-12
+
+
 def test_runs_are_bitwise_deterministic():
     kn, kw = WL.solver_kwargs(WL.C1)
     a, b = ugks.Solver(kn, **kw), ugks.Solver(kn, **kw)

@@ -133,3 +133,28 @@ def test_request_loop_end_to_end():
             assert np.array_equal(s.moments(), r.result)
         finally:
             s.close()
+
+
+def test_batch_mixing_chunked_and_unchunked_solvers():
+    """A solver capped at one velocity chunk (no chunk-sum workgroups) between chunked ones:
+    the chunk-sum launch must still find each chunked member, and every member steps
+    bitwise as it does alone with the same cap."""
+    import torch
+
+    caps = [0, 1, 0, 2]
+    alone = [_solver(c, "fp64", velocity_chunks=k) for c, k in zip(CASES, caps)]
+    for s in alone:
+        s.step(9)
+    run = torch.cuda.Stream()
+    batch = ugks.Batch(4, stream=run)
+    members = [_solver(c, "fp64", stream=run, velocity_chunks=k) for c, k in zip(CASES, caps)]
+    try:
+        batch.step(members, 9)
+        for a, m in zip(alone, members):
+            fa, Wa = a.state()
+            fm, Wm = m.state()
+            assert np.array_equal(fa, fm) and np.array_equal(Wa, Wm)
+    finally:
+        for s in alone + members:
+            s.close()
+        batch.close()
