@@ -303,13 +303,15 @@ __device__ __forceinline__ void chunk_range(int count, int g, int G, int& a0, in
   a1 = (int)((long long)(g + 1) * count / G);
 }
 
-// Workgroup L of a cell kernel: row segment t, velocity chunk g, row j (rows fastest, so
-// that the workgroups an XCD runs at once are neighbouring rows of one chunk).
-__device__ __forceinline__ void cell_block(int L, int ny, int G, int& t, int& g, int& j) {
-  j = L % ny;
-  const int tg = L / ny;
-  t = tg / G;
-  g = tg - t * G;
+// Workgroup L of a cell kernel: row segment t (fastest), row j, velocity chunk g.  The
+// workgroups an XCD runs at once then cover whole rows of a band of neighbouring rows, so the
+// cache lines a segment shares with the next one, and the rows j +- 1, j +- 2 it reads, come
+// from that XCD's L2.
+__device__ __forceinline__ void cell_block(int L, int ny, int ntx, int& t, int& g, int& j) {
+  t = L % ntx;
+  const int r = L / ntx;
+  j = r % ny;
+  g = r / ny;
 }
 
 // ------------------------------------------------------------------ launch plans
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   const UGKS_GLOBAL S* f = static_cast<const UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
   const int G = I->gsplit;
   int t, g, j;
-  cell_block(b - first_block(pv.off_sums, ii), P.ny, G, t, g, j);
+  cell_block(b - first_block(pv.off_sums, ii), P.ny, (P.nx + kTileS - 1) / kTileS, t, g, j);
   UGKS_GLOBAL double* hs = I->hs + (size_t)g * kSlots * ((size_t)P.nx * P.ny);
   const int i = t * kTileS - 1 + lane;
   const bool valid = lane >= 1 && lane <= kTileS && i < P.nx;
@@ -1103,7 +1105,7 @@ void update_kernel(PlanView pv) {
   UGKS_GLOBAL double* Wout = I->W[parity ^ 1];
   const int G = I->gsplit;
   int t, g, j;
-  cell_block(b - first_block(pv.off_upd, ii), P.ny, G, t, g, j);
+  cell_block(b - first_block(pv.off_upd, ii), P.ny, (P.nx + kTileU - 1) / kTileU, t, g, j);
   const int i0 = t * kTileU;
   const int i = i0 - kHalo + lane;
   const bool valid = lane >= kHalo && lane < kHalo + kTileU && i < P.nx;
