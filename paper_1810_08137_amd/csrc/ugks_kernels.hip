@@ -499,7 +499,11 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   const unsigned oN = (unsigned)(o + P.Lx) * bs;
   const double my = (P.bc == UGKS_BC_CHANNEL && (j == 0 || j == P.ny - 1)) ? 0.0 : 1.0;
   const int su = quad_su(q), sv = quad_sv(q);
-  const Half hu = axis_half(P.K, su, true), hv = axis_half(P.M, sv, true);
+  // each half is walked inwards, towards v = 0 and u = 0: the update kernel walks it
+  // outwards, so each kernel starts on the planes the other touched last
+  const Half hu0 = axis_half(P.K, su, true), hv0 = axis_half(P.M, sv, true);
+  const Half hu = {hu0.first + (hu0.count - 1) * hu0.step, hu0.count, -hu0.step};
+  const Half hv = {hv0.first + (hv0.count - 1) * hv0.step, hv0.count, -hv0.step};
   const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
   double ax[16], ay[16];
 #pragma unroll
