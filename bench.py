@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--paper-sweep", action="store_true",
                     help="also time the paper's meshes M1-M4 at 29^2, 49^2 and 69^2 velocities")
     ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--shard-share", action="store_true",
+                    help="also time one GPU's share of the 400x100 case split 8 ways along x")
     return ap.parse_args()
 
 
@@ -132,6 +134,25 @@ def kernel_profile(solver, steps):
     t = solver.kernel_timing()
     solver.kernel_timing(False)
     return {k: {"avg_ms": (ms / n if n else None), "launches": n} for k, (ms, n) in t.items()}
+
+
+def shard_share(WL, ugks, steps, warmup):
+    """One GPU's share of C2 in an 8-way slab split along x (50x100 cells x 40^2, FP64), and
+    the halo each neighbour pair would exchange per step: two columns of every velocity plane
+    per side, at one xGMI link's ~153 GB/s."""
+    case = WL.C2_SHARE8
+    kn, kw = WL.solver_kwargs(case, "fp64")
+    s = ugks.Solver(kn, **kw)
+    try:
+        ms, _ = time_solver(s, steps, warmup)
+        prof = kernel_profile(s, min(steps, 200))
+        s.moments()
+    finally:
+        s.close()
+    halo_bytes = 2 * case["ny"] * case["nu"] * case["nv"] * 8
+    return {"cells": [case["nx"], case["ny"]], "velocities": [case["nu"], case["nv"]],
+            "ms_per_step": ms / steps, "updates_per_s": WL.updates(case) * steps / (ms * 1e-3),
+            "kernels": prof, "halo_bytes_per_side": halo_bytes, "halo_us_at_153GBs": halo_bytes / 153e9 * 1e6}
 
 
 def run_form(WL, ugks, precision, steps, warmup):
@@ -327,6 +348,8 @@ def main():
         out["serving"] = serving(args, fp64["updates_per_s"])
     if args.paper_sweep:
         out["paper_sweep"] = paper_sweep(WL, ugks, args.sweep_steps)
+    if args.shard_share:
+        out["shard_share"] = shard_share(WL, ugks, min(args.steps, 500), args.warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(WL, args.cpu_seconds)
     out["paper_context"] = ("paper: 118.38x speed-up of a Tesla V100 over one E5-2650 thread "

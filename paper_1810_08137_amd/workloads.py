@@ -29,6 +29,10 @@ C3 = _case(nx=200, ny=50, lx=4.0, ly=1.0, nu=101, nv=101, umax=20.0, vmax=20.0, 
            p_ratio=1.5, inlet_fixed_u=1, U_in=0.1, U_noise=0.05, noise=0.0, seed=3)
 C3_STEPS = 500
 
+# One GPU's share of C2 split over 8 GPUs along x: a 50x100 slab of the same channel (its
+# inlet/outlet ghost columns stand where the neighbours' halo columns would be).
+C2_SHARE8 = dict(C2, nx=50, lx=0.5)
+
 # Precision form: C2 with f stored in FP32.
 C4 = dict(C2)
 C4_PRECISION = "fp32_store"
