@@ -2,8 +2,9 @@
 
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark import this module.
 It loads ``libugks_oracle.so`` built from ``ugks_oracle.c`` and never touches the HIP library.
-Arrays come back as numpy float64 in the oracle's layout: f[ny, nx, nu*nv] with the velocity
-index k*nv + m, W[ny, nx, 4] = (rho, rho U, rho V, rho E).
+Arrays come back as numpy float64 in the oracle's layout: f[ny, nx, NF] with the velocity
+index k*nv + m (NF = nu*nv; with internal degrees of freedom NF = 2*nu*nv, G then H),
+W[ny, nx, 4] = (rho, rho U, rho V, rho E).
 """
 import ctypes
 import math
@@ -31,6 +32,7 @@ class RefCase(ctypes.Structure):
         ("rho0", ctypes.c_double), ("T0", ctypes.c_double), ("noise", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("dt_override", ctypes.c_double),
+        ("dof", ctypes.c_int),
     ]
 
 
@@ -65,17 +67,18 @@ def lib():
         L.ugks_ref_nodes.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.ugks_ref_maxwellian.restype = ctypes.c_double
         L.ugks_ref_maxwellian.argtypes = [_dp, ctypes.c_double, ctypes.c_double]
-        L.ugks_ref_prim.argtypes = [_dp, _dp]
+        L.ugks_ref_prim.argtypes = [_dp, _dp, ctypes.c_int]
         L.ugks_ref_vanleer.restype = ctypes.c_double
         L.ugks_ref_vanleer.argtypes = [ctypes.c_double, ctypes.c_double]
         L.ugks_ref_moments_1d.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
-        L.ugks_ref_micro_slope.argtypes = [_dp, _dp, _dp]
+        L.ugks_ref_micro_slope.argtypes = [_dp, _dp, _dp, ctypes.c_int]
         L.ugks_ref_time_weights.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
-        L.ugks_ref_time_slope.argtypes = [_dp, _dp, _dp, _dp, _dp]
-        L.ugks_ref_equilibrium_flux.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.ugks_ref_time_slope.argtypes = [_dp, _dp, _dp, _dp, _dp, ctypes.c_int]
+        L.ugks_ref_equilibrium_flux.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                                ctypes.c_int]
         L.ugks_ref_face.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_int, _dp, _dp]
+                                    ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -112,10 +115,10 @@ def maxwellian(prim, u, v):
     return float(lib().ugks_ref_maxwellian(_ptr(p), u, v))
 
 
-def prim(W):
+def prim(W, dof=0):
     w = _vec(W, 4)
     p = np.zeros(4)
-    rc = lib().ugks_ref_prim(_ptr(w), _ptr(p))
+    rc = lib().ugks_ref_prim(_ptr(w), _ptr(p), int(dof))
     return rc, p
 
 
@@ -129,9 +132,9 @@ def moments_1d(U, lam):
     return full, pos, neg
 
 
-def micro_slope(prim, s):
+def micro_slope(prim, s, dof=0):
     p, sv, a = _vec(prim, 4), _vec(s, 4), np.zeros(4)
-    lib().ugks_ref_micro_slope(_ptr(p), _ptr(sv), _ptr(a))
+    lib().ugks_ref_micro_slope(_ptr(p), _ptr(sv), _ptr(a), int(dof))
     return a
 
 
@@ -141,28 +144,31 @@ def time_weights(dt, tau):
     return Mt
 
 
-def time_slope(prim, aL, aR, b):
+def time_slope(prim, aL, aR, b, dof=0):
     A = np.zeros(4)
     args = [_vec(x, 4) for x in (prim, aL, aR, b)]
-    lib().ugks_ref_time_slope(*[_ptr(x) for x in args], _ptr(A))
+    lib().ugks_ref_time_slope(*[_ptr(x) for x in args], _ptr(A), int(dof))
     return A
 
 
-def equilibrium_flux(prim, aL, aR, b, A, Mt):
+def equilibrium_flux(prim, aL, aR, b, A, Mt, dof=0):
     F = np.zeros(4)
     args = [_vec(x, 4) for x in (prim, aL, aR, b, A)] + [_vec(Mt, 5)]
-    lib().ugks_ref_equilibrium_flux(*[_ptr(x) for x in args], _ptr(F))
+    lib().ugks_ref_equilibrium_flux(*[_ptr(x) for x in args], _ptr(F), int(dof))
     return F
 
 
-def face(un, ut, w, fhat, sn, st, WL, WR, dn, length, dt, mu_ref, collisionless=False):
+def face(un, ut, w, fhat, sn, st, WL, WR, dn, length, dt, mu_ref, collisionless=False, dof=0):
+    """fhat, sn, st: nvel values (G), followed by nvel values of H when dof > 0."""
     n = len(un)
-    arrs = [_vec(x, n) for x in (un, ut, w, fhat, sn, st)]
+    nf = n * (2 if dof > 0 else 1)
+    u3 = [_vec(x, n) for x in (un, ut, w)]
+    f3 = [_vec(x, nf) for x in (fhat, sn, st)]
     wl, wr = _vec(WL, 4), _vec(WR, 4)
     FW = np.zeros(4)
-    Ff = np.zeros(n)
-    rc = lib().ugks_ref_face(n, *[_ptr(a) for a in arrs], _ptr(wl), _ptr(wr), dn, length, dt,
-                             mu_ref, int(collisionless), _ptr(FW), _ptr(Ff))
+    Ff = np.zeros(nf)
+    rc = lib().ugks_ref_face(n, *[_ptr(a) for a in u3 + f3], _ptr(wl), _ptr(wr), dn, length,
+                             dt, mu_ref, int(collisionless), _ptr(FW), _ptr(Ff), int(dof))
     return rc, FW, Ff
 
 
@@ -182,7 +188,7 @@ def mu_ref_of_kn(kn):
 # ----------------------------------------------------------------------------- state
 CASE_DEFAULTS = dict(lx=1.0, ly=1.0, umax=5.0, vmax=5.0, kn=0.1, bc=1, inlet_fixed_u=0,
                      p_ratio=2.0, T_in=1.0, T_wall=1.0, U_in=0.0, U_noise=0.0, cfl=0.8,
-                     rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0)
+                     rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, dof=0)
 
 
 class Oracle:
@@ -195,6 +201,8 @@ class Oracle:
         self._c = RefCase(**c)
         self.nx, self.ny, self.nu, self.nv = c["nx"], c["ny"], c["nu"], c["nv"]
         self.NV = self.nu * self.nv
+        self.dof = c["dof"]
+        self.NF = self.NV * (2 if self.dof > 0 else 1)   # G, then H
         h = lib().ugks_ref_create(ctypes.byref(self._c))
         if not h:
             raise ValueError("ugks_ref_create rejected the case")
@@ -220,7 +228,7 @@ class Oracle:
         return float(lib().ugks_ref_tau_ref(self._h))
 
     def state(self):
-        f = np.empty((self.ny, self.nx, self.NV))
+        f = np.empty((self.ny, self.nx, self.NF))
         W = np.empty((self.ny, self.nx, 4))
         lib().ugks_ref_get_state(self._h, _ptr(f), _ptr(W))
         return f, W
@@ -229,7 +237,7 @@ class Oracle:
         fa = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
         Wa = None if W is None else np.ascontiguousarray(W, dtype=np.float64)
         if fa is not None:
-            assert fa.size == self.ny * self.nx * self.NV
+            assert fa.size == self.ny * self.nx * self.NF
         if Wa is not None:
             assert Wa.size == self.ny * self.nx * 4
         lib().ugks_ref_set_state(self._h, _ptr(fa) if fa is not None else None,
@@ -242,14 +250,14 @@ class Oracle:
         return Fx, Fy
 
     def micro_flux(self):
-        Ffx = np.empty((self.ny, self.nx + 1, self.NV))
-        Ffy = np.empty((self.ny + 1, self.nx, self.NV))
+        Ffx = np.empty((self.ny, self.nx + 1, self.NF))
+        Ffy = np.empty((self.ny + 1, self.nx, self.NF))
         lib().ugks_ref_get_micro_flux(self._h, _ptr(Ffx), _ptr(Ffy))
         return Ffx, Ffy
 
     def ghost(self):
         Wg = np.empty((2, self.ny, 4))
-        fg = np.empty((2, self.ny, self.NV))
+        fg = np.empty((2, self.ny, self.NF))
         lib().ugks_ref_get_ghost(self._h, _ptr(Wg), _ptr(fg))
         return Wg, fg
 
@@ -264,6 +272,6 @@ class Oracle:
         out = np.empty((self.ny, self.nx, 4))
         for j in range(self.ny):
             for i in range(self.nx):
-                rc, p = prim(W[j, i])
+                rc, p = prim(W[j, i], self.dof)
                 out[j, i] = (p[0], p[1], p[2], 1.0 / p[3]) if rc == 0 else (np.nan,) * 4
         return out

@@ -3,6 +3,13 @@
  * tests, the smoke check and the CPU-baseline leg of the benchmark, never by the product.
  * Built with -O2 -ffp-contract=off (no fused multiply-add, no fast math).
  *
+ * Internal degrees of freedom (dof > 0, a variant beyond the paper's monatomic 2D gas): the
+ * distribution is carried as the two reduced functions G = int f dxi and H = int |xi|^2 f dxi
+ * over the dof internal coordinates xi, stored one after the other per cell (G then H).  The
+ * equilibrium of H is dof/(2 lambda) times that of G and the energy variable is
+ * psi_4 = (u^2 + v^2 + |xi|^2)/2, whose Gaussian moments need <|xi|^2> = dof/(2 lambda) and
+ * <|xi|^4> = dof (dof + 2)/(4 lambda^2).
+ *
  * Every function cites the part of the paper it follows.  Where the paper is silent (it
  * leaves the interface-flux construction to its references), the step is restated from the
  * integral solution, Eq. (2), and the reading taken is named in the comment ("reading: ...").
@@ -21,6 +28,7 @@
 struct ugks_ref {
   ugks_ref_case c;
   int K, M, NV;
+  int NC, NF;                   /* reduced functions per velocity (1, or 2 with dof > 0); NC*NV */
   double dx, dy, dt, mu_ref;
   int collisionless;
   double *uk, *vm, *wk, *wm;    /* 1D nodes and trapezoid weights */
@@ -73,28 +81,35 @@ double ugks_ref_maxwellian(const double p[4], double u, double v) {
   return p[0] * (p[3] / M_PI) * exp(-p[3] * (du * du + dv * dv));
 }
 
-/* Conservative W = (rho, rho U, rho V, rho E) <-> prim; 2D monatomic gas without internal
-   degrees of freedom: rho E = rho (U^2 + V^2)/2 + rho/(2 lambda) (reading). */
-int ugks_ref_prim(const double W[4], double p[4]) {
+/* Conservative W = (rho, rho U, rho V, rho E) <-> prim.  Two translational and dof internal
+   degrees of freedom, each holding 1/(4 lambda) per unit mass:
+   rho E = rho (U^2 + V^2)/2 + (dof + 2) rho/(4 lambda) (reading; dof = 0 is the paper's gas). */
+int ugks_ref_prim(const double W[4], double p[4], int dof) {
   double rho = W[0];
   if (!(rho > 0.0) || !isfinite(rho)) return -4;
   double U = W[1] / rho;
   double V = W[2] / rho;
-  double e = W[3] - 0.5 * rho * (U * U + V * V); /* = rho / (2 lambda) */
+  double e = W[3] - 0.5 * rho * (U * U + V * V); /* = (dof + 2) rho / (4 lambda) */
   if (!(e > 0.0) || !isfinite(e)) return -4;
   p[0] = rho;
   p[1] = U;
   p[2] = V;
-  p[3] = 0.5 * rho / e;
+  p[3] = 0.25 * (double)(dof + 2) * rho / e;
   if (!isfinite(p[1]) || !isfinite(p[2]) || !isfinite(p[3])) return -4;
   return 0;
 }
 
-static void cons_from_prim(const double p[4], double W[4]) {
+static void cons_from_prim(const double p[4], int dof, double W[4]) {
   W[0] = p[0];
   W[1] = p[0] * p[1];
   W[2] = p[0] * p[2];
-  W[3] = 0.5 * p[0] * (p[1] * p[1] + p[2] * p[2]) + 0.5 * p[0] / p[3];
+  W[3] = 0.5 * p[0] * (p[1] * p[1] + p[2] * p[2]) + 0.25 * (double)(dof + 2) * p[0] / p[3];
+}
+
+/* Gaussian moments of the internal coordinates at lambda: <|xi|^2> and <|xi|^4> */
+static void xi_moments(double lam, int dof, double* x2, double* x4) {
+  *x2 = (double)dof / (2.0 * lam);
+  *x4 = (double)(dof * (dof + 2)) / (4.0 * lam * lam);
 }
 
 /* Collision time of the BGK operator, Eq. (1).  Reading: tau = mu/p with a hard-sphere
@@ -141,39 +156,45 @@ void ugks_ref_moments_1d(double U, double lam, double full[7], double pos[7], do
   }
 }
 
-/* <u^a v^b psi>, psi = (1, u, v, (u^2+v^2)/2), with normal moments Mu and tangential Mv */
-static void mom_psi(const double* Mu, const double* Mv, int a, int b, double out[4]) {
+/* <u^a v^b psi>, psi = (1, u, v, (u^2 + v^2 + |xi|^2)/2), with normal moments Mu, tangential
+   Mv and x2 = <|xi|^2> (xi independent of u and v) */
+static void mom_psi(const double* Mu, const double* Mv, int a, int b, double x2, double out[4]) {
   out[0] = Mu[a] * Mv[b];
   out[1] = Mu[a + 1] * Mv[b];
   out[2] = Mu[a] * Mv[b + 1];
-  out[3] = 0.5 * (Mu[a + 2] * Mv[b] + Mu[a] * Mv[b + 2]);
+  out[3] = 0.5 * (Mu[a + 2] * Mv[b] + Mu[a] * Mv[b + 2] + x2 * Mu[a] * Mv[b]);
 }
 
-/* <u^a v^b psi (c . psi)> */
-static void mom_psi_c(const double* Mu, const double* Mv, int a, int b, const double c[4],
-                      double out[4]) {
-  double t0[4], t1[4], t2[4], t3[4], t4[4];
-  mom_psi(Mu, Mv, a, b, t0);
-  mom_psi(Mu, Mv, a + 1, b, t1);
-  mom_psi(Mu, Mv, a, b + 1, t2);
-  mom_psi(Mu, Mv, a + 2, b, t3);
-  mom_psi(Mu, Mv, a, b + 2, t4);
+/* <u^a v^b psi (c . psi)>; the |xi|^2 part of c_4 psi_4 brings <|xi|^2 u^a v^b psi> */
+static void mom_psi_c(const double* Mu, const double* Mv, int a, int b, double x2, double x4,
+                      const double c[4], double out[4]) {
+  double t0[4], t1[4], t2[4], t3[4], t4[4], tx[4];
+  mom_psi(Mu, Mv, a, b, x2, t0);
+  mom_psi(Mu, Mv, a + 1, b, x2, t1);
+  mom_psi(Mu, Mv, a, b + 1, x2, t2);
+  mom_psi(Mu, Mv, a + 2, b, x2, t3);
+  mom_psi(Mu, Mv, a, b + 2, x2, t4);
+  tx[0] = x2 * Mu[a] * Mv[b];
+  tx[1] = x2 * Mu[a + 1] * Mv[b];
+  tx[2] = x2 * Mu[a] * Mv[b + 1];
+  tx[3] = 0.5 * (x2 * (Mu[a + 2] * Mv[b] + Mu[a] * Mv[b + 2]) + x4 * Mu[a] * Mv[b]);
   for (int q = 0; q < 4; ++q)
-    out[q] = c[0] * t0[q] + c[1] * t1[q] + c[2] * t2[q] + 0.5 * c[3] * (t3[q] + t4[q]);
+    out[q] = c[0] * t0[q] + c[1] * t1[q] + c[2] * t2[q] +
+             0.5 * c[3] * (t3[q] + t4[q] + tx[q]);
 }
 
 /* ---------------------------------------------------------------------------------------
  * S4: micro slope.  Given prim and a moment vector s, find a = (a1..a4) such that the
  * moments of rho g (a . psi) equal s.  The 4x4 system has the closed-form solution below
- * (2D gas, no internal degrees of freedom).
+ * (2D gas with dof internal degrees of freedom; the energy row carries (dof + 2)).
  * ------------------------------------------------------------------------------------- */
-void ugks_ref_micro_slope(const double p[4], const double s[4], double a[4]) {
+void ugks_ref_micro_slope(const double p[4], const double s[4], double a[4], int dof) {
   double rho = p[0], U = p[1], V = p[2], lam = p[3];
-  double q2 = U * U + V * V + 1.0 / lam;
+  double q2 = U * U + V * V + (double)(dof + 2) / (2.0 * lam);
   double R2 = s[1] - U * s[0];
   double R3 = s[2] - V * s[0];
   double R4 = 2.0 * s[3] - q2 * s[0];
-  a[3] = 2.0 * lam * lam / rho * (R4 - 2.0 * U * R2 - 2.0 * V * R3);
+  a[3] = 4.0 * lam * lam / ((double)(dof + 2) * rho) * (R4 - 2.0 * U * R2 - 2.0 * V * R3);
   a[2] = 2.0 * lam * R3 / rho - V * a[3];
   a[1] = 2.0 * lam * R2 / rho - U * a[3];
   a[0] = s[0] / rho - U * a[1] - V * a[2] - 0.5 * a[3] * q2;
@@ -210,16 +231,17 @@ void ugks_ref_time_weights(double dt, double tau, double Mt[5]) {
    equation, int psi (A + u (a . psi) + v (b . psi)) g = 0, where the normal slope is aL for
    u > 0 and aR for u < 0. */
 void ugks_ref_time_slope(const double p[4], const double aL[4], const double aR[4],
-                         const double b[4], double A[4]) {
-  double full[7], pos[7], neg[7], tf[7], tp[7], tn[7];
+                         const double b[4], double A[4], int dof) {
+  double full[7], pos[7], neg[7], tf[7], tp[7], tn[7], x2, x4;
   ugks_ref_moments_1d(p[1], p[3], full, pos, neg);
   ugks_ref_moments_1d(p[2], p[3], tf, tp, tn);
+  xi_moments(p[3], dof, &x2, &x4);
   double m1[4], m2[4], m3[4], s[4];
-  mom_psi_c(pos, tf, 1, 0, aL, m1);
-  mom_psi_c(neg, tf, 1, 0, aR, m2);
-  mom_psi_c(full, tf, 0, 1, b, m3);
+  mom_psi_c(pos, tf, 1, 0, x2, x4, aL, m1);
+  mom_psi_c(neg, tf, 1, 0, x2, x4, aR, m2);
+  mom_psi_c(full, tf, 0, 1, x2, x4, b, m3);
   for (int q = 0; q < 4; ++q) s[q] = -p[0] * (m1[q] + m2[q] + m3[q]);
-  ugks_ref_micro_slope(p, s, A);
+  ugks_ref_micro_slope(p, s, A, dof);
 }
 
 /* S5: equilibrium part of the macroscopic flux, from the analytic Maxwellian moments:
@@ -227,22 +249,25 @@ void ugks_ref_time_slope(const double p[4], const double aL[4], const double aR[
         + <u v psi (b.psi)>) + Mt3 <u psi (A.psi)>] */
 void ugks_ref_equilibrium_flux(const double p[4], const double aL[4], const double aR[4],
                                const double b[4], const double A[4], const double Mt[5],
-                               double Feq[4]) {
-  double full[7], pos[7], neg[7], tf[7], tp[7], tn[7];
+                               double Feq[4], int dof) {
+  double full[7], pos[7], neg[7], tf[7], tp[7], tn[7], x2, x4;
   ugks_ref_moments_1d(p[1], p[3], full, pos, neg);
   ugks_ref_moments_1d(p[2], p[3], tf, tp, tn);
+  xi_moments(p[3], dof, &x2, &x4);
   double m0[4], mL[4], mR[4], mb[4], mA[4];
-  mom_psi(full, tf, 1, 0, m0);
-  mom_psi_c(pos, tf, 2, 0, aL, mL);
-  mom_psi_c(neg, tf, 2, 0, aR, mR);
-  mom_psi_c(full, tf, 1, 1, b, mb);
-  mom_psi_c(full, tf, 1, 0, A, mA);
+  mom_psi(full, tf, 1, 0, x2, m0);
+  mom_psi_c(pos, tf, 2, 0, x2, x4, aL, mL);
+  mom_psi_c(neg, tf, 2, 0, x2, x4, aR, mR);
+  mom_psi_c(full, tf, 1, 1, x2, x4, b, mb);
+  mom_psi_c(full, tf, 1, 0, x2, x4, A, mA);
   for (int q = 0; q < 4; ++q)
     Feq[q] = p[0] * (Mt[0] * m0[q] + Mt[1] * (mL[q] + mR[q] + mb[q]) + Mt[2] * mA[q]);
 }
 
-static double dot_psi(const double c[4], double un, double ut) {
-  return c[0] + c[1] * un + c[2] * ut + c[3] * 0.5 * (un * un + ut * ut);
+/* c . psi averaged over the internal coordinates with weight 1 (G, shift x2 = <|xi|^2>) or
+   with weight |xi|^2 / <|xi|^2> (H, shift <|xi|^4>/<|xi|^2> = (dof + 2)/(2 lambda)) */
+static double dot_psi(const double c[4], double un, double ut, double shift) {
+  return c[0] + c[1] * un + c[2] * ut + c[3] * 0.5 * (un * un + ut * ut + shift);
 }
 
 /* ---------------------------------------------------------------------------------------
@@ -261,11 +286,14 @@ static double dot_psi(const double c[4], double un, double ut) {
  *       (the four sums of S7).
  *   S8  distribution flux per velocity.
  * Fluxes are integrated over the step and multiplied by the face length.
+ * With dof > 0 the arrays fhat, sn, st and Ff hold 2*nvel values: G, then H, whose psi is
+ * (0, 0, 0, 1/2) in the sums and whose equilibrium is dof/(2 lambda0) times that of G.
  * ------------------------------------------------------------------------------------- */
 int ugks_ref_face(int nvel, const double* un, const double* ut, const double* w,
                   const double* fhat, const double* sn, const double* st, const double WL[4],
                   const double WR[4], double dn, double len, double dt, double mu_ref,
-                  int collisionless, double FW[4], double* Ff) {
+                  int collisionless, double FW[4], double* Ff, int dof) {
+  int nc = dof > 0 ? 2 : 1;
   double W0[4] = {0, 0, 0, 0}, Wt[4] = {0, 0, 0, 0}, Q1[4] = {0, 0, 0, 0},
          Q2[4] = {0, 0, 0, 0};
   for (int v = 0; v < nvel; ++v) {
@@ -278,17 +306,27 @@ int ugks_ref_face(int nvel, const double* un, const double* ut, const double* w,
       Q2[q] += w[v] * un[v] * psi[q] * tr;
     }
   }
+  for (int v = nvel; v < nc * nvel; ++v) {
+    int x = v - nvel;
+    double tr = un[x] * sn[v] + ut[x] * st[v];
+    W0[3] += w[x] * 0.5 * fhat[v];
+    Wt[3] += w[x] * 0.5 * st[v];
+    Q1[3] += w[x] * un[x] * 0.5 * fhat[v];
+    Q2[3] += w[x] * un[x] * 0.5 * tr;
+  }
   double Mt[5];
   if (collisionless) {
     ugks_ref_time_weights(dt, INFINITY, Mt);
     for (int q = 0; q < 4; ++q) FW[q] = len * (Mt[3] * Q1[q] - Mt[4] * Q2[q]);
     if (Ff)
-      for (int v = 0; v < nvel; ++v)
-        Ff[v] = len * un[v] * (Mt[3] * fhat[v] - Mt[4] * (un[v] * sn[v] + ut[v] * st[v]));
+      for (int v = 0; v < nc * nvel; ++v) {
+        int x = v % nvel;
+        Ff[v] = len * un[x] * (Mt[3] * fhat[v] - Mt[4] * (un[x] * sn[v] + ut[x] * st[v]));
+      }
     return 0;
   }
   double p0[4];
-  if (ugks_ref_prim(W0, p0)) return -4;
+  if (ugks_ref_prim(W0, p0, dof)) return -4;
   double tau0 = collision_time(mu_ref, p0);
   ugks_ref_time_weights(dt, tau0, Mt);
   double swL[4], swR[4], Wt_[4];
@@ -298,23 +336,28 @@ int ugks_ref_face(int nvel, const double* un, const double* ut, const double* w,
     Wt_[q] = Wt[q];
   }
   double aL[4], aR[4], b[4], A[4], Feq[4];
-  ugks_ref_micro_slope(p0, swL, aL);
-  ugks_ref_micro_slope(p0, swR, aR);
-  ugks_ref_micro_slope(p0, Wt_, b);
-  ugks_ref_time_slope(p0, aL, aR, b, A);
-  ugks_ref_equilibrium_flux(p0, aL, aR, b, A, Mt, Feq);
+  ugks_ref_micro_slope(p0, swL, aL, dof);
+  ugks_ref_micro_slope(p0, swR, aR, dof);
+  ugks_ref_micro_slope(p0, Wt_, b, dof);
+  ugks_ref_time_slope(p0, aL, aR, b, A, dof);
+  ugks_ref_equilibrium_flux(p0, aL, aR, b, A, Mt, Feq, dof);
   for (int q = 0; q < 4; ++q) FW[q] = len * (Feq[q] + Mt[3] * Q1[q] - Mt[4] * Q2[q]);
   if (Ff) {
-    for (int v = 0; v < nvel; ++v) {
-      double H = un[v] > 0.0 ? 1.0 : (un[v] < 0.0 ? 0.0 : 0.5);
+    double x2, x4;
+    xi_moments(p0[3], dof, &x2, &x4);
+    for (int v = 0; v < nc * nvel; ++v) {
+      int x = v % nvel, h = v >= nvel;
+      double H = un[x] > 0.0 ? 1.0 : (un[x] < 0.0 ? 0.0 : 0.5);
       double a[4];
       for (int q = 0; q < 4; ++q) a[q] = H * aL[q] + (1.0 - H) * aR[q];
-      double G = ugks_ref_maxwellian(p0, un[v], ut[v]);
-      double poly = Mt[0] + Mt[1] * (un[v] * dot_psi(a, un[v], ut[v]) +
-                                     ut[v] * dot_psi(b, un[v], ut[v])) +
-                    Mt[2] * dot_psi(A, un[v], ut[v]);
-      Ff[v] = len * un[v] *
-              (G * poly + Mt[3] * fhat[v] - Mt[4] * (un[v] * sn[v] + ut[v] * st[v]));
+      /* H: weight |xi|^2 gives the factor x2 and the shift x4/x2 */
+      double G = ugks_ref_maxwellian(p0, un[x], ut[x]) * (h ? x2 : 1.0);
+      double shift = h ? x4 / x2 : x2;
+      double poly = Mt[0] + Mt[1] * (un[x] * dot_psi(a, un[x], ut[x], shift) +
+                                     ut[x] * dot_psi(b, un[x], ut[x], shift)) +
+                    Mt[2] * dot_psi(A, un[x], ut[x], shift);
+      Ff[v] = len * un[x] *
+              (G * poly + Mt[3] * fhat[v] - Mt[4] * (un[x] * sn[v] + ut[x] * st[v]));
     }
   }
   return 0;
@@ -330,12 +373,15 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
   if (!(c->lx > 0) || !(c->ly > 0) || !(c->umax > 0) || !(c->vmax > 0)) return NULL;
   if (!(c->kn > 0) || !(c->rho0 > 0) || !(c->T0 > 0)) return NULL;
   if (c->bc != 0 && c->bc != 1) return NULL;
+  if (c->dof < 0 || c->dof > 16) return NULL;
   if (c->bc == 1 && (!(c->p_ratio > 0) || !(c->T_in > 0) || !(c->T_wall > 0))) return NULL;
   ugks_ref* s = (ugks_ref*)calloc(1, sizeof(ugks_ref));
   s->c = *c;
   s->K = c->nu;
   s->M = c->nv;
   s->NV = c->nu * c->nv;
+  s->NC = c->dof > 0 ? 2 : 1;
+  s->NF = s->NC * s->NV;
   s->dx = c->lx / c->nx;
   s->dy = c->ly / c->ny;
   s->collisionless = isinf(c->kn) ? 1 : 0;
@@ -343,7 +389,7 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
   /* reading: fixed step from the CFL number and the largest discrete speeds */
   s->dt = c->dt_override > 0 ? c->dt_override
                              : c->cfl / (c->umax / s->dx + c->vmax / s->dy);
-  size_t nc = (size_t)c->nx * c->ny, NV = (size_t)s->NV;
+  size_t nc = (size_t)c->nx * c->ny, NV = (size_t)s->NF;
   s->uk = malloc(sizeof(double) * s->K);
   s->wk = malloc(sizeof(double) * s->K);
   s->vm = malloc(sizeof(double) * s->M);
@@ -376,10 +422,14 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
       size_t ci = cidx(s, i, j);
       double p[4] = {c->rho0 * (1.0 + c->noise * ugks_ref_unit_noise(c->seed, ci)), 0.0, 0.0,
                      1.0 / c->T0};
-      cons_from_prim(p, s->W + 4 * ci);
+      cons_from_prim(p, c->dof, s->W + 4 * ci);
+      double kap = (double)c->dof / (2.0 * p[3]);  /* H = dof/(2 lambda) G at equilibrium */
       for (int k = 0; k < s->K; ++k)
-        for (int m = 0; m < s->M; ++m)
-          s->f[ci * NV + (size_t)k * s->M + m] = ugks_ref_maxwellian(p, s->uk[k], s->vm[m]);
+        for (int m = 0; m < s->M; ++m) {
+          size_t v = ci * NV + (size_t)k * s->M + m;
+          s->f[v] = ugks_ref_maxwellian(p, s->uk[k], s->vm[m]);
+          if (s->NC > 1) s->f[v + s->NV] = kap * s->f[v];
+        }
     }
   }
   return s;
@@ -417,12 +467,12 @@ int ugks_ref_get_threads(void) {
 
 void ugks_ref_get_state(const ugks_ref* s, double* f, double* W) {
   size_t nc = (size_t)s->c.nx * s->c.ny;
-  if (f) memcpy(f, s->f, sizeof(double) * nc * s->NV);
+  if (f) memcpy(f, s->f, sizeof(double) * nc * s->NF);
   if (W) memcpy(W, s->W, sizeof(double) * nc * 4);
 }
 void ugks_ref_set_state(ugks_ref* s, const double* f, const double* W) {
   size_t nc = (size_t)s->c.nx * s->c.ny;
-  if (f) memcpy(s->f, f, sizeof(double) * nc * s->NV);
+  if (f) memcpy(s->f, f, sizeof(double) * nc * s->NF);
   if (W) memcpy(s->W, W, sizeof(double) * nc * 4);
 }
 void ugks_ref_get_face_flux(const ugks_ref* s, double* Fx, double* Fy) {
@@ -430,13 +480,13 @@ void ugks_ref_get_face_flux(const ugks_ref* s, double* Fx, double* Fy) {
   if (Fy) memcpy(Fy, s->Fy, sizeof(double) * (size_t)s->c.nx * (s->c.ny + 1) * 4);
 }
 void ugks_ref_get_micro_flux(const ugks_ref* s, double* Ffx, double* Ffy) {
-  size_t NV = (size_t)s->NV;
+  size_t NV = (size_t)s->NF;
   if (Ffx) memcpy(Ffx, s->Ffx, sizeof(double) * (size_t)(s->c.nx + 1) * s->c.ny * NV);
   if (Ffy) memcpy(Ffy, s->Ffy, sizeof(double) * (size_t)s->c.nx * (s->c.ny + 1) * NV);
 }
 void ugks_ref_get_ghost(const ugks_ref* s, double* Wg, double* fg) {
   if (Wg) memcpy(Wg, s->Wg, sizeof(double) * 2 * (size_t)s->c.ny * 4);
-  if (fg) memcpy(fg, s->fg, sizeof(double) * 2 * (size_t)s->c.ny * s->NV);
+  if (fg) memcpy(fg, s->fg, sizeof(double) * 2 * (size_t)s->c.ny * s->NF);
 }
 
 /* ---------------------------------------------------------------------------------------
@@ -444,7 +494,8 @@ void ugks_ref_get_ghost(const ugks_ref* s, double* Wg, double* fg) {
  * Reading: the mean of p_in and p_out is p0 = rho0 T0 / 2 and their ratio is p_ratio.
  * Inlet: p_in and T_in fixed, (U, V) taken from the first column (or a fixed, seeded U).
  * Outlet: p_out fixed, (U, V, T) taken from the last column.  Ghost rho = 2 p / T, ghost
- * f = discrete Maxwellian of the ghost state; ghost slopes are zero.
+ * f = discrete Maxwellian of the ghost state (H: dof/(2 lambda) times it); ghost slopes are
+ * zero.
  * ------------------------------------------------------------------------------------- */
 static int channel_ghosts(ugks_ref* s) {
   const ugks_ref_case* c = &s->c;
@@ -453,7 +504,7 @@ static int channel_ghosts(ugks_ref* s) {
   double p_out = 2.0 * p0 / (c->p_ratio + 1.0);
   for (int j = 0; j < c->ny; ++j) {
     double pin[4], pout[4], pr[4];
-    if (ugks_ref_prim(s->W + 4 * cidx(s, 0, j), pr)) return -4;
+    if (ugks_ref_prim(s->W + 4 * cidx(s, 0, j), pr, c->dof)) return -4;
     if (c->inlet_fixed_u) {
       pin[1] = c->U_in * (1.0 + c->U_noise * s->xi_in[j]);
       pin[2] = 0.0;
@@ -463,19 +514,26 @@ static int channel_ghosts(ugks_ref* s) {
     }
     pin[3] = 1.0 / c->T_in;
     pin[0] = 2.0 * p_in / c->T_in;
-    if (ugks_ref_prim(s->W + 4 * cidx(s, c->nx - 1, j), pr)) return -4;
+    if (ugks_ref_prim(s->W + 4 * cidx(s, c->nx - 1, j), pr, c->dof)) return -4;
     double Tout = 1.0 / pr[3];
     pout[0] = 2.0 * p_out / Tout;
     pout[1] = pr[1];
     pout[2] = pr[2];
     pout[3] = pr[3];
-    cons_from_prim(pin, s->Wg + 4 * (size_t)j);
-    cons_from_prim(pout, s->Wg + 4 * ((size_t)c->ny + j));
+    cons_from_prim(pin, c->dof, s->Wg + 4 * (size_t)j);
+    cons_from_prim(pout, c->dof, s->Wg + 4 * ((size_t)c->ny + j));
+    double kin = (double)c->dof / (2.0 * pin[3]), kout = (double)c->dof / (2.0 * pout[3]);
+    double* gin = s->fg + (size_t)j * s->NF;
+    double* gout = s->fg + ((size_t)c->ny + j) * s->NF;
     for (int k = 0; k < s->K; ++k)
       for (int m = 0; m < s->M; ++m) {
         size_t v = (size_t)k * s->M + m;
-        s->fg[(size_t)j * s->NV + v] = ugks_ref_maxwellian(pin, s->uk[k], s->vm[m]);
-        s->fg[((size_t)c->ny + j) * s->NV + v] = ugks_ref_maxwellian(pout, s->uk[k], s->vm[m]);
+        gin[v] = ugks_ref_maxwellian(pin, s->uk[k], s->vm[m]);
+        gout[v] = ugks_ref_maxwellian(pout, s->uk[k], s->vm[m]);
+        if (s->NC > 1) {
+          gin[v + s->NV] = kin * gin[v];
+          gout[v + s->NV] = kout * gout[v];
+        }
       }
   }
   return 0;
@@ -484,9 +542,9 @@ static int channel_ghosts(ugks_ref* s) {
 /* f of the x-neighbour (i + di, j): a cell, a wrapped cell, or a channel ghost */
 static const double* fx_nb(const ugks_ref* s, int i, int j) {
   int nx = s->c.nx;
-  if (i >= 0 && i < nx) return s->f + cidx(s, i, j) * s->NV;
-  if (s->c.bc == 0) return s->f + cidx(s, (i + nx) % nx, j) * s->NV;
-  return s->fg + ((size_t)(i < 0 ? 0 : s->c.ny) + j) * s->NV;
+  if (i >= 0 && i < nx) return s->f + cidx(s, i, j) * s->NF;
+  if (s->c.bc == 0) return s->f + cidx(s, (i + nx) % nx, j) * s->NF;
+  return s->fg + ((size_t)(i < 0 ? 0 : s->c.ny) + j) * s->NF;
 }
 
 /* ---------------------------------------------------------------------------------------
@@ -495,7 +553,7 @@ static const double* fx_nb(const ugks_ref* s, int i, int j) {
  * columns next to the inlet and outlet use the ghost value.
  * ------------------------------------------------------------------------------------- */
 static void slopes(ugks_ref* s) {
-  int nx = s->c.nx, ny = s->c.ny, NV = s->NV;
+  int nx = s->c.nx, ny = s->c.ny, NV = s->NF;  /* G and H alike */
 #pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
@@ -518,10 +576,12 @@ static void slopes(ugks_ref* s) {
  * Diffuse isothermal wall (not described in the paper; reading).  Particles leaving the
  * wall follow rho_w g(1, 0, 0, T_wall) with rho_w set by zero net discrete mass flux;
  * particles reaching it carry the wall-row cell value (first order in space and time).
- * F_f = dx dt v f_wall, F_W = sum w psi F_f.  top != 0: wall above the cell.
+ * F_f = dx dt v f_wall, F_W = sum w psi F_f.  top != 0: wall above the cell.  With dof > 0
+ * the reflected H is dof/(2 lambda_w) times the reflected G and adds its energy to F_W.
  * ------------------------------------------------------------------------------------- */
 static void wall_face(const ugks_ref* s, const double* fc, int top, double FW[4], double* Ff) {
   double pw[4] = {1.0, 0.0, 0.0, 1.0 / s->c.T_wall};
+  double kw = (double)s->c.dof * s->c.T_wall / 2.0;
   double num = 0.0, den = 0.0;
   for (int k = 0; k < s->K; ++k)
     for (int m = 0; m < s->M; ++m) {
@@ -543,12 +603,19 @@ static void wall_face(const ugks_ref* s, const double* fc, int top, double FW[4]
       Ff[v] = s->dx * s->dt * vv * fw;
       double psi[4] = {1.0, uu, vv, 0.5 * (uu * uu + vv * vv)};
       for (int q = 0; q < 4; ++q) FW[q] += w * psi[q] * Ff[v];
+      if (s->NC > 1) {
+        size_t h = v + (size_t)s->NV;
+        double hw = from ? kw * rho_w * ugks_ref_maxwellian(pw, uu, vv) : fc[h];
+        Ff[h] = s->dx * s->dt * vv * hw;
+        FW[3] += w * 0.5 * Ff[h];
+      }
     }
 }
 
 /* O3-O5: all faces of the mesh.  x-face i of row j lies between cells i-1 and i. */
 static int faces(ugks_ref* s) {
-  int nx = s->c.nx, ny = s->c.ny, NV = s->NV, K = s->K, M = s->M;
+  int nx = s->c.nx, ny = s->c.ny, NV = s->NV, NF = s->NF, K = s->K, M = s->M;
+  int dof = s->c.dof;
   int per = s->c.bc == 0;
   int err = 0;
 #pragma omp parallel reduction(| : err)
@@ -556,9 +623,9 @@ static int faces(ugks_ref* s) {
     double* un = malloc(sizeof(double) * NV);
     double* ut = malloc(sizeof(double) * NV);
     double* w = malloc(sizeof(double) * NV);
-    double* fh = malloc(sizeof(double) * NV);
-    double* sn = malloc(sizeof(double) * NV);
-    double* st = malloc(sizeof(double) * NV);
+    double* fh = malloc(sizeof(double) * NF);
+    double* sn = malloc(sizeof(double) * NF);
+    double* st = malloc(sizeof(double) * NF);
     /* x-faces: normal u, tangential v, local W = W */
 #pragma omp for schedule(static)
     for (int j = 0; j < ny; ++j)
@@ -568,21 +635,21 @@ static int faces(ugks_ref* s) {
         const double *WL, *WR;
         if (per) il = (il + nx) % nx;
         if (il >= 0) {
-          fL = s->f + cidx(s, il, j) * NV;
-          sxL = s->sx + cidx(s, il, j) * NV;
-          syL = s->sy + cidx(s, il, j) * NV;
+          fL = s->f + cidx(s, il, j) * NF;
+          sxL = s->sx + cidx(s, il, j) * NF;
+          syL = s->sy + cidx(s, il, j) * NF;
           WL = s->W + 4 * cidx(s, il, j);
         } else {
-          fL = s->fg + (size_t)j * NV;
+          fL = s->fg + (size_t)j * NF;
           WL = s->Wg + 4 * (size_t)j;
         }
         if (ir < nx) {
-          fR = s->f + cidx(s, ir, j) * NV;
-          sxR = s->sx + cidx(s, ir, j) * NV;
-          syR = s->sy + cidx(s, ir, j) * NV;
+          fR = s->f + cidx(s, ir, j) * NF;
+          sxR = s->sx + cidx(s, ir, j) * NF;
+          syR = s->sy + cidx(s, ir, j) * NF;
           WR = s->W + 4 * cidx(s, ir, j);
         } else {
-          fR = s->fg + ((size_t)ny + j) * NV;
+          fR = s->fg + ((size_t)ny + j) * NF;
           WR = s->Wg + 4 * ((size_t)ny + j);
         }
         for (int k = 0; k < K; ++k)
@@ -593,15 +660,17 @@ static int faces(ugks_ref* s) {
             w[v] = s->wk[k] * s->wm[m];
             /* reading: H(0) = 1/2 */
             double H = un[v] > 0.0 ? 1.0 : (un[v] < 0.0 ? 0.0 : 0.5);
-            double sxl = sxL ? sxL[v] : 0.0, syl = syL ? syL[v] : 0.0;
-            double sxr = sxR ? sxR[v] : 0.0, syr = syR ? syR[v] : 0.0;
-            fh[v] = H * (fL[v] + 0.5 * s->dx * sxl) + (1.0 - H) * (fR[v] - 0.5 * s->dx * sxr);
-            sn[v] = H * sxl + (1.0 - H) * sxr;
-            st[v] = H * syl + (1.0 - H) * syr;
+            for (int x = v; x < NF; x += NV) {  /* G, then H */
+              double sxl = sxL ? sxL[x] : 0.0, syl = syL ? syL[x] : 0.0;
+              double sxr = sxR ? sxR[x] : 0.0, syr = syR ? syR[x] : 0.0;
+              fh[x] = H * (fL[x] + 0.5 * s->dx * sxl) + (1.0 - H) * (fR[x] - 0.5 * s->dx * sxr);
+              sn[x] = H * sxl + (1.0 - H) * sxr;
+              st[x] = H * syl + (1.0 - H) * syr;
+            }
           }
         size_t fi = (size_t)j * (nx + 1) + i;
         if (ugks_ref_face(NV, un, ut, w, fh, sn, st, WL, WR, s->dx, s->dy, s->dt, s->mu_ref,
-                          s->collisionless, s->Fx + 4 * fi, s->Ffx + fi * NV))
+                          s->collisionless, s->Fx + 4 * fi, s->Ffx + fi * NF, dof))
           err |= 1;
       }
     /* y-faces: normal v, tangential u, local W = (rho, rho V, rho U, rho E) */
@@ -610,15 +679,15 @@ static int faces(ugks_ref* s) {
       for (int i = 0; i < nx; ++i) {
         size_t fi = (size_t)j * nx + i;
         if (!per && (j == 0 || j == ny)) {
-          wall_face(s, s->f + cidx(s, i, j == 0 ? 0 : ny - 1) * NV, j == ny, s->Fy + 4 * fi,
-                    s->Ffy + fi * NV);
+          wall_face(s, s->f + cidx(s, i, j == 0 ? 0 : ny - 1) * NF, j == ny, s->Fy + 4 * fi,
+                    s->Ffy + fi * NF);
           continue;
         }
         int jl = per ? (j - 1 + ny) % ny : j - 1, jr = j;
         size_t cl = cidx(s, i, jl), cr = cidx(s, i, jr);
-        const double *fL = s->f + cl * NV, *fR = s->f + cr * NV;
-        const double *sxL = s->sx + cl * NV, *syL = s->sy + cl * NV;
-        const double *sxR = s->sx + cr * NV, *syR = s->sy + cr * NV;
+        const double *fL = s->f + cl * NF, *fR = s->f + cr * NF;
+        const double *sxL = s->sx + cl * NF, *syL = s->sy + cl * NF;
+        const double *sxR = s->sx + cr * NF, *syR = s->sy + cr * NF;
         const double* WLg = s->W + 4 * cl;
         const double* WRg = s->W + 4 * cr;
         double WL[4] = {WLg[0], WLg[2], WLg[1], WLg[3]};
@@ -630,13 +699,15 @@ static int faces(ugks_ref* s) {
             ut[v] = s->uk[k];
             w[v] = s->wk[k] * s->wm[m];
             double H = un[v] > 0.0 ? 1.0 : (un[v] < 0.0 ? 0.0 : 0.5);
-            fh[v] = H * (fL[v] + 0.5 * s->dy * syL[v]) + (1.0 - H) * (fR[v] - 0.5 * s->dy * syR[v]);
-            sn[v] = H * syL[v] + (1.0 - H) * syR[v];
-            st[v] = H * sxL[v] + (1.0 - H) * sxR[v];
+            for (int x = v; x < NF; x += NV) {
+              fh[x] = H * (fL[x] + 0.5 * s->dy * syL[x]) + (1.0 - H) * (fR[x] - 0.5 * s->dy * syR[x]);
+              sn[x] = H * syL[x] + (1.0 - H) * syR[x];
+              st[x] = H * sxL[x] + (1.0 - H) * sxR[x];
+            }
           }
         double FWl[4];
         if (ugks_ref_face(NV, un, ut, w, fh, sn, st, WL, WR, s->dy, s->dx, s->dt, s->mu_ref,
-                          s->collisionless, FWl, s->Ffy + fi * NV))
+                          s->collisionless, FWl, s->Ffy + fi * NF, dof))
           err |= 1;
         double* F = s->Fy + 4 * fi;
         F[0] = FWl[0];
@@ -651,11 +722,11 @@ static int faces(ugks_ref* s) {
     for (int j = 0; j < ny; ++j) {
       memcpy(s->Fx + 4 * ((size_t)j * (nx + 1) + nx), s->Fx + 4 * ((size_t)j * (nx + 1)),
              sizeof(double) * 4);
-      memcpy(s->Ffx + ((size_t)j * (nx + 1) + nx) * NV, s->Ffx + ((size_t)j * (nx + 1)) * NV,
-             sizeof(double) * NV);
+      memcpy(s->Ffx + ((size_t)j * (nx + 1) + nx) * NF, s->Ffx + ((size_t)j * (nx + 1)) * NF,
+             sizeof(double) * NF);
     }
     memcpy(s->Fy + 4 * (size_t)ny * nx, s->Fy, sizeof(double) * 4 * nx);
-    memcpy(s->Ffy + (size_t)ny * nx * NV, s->Ffy, sizeof(double) * (size_t)nx * NV);
+    memcpy(s->Ffy + (size_t)ny * nx * NF, s->Ffy, sizeof(double) * (size_t)nx * NF);
   }
   return err ? -4 : 0;
 }
@@ -666,10 +737,12 @@ static int faces(ugks_ref* s) {
  * in f^{n+1} through g^{n+1} and tau^{n+1} built from W^{n+1}:
  *   f^{n+1} = [f^n + dF/(dx dy) + dt/2 (g^{n+1}/tau^{n+1} + (g^n - f^n)/tau^n)]
  *             / (1 + dt/(2 tau^{n+1})).
- * The collisionless limit drops the collision term.
+ * The collisionless limit drops the collision term.  H takes the same update with the
+ * equilibria dof/(2 lambda^n) g^n and dof/(2 lambda^{n+1}) g^{n+1}.
  * ------------------------------------------------------------------------------------- */
 static int update(ugks_ref* s) {
-  int nx = s->c.nx, ny = s->c.ny, NV = s->NV, K = s->K, M = s->M;
+  int nx = s->c.nx, ny = s->c.ny, NV = s->NF, NG = s->NV, K = s->K, M = s->M;
+  int dof = s->c.dof;
   double area = s->dx * s->dy, dt = s->dt;
   int err = 0;
 #pragma omp parallel for schedule(static) reduction(| : err)
@@ -694,19 +767,25 @@ static int update(ugks_ref* s) {
         continue;
       }
       double pn[4], pn1[4];
-      if (ugks_ref_prim(W, pn) || ugks_ref_prim(Wn, pn1)) {
+      if (ugks_ref_prim(W, pn, dof) || ugks_ref_prim(Wn, pn1, dof)) {
         err |= 1;
         continue;
       }
       double tn = collision_time(s->mu_ref, pn), tn1 = collision_time(s->mu_ref, pn1);
+      double kn = (double)dof / (2.0 * pn[3]), kn1 = (double)dof / (2.0 * pn1[3]);
       for (int k = 0; k < K; ++k)
-        for (int m = 0; m < M; ++m) {
-          int v = k * M + m;
-          double gn = ugks_ref_maxwellian(pn, s->uk[k], s->vm[m]);
-          double gn1 = ugks_ref_maxwellian(pn1, s->uk[k], s->vm[m]);
-          double dF = (Ffl[v] - Ffr[v] + Ffb[v] - Fft[v]) / area;
-          fn[v] = (f[v] + dF + 0.5 * dt * (gn1 / tn1 + (gn - f[v]) / tn)) / (1.0 + 0.5 * dt / tn1);
-        }
+        for (int m = 0; m < M; ++m)
+          for (int v = k * M + m; v < NV; v += NG) {  /* G, then H */
+            double gn = ugks_ref_maxwellian(pn, s->uk[k], s->vm[m]);
+            double gn1 = ugks_ref_maxwellian(pn1, s->uk[k], s->vm[m]);
+            if (v >= NG) {
+              gn *= kn;
+              gn1 *= kn1;
+            }
+            double dF = (Ffl[v] - Ffr[v] + Ffb[v] - Fft[v]) / area;
+            fn[v] = (f[v] + dF + 0.5 * dt * (gn1 / tn1 + (gn - f[v]) / tn)) /
+                    (1.0 + 0.5 * dt / tn1);
+          }
     }
   return err ? -4 : 0;
 }
@@ -726,7 +805,7 @@ int ugks_ref_step(ugks_ref* s, int n) {
     s->Wnew = t;
     for (size_t c = 0; c < nc; ++c) {
       double p[4];
-      if (ugks_ref_prim(s->W + 4 * c, p)) return -4;
+      if (ugks_ref_prim(s->W + 4 * c, p, s->c.dof)) return -4;
     }
   }
   return 0;
