@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--paper-sweep", action="store_true",
                     help="also time the paper's meshes M1-M4 at 29^2, 49^2 and 69^2 velocities")
     ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--no-internal-dof", action="store_true",
+                    help="skip the gas with one internal degree of freedom (G and H)")
     ap.add_argument("--shard-share", action="store_true",
                     help="also time one GPU's share of the 400x100 case split 8 ways along x")
     return ap.parse_args()
@@ -153,6 +155,28 @@ def shard_share(WL, ugks, steps, warmup):
     return {"cells": [case["nx"], case["ny"]], "velocities": [case["nu"], case["nv"]],
             "ms_per_step": ms / steps, "updates_per_s": WL.updates(case) * steps / (ms * 1e-3),
             "kernels": prof, "halo_bytes_per_side": halo_bytes, "halo_us_at_153GBs": halo_bytes / 153e9 * 1e6}
+
+
+def internal_dof(WL, ugks, steps, warmup):
+    """The 400x100 x 40^2 channel for a gas with one internal degree of freedom (FP64): every
+    cell-velocity update advances both G and H, so the algorithmic traffic is 32 B."""
+    case = WL.C2_DOF
+    kn, kw = WL.solver_kwargs(case, "fp64")
+    s = ugks.Solver(kn, **kw)
+    try:
+        ms, _ = time_solver(s, steps, warmup)
+        prof = kernel_profile(s, min(steps, 200))
+        s.moments()
+    finally:
+        s.close()
+    upd = WL.updates(case)
+    upd_ms = prof["update"]["avg_ms"]
+    return {"internal_dof": case["dof"], "ms_per_step": ms / steps,
+            "updates_per_s": upd * steps / (ms * 1e-3),
+            "distribution_values_per_s": 2 * upd * steps / (ms * 1e-3),
+            "update_kernel_GBs": 32.0 * upd / (upd_ms * 1e-3) / 1e9,
+            "step_hbm_frac": 32.0 * upd / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernels": prof}
 
 
 def run_form(WL, ugks, precision, steps, warmup):
@@ -348,6 +372,8 @@ def main():
         out["serving"] = serving(args, fp64["updates_per_s"])
     if args.paper_sweep:
         out["paper_sweep"] = paper_sweep(WL, ugks, args.sweep_steps)
+    if not args.no_internal_dof:
+        out["internal_dof"] = internal_dof(WL, ugks, min(args.steps, 500), args.warmup)
     if args.shard_share:
         out["shard_share"] = shard_share(WL, ugks, min(args.steps, 500), args.warmup)
     if not args.no_cpu_baseline:

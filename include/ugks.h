@@ -4,9 +4,10 @@
  *
  * The problem follows the paper "Performance Comparison on Parallel CPU and GPU Algorithms
  * for Unified Gas-Kinetic Scheme" (Liu, Hu & Li):
- *   - BGK-Boltzmann equation with a Maxwellian equilibrium, Eq. (1); 2D monatomic gas
- *     without internal degrees of freedom; velocities in units of sqrt(2kT0/m), so the
- *     Maxwellian is rho (lambda/pi) exp(-lambda |c - U|^2) with lambda = 1/T.
+ *   - BGK-Boltzmann equation with a Maxwellian equilibrium, Eq. (1); 2D gas, velocities in
+ *     units of sqrt(2kT0/m), so the Maxwellian is rho (lambda/pi) exp(-lambda |c - U|^2)
+ *     with lambda = 1/T.  The paper's gas has no internal degrees of freedom; a gas with
+ *     internal_dof > 0 (ugks_vgrid) carries a second reduced distribution for their energy.
  *   - Finite volumes over nx*ny uniform Cartesian cells, nu*nv discrete molecular
  *     velocities per cell (Sec. 2).
  *   - Interface fluxes from the integral solution of the BGK equation, Eq. (2), built
@@ -21,7 +22,9 @@
  *     unless the caller passes a workspace in ugks_opts, which then stays the caller's and
  *     must outlive the handle.
  *   - Host arrays use the canonical layout: cell (i, j) is at index j*nx + i (x fastest);
- *     the velocity index is k*nv + m for (u_k, v_m); f[(j*nx + i)*nu*nv + k*nv + m];
+ *     the velocity index is k*nv + m for (u_k, v_m); f[(j*nx + i)*NF + c*nu*nv + k*nv + m]
+ *     with NF = nc*nu*nv values per cell, nc = 1 (c = 0 only) or, with internal degrees of
+ *     freedom, nc = 2 (c = 0: G, c = 1: H);
  *     W[(j*nx + i)*4 + q] with W = (rho, rho U, rho V, rho E).
  *   - Work is enqueued on the stream given in ugks_opts (hipStream_t; NULL = the default
  *     stream).  Only ugks_moments, ugks_get_state, ugks_set_state, ugks_get_face_flux,
@@ -56,10 +59,17 @@ typedef struct {
 
 /* Discrete velocity grid (Sec. 2: K x M points (u_k, v_m)): nu uniform points on
    [-umax, umax] and nv on [-vmax, vmax], both ends included, trapezoid weights, built
-   exactly mirror-symmetric.  2 <= nu, nv <= 1024; otherwise UGKS_E_INVAL. */
+   exactly mirror-symmetric.  2 <= nu, nv <= 1024; otherwise UGKS_E_INVAL.
+   internal_dof (0..16): degrees of freedom of the molecule beyond the two velocities of the
+   plane (0: the paper's gas, gamma = 2; 1: a monatomic gas in 3D seen in the plane,
+   gamma = 5/3; 3: diatomic, gamma = 7/5).  With internal_dof > 0 each velocity carries
+   G = int f dxi and H = int |xi|^2 f dxi over the internal coordinates xi, the energy is
+   rho E = sum w (u^2 + v^2)/2 G + sum w H/2 = rho |U|^2/2 + (2 + internal_dof) rho T/4, and
+   the equilibrium of H is internal_dof T/2 times that of G.  It doubles the f storage. */
 typedef struct {
   int nu, nv;
   double umax, vmax;
+  int internal_dof;
 } ugks_vgrid;
 
 #define UGKS_BC_PERIODIC 0 /* periodic in x and y */
@@ -86,7 +96,7 @@ typedef struct {
    precision        UGKS_FP64 or UGKS_FP32_STORE.
    cfl              time step dt = cfl / (umax/dx + vmax/dy) unless dt_override > 0.
    rho0, T0, noise  initial state: rho = rho0 (1 + noise xi_c), U = V = 0, T = T0, and f the
-                    discrete Maxwellian of that state (|noise| < 1).
+                    discrete Maxwellian of that state (|noise| < 1; H = internal_dof T0/2 G).
    velocity_chunks  Each velocity quadrant of a row segment is split over G workgroups.
                     0: automatic, enough to fill the GPU with this solver alone (at most 16
                     and nu/2); n in 1..16: at most n (the automatic choice capped at n).
@@ -116,6 +126,7 @@ typedef struct {
   int plane_stride; /* values between the velocity planes of f in device memory: f is
                        stored per velocity as (ny+4) x (nx+4) padded planes */
   int precision;
+  int internal_dof;
   double dx, dy, dt;
   double tau_ref;  /* collision time at rho = T = 1; +inf in the collisionless limit */
   int64_t steps;   /* steps enqueued so far */
@@ -155,7 +166,7 @@ const char* ugks_last_error(const ugks_handle* h);
 /* Shape, step and memory of a handle. */
 int ugks_get_info(const ugks_handle* h, ugks_info* out);
 
-/* Checkpoint / test hooks.  f: nx*ny*nu*nv doubles, W: 4*nx*ny doubles, canonical layout,
+/* Checkpoint / test hooks.  f: nx*ny*NF doubles, W: 4*nx*ny doubles, canonical layout,
    caller-owned host memory; either may be NULL.  get waits for the stream; set replaces
    the current state (in FP32-store mode f is rounded to FP32). */
 int ugks_get_state(ugks_handle* h, double* f, double* W);

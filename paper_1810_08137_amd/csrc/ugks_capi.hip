@@ -135,6 +135,7 @@ double noise_unit(uint64_t s, uint64_t k) {
 
 struct Shape {
   int nx, ny, K, M, NV;
+  int dof, NC;  // internal degrees of freedom; reduced distributions per velocity
   int Lx, Ly;
   size_t PS;  // values per velocity plane
   size_t nc;
@@ -165,6 +166,10 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
     why = "umax and vmax must be positive and finite";
     return false;
   }
+  if (vg->internal_dof < 0 || vg->internal_dof > 16) {
+    why = "internal_dof must be in 0..16";
+    return false;
+  }
   // the kernels address a plane (cells and halo) with 32-bit byte offsets
   if (((double)mesh->nx + 2 * kHalo) * ((double)mesh->ny + 2 * kHalo) > (double)(1 << 28)) {
     why = "too many cells: (nx + 4)(ny + 4) must not exceed 2^28";
@@ -175,6 +180,8 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
   s.K = vg->nu;
   s.M = vg->nv;
   s.NV = vg->nu * vg->nv;
+  s.dof = vg->internal_dof;
+  s.NC = s.dof > 0 ? 2 : 1;
   s.Lx = s.nx + 2 * kHalo;
   s.Ly = s.ny + 2 * kHalo;
   s.PS = round_up((size_t)s.Lx * (size_t)s.Ly, (size_t)kWave);
@@ -185,22 +192,22 @@ bool shape_ok(const ugks_mesh* mesh, const ugks_vgrid* vg, Shape& s, std::string
 // Offsets of every buffer inside the workspace.
 // Velocity chunks of a solver: the automatic choice, capped at the requested number.
 int chunks_of(const Shape& s, int cap) {
-  const int a = velocity_chunks(s.nx, s.ny, s.K);
+  const int a = velocity_chunks(s.nx, s.ny, s.K, s.NC);
   return cap > 0 && cap < a ? cap : a;
 }
 
 Layout layout_of(const Shape& s, int prec, int chunks) {
   const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
   const size_t sizes[14] = {
-      (size_t)s.NV * s.PS * ss,                 // f0: NV planes
-      (size_t)s.NV * s.PS * ss,                 // f1
+      (size_t)s.NC * s.NV * s.PS * ss,          // f0: NC NV planes
+      (size_t)s.NC * s.NV * s.PS * ss,          // f1
       s.nc * 4 * 8,                             // W0
       s.nc * 4 * 8,                             // W1
       2 * (size_t)s.ny * 4 * 8,                 // Wg
-      (size_t)chunks * s.nc * kSlots * 8,      // hs: per-chunk partial sums
+      (size_t)s.NC * chunks * s.nc * kSlots * 8,  // hs: per-chunk partial sums
       2 * (size_t)s.ny * 16 * 8,                // hsg
-      (size_t)s.ny * (s.nx + 1) * kRec * 8,     // recx
-      (size_t)(s.ny + 1) * s.nx * kRec * 8,     // recy
+      (size_t)s.NC * s.ny * (s.nx + 1) * kRec * 8,  // recx
+      (size_t)s.NC * (s.ny + 1) * s.nx * kRec * 8,  // recy
       (size_t)(s.K + 6 * s.M) * 8,              // wk, wm, vmom
       (size_t)s.K * 8,                          // uk
       (size_t)s.M * 8,                          // vm
@@ -367,6 +374,11 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   P.K = s.K;
   P.M = s.M;
   P.NV = s.NV;
+  P.NC = s.NC;
+  P.dof = s.dof;
+  P.lam_c = 0.25 * (double)(2 + s.dof);
+  P.q_c = 0.5 * (double)(2 + s.dof);
+  P.a4_c = 4.0 / (double)(2 + s.dof);
   P.Lx = s.Lx;
   P.Ly = s.Ly;
   P.gmax = chunks;
@@ -390,6 +402,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   P.T_in = bc->kind == UGKS_BC_CHANNEL ? bc->T_in : 1.0;
   const double Tw = bc->kind == UGKS_BC_CHANNEL ? bc->T_wall : 1.0;
   P.lam_w = 1.0 / Tw;
+  P.kap_w = (double)s.dof / (2.0 * P.lam_w);
   P.U_in = bc->U_in;
   P.U_noise = bc->U_noise;
 
@@ -415,6 +428,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
         for (int q = 0; q < 4; ++q) P.wall_G_top[q] += w * v * psi[q] * gw;
       }
     }
+  // the wall's H (kap_w times its G) carries energy: psi = (0, 0, 0, 1/2)
+  P.wall_G_bot[3] += 0.5 * P.kap_w * P.wall_den_bot;
+  P.wall_G_top[3] += 0.5 * P.kap_w * P.wall_den_top;
   std::vector<double> W0(4 * s.nc), xi(s.ny);
   for (int j = 0; j < s.ny; ++j) {
     xi[j] = noise_unit(opts->seed, s.nc + (uint64_t)j);
@@ -424,7 +440,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
       W0[4 * c + 0] = rho;
       W0[4 * c + 1] = 0.0;
       W0[4 * c + 2] = 0.0;
-      W0[4 * c + 3] = 0.5 * rho * opts->T0;  // rho/(2 lambda)
+      W0[4 * c + 3] = P.lam_c * rho * opts->T0;  // (2 + dof) rho/(4 lambda)
     }
   }
   Buffers& B = h->B;
@@ -488,10 +504,11 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   if (rc == UGKS_OK) {
     // the halo rows and columns start at zero; a channel never writes the halo outside its
     // ghost columns, whose values the kernels then read as zero
-    e = hipMemsetAsync(B.f[0], 0, (size_t)s.NV * s.PS * h->ssize, h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(B.f[1], 0, (size_t)s.NV * s.PS * h->ssize, h->stream);
+    const size_t fbytes = (size_t)s.NC * s.NV * s.PS * h->ssize;
+    e = hipMemsetAsync(B.f[0], 0, fbytes, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(B.f[1], 0, fbytes, h->stream);
     if (e == hipSuccess)
-      e = launch_init(h->pv, I.fp32, (long long)s.nc * (long long)s.NV, h->stream);
+      e = launch_init(h->pv, I.fp32, (long long)s.nc * (long long)s.NV * s.NC, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = hip_fail(nullptr, e, "initial state");
   }
@@ -536,7 +553,7 @@ int ugks_moments(ugks_handle* h, double* host_out) {
   for (size_t c = 0; c < nc; ++c) {
     const double* w = &W[4 * c];
     const double rho = w[0], U = w[1] / rho, V = w[2] / rho;
-    const double T = 2.0 * (w[3] - 0.5 * rho * (U * U + V * V)) / rho;
+    const double T = (w[3] - 0.5 * rho * (U * U + V * V)) / (h->P.lam_c * rho);
     host_out[4 * c + 0] = rho;
     host_out[4 * c + 1] = U;
     host_out[4 * c + 2] = V;
@@ -573,6 +590,7 @@ int ugks_get_info(const ugks_handle* h, ugks_info* out) {
   out->nv = h->P.M;
   out->plane_stride = h->P.PS;
   out->precision = h->prec;
+  out->internal_dof = h->P.dof;
   out->dx = h->P.dx;
   out->dy = h->P.dy;
   out->dt = h->P.dt;
@@ -586,7 +604,8 @@ int ugks_get_state(ugks_handle* h, double* f, double* W) {
   if (!h) return UGKS_E_INVAL;
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
-  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = h->P.NV, PS = (size_t)h->P.PS;
+  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = (size_t)h->P.NV * h->P.NC;
+  const size_t PS = (size_t)h->P.PS;
   hipError_t e = hipSuccess;
   std::vector<char> raw;
   if (f) {
@@ -620,7 +639,8 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
   if (!h) return UGKS_E_INVAL;
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
-  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = h->P.NV, PS = (size_t)h->P.PS;
+  const size_t nc = (size_t)h->P.nx * h->P.ny, NV = (size_t)h->P.NV * h->P.NC;
+  const size_t PS = (size_t)h->P.PS;
   std::vector<char> raw;
   hipError_t e = hipSuccess;
   if (f) {

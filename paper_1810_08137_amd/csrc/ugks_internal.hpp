@@ -52,9 +52,15 @@ enum FaceSide { S_XP = 0, S_XM = 1, S_YP = 2, S_YM = 3 };
 
 // f is stored velocity-major: plane p = k M + m holds f(u_k, v_m) of every cell, laid out as
 // (ny + 4) rows of Lx = nx + 4 values (cell (i, j) at (j + 2) Lx + i + 2), with two halo
-// columns and rows on each side; planes are PS values apart.
+// columns and rows on each side; planes are PS values apart.  With internal degrees of
+// freedom the NV planes of H (the distribution's internal energy) follow those of G.
 struct KParams {
   int nx, ny, K, M, NV;
+  int NC;           // reduced distributions: 1 (G), or 2 (G, H) with internal degrees of freedom
+  int dof;          // internal degrees of freedom
+  double lam_c;     // (2 + dof)/4: lambda = lam_c rho / (rho E - rho |U|^2/2)
+  double q_c;       // (2 + dof)/2: the energy row of the micro-slope solve, q2 = |U|^2 + q_c/lambda
+  double a4_c;      // 4/(2 + dof): its energy coefficient, a4 = a4_c lambda^2/rho (...)
   int Lx, Ly;       // padded row length and row count of a plane
   int bc, collisionless, inlet_fixed_u;
   int gmax;         // velocity chunks per quadrant the moment-sum buffer has room for
@@ -62,9 +68,11 @@ struct KParams {
   double dx, dy, dt, inv_dx, inv_dy, area, mu_ref;
   double du, dv;    // node spacing of the uniform u and v grids
   double p_in, p_out, T_in, lam_w;
+  double kap_w;     // H / G of the wall Maxwellian: dof/(2 lambda_w)
   double U_in, U_noise;
   double wall_den_bot, wall_den_top;  // sum over wall-leaving velocities of w v g_w
   double wall_G_bot[4], wall_G_top[4];  // sum of w v psi_local g_w over the same velocities
+                                        // (energy: with the wall's H)
   const UGKS_GLOBAL double* uk;    // [K]
   const UGKS_GLOBAL double* vm;    // [M]
   const UGKS_GLOBAL double* wk;    // [K] weights of the u nodes
@@ -76,14 +84,14 @@ struct KParams {
 
 // Device buffers carved out of one workspace.
 struct Buffers {
-  void* f[2];       // [NV][PS] storage type
+  void* f[2];       // [NC NV][PS] storage type
   double* W[2];     // [nx*ny][4], ping-pong with f
   double* Wg;       // [2][ny][4]
-  double* hs;       // [gmax][64][nx*ny]: partial g of sum q of face side s of cell c at
-                    // ((g 64) + 16 s + q) nx ny + c
+  double* hs;       // [NC gmax][64][nx*ny]: partial g of sum q of face side s of cell c at
+                    // ((g 64) + 16 s + q) nx ny + c; chunks of H after those of G
   double* hsg;      // [2][ny][16]
-  double* recx;     // [ny][nx+1][32]
-  double* recy;     // [ny+1][nx][32]
+  double* recx;     // [NC][ny][nx+1][32]: records of G, then of H
+  double* recy;     // [NC][ny+1][nx][32]
   double* wk;       // [K], followed by wm [M], then vmom [M][5]
   double* uk;       // [K]
   double* vm;       // [M]
@@ -109,7 +117,8 @@ struct Inst {
   UGKS_GLOBAL double* recy;
   int cur;   // f[(cur + step) & 1] and W[(cur + step) & 1] are read, the others written
   int fp32;  // storage type of f
-  int gsplit;  // velocity chunks per quadrant (P.gmax; set by build_plan)
+  int gsplit;  // velocity chunks per quadrant and reduced distribution (P.gmax; set by
+               // build_plan); a segment has NC gsplit workgroups, those of H after those of G
 };
 
 // A launch plan: instances plus, per kernel, the prefix sum of the workgroups each instance
@@ -135,8 +144,9 @@ struct PlanTotals {
 // Bytes of a device plan with n instances, and its host image (offsets into one buffer).
 size_t plan_bytes(int n);
 // Velocity chunks per quadrant of an instance: enough update workgroups to fill the GPU
-// when the instance runs alone, at least one u node per chunk and at most 16 chunks.
-int velocity_chunks(int nx, int ny, int K);
+// when the instance runs alone (NC reduced distributions each take their own chunks), at
+// least one u node per chunk and at most 16 chunks.
+int velocity_chunks(int nx, int ny, int K, int NC);
 // Build the host image of a plan for `n` instances into `buf` (plan_bytes(n) bytes) and return
 // the totals; `dev` is the device address the image will be copied to.
 PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, PlanView* view);

@@ -144,10 +144,11 @@ struct Prim {
   double rho, U, V, lam;  // lambda = 1/T
 };
 
-// Primitive variables of W = (rho, rho U, rho V, rho E), 2D gas without internal energy
-// modes: rho E = rho (U^2 + V^2)/2 + rho/(2 lambda).  false on an invalid state.
+// Primitive variables of W = (rho, rho U, rho V, rho E) of a 2D gas with dof internal degrees
+// of freedom: rho E = rho (U^2 + V^2)/2 + (2 + dof) rho/(4 lambda), lam_c = (2 + dof)/4 (the
+// paper's gas: dof = 0).  false on an invalid state.
 template <typename Ptr>
-__device__ __forceinline__ bool prim_of(Ptr W, Prim& p) {
+__device__ __forceinline__ bool prim_of(Ptr W, Prim& p, double lam_c) {
   const double rho = W[0];
   const double U = W[1] / rho;
   const double V = W[2] / rho;
@@ -155,7 +156,7 @@ __device__ __forceinline__ bool prim_of(Ptr W, Prim& p) {
   p.rho = rho;
   p.U = U;
   p.V = V;
-  p.lam = 0.5 * rho / e;
+  p.lam = lam_c * rho / e;
   return rho > 0.0 && e > 0.0 && isfinite(rho) && isfinite(e) && isfinite(U) && isfinite(V) &&
          isfinite(p.lam);
 }
@@ -184,35 +185,59 @@ __device__ void axis_moments(double U, double lam, double* full, double* pos, do
   }
 }
 
-// <un^a ut^b psi>, psi = (1, un, ut, (un^2 + ut^2)/2)
-__device__ __forceinline__ void mpsi(const double* mu, const double* mv, int a, int b, double* o) {
+// Gaussian moments of the internal coordinates xi at lambda: x2 = <|xi|^2> = dof/(2 lambda),
+// x4 = <|xi|^4> = dof (dof + 2)/(4 lambda^2).  They enter through psi_4 = (un^2 + ut^2 + |xi|^2)/2;
+// kXi = false is the paper's gas, whose moments carry no xi terms.
+struct Xi {
+  double x2, x4;
+};
+
+// <un^a ut^b psi>, psi = (1, un, ut, psi_4)
+template <bool kXi>
+__device__ __forceinline__ void mpsi(const double* mu, const double* mv, int a, int b,
+                                     const Xi& xi, double* o) {
   o[0] = mu[a] * mv[b];
   o[1] = mu[a + 1] * mv[b];
   o[2] = mu[a] * mv[b + 1];
-  o[3] = 0.5 * (mu[a + 2] * mv[b] + mu[a] * mv[b + 2]);
+  if constexpr (kXi)
+    o[3] = 0.5 * (mu[a + 2] * mv[b] + mu[a] * mv[b + 2] + xi.x2 * (mu[a] * mv[b]));
+  else
+    o[3] = 0.5 * (mu[a + 2] * mv[b] + mu[a] * mv[b + 2]);
 }
 
-// <un^a ut^b psi (c . psi)>
+// <un^a ut^b psi (c . psi)>; the |xi|^2 of c_4 psi_4 brings <|xi|^2 un^a ut^b psi>
+template <bool kXi>
 __device__ __forceinline__ void mpsi_c(const double* mu, const double* mv, int a, int b,
-                                       const double* c, double* o) {
+                                       const Xi& xi, const double* c, double* o) {
   double t0[4], t1[4], t2[4], t3[4], t4[4];
-  mpsi(mu, mv, a, b, t0);
-  mpsi(mu, mv, a + 1, b, t1);
-  mpsi(mu, mv, a, b + 1, t2);
-  mpsi(mu, mv, a + 2, b, t3);
-  mpsi(mu, mv, a, b + 2, t4);
+  mpsi<kXi>(mu, mv, a, b, xi, t0);
+  mpsi<kXi>(mu, mv, a + 1, b, xi, t1);
+  mpsi<kXi>(mu, mv, a, b + 1, xi, t2);
+  mpsi<kXi>(mu, mv, a + 2, b, xi, t3);
+  mpsi<kXi>(mu, mv, a, b + 2, xi, t4);
+  if constexpr (kXi) {
+    const double m00 = mu[a] * mv[b];
+    const double tx[4] = {xi.x2 * m00, xi.x2 * (mu[a + 1] * mv[b]), xi.x2 * (mu[a] * mv[b + 1]),
+                          0.5 * (xi.x2 * (mu[a + 2] * mv[b] + mu[a] * mv[b + 2]) + xi.x4 * m00)};
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    o[q] = c[0] * t0[q] + c[1] * t1[q] + c[2] * t2[q] + 0.5 * c[3] * (t3[q] + t4[q]);
+    for (int q = 0; q < 4; ++q)
+      o[q] = c[0] * t0[q] + c[1] * t1[q] + c[2] * t2[q] + 0.5 * c[3] * (t3[q] + t4[q] + tx[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      o[q] = c[0] * t0[q] + c[1] * t1[q] + c[2] * t2[q] + 0.5 * c[3] * (t3[q] + t4[q]);
+  }
 }
 
-// S4 micro slope: a such that the moments of rho g (a . psi) equal s (closed form, 2D gas).
-__device__ __forceinline__ void micro_slope(const Prim& p, const double* s, double* a) {
-  const double q2 = p.U * p.U + p.V * p.V + 1.0 / p.lam;
+// S4 micro slope: a such that the moments of rho g (a . psi) equal s (closed form, 2D gas with
+// q_c = (2 + dof)/2 and a4_c = 4/(2 + dof); the paper's gas has 1 and 2).
+__device__ __forceinline__ void micro_slope(const Prim& p, const double* s, double* a,
+                                            double q_c, double a4_c) {
+  const double q2 = p.U * p.U + p.V * p.V + q_c / p.lam;
   const double R2 = s[1] - p.U * s[0];
   const double R3 = s[2] - p.V * s[0];
   const double R4 = 2.0 * s[3] - q2 * s[0];
-  a[3] = 2.0 * p.lam * p.lam / p.rho * (R4 - 2.0 * p.U * R2 - 2.0 * p.V * R3);
+  a[3] = a4_c * p.lam * p.lam / p.rho * (R4 - 2.0 * p.U * R2 - 2.0 * p.V * R3);
   a[2] = 2.0 * p.lam * R3 / p.rho - p.V * a[3];
   a[1] = 2.0 * p.lam * R2 / p.rho - p.U * a[3];
   a[0] = s[0] / p.rho - p.U * a[1] - p.V * a[2] - 0.5 * a[3] * q2;
@@ -342,7 +367,8 @@ __device__ __forceinline__ const Inst* inst_at(const PlanView& pv, int ii) {
 }
 
 // ================================================================== kernels
-// Discrete Maxwellian of each cell's W (initial state), one thread per plane value.
+// Discrete Maxwellian of each cell's W (initial state), one thread per plane value; the
+// planes of H hold dof/(2 lambda) times those of G.
 template <typename S>
 __global__ __launch_bounds__(256) void init_kernel(PlanView pv) {
   const Inst* __restrict__ I = inst_at(pv, 0);
@@ -351,22 +377,26 @@ __global__ __launch_bounds__(256) void init_kernel(PlanView pv) {
   const UGKS_GLOBAL double* W = I->W[I->cur];
   const long long nc = (long long)P.nx * P.ny;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nc * P.NV) return;
+  if (e >= nc * P.NV * P.NC) return;
   const int p = (int)(e / nc);
   const int c = (int)(e - (long long)p * nc);
   const int j = c / P.nx, i = c - j * P.nx;
   Prim pr;
-  if (!prim_of(W + 4 * (size_t)c, pr) && p == 0) *P.flag = 1;
-  const int k = p / P.M, m = p - k * P.M;
+  if (!prim_of(W + 4 * (size_t)c, pr, P.lam_c) && p == 0) *P.flag = 1;
+  const bool h = p >= P.NV;
+  const int pg = h ? p - P.NV : p;
+  const int k = pg / P.M, m = pg - k * P.M;
   const double du = P.uk[k] - pr.U, dv = P.vm[m] - pr.V;
-  const double g = pr.rho * pr.lam / kPi * exp(-pr.lam * (du * du + dv * dv));
+  double g = pr.rho * pr.lam / kPi * exp(-pr.lam * (du * du + dv * dv));
+  if (h) g *= (double)P.dof / (2.0 * pr.lam);
   stv(plane_of(f, P, p), pidx(P, i, j), g);
 }
 
 // Halo of the current f.  Channel: one workgroup per (side, row) writes the inlet (side 0)
-// or outlet (side 1) ghost Maxwellian into that row's ghost column of every plane and sums
-// its moments towards the domain (its slopes are zero); the other halo values stay zero.
-// Periodic: one thread per halo value of every plane copies the periodic image.
+// or outlet (side 1) ghost Maxwellian into that row's ghost column of every plane (H:
+// dof/(2 lambda) times it) and sums its moments towards the domain (its slopes are zero); the
+// other halo values stay zero.  Periodic: one thread per halo value of every plane copies the
+// periodic image.
 constexpr int kGhostThreads = 256;
 template <typename S>
 __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
@@ -381,7 +411,7 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
   if (P.bc != UGKS_BC_CHANNEL) {
     const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
     const long long e = (long long)local * kGhostThreads + tid;
-    if (e >= frame * P.NV) return;
+    if (e >= frame * P.NV * P.NC) return;
     const int p = (int)(e / frame);
     int r = (int)(e - (long long)p * frame);
     // frame order: the 2 halo rows below, then ny rows of 4 halo columns, then 2 rows above
@@ -411,7 +441,7 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
   const int side = local / P.ny, j = local - side * P.ny;
   const int col = side == 0 ? 0 : P.nx - 1;
   Prim pc, pg;
-  const bool ok = prim_of(W + 4 * ((size_t)j * P.nx + col), pc);
+  const bool ok = prim_of(W + 4 * ((size_t)j * P.nx + col), pc, P.lam_c);
   if (side == 0) {
     const double T = P.T_in;
     pg.lam = 1.0 / T;
@@ -436,9 +466,10 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
     wg[0] = pg.rho;
     wg[1] = pg.rho * pg.U;
     wg[2] = pg.rho * pg.V;
-    wg[3] = 0.5 * pg.rho * (pg.U * pg.U + pg.V * pg.V) + 0.5 * pg.rho / pg.lam;
+    wg[3] = 0.5 * pg.rho * (pg.U * pg.U + pg.V * pg.V) + P.lam_c * pg.rho / pg.lam;
   }
   const double coef = pg.rho * pg.lam / kPi;
+  const double kap = (double)P.dof / (2.0 * pg.lam);
   const int at = pidx(P, side == 0 ? -1 : P.nx, j);
   double acc[16];
 #pragma unroll
@@ -453,6 +484,14 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
     const double up = u > 0.0 ? 1.0 : (u < 0.0 ? 0.0 : 0.5);
     const double h = side == 0 ? up : 1.0 - up;
     add_side(acc, w * h, u, vv, 0.5 * (u * u + vv * vv), (double)gs, 0.0, 0.0);
+    if (P.NC > 1) {
+      // H carries energy only: psi = (0, 0, 0, 1/2)
+      const S hg = static_cast<S>(kap * g);
+      stv(plane_of(f, P, P.NV + p), at, (double)hg);
+      const double x0 = 0.5 * (w * h) * (double)hg;
+      acc[3] += x0;
+      acc[11] = fma(x0, u, acc[11]);
+    }
   }
   const int w = tid >> 6;
 #pragma unroll
@@ -476,7 +515,9 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
 //   F^n = sum_m w_m v^n f,  X^n = sum_m w_m v^n hx,  Y^n = sum_m w_m v^n hy
 // (hx, hy: half-cell changes; n up to 3, 3 and 4), with f_hat = f + s hx (or s hy) and
 // D = (2u/dx) hx + (2v/dy) hy; the 32 face sums take them in once per line.  The two partial
-// sums of each face side meet in LDS at the end.
+// sums of each face side meet in LDS at the end.  With internal degrees of freedom the
+// chunks G..2G-1 of a segment walk the planes of H, whose psi is (0, 0, 0, 1/2): they add to
+// the energy sums only.
 template <typename S>
 __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   __shared__ double red[4][16][kWave];
@@ -486,11 +527,14 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   const int ii = find_inst(pv.off_sums, pv.ninst, b);
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
-  const UGKS_GLOBAL S* f = static_cast<const UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
   const int G = I->gsplit;
-  int t, g, j;
-  cell_block(b - first_block(pv.off_sums, ii), P.ny, (P.nx + kTileS - 1) / kTileS, t, g, j);
-  UGKS_GLOBAL double* hs = I->hs + (size_t)g * kSlots * ((size_t)P.nx * P.ny);
+  int t, gg, j;
+  cell_block(b - first_block(pv.off_sums, ii), P.ny, (P.nx + kTileS - 1) / kTileS, t, gg, j);
+  const bool hpart = gg >= G;  // planes of H
+  const int g = hpart ? gg - G : gg;
+  const UGKS_GLOBAL S* f = static_cast<const UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]) +
+                           (hpart ? (long long)P.NV * P.PS : 0ll);
+  UGKS_GLOBAL double* hs = I->hs + (size_t)gg * kSlots * ((size_t)P.nx * P.ny);
   const int i = t * kTileS - 1 + lane;
   const bool valid = lane >= 1 && lane <= kTileS && i < P.nx;
   const int o = pidx(P, i < P.nx + 1 ? i : P.nx + 1, j);
@@ -558,6 +602,21 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     if (c < hv.count) node(va, c);
     // moments of the x-face reconstruction (S), the y-face one (R) and of D
     const double ucx = u * two_idx, u2h = 0.5 * u * u, wuu = wu * u;
+    if (hpart) {
+      const double wh = 0.5 * wu, whu = 0.5 * wuu;
+      const double S0 = su > 0 ? F0 + X0 : F0 - X0;
+      const double R0 = sv > 0 ? F0 + Y0 : F0 - Y0, R1 = sv > 0 ? F1 + Y1 : F1 - Y1;
+      const double D0 = fma(ucx, X0, two_idy * Y1), D1 = fma(ucx, X1, two_idy * Y2);
+      ax[3] = fma(wh, S0, ax[3]);
+      ax[7] = fma(wh, Y0, ax[7]);
+      ax[11] = fma(whu, S0, ax[11]);
+      ax[15] = fma(whu, D0, ax[15]);
+      ay[3] = fma(wh, R0, ay[3]);
+      ay[7] = fma(wh, X0, ay[7]);
+      ay[11] = fma(wh, R1, ay[11]);
+      ay[15] = fma(wh, D1, ay[15]);
+      continue;
+    }
     const double S0 = su > 0 ? F0 + X0 : F0 - X0, S1 = su > 0 ? F1 + X1 : F1 - X1;
     const double S2 = su > 0 ? F2 + X2 : F2 - X2;
     const double R0 = sv > 0 ? F0 + Y0 : F0 - Y0, R1 = sv > 0 ? F1 + Y1 : F1 - Y1;
@@ -629,8 +688,9 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   }
 }
 
-// With several velocity chunks per quadrant the moment kernel leaves G partial sums per
-// value; one thread per (sum, cell) adds them, in chunk order, into the first.
+// With several velocity chunks per quadrant, or the chunks of H, the moment kernel leaves
+// NC G partial sums per value; one thread per (sum, cell) adds them, in chunk order, into the
+// first.
 __global__ __launch_bounds__(256) void chunk_sum_kernel(PlanView pv) {
   const int b = blockIdx.x;
   const int ii = find_inst(pv.off_red, pv.ninst, b);
@@ -642,15 +702,21 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(PlanView pv) {
   UGKS_GLOBAL double* at = I->hs + e;
   const size_t gstride = (size_t)kSlots * nc;
   double x = at[0];
-  for (int g = 1; g < I->gsplit; ++g) x += at[(size_t)g * gstride];
+  for (int g = 1; g < I->gsplit * P.NC; ++g) x += at[(size_t)g * gstride];
   at[0] = x;
 }
 
 // S2-S5 at one interior interface, local frame.  S = [W0, Wt, Q1, Q2].  Writes the local
-// macroscopic flux to F and the folded coefficients of the distribution flux to rec.
+// macroscopic flux to F and the folded coefficients of the distribution flux to rec; with
+// internal degrees of freedom (kXi) also those of H to recH.  Averaged over xi, the energy
+// term c_4 psi_4 of a slope c contributes c_4 (un^2 + ut^2 + s)/2 to the polynomial of G with
+// s = <|xi|^2> = x2, and to that of H, whose Maxwellian is x2 times that of G, with
+// s = <|xi|^4>/<|xi|^2> = x4/x2: the constant shifts e0, e1 and e2 by c_4 s/2.
+template <bool kXi>
 __device__ void interface_scalars(const KParams& P, const double* S, const double* WL,
                                   const double* WR, double dn, double len, double* F,
-                                  UGKS_GLOBAL double* rec, double& U0, double& V0) {
+                                  UGKS_GLOBAL double* rec, UGKS_GLOBAL double* recH,
+                                  double& U0, double& V0) {
   const double* W0 = S;
   const double* Wt = S + 4;
   const double* Q1 = S + 8;
@@ -666,11 +732,20 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
     rec[R_M4] = len * Mt4;
     rec[R_M5] = len * Mt5;
     rec[R_KIND] = K_FREE;
+    if constexpr (kXi) {
+#pragma unroll
+      for (int q = R_GC; q < kRec; ++q) recH[q] = rec[q];
+    }
     U0 = V0 = 0.0;
     return;
   }
   Prim p0;
-  if (!prim_of(W0, p0)) *P.flag = 1;
+  if (!prim_of(W0, p0, P.lam_c)) *P.flag = 1;
+  Xi xi{0.0, 0.0};
+  if constexpr (kXi) {
+    xi.x2 = (double)P.dof / (2.0 * p0.lam);
+    xi.x4 = (double)(P.dof * (P.dof + 2)) / (4.0 * p0.lam * p0.lam);
+  }
   const double tau0 = collision_time(p0, P.mu_ref);
   double Mt[5];
   time_weights(P.dt, tau0, Mt);
@@ -680,25 +755,25 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
     swL[q] = (W0[q] - WL[q]) / (0.5 * dn);
     swR[q] = (WR[q] - W0[q]) / (0.5 * dn);
   }
-  micro_slope(p0, swL, aL);
-  micro_slope(p0, swR, aR);
-  micro_slope(p0, Wt, b);
+  micro_slope(p0, swL, aL, P.q_c, P.a4_c);
+  micro_slope(p0, swR, aR, P.q_c, P.a4_c);
+  micro_slope(p0, Wt, b, P.q_c, P.a4_c);
   double mu[7], mp[7], mn[7], mv[7], tp[7], tn[7];
   axis_moments(p0.U, p0.lam, mu, mp, mn);
   axis_moments(p0.V, p0.lam, mv, tp, tn);
   double m1[4], m2[4], m3[4], sA[4];
-  mpsi_c(mp, mv, 1, 0, aL, m1);
-  mpsi_c(mn, mv, 1, 0, aR, m2);
-  mpsi_c(mu, mv, 0, 1, b, m3);
+  mpsi_c<kXi>(mp, mv, 1, 0, xi, aL, m1);
+  mpsi_c<kXi>(mn, mv, 1, 0, xi, aR, m2);
+  mpsi_c<kXi>(mu, mv, 0, 1, xi, b, m3);
 #pragma unroll
   for (int q = 0; q < 4; ++q) sA[q] = -p0.rho * (m1[q] + m2[q] + m3[q]);
-  micro_slope(p0, sA, A);
+  micro_slope(p0, sA, A, P.q_c, P.a4_c);
   double e0[4], eL[4], eR[4], eb[4], eA[4];
-  mpsi(mu, mv, 1, 0, e0);
-  mpsi_c(mp, mv, 2, 0, aL, eL);
-  mpsi_c(mn, mv, 2, 0, aR, eR);
-  mpsi_c(mu, mv, 1, 1, b, eb);
-  mpsi_c(mu, mv, 1, 0, A, eA);
+  mpsi<kXi>(mu, mv, 1, 0, xi, e0);
+  mpsi_c<kXi>(mp, mv, 2, 0, xi, aL, eL);
+  mpsi_c<kXi>(mn, mv, 2, 0, xi, aR, eR);
+  mpsi_c<kXi>(mu, mv, 1, 1, xi, b, eb);
+  mpsi_c<kXi>(mu, mv, 1, 0, xi, A, eA);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const double feq = p0.rho * (Mt[0] * e0[q] + Mt[1] * (eL[q] + eR[q] + eb[q]) + Mt[2] * eA[q]);
@@ -723,11 +798,29 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
   rec[R_M4] = len * Mt[3];
   rec[R_M5] = len * Mt[4];
   rec[R_KIND] = K_INTERIOR;
+  if constexpr (kXi) {
+#pragma unroll
+    for (int q = R_GC; q < kRec; ++q) recH[q] = rec[q];
+    recH[R_GC] = rec[R_GC] * xi.x2;
+    const double sh = 0.5 * xi.x4 / xi.x2, sg = 0.5 * xi.x2;
+    const double e3 = rec[R_E + 3], e7 = rec[R_E + 7], e8 = rec[R_E + 8];
+    const double e7r = rec[R_ER + 3];
+    recH[R_E + 0] = fma(sh, e3, rec[R_E + 0]);
+    recH[R_E + 1] = fma(sh, e7, rec[R_E + 1]);
+    recH[R_E + 2] = fma(sh, e8, rec[R_E + 2]);
+    recH[R_ER + 0] = fma(sh, e7r, rec[R_ER + 0]);
+    rec[R_E + 0] = fma(sg, e3, rec[R_E + 0]);
+    rec[R_E + 1] = fma(sg, e7, rec[R_E + 1]);
+    rec[R_E + 2] = fma(sg, e8, rec[R_E + 2]);
+    rec[R_ER + 0] = fma(sg, e7r, rec[R_ER + 0]);
+  }
   U0 = p0.U;
   V0 = p0.V;
 }
 
 // One thread per interface: x-faces first (ny rows of nx+1), then y-faces (ny+1 rows of nx).
+// With internal degrees of freedom each face also gets the record of H, nfx (nfy) records
+// after those of G; it repeats the macroscopic flux, so either record serves Eq. (4).
 __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   const int b = blockIdx.x;
   const int ii = find_inst(pv.off_face, pv.ninst, b);
@@ -777,17 +870,25 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
       wr[q] = WR[q];
     }
     UGKS_GLOBAL double* rec = recx + (size_t)e * kRec;
-    interface_scalars(P, S, wl, wr, P.dx, P.dy, F, rec, U0, V0);
+    UGKS_GLOBAL double* recH = rec + (size_t)nfx * kRec;
+    if (P.NC > 1)
+      interface_scalars<true>(P, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0);
+    else
+      interface_scalars<false>(P, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0);
+    for (int c = 0; c < P.NC; ++c) {
+      UGKS_GLOBAL double* r = c ? recH : rec;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) rec[R_FX + q] = F[q];
-    rec[R_UX] = U0;
-    rec[R_VY] = V0;
+      for (int q = 0; q < 4; ++q) r[R_FX + q] = F[q];
+      r[R_UX] = U0;
+      r[R_VY] = V0;
+    }
     return;
   }
   if (e >= nfx + nfy) return;
   const long e2 = e - nfx;
   const int j = (int)(e2 / P.nx), i = (int)(e2 % P.nx);
   UGKS_GLOBAL double* rec = recy + (size_t)e2 * kRec;
+  UGKS_GLOBAL double* recH = rec + (size_t)nfy * kRec;
   if (chan && (j == 0 || j == P.ny)) {
     // diffuse wall: sums of the wall-row cell towards the wall; local frame (v, u)
     const bool top = j == P.ny;
@@ -801,19 +902,23 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
     double Fl[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) Fl[q] = s * (Q1[q] + rho_w * Gw[q]);
-    rec[R_FX + 0] = Fl[0];
-    rec[R_FX + 1] = Fl[2];
-    rec[R_FX + 2] = Fl[1];
-    rec[R_FX + 3] = Fl[3];
-    rec[R_GC] = s * rho_w * P.lam_w / kPi;
-    rec[R_LAM] = P.lam_w;
-    rec[R_UX] = 0.0;
-    rec[R_VY] = 0.0;
-    rec[R_M4] = s;
-    rec[R_M5] = 0.0;
-    rec[R_KIND] = K_WALL;
+    // H leaves the wall with kap_w times the Maxwellian of G
+    for (int c = 0; c < P.NC; ++c) {
+      UGKS_GLOBAL double* r = c ? recH : rec;
+      r[R_FX + 0] = Fl[0];
+      r[R_FX + 1] = Fl[2];
+      r[R_FX + 2] = Fl[1];
+      r[R_FX + 3] = Fl[3];
+      r[R_GC] = s * rho_w * P.lam_w / kPi * (c ? P.kap_w : 1.0);
+      r[R_LAM] = P.lam_w;
+      r[R_UX] = 0.0;
+      r[R_VY] = 0.0;
+      r[R_M4] = s;
+      r[R_M5] = 0.0;
+      r[R_KIND] = K_WALL;
 #pragma unroll
-    for (int q = 0; q < 13; ++q) rec[R_E + q] = 0.0;  // a wall carries no polynomial
+      for (int q = 0; q < 13; ++q) r[R_E + q] = 0.0;  // a wall carries no polynomial
+    }
     if (!(rho_w > 0.0) || !isfinite(rho_w)) *P.flag = 1;
     return;
   }
@@ -825,13 +930,19 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   for (int q = 0; q < 16; ++q) S[q] = sL[q * nc] + sR[q * nc];
   const double wl[4] = {W[4 * cl], W[4 * cl + 2], W[4 * cl + 1], W[4 * cl + 3]};
   const double wr[4] = {W[4 * cr], W[4 * cr + 2], W[4 * cr + 1], W[4 * cr + 3]};
-  interface_scalars(P, S, wl, wr, P.dy, P.dx, F, rec, U0, V0);
-  rec[R_FX + 0] = F[0];
-  rec[R_FX + 1] = F[2];
-  rec[R_FX + 2] = F[1];
-  rec[R_FX + 3] = F[3];
-  rec[R_UX] = V0;  // local (normal, tangential) = global (y, x)
-  rec[R_VY] = U0;
+  if (P.NC > 1)
+    interface_scalars<true>(P, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0);
+  else
+    interface_scalars<false>(P, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0);
+  for (int c = 0; c < P.NC; ++c) {
+    UGKS_GLOBAL double* r = c ? recH : rec;
+    r[R_FX + 0] = F[0];
+    r[R_FX + 1] = F[2];
+    r[R_FX + 2] = F[1];
+    r[R_FX + 3] = F[3];
+    r[R_UX] = V0;  // local (normal, tangential) = global (y, x)
+    r[R_VY] = U0;
+  }
 }
 
 // ------------------------------------------------------------------ update kernel
@@ -1101,15 +1212,21 @@ void update_kernel(PlanView pv) {
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
   const int parity = (I->cur + pv.step) & 1;
-  const UGKS_GLOBAL S* fin = static_cast<const UGKS_GLOBAL S*>(I->f[parity]);
-  UGKS_GLOBAL S* fout = static_cast<UGKS_GLOBAL S*>(I->f[parity ^ 1]);
-  const UGKS_GLOBAL double* recx = I->recx;
-  const UGKS_GLOBAL double* recy = I->recy;
+  const int G = I->gsplit;
+  int t, gg, j;
+  cell_block(b - first_block(pv.off_upd, ii), P.ny, (P.nx + kTileU - 1) / kTileU, t, gg, j);
+  // chunks G..2G-1 update H: its planes, its face records, its equilibria
+  const bool hpart = gg >= G;
+  const int g = hpart ? gg - G : gg;
+  const long long hoff = hpart ? (long long)P.NV * P.PS : 0ll;
+  const UGKS_GLOBAL S* fin = static_cast<const UGKS_GLOBAL S*>(I->f[parity]) + hoff;
+  UGKS_GLOBAL S* fout = static_cast<UGKS_GLOBAL S*>(I->f[parity ^ 1]) + hoff;
+  const UGKS_GLOBAL double* recx =
+      I->recx + (hpart ? (size_t)P.ny * (P.nx + 1) * kRec : (size_t)0);
+  const UGKS_GLOBAL double* recy =
+      I->recy + (hpart ? (size_t)(P.ny + 1) * P.nx * kRec : (size_t)0);
   const UGKS_GLOBAL double* W = I->W[parity];
   UGKS_GLOBAL double* Wout = I->W[parity ^ 1];
-  const int G = I->gsplit;
-  int t, g, j;
-  cell_block(b - first_block(pv.off_upd, ii), P.ny, (P.nx + kTileU - 1) / kTileU, t, g, j);
   const int i0 = t * kTileU;
   const int i = i0 - kHalo + lane;
   const bool valid = lane >= kHalo && lane < kHalo + kTileU && i < P.nx;
@@ -1152,14 +1269,14 @@ void update_kernel(PlanView pv) {
       W1[r] = valid ? Wn[r] + dW : Wn[r];
     }
     // every velocity chunk of the segment forms the same W^{n+1}; chunk 0 stores it
-    if (valid && g == 0) {
+    if (valid && gg == 0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) Wout[4 * cc + r] = W1[r];
     }
     Prim pn{}, p1{};
     double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
     if (!P.collisionless) {
-      const bool ok = prim_of(Wn, pn) && prim_of(W1, p1);
+      const bool ok = prim_of(Wn, pn, P.lam_c) && prim_of(W1, p1, P.lam_c);
       if (!ok && valid) *P.flag = 1;
       const double tn = collision_time(pn, P.mu_ref), t1 = collision_time(p1, P.mu_ref);
       const double hdt = 0.5 * P.dt;
@@ -1168,6 +1285,10 @@ void update_kernel(PlanView pv) {
       AdF = den / P.area;
       A1 = (p1.rho * p1.lam / kPi) * (hdt / t1) * den;
       An = (pn.rho * pn.lam / kPi) * (hdt / tn) * den;
+      if (hpart) {  // the equilibrium of H: dof/(2 lambda) times that of G
+        A1 *= (double)P.dof / (2.0 * p1.lam);
+        An *= (double)P.dof / (2.0 * pn.lam);
+      }
     }
     // every read of the flux fields by this wavefront is complete before they are reused
     __builtin_amdgcn_wave_barrier();
@@ -1218,8 +1339,8 @@ void update_kernel(PlanView pv) {
 // Update workgroups that fill the GPU once: 3 per CU (its LDS and registers allow 3).
 constexpr long long kFillWorkgroups = 256 * 3;
 
-int velocity_chunks(int nx, int ny, int K) {
-  const long long base = (long long)((nx + kTileU - 1) / kTileU) * ny;
+int velocity_chunks(int nx, int ny, int K, int NC) {
+  const long long base = (long long)((nx + kTileU - 1) / kTileU) * ny * NC;
   long long G = kFillWorkgroups / base;
   const int half = K / 2;  // nodes of the smaller half of the u axis
   if (G > half) G = half;
@@ -1247,7 +1368,7 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   for (int q = 0; q < n; ++q) img[q].gsplit = insts[q].P.gmax;
   for (int q = 0; q < n; ++q) {
     const KParams& P = insts[q].P;
-    const int G = img[q].gsplit;
+    const int G = img[q].gsplit * P.NC;  // chunks of G, then those of H
     const int nf = P.ny * (P.nx + 1) + (P.ny + 1) * P.nx;
     off[0][q] = t.sums;
     off[1][q] = t.upd;
@@ -1264,7 +1385,7 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
       t.ghost += 2 * P.ny;
     } else {
       const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
-      t.ghost += (int)((frame * P.NV + kGhostThreads - 1) / kGhostThreads);
+      t.ghost += (int)((frame * P.NV * P.NC + kGhostThreads - 1) / kGhostThreads);
     }
   }
   off[0][n] = t.sums;

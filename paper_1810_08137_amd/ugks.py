@@ -34,7 +34,8 @@ class ugks_mesh(ctypes.Structure):
 
 class ugks_vgrid(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_int), ("nv", ctypes.c_int),
-                ("umax", ctypes.c_double), ("vmax", ctypes.c_double)]
+                ("umax", ctypes.c_double), ("vmax", ctypes.c_double),
+                ("internal_dof", ctypes.c_int)]
 
 
 class ugks_bc(ctypes.Structure):
@@ -55,7 +56,7 @@ class ugks_opts(ctypes.Structure):
 class ugks_info(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nu", ctypes.c_int),
                 ("nv", ctypes.c_int), ("plane_stride", ctypes.c_int), ("precision", ctypes.c_int),
-                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
+                ("internal_dof", ctypes.c_int), ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
                 ("tau_ref", ctypes.c_double), ("steps", ctypes.c_int64),
                 ("device_bytes", ctypes.c_size_t)]
 
@@ -167,9 +168,14 @@ def ugks_get_info(h):
     return info
 
 
+def values_per_cell(info):
+    """f values per cell: nu*nv, twice that (G then H) with internal degrees of freedom."""
+    return info.nu * info.nv * (2 if info.internal_dof > 0 else 1)
+
+
 def ugks_get_state(h, want_f=True, want_W=True):
     info = ugks_get_info(h)
-    f = np.empty((info.ny, info.nx, info.nu * info.nv)) if want_f else None
+    f = np.empty((info.ny, info.nx, values_per_cell(info))) if want_f else None
     W = np.empty((info.ny, info.nx, 4)) if want_W else None
     _check(lib().ugks_get_state(h, _ptr(f), _ptr(W)), h)
     return f, W
@@ -179,7 +185,7 @@ def ugks_set_state(h, f=None, W=None):
     info = ugks_get_info(h)
     fa = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
     Wa = None if W is None else np.ascontiguousarray(W, dtype=np.float64)
-    if fa is not None and fa.size != info.nx * info.ny * info.nu * info.nv:
+    if fa is not None and fa.size != info.nx * info.ny * values_per_cell(info):
         raise ValueError("f has the wrong size")
     if Wa is not None and Wa.size != info.nx * info.ny * 4:
         raise ValueError("W has the wrong size")
@@ -234,9 +240,9 @@ def ugks_batch_last_error(b):
 def make_structs(nx, ny, lx, ly, nu, nv, umax, vmax, bc="channel", p_ratio=2.0, T_in=1.0,
                  T_wall=1.0, inlet_fixed_u=0, U_in=0.0, U_noise=0.0, precision="fp64", cfl=0.8,
                  rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, velocity_chunks=0,
-                 **_):
+                 dof=0, **_):
     mesh = ugks_mesh(int(nx), int(ny), float(lx), float(ly))
-    vgrid = ugks_vgrid(int(nu), int(nv), float(umax), float(vmax))
+    vgrid = ugks_vgrid(int(nu), int(nv), float(umax), float(vmax), int(dof))
     kind = {"periodic": UGKS_BC_PERIODIC, "channel": UGKS_BC_CHANNEL}[bc] if isinstance(bc, str) else int(bc)
     b = ugks_bc(kind, int(inlet_fixed_u), float(p_ratio), float(T_in), float(T_wall),
                 float(U_in), float(U_noise))

@@ -33,6 +33,11 @@ C3_STEPS = 500
 # inlet/outlet ghost columns stand where the neighbours' halo columns would be).
 C2_SHARE8 = dict(C2, nx=50, lx=0.5)
 
+# Internal degrees of freedom: the same channels for a monatomic gas seen in the plane (one
+# internal degree, gamma = 5/3), each velocity carrying G and H.
+C1_DOF = dict(C1, dof=1)
+C2_DOF = dict(C2, dof=1)
+
 # Precision form: C2 with f stored in FP32.
 C4 = dict(C2)
 C4_PRECISION = "fp32_store"
@@ -52,7 +57,7 @@ def oracle_kwargs(case):
     """Fields accepted by the oracle's case struct."""
     keys = ("nx", "ny", "lx", "ly", "nu", "nv", "umax", "vmax", "kn", "bc", "inlet_fixed_u",
             "p_ratio", "T_in", "T_wall", "U_in", "U_noise", "cfl", "rho0", "T0", "noise", "seed",
-            "dt_override")
+            "dt_override", "dof")
     return {k: case[k] for k in keys if k in case}
 
 

@@ -19,15 +19,22 @@ def oracle_threads():
     return n
 
 
-def moments_of_W(W):
+def moments_of_W(W, dof=0):
+    """(rho, U, V, T): rho E = rho |U|^2/2 + (2 + dof) rho T/4."""
     rho = W[..., 0]
     U = W[..., 1] / rho
     V = W[..., 2] / rho
-    T = 2.0 * (W[..., 3] - 0.5 * rho * (U * U + V * V)) / rho
+    T = 4.0 * (W[..., 3] - 0.5 * rho * (U * U + V * V)) / ((2 + dof) * rho)
     return np.stack([rho, U, V, T], -1)
 
 
-def errors(m_gpu, m_ref, f_gpu=None, f_ref=None):
+def errors(m_gpu, m_ref, f_gpu=None, f_ref=None, nv=None):
+    """With internal degrees of freedom (f holding G then H, nv values each) the two
+    distributions are measured separately, H as "h"."""
+    if f_gpu is not None and nv is not None and f_ref.shape[-1] == 2 * nv:
+        e = errors(m_gpu, m_ref, f_gpu[..., :nv], f_ref[..., :nv])
+        e["h"] = errors(m_gpu, m_ref, f_gpu[..., nv:], f_ref[..., nv:])["f"]
+        return e
     e = {
         "rho": float(np.max(np.abs(m_gpu[..., 0] - m_ref[..., 0]) / np.abs(m_ref[..., 0]))),
         "U": float(np.max(np.abs(m_gpu[..., 1] - m_ref[..., 1]))),
@@ -77,7 +84,8 @@ def run_and_compare(case, steps, precision="fp64", tol=FP64_TOL, check_f=True, l
         f_gpu, W_gpu = g.state() if check_f else (None, None)
         assert o.step(steps) == 0
         f_ref, W_ref = o.state()
-        e = errors(m_gpu, moments_of_W(W_ref), f_gpu, f_ref if check_f else None)
+        e = errors(m_gpu, moments_of_W(W_ref, case.get("dof", 0)), f_gpu,
+                   f_ref if check_f else None, nv=case["nu"] * case["nv"])
         print(f"[parity] {label} steps={steps} {precision}: {e}", flush=True)
         assert_within(e, tol, label)
         return e

@@ -72,7 +72,29 @@ def test_velocity_chunks_size_the_partial_sums():
     assert d >= 3 * 40 * 20 * 64 * 8
 
 
+def test_internal_dof_doubles_the_distribution_storage():
+    """G and H: twice the f planes, partial sums and face records."""
+    kn, (m0, v0, _, o0) = _structs()
+    kn, (m1, v1, _, o1) = _structs(dof=1)
+    n0 = ugks.ugks_required_bytes(m0, v0, o0)
+    n1 = ugks.ugks_required_bytes(m1, v1, o1)
+    f_bytes = 1600 * _plane(400, 100) * 8
+    assert n1 - n0 >= 2 * f_bytes
+    assert n1 <= 2 * n0
+    kn, (m3, v3, _, o3) = _structs(dof=3)
+    assert ugks.ugks_required_bytes(m3, v3, o3) == n1     # any dof > 0 stores G and H
+
+
+def test_struct_layouts_match_the_header():
+    """ctypes mirrors of the C structs: field order and size as the header declares them."""
+    assert ctypes.sizeof(ugks.ugks_vgrid) == 32           # 2 int, 2 double, 1 int + padding
+    assert ugks.ugks_vgrid.internal_dof.offset == 24
+    assert ugks.ugks_info.internal_dof.offset == 24
+    assert ugks.ugks_info.dx.offset == 32
+
+
 @pytest.mark.parametrize("field,value", [
+    ("dof", -1), ("dof", 17),
     ("nx", 0), ("ny", -1), ("lx", 0.0), ("nu", 1), ("nv", 0), ("umax", -1.0),
     ("nu", 2000), ("nu", 1025), ("noise", 1.5), ("rho0", 0.0), ("T0", -1.0),
     ("p_ratio", 0.0),

@@ -1,0 +1,128 @@
+"""GPU parity for a gas with internal degrees of freedom: G and H through the C ABI against
+the FP64 oracle on the same seeded inputs (FP64 bar 1e-12 on rho, T relative, U, V absolute,
+and per cell on each of G and H; FP32-store bar 1e-5)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1810_08137_amd import ugks
+from paper_1810_08137_amd import workloads as WL
+from tests import parity as PR
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(**kw):
+    c = dict(WL.CHANNEL_DEFAULTS)
+    c.update(kw)
+    return c
+
+
+def test_c1_with_internal_dof_first_step_fluxes_and_ghosts():
+    PR.oracle_threads()
+    g, o = PR.make_pair(WL.C1_DOF)
+    try:
+        g.step(1)
+        assert o.step(1) == 0
+        Fx, Fy = g.face_flux()
+        Rx, Ry = o.face_flux()
+        scale = np.max(np.abs(Rx), axis=(0, 1))
+        ex = np.max(np.abs(Fx - Rx), axis=(0, 1)) / scale
+        ey = np.max(np.abs(Fy - Ry), axis=(0, 1)) / np.maximum(np.max(np.abs(Ry), axis=(0, 1)), scale)
+        print("[parity] C1 dof=1 step 1 face flux errors", ex, ey, flush=True)
+        assert np.all(ex < 1e-12) and np.all(ey < 1e-12)
+        f_gpu, W_gpu = g.state()
+        f_ref, W_ref = o.state()
+        assert f_gpu.shape == f_ref.shape == (10, 40, 2 * 576)
+        e = PR.errors(PR.moments_of_W(W_gpu, 1), PR.moments_of_W(W_ref, 1), f_gpu, f_ref, nv=576)
+        PR.assert_within(e, PR.FP64_TOL, "C1 dof=1 step 1")
+    finally:
+        g.close()
+        o.close()
+
+
+def test_c1_with_internal_dof_full_run():
+    e = PR.run_and_compare(WL.C1_DOF, WL.C1_STEPS, label="C1 dof=1")
+    assert "h" in e
+
+
+def test_initial_state_carries_the_internal_energy():
+    kn, kw = WL.solver_kwargs(WL.C1_DOF)
+    s = ugks.Solver(kn, **kw)
+    try:
+        f, W = s.state()
+        m = s.moments()
+    finally:
+        s.close()
+    np.testing.assert_allclose(f[..., 576:], 0.5 * f[..., :576], rtol=1e-15)   # H = T0/2 G
+    np.testing.assert_allclose(m[..., 3], 1.0, rtol=1e-15)
+    np.testing.assert_allclose(W[..., 3], 0.75 * W[..., 0], rtol=1e-15)
+
+
+@pytest.mark.parametrize("dof,bc,nx,ny,nu,nv", [(1, 0, 13, 7, 11, 9), (3, 1, 9, 5, 7, 7),
+                                                 (2, 1, 17, 3, 6, 6), (5, 0, 6, 4, 9, 5)])
+def test_ragged_cases_with_internal_dof(dof, bc, nx, ny, nu, nv):
+    case = _case(nx=nx, ny=ny, lx=nx / 4.0, ly=1.0, nu=nu, nv=nv, umax=4.0, vmax=4.0, kn=0.08,
+                 bc=bc, noise=0.05, seed=3 + dof, dof=dof)
+    PR.run_and_compare(case, 12, label=f"ragged dof={dof} bc={bc} {nx}x{ny} {nu}x{nv}")
+
+
+@pytest.mark.parametrize("chunks", [1, 3])
+def test_internal_dof_with_capped_velocity_chunks(chunks):
+    """One chunk per quadrant leaves G and H one partial sum each; three leave six."""
+    case = dict(WL.C1_DOF, velocity_chunks=chunks)
+    PR.run_and_compare(case, 20, label=f"C1 dof=1 chunks<={chunks}")
+
+
+def test_collisionless_internal_energy_is_transported_like_the_mass():
+    case = _case(nx=12, ny=8, lx=1.0, ly=1.0, nu=12, nv=12, umax=3.0, vmax=3.0,
+                 kn=float("inf"), bc=0, noise=0.3, seed=5, dof=2)
+    PR.run_and_compare(case, 6, label="collisionless dof=2")
+
+
+def test_walls_at_another_temperature_with_internal_dof():
+    case = _case(nx=16, ny=8, lx=2.0, ly=1.0, nu=16, nv=16, umax=5.0, vmax=5.0, kn=0.1,
+                 T_wall=1.3, p_ratio=1.5, seed=8, dof=2)
+    PR.run_and_compare(case, 15, label="T_wall 1.3 dof=2")
+
+
+def test_fp32_store_with_internal_dof():
+    e = PR.run_and_compare(WL.C1_DOF, WL.C1_STEPS, precision="fp32_store",
+                           tol=PR.FP32_STORE_TOL, check_f=False, label="C1 dof=1 fp32-store")
+    assert e["rho"] > 1e-12          # the FP32 storage is in effect
+
+
+def test_c2_with_internal_dof_full_size_steps():
+    """The 400x100 x 40^2 channel with one internal degree of freedom, compared in full."""
+    PR.run_and_compare(WL.C2_DOF, 2, label="C2 dof=1 400x100 40^2")
+
+
+def test_batch_mixing_internal_dof_is_bitwise_the_lone_run():
+    """Solvers with and without internal degrees of freedom share the launches of a batch;
+    each result is bitwise the one it gets stepped alone."""
+    import torch
+
+    cases = [dict(WL.C1_DOF), dict(WL.C1), _case(nx=9, ny=5, lx=2.0, ly=1.0, nu=7, nv=7,
+                                                 umax=4.0, vmax=4.0, kn=0.2, seed=4, dof=3)]
+    alone, batched = [], []
+    for c in cases:
+        kn, kw = WL.solver_kwargs(c)
+        s = ugks.Solver(kn, **kw)
+        s.step(7)
+        alone.append(s.state())
+        s.close()
+    solvers = []
+    for c in cases:
+        kn, kw = WL.solver_kwargs(c)
+        solvers.append(ugks.Solver(kn, **kw))
+    b = ugks.Batch(len(solvers))
+    try:
+        b.step(solvers, 7)
+        torch.cuda.synchronize()
+        batched = [s.state() for s in solvers]
+    finally:
+        b.close()
+        for s in solvers:
+            s.close()
+    for (fa, Wa), (fb, Wb) in zip(alone, batched):
+        assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb)
