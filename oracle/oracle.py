@@ -33,6 +33,7 @@ class RefCase(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("dt_override", ctypes.c_double),
         ("dof", ctypes.c_int),
+        ("prandtl", ctypes.c_double),
     ]
 
 
@@ -78,7 +79,11 @@ def lib():
                                                 ctypes.c_int]
         L.ugks_ref_face.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_int]
+                                    ctypes.c_double, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                    ctypes.c_double]
+        L.ugks_ref_shakhov.restype = ctypes.c_double
+        L.ugks_ref_shakhov.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double]
         _lib = L
     return _lib
 
@@ -158,7 +163,8 @@ def equilibrium_flux(prim, aL, aR, b, A, Mt, dof=0):
     return F
 
 
-def face(un, ut, w, fhat, sn, st, WL, WR, dn, length, dt, mu_ref, collisionless=False, dof=0):
+def face(un, ut, w, fhat, sn, st, WL, WR, dn, length, dt, mu_ref, collisionless=False, dof=0,
+         prandtl=1.0):
     """fhat, sn, st: nvel values (G), followed by nvel values of H when dof > 0."""
     n = len(un)
     nf = n * (2 if dof > 0 else 1)
@@ -168,8 +174,15 @@ def face(un, ut, w, fhat, sn, st, WL, WR, dn, length, dt, mu_ref, collisionless=
     FW = np.zeros(4)
     Ff = np.zeros(nf)
     rc = lib().ugks_ref_face(n, *[_ptr(a) for a in u3 + f3], _ptr(wl), _ptr(wr), dn, length,
-                             dt, mu_ref, int(collisionless), _ptr(FW), _ptr(Ff), int(dof))
+                             dt, mu_ref, int(collisionless), _ptr(FW), _ptr(Ff), int(dof),
+                             float(prandtl))
     return rc, FW, Ff
+
+
+def shakhov(prim, q, prandtl, u, v):
+    """S of the Shakhov equilibrium g (1 + S) at (u, v)."""
+    p, qq = _vec(prim, 4), _vec(q, 2)
+    return float(lib().ugks_ref_shakhov(_ptr(p), _ptr(qq), float(prandtl), float(u), float(v)))
 
 
 def set_threads(n):
@@ -188,7 +201,8 @@ def mu_ref_of_kn(kn):
 # ----------------------------------------------------------------------------- state
 CASE_DEFAULTS = dict(lx=1.0, ly=1.0, umax=5.0, vmax=5.0, kn=0.1, bc=1, inlet_fixed_u=0,
                      p_ratio=2.0, T_in=1.0, T_wall=1.0, U_in=0.0, U_noise=0.0, cfl=0.8,
-                     rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, dof=0)
+                     rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, dof=0,
+                     prandtl=1.0)
 
 
 class Oracle:

@@ -10,6 +10,12 @@
  * psi_4 = (u^2 + v^2 + |xi|^2)/2, whose Gaussian moments need <|xi|^2> = dof/(2 lambda) and
  * <|xi|^4> = dof (dof + 2)/(4 lambda^2).
  *
+ * Shakhov collision model (prandtl < 1, a variant beyond the paper's BGK operator, for the gas
+ * without internal degrees of freedom): the equilibrium g is replaced by g (1 + S) with
+ * S = (1 - Pr) (lambda^2 / rho) (c . q) (2 lambda |c|^2 - 4), c = u - U, q = sum w c |c|^2 f / 2
+ * the heat flux; its heat flux is (1 - Pr) q and it carries no mass, momentum or energy.
+ * prandtl = 1 is BGK exactly.
+ *
  * Every function cites the part of the paper it follows.  Where the paper is silent (it
  * leaves the interface-flux construction to its references), the step is restated from the
  * integral solution, Eq. (2), and the reading taken is named in the comment ("reading: ...").
@@ -29,6 +35,7 @@ struct ugks_ref {
   ugks_ref_case c;
   int K, M, NV;
   int NC, NF;                   /* reduced functions per velocity (1, or 2 with dof > 0); NC*NV */
+  double pr;                    /* Prandtl number of the collision model (1: BGK) */
   double dx, dy, dt, mu_ref;
   int collisionless;
   double *uk, *vm, *wk, *wm;    /* 1D nodes and trapezoid weights */
@@ -271,6 +278,30 @@ static double dot_psi(const double c[4], double un, double ut, double shift) {
 }
 
 /* ---------------------------------------------------------------------------------------
+ * Shakhov correction (variant): g+ = g (1 + S) with
+ *   S = (1 - Pr) (lambda^2/rho) (c . q) (2 lambda |c|^2 - 4),  c = (u - U, v - V),
+ * the 2D form of the S-model written with p = rho/(2 lambda) and RT = 1/(2 lambda), so that
+ * sum over the Gaussian of c |c|^2/2 g S = (1 - Pr) q and of psi g S = 0.
+ * ------------------------------------------------------------------------------------- */
+double ugks_ref_shakhov(const double p[4], const double q[2], double pr, double u, double v) {
+  double cx = u - p[1], cy = v - p[2], lam = p[3];
+  double cq = cx * q[0] + cy * q[1];
+  return (1.0 - pr) * (lam * lam / p[0]) * cq * (2.0 * lam * (cx * cx + cy * cy) - 4.0);
+}
+
+/* Heat flux q = sum w c |c|^2 f / 2 about the velocity (U, V) of p (discrete, plain sum) */
+static void heat_flux(int nvel, const double* un, const double* ut, const double* w,
+                      const double* f, const double p[4], double q[2]) {
+  q[0] = q[1] = 0.0;
+  for (int v = 0; v < nvel; ++v) {
+    double cx = un[v] - p[1], cy = ut[v] - p[2];
+    double c2 = cx * cx + cy * cy;
+    q[0] += 0.5 * w[v] * cx * c2 * f[v];
+    q[1] += 0.5 * w[v] * cy * c2 * f[v];
+  }
+}
+
+/* ---------------------------------------------------------------------------------------
  * One interior interface in its local frame (S1-S8).  Inputs per velocity: normal and
  * tangential velocity, quadrature weight, the upwinded reconstruction of f at the face
  * (fhat) and the upwinded normal and tangential slopes of f (sn, st).
@@ -292,7 +323,7 @@ static double dot_psi(const double c[4], double un, double ut, double shift) {
 int ugks_ref_face(int nvel, const double* un, const double* ut, const double* w,
                   const double* fhat, const double* sn, const double* st, const double WL[4],
                   const double WR[4], double dn, double len, double dt, double mu_ref,
-                  int collisionless, double FW[4], double* Ff, int dof) {
+                  int collisionless, double FW[4], double* Ff, int dof, double pr) {
   int nc = dof > 0 ? 2 : 1;
   double W0[4] = {0, 0, 0, 0}, Wt[4] = {0, 0, 0, 0}, Q1[4] = {0, 0, 0, 0},
          Q2[4] = {0, 0, 0, 0};
@@ -341,6 +372,14 @@ int ugks_ref_face(int nvel, const double* un, const double* ut, const double* w,
   ugks_ref_micro_slope(p0, Wt_, b, dof);
   ugks_ref_time_slope(p0, aL, aR, b, A, dof);
   ugks_ref_equilibrium_flux(p0, aL, aR, b, A, Mt, Feq, dof);
+  /* Shakhov (variant): the correction of the initial interface equilibrium, g0 S0 with the
+     heat flux q0 of the reconstructed f, is held over the step like the Mt1 part; its only
+     macroscopic flux is the energy flux (1 - Pr) q0_n */
+  double q0[2] = {0.0, 0.0};
+  if (pr != 1.0) {
+    heat_flux(nvel, un, ut, w, fhat, p0, q0);
+    Feq[3] += Mt[0] * (1.0 - pr) * q0[0];
+  }
   for (int q = 0; q < 4; ++q) FW[q] = len * (Feq[q] + Mt[3] * Q1[q] - Mt[4] * Q2[q]);
   if (Ff) {
     double x2, x4;
@@ -356,6 +395,7 @@ int ugks_ref_face(int nvel, const double* un, const double* ut, const double* w,
       double poly = Mt[0] + Mt[1] * (un[x] * dot_psi(a, un[x], ut[x], shift) +
                                      ut[x] * dot_psi(b, un[x], ut[x], shift)) +
                     Mt[2] * dot_psi(A, un[x], ut[x], shift);
+      if (pr != 1.0) poly += Mt[0] * ugks_ref_shakhov(p0, q0, pr, un[x], ut[x]);
       Ff[v] = len * un[x] *
               (G * poly + Mt[3] * fhat[v] - Mt[4] * (un[x] * sn[v] + ut[x] * st[v]));
     }
@@ -374,6 +414,8 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
   if (!(c->kn > 0) || !(c->rho0 > 0) || !(c->T0 > 0)) return NULL;
   if (c->bc != 0 && c->bc != 1) return NULL;
   if (c->dof < 0 || c->dof > 16) return NULL;
+  if (!(c->prandtl > 0.0) || c->prandtl > 1.0) return NULL;
+  if (c->prandtl != 1.0 && c->dof != 0) return NULL;  /* Shakhov: gas without internal dof */
   if (c->bc == 1 && (!(c->p_ratio > 0) || !(c->T_in > 0) || !(c->T_wall > 0))) return NULL;
   ugks_ref* s = (ugks_ref*)calloc(1, sizeof(ugks_ref));
   s->c = *c;
@@ -382,6 +424,7 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
   s->NV = c->nu * c->nv;
   s->NC = c->dof > 0 ? 2 : 1;
   s->NF = s->NC * s->NV;
+  s->pr = c->prandtl;
   s->dx = c->lx / c->nx;
   s->dy = c->ly / c->ny;
   s->collisionless = isinf(c->kn) ? 1 : 0;
@@ -670,7 +713,7 @@ static int faces(ugks_ref* s) {
           }
         size_t fi = (size_t)j * (nx + 1) + i;
         if (ugks_ref_face(NV, un, ut, w, fh, sn, st, WL, WR, s->dx, s->dy, s->dt, s->mu_ref,
-                          s->collisionless, s->Fx + 4 * fi, s->Ffx + fi * NF, dof))
+                          s->collisionless, s->Fx + 4 * fi, s->Ffx + fi * NF, dof, s->pr))
           err |= 1;
       }
     /* y-faces: normal v, tangential u, local W = (rho, rho V, rho U, rho E) */
@@ -707,7 +750,7 @@ static int faces(ugks_ref* s) {
           }
         double FWl[4];
         if (ugks_ref_face(NV, un, ut, w, fh, sn, st, WL, WR, s->dy, s->dx, s->dt, s->mu_ref,
-                          s->collisionless, FWl, s->Ffy + fi * NF, dof))
+                          s->collisionless, FWl, s->Ffy + fi * NF, dof, s->pr))
           err |= 1;
         double* F = s->Fy + 4 * fi;
         F[0] = FWl[0];
@@ -738,7 +781,8 @@ static int faces(ugks_ref* s) {
  *   f^{n+1} = [f^n + dF/(dx dy) + dt/2 (g^{n+1}/tau^{n+1} + (g^n - f^n)/tau^n)]
  *             / (1 + dt/(2 tau^{n+1})).
  * The collisionless limit drops the collision term.  H takes the same update with the
- * equilibria dof/(2 lambda^n) g^n and dof/(2 lambda^{n+1}) g^{n+1}.
+ * equilibria dof/(2 lambda^n) g^n and dof/(2 lambda^{n+1}) g^{n+1}.  Shakhov (variant): g^n
+ * and g^{n+1} become g (1 + S) with the heat flux q^n of f^n at both levels (reading).
  * ------------------------------------------------------------------------------------- */
 static int update(ugks_ref* s) {
   int nx = s->c.nx, ny = s->c.ny, NV = s->NF, NG = s->NV, K = s->K, M = s->M;
@@ -773,6 +817,18 @@ static int update(ugks_ref* s) {
       }
       double tn = collision_time(s->mu_ref, pn), tn1 = collision_time(s->mu_ref, pn1);
       double kn = (double)dof / (2.0 * pn[3]), kn1 = (double)dof / (2.0 * pn1[3]);
+      double qn[2] = {0.0, 0.0};
+      if (s->pr != 1.0) {
+        double* cu = malloc(sizeof(double) * 3 * (size_t)NG);
+        for (int k = 0; k < K; ++k)
+          for (int m = 0; m < M; ++m) {
+            cu[k * M + m] = s->uk[k];
+            cu[NG + k * M + m] = s->vm[m];
+            cu[2 * NG + k * M + m] = s->wk[k] * s->wm[m];
+          }
+        heat_flux(NG, cu, cu + NG, cu + 2 * NG, f, pn, qn);
+        free(cu);
+      }
       for (int k = 0; k < K; ++k)
         for (int m = 0; m < M; ++m)
           for (int v = k * M + m; v < NV; v += NG) {  /* G, then H */
@@ -781,6 +837,10 @@ static int update(ugks_ref* s) {
             if (v >= NG) {
               gn *= kn;
               gn1 *= kn1;
+            }
+            if (s->pr != 1.0) {
+              gn *= 1.0 + ugks_ref_shakhov(pn, qn, s->pr, s->uk[k], s->vm[m]);
+              gn1 *= 1.0 + ugks_ref_shakhov(pn1, qn, s->pr, s->uk[k], s->vm[m]);
             }
             double dF = (Ffl[v] - Ffr[v] + Ffb[v] - Fft[v]) / area;
             fn[v] = (f[v] + dF + 0.5 * dt * (gn1 / tn1 + (gn - f[v]) / tn)) /

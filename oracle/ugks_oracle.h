@@ -16,6 +16,7 @@
  *     flux steps S1-S8 of Sec. 2.B (moments, Maxwellian moments, time weights, micro slopes,
  *     equilibrium flux, interface Maxwellian, free-transport flux, distribution flux).
  *   - Cell update of f with the trapezoidal collision term, Eq. (3), and of W, Eq. (4).
+ *   - Variant collision model: Shakhov's, for a Prandtl number below 1.
  * The construction inside S1-S8 that the paper leaves to its references is restated from the
  * mathematics; every reading taken where the paper is silent is listed in the repository's
  * design notes and repeated at the function that implements it.
@@ -52,6 +53,8 @@ typedef struct {
   uint64_t seed;
   double dt_override;      /* > 0 replaces the CFL step */
   int dof;                 /* internal degrees of freedom, 0..16 (0: the paper's gas) */
+  double prandtl;          /* collision model: 1 BGK (the paper's), < 1 Shakhov with this
+                              Prandtl number (dof = 0 only) */
 } ugks_ref_case;
 
 typedef struct ugks_ref ugks_ref;
@@ -92,7 +95,10 @@ void ugks_ref_equilibrium_flux(const double prim[4], const double aL[4], const d
 int ugks_ref_face(int nvel, const double* un, const double* ut, const double* w,
                   const double* fhat, const double* sn, const double* st,
                   const double WL[4], const double WR[4], double dn, double len, double dt,
-                  double mu_ref, int collisionless, double FW[4], double* Ff, int dof);
+                  double mu_ref, int collisionless, double FW[4], double* Ff, int dof,
+                  double prandtl);
+/* Shakhov factor S at velocity (u, v): g+ = g (1 + S); q = heat flux, pr = Prandtl number */
+double ugks_ref_shakhov(const double prim[4], const double q[2], double pr, double u, double v);
 
 #ifdef __cplusplus
 }

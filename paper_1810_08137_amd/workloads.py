@@ -38,6 +38,10 @@ C2_SHARE8 = dict(C2, nx=50, lx=0.5)
 C1_DOF = dict(C1, dof=1)
 C2_DOF = dict(C2, dof=1)
 
+# Shakhov collision model with the Prandtl number of a monatomic gas.
+C1_SHAKHOV = dict(C1, prandtl=2.0 / 3.0)
+C2_SHAKHOV = dict(C2, prandtl=2.0 / 3.0)
+
 # Precision form: C2 with f stored in FP32.
 C4 = dict(C2)
 C4_PRECISION = "fp32_store"
@@ -57,7 +61,7 @@ def oracle_kwargs(case):
     """Fields accepted by the oracle's case struct."""
     keys = ("nx", "ny", "lx", "ly", "nu", "nv", "umax", "vmax", "kn", "bc", "inlet_fixed_u",
             "p_ratio", "T_in", "T_wall", "U_in", "U_noise", "cfl", "rho0", "T0", "noise", "seed",
-            "dt_override", "dof")
+            "dt_override", "dof", "prandtl")
     return {k: case[k] for k in keys if k in case}
 
 
