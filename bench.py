@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--paper-sweep", action="store_true",
                     help="also time the paper's meshes M1-M4 at 29^2, 49^2 and 69^2 velocities")
     ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--no-shakhov", action="store_true",
+                    help="skip the Shakhov collision model (Prandtl number 2/3)")
     ap.add_argument("--no-internal-dof", action="store_true",
                     help="skip the gas with one internal degree of freedom (G and H)")
     ap.add_argument("--shard-share", action="store_true",
@@ -176,6 +178,24 @@ def internal_dof(WL, ugks, steps, warmup):
             "distribution_values_per_s": 2 * upd * steps / (ms * 1e-3),
             "update_kernel_GBs": 32.0 * upd / (upd_ms * 1e-3) / 1e9,
             "step_hbm_frac": 32.0 * upd / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernels": prof}
+
+
+def shakhov(WL, ugks, steps, warmup):
+    """The 400x100 x 40^2 channel with the Shakhov collision model (Pr = 2/3), FP64."""
+    case = WL.C2_SHAKHOV
+    kn, kw = WL.solver_kwargs(case, "fp64")
+    s = ugks.Solver(kn, **kw)
+    try:
+        ms, _ = time_solver(s, steps, warmup)
+        prof = kernel_profile(s, min(steps, 200))
+        s.moments()
+    finally:
+        s.close()
+    upd = WL.updates(case)
+    return {"prandtl": case["prandtl"], "ms_per_step": ms / steps,
+            "updates_per_s": upd * steps / (ms * 1e-3),
+            "update_kernel_GBs": 16.0 * upd / (prof["update"]["avg_ms"] * 1e-3) / 1e9,
             "kernels": prof}
 
 
@@ -372,6 +392,8 @@ def main():
         out["serving"] = serving(args, fp64["updates_per_s"])
     if args.paper_sweep:
         out["paper_sweep"] = paper_sweep(WL, ugks, args.sweep_steps)
+    if not args.no_shakhov:
+        out["shakhov"] = shakhov(WL, ugks, min(args.steps, 500), args.warmup)
     if not args.no_internal_dof:
         out["internal_dof"] = internal_dof(WL, ugks, min(args.steps, 500), args.warmup)
     if args.shard_share:

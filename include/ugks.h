@@ -108,7 +108,14 @@ typedef struct {
                     nx*ny + j.
    stream           hipStream_t for all work of the handle.
    workspace        optional device buffer of at least ugks_required_bytes() bytes, aligned
-                    to 256 bytes; NULL lets the library allocate. */
+                    to 256 bytes; NULL lets the library allocate.
+   prandtl          collision model: 0 or 1 selects the paper's BGK operator (Eq. (1));
+                    0 < prandtl < 1 the Shakhov model with that Prandtl number (2/3 for a
+                    monatomic gas): the equilibrium g becomes g (1 + S) with
+                    S = (1 - Pr)(lambda^2/rho)(c . q)(2 lambda |c|^2 - 4), c = u - U and q the
+                    heat flux; at an interface S comes from the reconstructed f and is held
+                    over the step, in a cell from f^n for both time levels of Eq. (3).
+                    Requires internal_dof = 0; other values give UGKS_E_INVAL. */
 typedef struct {
   int precision;
   int velocity_chunks;
@@ -119,6 +126,7 @@ typedef struct {
   void* stream;
   void* workspace;
   size_t workspace_bytes;
+  double prandtl;
 } ugks_opts;
 
 typedef struct {
@@ -194,7 +202,8 @@ int ugks_get_kernel_timing(ugks_handle* h, int kernel, double* total_ms, int64_t
  * A batch owns a device launch plan for up to max_instances handles (the kernels find their
  * instance in it), a pinned staging copy and an event.  ugks_step_batch enqueues n steps of
  * every handle in hs[0..count) with one launch per phase covering all of them and returns
- * without waiting.  Requirements: the handles are distinct and share one precision.  A handle
+ * without waiting.  Requirements: the handles are distinct and share one precision and one
+ * collision model (BGK, or Shakhov with any Prandtl numbers).  A handle
  * created on another stream is adopted: the batch's stream (the stream argument of
  * ugks_batch_create) first waits for the work already enqueued for it, and from then on the
  * handle's work, including ugks_moments and ugks_destroy, runs on the batch's stream.  Each

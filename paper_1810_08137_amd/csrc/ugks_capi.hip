@@ -196,7 +196,25 @@ int chunks_of(const Shape& s, int cap) {
   return cap > 0 && cap < a ? cap : a;
 }
 
-Layout layout_of(const Shape& s, int prec, int chunks) {
+// Collision model of the options: BGK for prandtl 0 or 1, Shakhov for 0 < prandtl < 1 (gas
+// without internal degrees of freedom only).  false with a message otherwise.
+bool collision_of(const ugks_opts* o, const Shape& s, bool& shak, std::string& why) {
+  const double pr = o ? o->prandtl : 0.0;
+  shak = false;
+  if (pr == 0.0 || pr == 1.0) return true;
+  if (!(pr > 0.0 && pr < 1.0)) {
+    why = "prandtl must be 0, 1 (BGK) or in (0, 1) (Shakhov)";
+    return false;
+  }
+  if (s.dof != 0) {
+    why = "the Shakhov model needs internal_dof = 0";
+    return false;
+  }
+  shak = true;
+  return true;
+}
+
+Layout layout_of(const Shape& s, int prec, int chunks, bool shak) {
   const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
   const size_t sizes[14] = {
       (size_t)s.NC * s.NV * s.PS * ss,          // f0: NC NV planes
@@ -204,8 +222,8 @@ Layout layout_of(const Shape& s, int prec, int chunks) {
       s.nc * 4 * 8,                             // W0
       s.nc * 4 * 8,                             // W1
       2 * (size_t)s.ny * 4 * 8,                 // Wg
-      (size_t)s.NC * chunks * s.nc * kSlots * 8,  // hs: per-chunk partial sums
-      2 * (size_t)s.ny * 16 * 8,                // hsg
+      (size_t)s.NC * chunks * s.nc * (shak ? kSlotsShakhov : kSlots) * 8,  // hs: partial sums
+      2 * (size_t)s.ny * kGhostSums * 8,        // hsg
       (size_t)s.NC * s.ny * (s.nx + 1) * kRec * 8,  // recx
       (size_t)s.NC * (s.ny + 1) * s.nx * kRec * 8,  // recy
       (size_t)(s.K + 6 * s.M) * 8,              // wk, wm, vmom
@@ -307,7 +325,9 @@ int ugks_required_bytes(const ugks_mesh* mesh, const ugks_vgrid* vgrid, const ug
     return fail(nullptr, UGKS_E_INVAL, "unknown precision%s");
   if (opts && (opts->velocity_chunks < 0 || opts->velocity_chunks > 16))
     return fail(nullptr, UGKS_E_INVAL, "velocity_chunks must be in 0..16%s");
-  *out_bytes = layout_of(s, prec, chunks_of(s, opts ? opts->velocity_chunks : 0)).total;
+  bool shak = false;
+  if (!collision_of(opts, s, shak, why)) return fail(nullptr, UGKS_E_INVAL, "%s", why.c_str());
+  *out_bytes = layout_of(s, prec, chunks_of(s, opts ? opts->velocity_chunks : 0), shak).total;
   return UGKS_OK;
 }
 
@@ -335,8 +355,10 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   if (!(opts->dt_override > 0) && !(opts->cfl > 0 && std::isfinite(opts->cfl)))
     return fail(nullptr, UGKS_E_INVAL, "need cfl > 0 or dt_override > 0%s");
 
+  bool shak = false;
+  if (!collision_of(opts, s, shak, why)) return fail(nullptr, UGKS_E_INVAL, "%s", why.c_str());
   const int chunks = chunks_of(s, opts->velocity_chunks);
-  const Layout L = layout_of(s, opts->precision, chunks);
+  const Layout L = layout_of(s, opts->precision, chunks, shak);
   if (opts->workspace && opts->workspace_bytes < L.total)
     return fail(nullptr, UGKS_E_NOMEM, "workspace smaller than ugks_required_bytes()%s");
   if (opts->workspace && (reinterpret_cast<uintptr_t>(opts->workspace) % kAlign) != 0)
@@ -379,6 +401,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   P.lam_c = 0.25 * (double)(2 + s.dof);
   P.q_c = 0.5 * (double)(2 + s.dof);
   P.a4_c = 4.0 / (double)(2 + s.dof);
+  P.shak = shak ? 1 : 0;
+  P.nslot = shak ? kSlotsShakhov : kSlots;
+  P.pr_c = shak ? 1.0 - opts->prandtl : 0.0;
   P.Lx = s.Lx;
   P.Ly = s.Ly;
   P.gmax = chunks;
@@ -744,6 +769,10 @@ int ugks_step_batch(ugks_batch* b, ugks_handle* const* hs, int count, int n) {
   for (int q = 0; q < count; ++q) {
     if (!hs[q]) {
       b->err = "NULL handle in the batch";
+      return UGKS_E_INVAL;
+    }
+    if (hs[q]->inst.P.shak != hs[0]->inst.P.shak) {
+      b->err = "a batch holds handles of one collision model";
       return UGKS_E_INVAL;
     }
     if (hs[q]->inst.fp32 != hs[0]->inst.fp32) {

@@ -21,6 +21,13 @@ inline UGKS_GLOBAL T* gp(T* p) {
 
 constexpr int kWave = 64;      // CDNA wavefront
 constexpr int kSlots = 64;     // per-cell outgoing moment sums: 4 faces x 16
+// Shakhov model: after the 64 sums, one more per face side (sum of ut (un^2 + ut^2)/2 f_hat, for
+// the interface heat flux) and eight raw moments of the cell's f (sum of f, u f, v f, u^2 f,
+// u v f, v^2 f, u |c|^2 f, v |c|^2 f with |c|^2 = u^2 + v^2) for its heat flux
+constexpr int kSlotHeat = 64;
+constexpr int kSlotCell = 68;
+constexpr int kSlotsShakhov = 76;
+constexpr int kGhostSums = 17;  // sums of a channel ghost cell towards the domain: 16 + the heat sum
 constexpr int kRec = 32;       // doubles per interface record
 constexpr int kHalo = 2;       // halo columns / rows on each side of a velocity plane
 constexpr int kMaxNodes = 1024;  // nodes per velocity axis
@@ -61,6 +68,9 @@ struct KParams {
   double lam_c;     // (2 + dof)/4: lambda = lam_c rho / (rho E - rho |U|^2/2)
   double q_c;       // (2 + dof)/2: the energy row of the micro-slope solve, q2 = |U|^2 + q_c/lambda
   double a4_c;      // 4/(2 + dof): its energy coefficient, a4 = a4_c lambda^2/rho (...)
+  int shak;         // Shakhov collision model (else BGK)
+  int nslot;        // per-cell sums per velocity chunk: kSlots, or kSlotsShakhov
+  double pr_c;      // 1 - Prandtl number (Shakhov)
   int Lx, Ly;       // padded row length and row count of a plane
   int bc, collisionless, inlet_fixed_u;
   int gmax;         // velocity chunks per quadrant the moment-sum buffer has room for
@@ -87,9 +97,9 @@ struct Buffers {
   void* f[2];       // [NC NV][PS] storage type
   double* W[2];     // [nx*ny][4], ping-pong with f
   double* Wg;       // [2][ny][4]
-  double* hs;       // [NC gmax][64][nx*ny]: partial g of sum q of face side s of cell c at
-                    // ((g 64) + 16 s + q) nx ny + c; chunks of H after those of G
-  double* hsg;      // [2][ny][16]
+  double* hs;       // [NC gmax][nslot][nx*ny]: partial g of sum q of face side s of cell c at
+                    // ((g nslot) + 16 s + q) nx ny + c; chunks of H after those of G
+  double* hsg;      // [2][ny][kGhostSums]
   double* recx;     // [NC][ny][nx+1][32]: records of G, then of H
   double* recy;     // [NC][ny+1][nx][32]
   double* wk;       // [K], followed by wm [M], then vmom [M][5]
@@ -139,6 +149,7 @@ struct PlanTotals {
   int sums, upd, face, ghost;  // workgroups of each launch
   int red;                     // workgroups of the chunk-sum launch (0: not launched)
   int max_m;                   // largest nv of the plan's instances
+  int shak;                    // the instances use the Shakhov model (all or none)
 };
 
 // Bytes of a device plan with n instances, and its host image (offsets into one buffer).

@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void init_kernel(PlanView pv) {
 constexpr int kGhostThreads = 256;
 template <typename S>
 __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
-  __shared__ double part[kGhostThreads / kWave][16];
+  __shared__ double part[kGhostThreads / kWave][kGhostSums];
   const int b = blockIdx.x;
   const int ii = find_inst(pv.off_ghost, pv.ninst, b);
   const Inst* __restrict__ I = inst_at(pv, ii);
@@ -471,9 +471,9 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
   const double coef = pg.rho * pg.lam / kPi;
   const double kap = (double)P.dof / (2.0 * pg.lam);
   const int at = pidx(P, side == 0 ? -1 : P.nx, j);
-  double acc[16];
+  double acc[kGhostSums];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kGhostSums; ++q) acc[q] = 0.0;
   for (int p = tid; p < P.NV; p += kGhostThreads) {
     const int k = p / P.M, m = p - k * P.M;
     const double u = P.uk[k], vv = P.vm[m], w = P.wk[k] * P.wm[m];
@@ -484,6 +484,8 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
     const double up = u > 0.0 ? 1.0 : (u < 0.0 ? 0.0 : 0.5);
     const double h = side == 0 ? up : 1.0 - up;
     add_side(acc, w * h, u, vv, 0.5 * (u * u + vv * vv), (double)gs, 0.0, 0.0);
+    // for the Shakhov heat flux of the interface: sum of ut (un^2 + ut^2)/2 f
+    acc[16] = fma((w * h) * (double)gs, vv * (0.5 * (u * u + vv * vv)), acc[16]);
     if (P.NC > 1) {
       // H carries energy only: psi = (0, 0, 0, 1/2)
       const S hg = static_cast<S>(kap * g);
@@ -495,16 +497,16 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
   }
   const int w = tid >> 6;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < kGhostSums; ++q) {
     const double t = wave_sum(acc[q]);
     if (lane == q) part[w][q] = t;
   }
   __syncthreads();
-  if (tid < 16) {
+  if (tid < kGhostSums) {
     double t = 0.0;
 #pragma unroll
     for (int r = 0; r < kGhostThreads / kWave; ++r) t += part[r][tid];
-    hsg[((size_t)side * P.ny + j) * 16 + tid] = t;
+    hsg[((size_t)side * P.ny + j) * kGhostSums + tid] = t;
   }
 }
 
@@ -517,10 +519,14 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
 // D = (2u/dx) hx + (2v/dy) hy; the 32 face sums take them in once per line.  The two partial
 // sums of each face side meet in LDS at the end.  With internal degrees of freedom the
 // chunks G..2G-1 of a segment walk the planes of H, whose psi is (0, 0, 0, 1/2): they add to
-// the energy sums only.
-template <typename S>
+// the energy sums only.  The Shakhov instantiation (kShak) also sums, per face side, ut c2h
+// of the reconstruction (c2h = (un^2 + ut^2)/2) and, per cell, eight raw moments of f for
+// the heat fluxes.
+template <typename S, bool kShak>
 __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
-  __shared__ double red[4][16][kWave];
+  constexpr int kR = kShak ? 17 : 16;
+  __shared__ double red[4][kR][kWave];
+  __shared__ double cellred[kShak ? 3 : 1][8][kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   const int g = hpart ? gg - G : gg;
   const UGKS_GLOBAL S* f = static_cast<const UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]) +
                            (hpart ? (long long)P.NV * P.PS : 0ll);
-  UGKS_GLOBAL double* hs = I->hs + (size_t)gg * kSlots * ((size_t)P.nx * P.ny);
+  UGKS_GLOBAL double* hs = I->hs + (size_t)gg * P.nslot * ((size_t)P.nx * P.ny);
   const int i = t * kTileS - 1 + lane;
   const bool valid = lane >= 1 && lane <= kTileS && i < P.nx;
   const int o = pidx(P, i < P.nx + 1 ? i : P.nx + 1, j);
@@ -549,9 +555,13 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   const Half hu = {hu0.first + (hu0.count - 1) * hu0.step, hu0.count, -hu0.step};
   const Half hv = {hv0.first + (hv0.count - 1) * hv0.step, hv0.count, -hv0.step};
   const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
-  double ax[16], ay[16];
+  double ax[kR], ay[kR];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) ax[r] = ay[r] = 0.0;
+  for (int r = 0; r < kR; ++r) ax[r] = ay[r] = 0.0;
+  // raw cell moments (kShak): f, u f, v f, u^2 f, u v f, v^2 f, u |c|^2 f, v |c|^2 f
+  double cm[kShak ? 8 : 1];
+#pragma unroll
+  for (int r = 0; r < (kShak ? 8 : 1); ++r) cm[r] = 0.0;
   int a0, a1;
   chunk_range(hu.count, g, G, a0, a1);
   for (int a = a0; a < a1; ++a) {
@@ -661,15 +671,36 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     ay[13] = fma(wu, D2, ay[13]);
     ay[14] = fma(wuu, D1, ay[14]);
     ay[15] = fma(wu, cD1, ay[15]);
+    if constexpr (kShak) {
+      const double S3 = su > 0 ? F3 + X3 : F3 - X3;
+      ax[16] = fma(wu, fma(u2h, S1, 0.5 * S3), ax[16]);
+      ay[16] = fma(wuu, cR, ay[16]);
+      const double wu2 = wuu * u;
+      cm[0] = fma(wu, F0, cm[0]);
+      cm[1] = fma(wuu, F0, cm[1]);
+      cm[2] = fma(wu, F1, cm[2]);
+      cm[3] = fma(wu2, F0, cm[3]);
+      cm[4] = fma(wuu, F1, cm[4]);
+      cm[5] = fma(wu, F2, cm[5]);
+      cm[6] = fma(wuu, fma(u * u, F0, F2), cm[6]);
+      cm[7] = fma(wu, fma(u * u, F1, F3), cm[7]);
+    }
   }
   // x faces: (+) from waves 0 and 3, (-) from 1 and 2; y faces: (+) from 0 and 1, (-) from
   // 2 and 3.  Waves 1 and 3 hand their sums over, waves 0 and 2 add and write.
   if (q == 1 || q == 3) {
     const int s = q == 1 ? 0 : 1;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < kR; ++r) {
       red[s][r][lane] = ay[r];
       red[2 + s][r][lane] = ax[r];
+    }
+  }
+  if constexpr (kShak) {
+    // every quadrant holds part of each cell's moments; wavefront 0 adds them
+    if (q > 0) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) cellred[q - 1][r][lane] = cm[r];
     }
   }
   __syncthreads();
@@ -685,6 +716,16 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
       hs[(size_t)(16 * fx + r) * nc + cell] = sx;
       hs[(size_t)(16 * fy + r) * nc + cell] = sy;
     }
+    if constexpr (kShak) {
+      hs[(size_t)(kSlotHeat + fx) * nc + cell] = ax[16] + red[ox][16][lane];
+      hs[(size_t)(kSlotHeat + fy) * nc + cell] = ay[16] + red[oy][16][lane];
+      if (q == 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          hs[(size_t)(kSlotCell + r) * nc + cell] =
+              ((cm[r] + cellred[0][r][lane]) + cellred[1][r][lane]) + cellred[2][r][lane];
+      }
+    }
   }
 }
 
@@ -698,9 +739,9 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(PlanView pv) {
   const KParams P = I->P;
   const size_t nc = (size_t)P.nx * P.ny;
   const size_t e = (size_t)(b - first_block(pv.off_red, ii)) * blockDim.x + threadIdx.x;
-  if (e >= kSlots * nc) return;
+  if (e >= (size_t)P.nslot * nc) return;
   UGKS_GLOBAL double* at = I->hs + e;
-  const size_t gstride = (size_t)kSlots * nc;
+  const size_t gstride = (size_t)P.nslot * nc;
   double x = at[0];
   for (int g = 1; g < I->gsplit * P.NC; ++g) x += at[(size_t)g * gstride];
   at[0] = x;
@@ -712,11 +753,44 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(PlanView pv) {
 // term c_4 psi_4 of a slope c contributes c_4 (un^2 + ut^2 + s)/2 to the polynomial of G with
 // s = <|xi|^2> = x2, and to that of H, whose Maxwellian is x2 times that of G, with
 // s = <|xi|^4>/<|xi|^2> = x4/x2: the constant shifts e0, e1 and e2 by c_4 s/2.
+// Heat flux q = sum w c |c|^2 f / 2 about (U, V) from raw sums of f: m0 = sum f, mn = sum un f,
+// mt = sum ut f, mnn, mnt, mtt = sum un^2 f, un ut f, ut^2 f, Kn = sum un |c|^2 f,
+// Kt = sum ut |c|^2 f, K0 = sum |c|^2 f (|c|^2 = un^2 + ut^2).
+__device__ __forceinline__ void heat_flux(double m0, double mn, double mt, double mnn,
+                                          double mnt, double mtt, double Kn, double Kt,
+                                          double K0, double U, double V, double* q) {
+  const double UV2 = U * U + V * V;
+  const double c2 = K0 - 2.0 * (U * mn + V * mt) + UV2 * m0;  // sum |u - U|^2 f
+  q[0] = 0.5 * (Kn - 2.0 * (U * mnn + V * mnt) + UV2 * mn - U * c2);
+  q[1] = 0.5 * (Kt - 2.0 * (U * mnt + V * mtt) + UV2 * mt - V * c2);
+}
+
+// Shakhov term of an interface: g0 S0 held over the step adds Mt1 g0 S0 to the distribution
+// flux, S0 = k (c . q)(2 lambda |c|^2 - 4), k = (1 - Pr) lambda^2/rho, c = (un - U, ut - V);
+// expanded in the record's basis {1, un, ut, c2h, un^2, un ut, ut^2, un c2h, ut c2h} it adds
+// to every coefficient of both upwind sides.
+__device__ __forceinline__ void fold_shakhov(UGKS_GLOBAL double* rec, const Prim& p0,
+                                             const double* q, double km) {
+  const double lam = p0.lam, U = p0.U, V = p0.V;
+  const double Q0 = q[0] * U + q[1] * V;
+  const double C0 = 2.0 * lam * (U * U + V * V) - 4.0;
+  const double l4 = 4.0 * lam;
+  const double d[9] = {-C0 * Q0,          l4 * U * Q0 + C0 * q[0], l4 * V * Q0 + C0 * q[1],
+                       -l4 * Q0,          -l4 * U * q[0],          -l4 * (V * q[0] + U * q[1]),
+                       -l4 * V * q[1],    l4 * q[0],               l4 * q[1]};
+#pragma unroll
+  for (int n = 0; n < 9; ++n) rec[R_E + n] = fma(km, d[n], rec[R_E + n]);
+  rec[R_ER + 0] = fma(km, d[1], rec[R_ER + 0]);
+  rec[R_ER + 1] = fma(km, d[4], rec[R_ER + 1]);
+  rec[R_ER + 2] = fma(km, d[5], rec[R_ER + 2]);
+  rec[R_ER + 3] = fma(km, d[7], rec[R_ER + 3]);
+}
+
 template <bool kXi>
 __device__ void interface_scalars(const KParams& P, const double* S, const double* WL,
                                   const double* WR, double dn, double len, double* F,
                                   UGKS_GLOBAL double* rec, UGKS_GLOBAL double* recH,
-                                  double& U0, double& V0) {
+                                  double& U0, double& V0, double T3 = 0.0) {
   const double* W0 = S;
   const double* Wt = S + 4;
   const double* Q1 = S + 8;
@@ -774,9 +848,16 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
   mpsi_c<kXi>(mn, mv, 2, 0, xi, aR, eR);
   mpsi_c<kXi>(mu, mv, 1, 1, xi, b, eb);
   mpsi_c<kXi>(mu, mv, 1, 0, xi, A, eA);
+  // Shakhov: heat flux of the reconstruction at the interface (local frame); T3 is the sum of
+  // ut c2h f_hat, the other raw sums are W0 and Q1
+  double qh[2] = {0.0, 0.0};
+  if (P.shak)
+    heat_flux(W0[0], W0[1], W0[2], Q1[1], Q1[2], 2.0 * W0[3] - Q1[1], 2.0 * Q1[3], 2.0 * T3,
+              2.0 * W0[3], p0.U, p0.V, qh);
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const double feq = p0.rho * (Mt[0] * e0[q] + Mt[1] * (eL[q] + eR[q] + eb[q]) + Mt[2] * eA[q]);
+    double feq = p0.rho * (Mt[0] * e0[q] + Mt[1] * (eL[q] + eR[q] + eb[q]) + Mt[2] * eA[q]);
+    if (q == 3 && P.shak) feq = fma(Mt[0] * P.pr_c, qh[0], feq);
     F[q] = len * (feq + Mt[3] * Q1[q] - Mt[4] * Q2[q]);
   }
   // folded polynomial of the equilibrium part of the distribution flux
@@ -793,6 +874,7 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
   rec[R_ER + 1] = Mt[1] * aR[1];
   rec[R_ER + 2] = Mt[1] * (aR[2] + b[1]);
   rec[R_ER + 3] = Mt[1] * aR[3];
+  if (P.shak) fold_shakhov(rec, p0, qh, Mt[0] * P.pr_c * p0.lam * p0.lam / p0.rho);
   rec[R_GC] = len * p0.rho * p0.lam / kPi;
   rec[R_LAM] = p0.lam;
   rec[R_M4] = len * Mt[3];
@@ -838,31 +920,37 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   const bool chan = P.bc == UGKS_BC_CHANNEL;
   const size_t nc = (size_t)P.nx * P.ny;
   double S[16], F[4];
-  double U0, V0;
+  double U0, V0, T3 = 0.0;
   if (e < nfx) {
     const int j = (int)(e / (P.nx + 1)), i = (int)(e % (P.nx + 1));
     const UGKS_GLOBAL double *sL, *sR, *WL, *WR;
     size_t stL = nc, stR = nc;
+    const UGKS_GLOBAL double *hL, *hR;  // the heat sums of the two sides (Shakhov)
     if (i > 0 || !chan) {
       const size_t cl = (size_t)j * P.nx + wrap(i - 1, P.nx);
       sL = hs + 16 * S_XP * nc + cl;
+      hL = hs + (kSlotHeat + S_XP) * nc + cl;
       WL = W + 4 * cl;
     } else {
-      sL = hsg + (size_t)j * 16;
+      sL = hsg + (size_t)j * kGhostSums;
+      hL = sL + 16;
       stL = 1;
       WL = Wg + 4 * (size_t)j;
     }
     if (i < P.nx || !chan) {
       const size_t cr = (size_t)j * P.nx + wrap(i, P.nx);
       sR = hs + 16 * S_XM * nc + cr;
+      hR = hs + (kSlotHeat + S_XM) * nc + cr;
       WR = W + 4 * cr;
     } else {
-      sR = hsg + ((size_t)P.ny + j) * 16;
+      sR = hsg + ((size_t)P.ny + j) * kGhostSums;
+      hR = sR + 16;
       stR = 1;
       WR = Wg + 4 * ((size_t)P.ny + j);
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) S[q] = sL[q * stL] + sR[q * stR];
+    if (P.shak) T3 = *hL + *hR;
     double wl[4], wr[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -874,7 +962,7 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
     if (P.NC > 1)
       interface_scalars<true>(P, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0);
     else
-      interface_scalars<false>(P, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0);
+      interface_scalars<false>(P, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0, T3);
     for (int c = 0; c < P.NC; ++c) {
       UGKS_GLOBAL double* r = c ? recH : rec;
 #pragma unroll
@@ -928,12 +1016,13 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   const UGKS_GLOBAL double* sR = hs + 16 * S_YM * nc + cr;
 #pragma unroll
   for (int q = 0; q < 16; ++q) S[q] = sL[q * nc] + sR[q * nc];
+  if (P.shak) T3 = hs[(kSlotHeat + S_YP) * nc + cl] + hs[(kSlotHeat + S_YM) * nc + cr];
   const double wl[4] = {W[4 * cl], W[4 * cl + 2], W[4 * cl + 1], W[4 * cl + 3]};
   const double wr[4] = {W[4 * cr], W[4 * cr + 2], W[4 * cr + 1], W[4 * cr + 3]};
   if (P.NC > 1)
     interface_scalars<true>(P, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0);
   else
-    interface_scalars<false>(P, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0);
+    interface_scalars<false>(P, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0, T3);
   for (int c = 0; c < P.NC; ++c) {
     UGKS_GLOBAL double* r = c ? recH : rec;
     r[R_FX + 0] = F[0];
@@ -1039,8 +1128,25 @@ __device__ __forceinline__ void load_e(const double (*st)[kWave], int col, int s
 // recurrences.  Walls fold into the same form: the face leaving a wall carries only its
 // Maxwellian (P = 1, no free-transport part), the face reaching a wall only the first-order
 // free transport of the wall row.
-template <typename S, int SU>
+// Shakhov: S of one cell at fixed u as a cubic in v.  kqx, kqy = (1 - Pr)(lambda^2/rho) q;
+// S = (A + B v)(a2 v^2 + a1 v + a0) with A + B v = k (c . q), a2 v^2 + a1 v + a0 = 2 lambda |c|^2 - 4.
+__device__ __forceinline__ Cubic shakhov_in_v(double u, double kqx, double kqy, double lam,
+                                              double U, double V) {
+  const double du = u - U;
+  const double A = fma(du, kqx, -V * kqy), B = kqy;
+  const double a2 = 2.0 * lam, a1 = -4.0 * lam * V;
+  const double a0 = fma(2.0 * lam, fma(du, du, V * V), -4.0);
+  Cubic c;
+  c.c0 = A * a0;
+  c.c1 = fma(A, a1, B * a0);
+  c.c2 = fma(A, a2, B * a1);
+  c.c3 = B * a2;
+  return c;
+}
+
+template <typename S, int SU, bool kShak>
 __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& st,
+                                                const double (*sk)[kWave],
                                                 const double* vnode, int q, int lane, int sv,
                                                 int j, int g, int G,
                                                 bool valid, bool ghost_lane,
@@ -1145,6 +1251,14 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
       cun = cell_row(st, C_AN)[lane] * exp(-cell_row(st, C_LAMN)[lane] * dn * dn);
       cu1 = cell_row(st, C_A1)[lane] * exp(-cell_row(st, C_LAM1)[lane] * d1 * d1);
     }
+    // Shakhov: the factors (1 + S) of g^n and g^{n+1} as cubics in v
+    Cubic sn3{}, s13{};
+    if constexpr (kShak) {
+      sn3 = shakhov_in_v(u, sk[0][lane], sk[1][lane], cell_row(st, C_LAMN)[lane],
+                         cell_row(st, C_UN)[lane], cell_row(st, C_VN)[lane]);
+      s13 = shakhov_in_v(u, sk[2][lane], sk[3][lane], cell_row(st, C_LAM1)[lane],
+                         cell_row(st, C_U1)[lane], cell_row(st, C_V1)[lane]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     // v-direction Gaussians at the first node of the half and their ratios
     const int hf = sv > 0 ? 0 : 1;
@@ -1178,7 +1292,11 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
       // y: outgoing and incoming faces
       const double Fyo = av * fma(eo, horner(co, vv), fma(m4o, fhy, -m5o * D0));
       const double Fyi = av * fma(ei, horner(ci, vv), fma(m4i, fhY, -m5i * DY));
-      const double g = fma(cu1, e1, cun * en);
+      double g;
+      if constexpr (kShak)
+        g = fma(cu1 * e1, 1.0 + horner(s13, vv), (cun * en) * (1.0 + horner(sn3, vv)));
+      else
+        g = fma(cu1, e1, cun * en);
       const double f1 = fma(Af, fc, fma(AdF, (Fxi - Fxo) + (Fyi - Fyo), g));
       // lanes outside the segment store past the plane's range, which the hardware drops
       bstore(plane_rsrc(wline + (long long)m * P.PS, P), valid ? oc : kDropOffset, f1, S{});
@@ -1200,11 +1318,12 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
   }
 }
 
-template <typename S>
-__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(3)))
-void update_kernel(PlanView pv) {
+// The body of the update kernel; kShak: the Shakhov collision model.
+template <typename S, bool kShak>
+__device__ __forceinline__ void update_body(const PlanView& pv, double* vnode) {
   __shared__ Stage st;
-  extern __shared__ double vnode[];  // the v nodes of the largest instance of the plan
+  // Shakhov: (1 - Pr)(lambda^2/rho) q of each lane's cell at t^n and t^{n+1}
+  __shared__ double sk[kShak ? 4 : 1][kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -1290,6 +1409,22 @@ void update_kernel(PlanView pv) {
         An *= (double)P.dof / (2.0 * pn.lam);
       }
     }
+    if constexpr (kShak) {
+      // heat flux of f^n about U^n from the cell's raw moments (moment kernel, chunk 0)
+      const UGKS_GLOBAL double* cm = I->hs + (size_t)kSlotCell * ((size_t)P.nx * P.ny) + cc;
+      const size_t nc = (size_t)P.nx * P.ny;
+      double m[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) m[r] = valid ? cm[(size_t)r * nc] : 0.0;
+      double qn[2];
+      heat_flux(m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[3] + m[5], pn.U, pn.V, qn);
+      const double kn = P.collisionless ? 0.0 : P.pr_c * pn.lam * pn.lam / pn.rho;
+      const double k1 = P.collisionless ? 0.0 : P.pr_c * p1.lam * p1.lam / p1.rho;
+      sk[0][lane] = kn * qn[0];
+      sk[1][lane] = kn * qn[1];
+      sk[2][lane] = k1 * qn[0];
+      sk[3][lane] = k1 * qn[1];
+    }
     // every read of the flux fields by this wavefront is complete before they are reused
     __builtin_amdgcn_wave_barrier();
     const double cell[C_COUNT] = {pn.lam, pn.U, pn.V, p1.lam, p1.U, p1.V, An, A1, Af, AdF};
@@ -1327,10 +1462,26 @@ void update_kernel(PlanView pv) {
   }
   __syncthreads();
   if (quad_su(q) > 0)
-    update_quadrant<S, 1>(P, st, vnode, q, lane, sv, j, g, G, valid, ghost_lane, fin, fout, o);
+    update_quadrant<S, 1, kShak>(P, st, sk, vnode, q, lane, sv, j, g, G, valid, ghost_lane,
+                                 fin, fout, o);
   else
-    update_quadrant<S, -1>(P, st, vnode, q, lane, sv, j, g, G, valid, ghost_lane, fin, fout,
-                           o);
+    update_quadrant<S, -1, kShak>(P, st, sk, vnode, q, lane, sv, j, g, G, valid, ghost_lane,
+                                  fin, fout, o);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(3)))
+void update_kernel(PlanView pv) {
+  extern __shared__ double vnode[];  // the v nodes of the largest instance of the plan
+  update_body<S, false>(pv, vnode);
+}
+
+// The Shakhov variant carries two more cubics per u node: two waves per SIMD.
+template <typename S>
+__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(2)))
+void update_kernel_shakhov(PlanView pv) {
+  extern __shared__ double vnode[];
+  update_body<S, true>(pv, vnode);
 }
 
 }  // namespace
@@ -1376,7 +1527,8 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
     off[3][q] = t.ghost;
     off[4][q] = t.red;
     off[5][q] = 0;
-    if (G > 1) t.red += (int)((kSlots * (long long)P.nx * P.ny + 255) / 256);
+    if (G > 1) t.red += (int)(((long long)P.nslot * P.nx * P.ny + 255) / 256);
+    t.shak = t.shak || P.shak;
     t.sums += ((P.nx + kTileS - 1) / kTileS) * P.ny * G;
     t.upd += ((P.nx + kTileU - 1) / kTileU) * P.ny * G;
     t.max_m = P.M > t.max_m ? P.M : t.max_m;
@@ -1426,10 +1578,17 @@ hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int p
         ghost_kernel<double><<<(unsigned)t.ghost, kGhostThreads, 0, s>>>(pv);
       break;
     case 1:
-      if (fp32)
-        sums_kernel<float><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
-      else
-        sums_kernel<double><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
+      if (t.shak) {
+        if (fp32)
+          sums_kernel<float, true><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
+        else
+          sums_kernel<double, true><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
+      } else {
+        if (fp32)
+          sums_kernel<float, false><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
+        else
+          sums_kernel<double, false><<<(unsigned)t.sums, kWave * kQuads, 0, s>>>(pv);
+      }
       if (t.red > 0) {
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1439,11 +1598,20 @@ hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int p
     case 2:
       faces_kernel<<<(unsigned)t.face, 256, 0, s>>>(pv);
       break;
-    default:
-      if (fp32)
-        update_kernel<float><<<(unsigned)t.upd, kWave * kQuads, 8 * (size_t)t.max_m, s>>>(pv);
-      else
-        update_kernel<double><<<(unsigned)t.upd, kWave * kQuads, 8 * (size_t)t.max_m, s>>>(pv);
+    default: {
+      const size_t lds = 8 * (size_t)t.max_m;
+      if (t.shak) {
+        if (fp32)
+          update_kernel_shakhov<float><<<(unsigned)t.upd, kWave * kQuads, lds, s>>>(pv);
+        else
+          update_kernel_shakhov<double><<<(unsigned)t.upd, kWave * kQuads, lds, s>>>(pv);
+      } else {
+        if (fp32)
+          update_kernel<float><<<(unsigned)t.upd, kWave * kQuads, lds, s>>>(pv);
+        else
+          update_kernel<double><<<(unsigned)t.upd, kWave * kQuads, lds, s>>>(pv);
+      }
+    }
   }
   return hipGetLastError();
 }

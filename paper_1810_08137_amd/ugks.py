@@ -50,7 +50,8 @@ class ugks_opts(ctypes.Structure):
                 ("cfl", ctypes.c_double), ("rho0", ctypes.c_double), ("T0", ctypes.c_double),
                 ("noise", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("dt_override", ctypes.c_double), ("stream", ctypes.c_void_p),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("prandtl", ctypes.c_double)]
 
 
 class ugks_info(ctypes.Structure):
@@ -240,7 +241,7 @@ def ugks_batch_last_error(b):
 def make_structs(nx, ny, lx, ly, nu, nv, umax, vmax, bc="channel", p_ratio=2.0, T_in=1.0,
                  T_wall=1.0, inlet_fixed_u=0, U_in=0.0, U_noise=0.0, precision="fp64", cfl=0.8,
                  rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, velocity_chunks=0,
-                 dof=0, **_):
+                 dof=0, prandtl=1.0, **_):
     mesh = ugks_mesh(int(nx), int(ny), float(lx), float(ly))
     vgrid = ugks_vgrid(int(nu), int(nv), float(umax), float(vmax), int(dof))
     kind = {"periodic": UGKS_BC_PERIODIC, "channel": UGKS_BC_CHANNEL}[bc] if isinstance(bc, str) else int(bc)
@@ -248,7 +249,7 @@ def make_structs(nx, ny, lx, ly, nu, nv, umax, vmax, bc="channel", p_ratio=2.0, 
                 float(U_in), float(U_noise))
     prec = {"fp64": UGKS_FP64, "fp32_store": UGKS_FP32_STORE}[precision] if isinstance(precision, str) else int(precision)
     o = ugks_opts(prec, int(velocity_chunks), float(cfl), float(rho0), float(T0), float(noise),
-                  int(seed), float(dt_override), None, None, 0)
+                  int(seed), float(dt_override), None, None, 0, float(prandtl))
     return mesh, vgrid, b, o
 
 

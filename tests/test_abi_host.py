@@ -93,7 +93,18 @@ def test_struct_layouts_match_the_header():
     assert ugks.ugks_info.dx.offset == 32
 
 
+def test_shakhov_adds_heat_sums_to_the_partial_sums():
+    """The Shakhov model keeps 76 partial sums per cell and chunk instead of 64."""
+    kn, (m0, v0, _, o0) = _structs()
+    kn, (m1, v1, _, o1) = _structs(prandtl=2.0 / 3.0)
+    d = ugks.ugks_required_bytes(m1, v1, o1) - ugks.ugks_required_bytes(m0, v0, o0)
+    assert d >= 12 * 400 * 100 * 8
+    kn, (m2, v2, _, o2) = _structs(prandtl=1.0)      # 1 (like 0) is BGK
+    assert ugks.ugks_required_bytes(m2, v2, o2) == ugks.ugks_required_bytes(m0, v0, o0)
+
+
 @pytest.mark.parametrize("field,value", [
+    ("prandtl", -0.5), ("prandtl", 1.5), ("prandtl", float("nan")),
     ("dof", -1), ("dof", 17),
     ("nx", 0), ("ny", -1), ("lx", 0.0), ("nu", 1), ("nv", 0), ("umax", -1.0),
     ("nu", 2000), ("nu", 1025), ("noise", 1.5), ("rho0", 0.0), ("T0", -1.0),
@@ -112,6 +123,17 @@ def test_create_rejects_invalid_arguments(field, value):
     assert rc == ugks.UGKS_E_INVAL
     assert not h.value
     assert ugks.ugks_last_error(None)
+
+
+def test_shakhov_needs_a_gas_without_internal_dof():
+    c = dict(WL.C1, prandtl=2.0 / 3.0, dof=1)
+    kn = c.pop("kn")
+    mesh, vgrid, bc, opts = ugks.make_structs(**c)
+    h = ctypes.c_void_p(None)
+    rc = ugks.lib().ugks_create(ctypes.byref(mesh), ctypes.byref(vgrid), kn, ctypes.byref(bc),
+                                ctypes.byref(opts), ctypes.byref(h))
+    assert rc == ugks.UGKS_E_INVAL and not h.value
+    assert "internal_dof" in ugks.ugks_last_error(None)
 
 
 @pytest.mark.parametrize("kn", [0.0, -0.1, float("nan")])

@@ -1,0 +1,142 @@
+"""GPU parity for the Shakhov collision model: the HIP path through the C ABI against the FP64
+oracle on the same seeded inputs (FP64 bar 1e-12 on rho, T relative, U, V absolute and f per
+cell; FP32-store 1e-5)."""
+import numpy as np
+import pytest
+
+from paper_1810_08137_amd import ugks
+from paper_1810_08137_amd import workloads as WL
+from tests import parity as PR
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(**kw):
+    c = dict(WL.CHANNEL_DEFAULTS)
+    c.update(kw)
+    return c
+
+
+def test_c1_shakhov_first_step_fluxes():
+    PR.oracle_threads()
+    g, o = PR.make_pair(WL.C1_SHAKHOV)
+    try:
+        g.step(1)
+        assert o.step(1) == 0
+        Fx, Fy = g.face_flux()
+        Rx, Ry = o.face_flux()
+        scale = np.max(np.abs(Rx), axis=(0, 1))
+        ex = np.max(np.abs(Fx - Rx), axis=(0, 1)) / scale
+        ey = np.max(np.abs(Fy - Ry), axis=(0, 1)) / np.maximum(np.max(np.abs(Ry), axis=(0, 1)), scale)
+        print("[parity] C1 Shakhov step 1 face flux errors", ex, ey, flush=True)
+        assert np.all(ex < 1e-12) and np.all(ey < 1e-12)
+        f_gpu, W_gpu = g.state()
+        f_ref, W_ref = o.state()
+        e = PR.errors(PR.moments_of_W(W_gpu), PR.moments_of_W(W_ref), f_gpu, f_ref)
+        PR.assert_within(e, PR.FP64_TOL, "C1 Shakhov step 1")
+    finally:
+        g.close()
+        o.close()
+
+
+def test_c1_shakhov_full_run():
+    PR.run_and_compare(WL.C1_SHAKHOV, WL.C1_STEPS, label="C1 Shakhov Pr 2/3")
+    # the model is in effect: its flow differs from the BGK one far above the parity bar
+    kn, kw = WL.solver_kwargs(WL.C1)
+    ms = []
+    for c in (WL.C1, WL.C1_SHAKHOV):
+        kn, kw = WL.solver_kwargs(c)
+        s = ugks.Solver(kn, **kw)
+        try:
+            s.step(WL.C1_STEPS)
+            ms.append(s.moments())
+        finally:
+            s.close()
+    dT = float(np.max(np.abs(ms[0][..., 3] - ms[1][..., 3])))
+    print(f"[parity] C1 Shakhov vs BGK max |dT| {dT:.3g}", flush=True)
+    assert dT > 1e-6
+
+
+@pytest.mark.parametrize("pr,bc,nx,ny,nu,nv", [(0.4, 0, 13, 7, 11, 9), (2 / 3, 1, 9, 5, 7, 7),
+                                               (0.9, 1, 17, 3, 6, 6)])
+def test_ragged_shakhov_cases(pr, bc, nx, ny, nu, nv):
+    case = _case(nx=nx, ny=ny, lx=nx / 4.0, ly=1.0, nu=nu, nv=nv, umax=4.0, vmax=4.0, kn=0.08,
+                 bc=bc, noise=0.05, seed=6, prandtl=pr)
+    PR.run_and_compare(case, 12, label=f"ragged Shakhov Pr {pr:.3g} bc={bc} {nx}x{ny} {nu}x{nv}")
+
+
+@pytest.mark.parametrize("chunks", [1, 3])
+def test_shakhov_with_capped_velocity_chunks(chunks):
+    PR.run_and_compare(dict(WL.C1_SHAKHOV, velocity_chunks=chunks), 20,
+                       label=f"C1 Shakhov chunks<={chunks}")
+
+
+def test_shakhov_near_continuum():
+    """Kn 0.005: dt/tau ~ 1.5, where the heat-flux term weighs most."""
+    PR.run_and_compare(dict(WL.C1_SHAKHOV, kn=0.005), 50, label="C1 Shakhov Kn 0.005")
+
+
+def test_fp32_store_shakhov():
+    PR.run_and_compare(WL.C1_SHAKHOV, WL.C1_STEPS, precision="fp32_store",
+                       tol=PR.FP32_STORE_TOL, check_f=False, label="C1 Shakhov fp32-store")
+
+
+def test_c2_shakhov_full_size_steps():
+    PR.run_and_compare(WL.C2_SHAKHOV, 2, label="C2 Shakhov 400x100 40^2")
+
+
+def _run(case, steps):
+    kn, kw = WL.solver_kwargs(case)
+    s = ugks.Solver(kn, **kw)
+    try:
+        s.step(steps)
+        return s.state()
+    finally:
+        s.close()
+
+
+def test_collisionless_shakhov_is_bgk_bit_for_bit():
+    case = _case(nx=12, ny=8, lx=1.0, ly=1.0, nu=12, nv=12, umax=3.0, vmax=3.0,
+                 kn=float("inf"), bc=0, noise=0.3, seed=5)
+    fa, Wa = _run(case, 5)
+    fb, Wb = _run(dict(case, prandtl=2.0 / 3.0), 5)
+    assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb)
+
+
+def test_batch_of_shakhov_solvers_is_bitwise_the_lone_runs():
+    import torch
+
+    cases = [dict(WL.C1_SHAKHOV), dict(WL.C1, prandtl=0.4, seed=7),
+             _case(nx=9, ny=5, lx=2.0, ly=1.0, nu=7, nv=7, umax=4.0, vmax=4.0, kn=0.2, seed=4,
+                   prandtl=0.8)]
+    alone = [_run(c, 7) for c in cases]
+    solvers = []
+    for c in cases:
+        kn, kw = WL.solver_kwargs(c)
+        solvers.append(ugks.Solver(kn, **kw))
+    b = ugks.Batch(len(solvers))
+    try:
+        b.step(solvers, 7)
+        torch.cuda.synchronize()
+        batched = [s.state() for s in solvers]
+    finally:
+        b.close()
+        for s in solvers:
+            s.close()
+    for (fa, Wa), (fb, Wb) in zip(alone, batched):
+        assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb)
+
+
+def test_batch_refuses_mixed_collision_models():
+    solvers = []
+    for c in (WL.C1, WL.C1_SHAKHOV):
+        kn, kw = WL.solver_kwargs(c)
+        solvers.append(ugks.Solver(kn, **kw))
+    b = ugks.Batch(2)
+    try:
+        with pytest.raises(ugks.UgksError):
+            b.step(solvers, 1)
+    finally:
+        b.close()
+        for s in solvers:
+            s.close()
