@@ -26,9 +26,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "529201b6068bc9bd50e09ff08aef569f20b0afe83a24436375cdabcf50de173d",
-    "fp64": 1.4809e9,
-    "fp32_store": 0.7238e9,
+    "source_sha256": "18b7b298fd637453d0841556126f4e42bc6edd0714d92029801ff49d3d456323",
+    "fp64": 1.4775e9,
+    "fp32_store": 0.7236e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
     "valu_fp64": 1.279e8,
 }

@@ -42,7 +42,6 @@ def test_c1_shakhov_first_step_fluxes():
 def test_c1_shakhov_full_run():
     PR.run_and_compare(WL.C1_SHAKHOV, WL.C1_STEPS, label="C1 Shakhov Pr 2/3")
     # the model is in effect: its flow differs from the BGK one far above the parity bar
-    kn, kw = WL.solver_kwargs(WL.C1)
     ms = []
     for c in (WL.C1, WL.C1_SHAKHOV):
         kn, kw = WL.solver_kwargs(c)
