@@ -1476,9 +1476,10 @@ void update_kernel(PlanView pv) {
   update_body<S, false>(pv, vnode);
 }
 
-// The Shakhov variant carries two more cubics per u node: two waves per SIMD.
+// The Shakhov variant carries two more cubics per u node.  Held to three waves per SIMD it
+// spills one double per u node, outside the v loop.
 template <typename S>
-__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(3)))
 void update_kernel_shakhov(PlanView pv) {
   extern __shared__ double vnode[];
   update_body<S, true>(pv, vnode);
