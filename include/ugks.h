@@ -141,7 +141,8 @@ typedef struct {
   size_t device_bytes;
 } ugks_info;
 
-/* Device bytes a handle of this shape needs (f twice, ghosts, moment sums, face records,
+/* Device bytes a handle of this shape needs (f twice, twice more with internal degrees of
+   freedom; ghosts, moment sums, more of them with the Shakhov model, face records,
    W, velocity tables).  Pure host arithmetic: no HIP call. */
 int ugks_required_bytes(const ugks_mesh* mesh, const ugks_vgrid* vgrid, const ugks_opts* opts,
                         size_t* out_bytes);
