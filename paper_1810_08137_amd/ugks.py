@@ -105,7 +105,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"libugks.so not built ({LIB_PATH}); run __graft_entry__.build()")
+            raise RuntimeError(f"libugks.so not built ({LIB_PATH}); run python paper_1810_08137_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
