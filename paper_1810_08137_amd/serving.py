@@ -71,7 +71,9 @@ def serving_requests(n, rate, seed=4, steps=500, precision="fp32_store", meshes=
 
 
 class GpuExecutor:
-    """Runs requests as UGKS solvers on the current GPU, stepped together in one batch.
+    """Runs requests as UGKS solvers on the current GPU, stepped together: one batch per
+    storage precision and collision model (BGK or Shakhov) present, all on one stream, so a
+    step of the resident requests is one launch per phase and group.
     ``velocity_chunks`` caps every solver's velocity chunks (0: automatic).  A batch of
     resident requests fills the GPU by itself, so a small cap saves per-chunk setup; the
     default 4 keeps the low-load latency of the automatic choice."""
@@ -85,7 +87,8 @@ class GpuExecutor:
         self.ugks = ugks
         self.run_stream = torch.cuda.Stream()
         self.admit_stream = torch.cuda.Stream()
-        self.batch = ugks.Batch(max_slots, stream=self.run_stream)
+        self.max_slots = max_slots
+        self.batches = {}   # (precision, Shakhov model) -> Batch
         self.velocity_chunks = int(velocity_chunks)
         self.done_event = None
 
@@ -94,14 +97,27 @@ class GpuExecutor:
         mesh, vgrid, bc, opts = self.ugks.make_structs(velocity_chunks=self.velocity_chunks, **kw)
         return self.ugks.ugks_required_bytes(mesh, vgrid, opts)
 
+    @staticmethod
+    def group_of(req):
+        pr = req.case.get("prandtl", 1.0)
+        return (req.precision, 0.0 < pr < 1.0)
+
     def create(self, req):
         kn, kw = WL.solver_kwargs(req.case, req.precision)
         with self.torch.cuda.stream(self.admit_stream):
-            return self.ugks.Solver(kn, stream=self.admit_stream,
-                                    velocity_chunks=self.velocity_chunks, **kw)
+            s = self.ugks.Solver(kn, stream=self.admit_stream,
+                                 velocity_chunks=self.velocity_chunks, **kw)
+        s.serving_group = self.group_of(req)
+        return s
 
     def step(self, solvers, n):
-        self.batch.step(solvers, n)
+        groups = {}
+        for s in solvers:
+            groups.setdefault(s.serving_group, []).append(s)
+        for key in sorted(groups):
+            if key not in self.batches:
+                self.batches[key] = self.ugks.Batch(self.max_slots, stream=self.run_stream)
+            self.batches[key].step(groups[key], n)
         ev = self.torch.cuda.Event()
         ev.record(self.run_stream)
         self.done_event = ev
@@ -117,7 +133,9 @@ class GpuExecutor:
         solver.close()
 
     def close(self):
-        self.batch.close()
+        for b in self.batches.values():
+            b.close()
+        self.batches = {}
 
 
 class Server:

@@ -135,6 +135,34 @@ def test_request_loop_end_to_end():
             s.close()
 
 
+def test_request_loop_with_mixed_gases_and_collision_models():
+    """BGK, Shakhov and internal-degree-of-freedom requests in one request loop: the executor
+    steps one batch per collision model and every request ends as it would alone."""
+    reqs = SV.serving_requests(9, rate=400.0, seed=11, steps=15, precision="fp32_store",
+                               meshes=[(50, 12), (100, 25)], vgrids=[24])
+    for k, r in enumerate(reqs):
+        if k % 3 == 1:
+            r.case["prandtl"] = 2.0 / 3.0
+        elif k % 3 == 2:
+            r.case["dof"] = 1
+    ex = SV.GpuExecutor(max_slots=16)
+    try:
+        srv = SV.Server(ex, budget_bytes=8 << 30, max_slots=16, quantum=5)
+        stats = srv.run(reqs)
+        groups = sorted(ex.batches)
+    finally:
+        ex.close()
+    print("[serving] mixed run", stats, "groups", groups, flush=True)
+    assert stats["done"] == 9 and len(groups) == 2
+    for r in reqs[:3]:
+        s = _solver(r.case, "fp32_store", velocity_chunks=ex.velocity_chunks)
+        try:
+            s.step(r.steps)
+            assert np.array_equal(s.moments(), r.result)
+        finally:
+            s.close()
+
+
 def test_batch_mixing_chunked_and_unchunked_solvers():
     """A solver capped at one velocity chunk (no chunk-sum workgroups) between chunked ones:
     the chunk-sum launch must still find each chunked member, and every member steps
