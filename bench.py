@@ -24,11 +24,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # HBM bytes per launch of the update kernel on this workload: rocprofv3 FETCH_SIZE and
 # WRITE_SIZE of that kernel, each scaled by what the same counter reads for a device copy of
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
-# (This source differs from the one counted only in the Shakhov update kernel's occupancy
-# attribute; the update and moment kernels measured here compile to the same instructions.)
+# (This source differs from the one counted only in comments and in the Shakhov update
+# kernel's occupancy attribute; the kernels measured here compile to the same instructions.)
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "ed39b8c89208230ecd7e422974962de721569c4f28d3b09a315d1492bf9834af",
+    "source_sha256": "f1326c0deb37c17c8f1b3774369ccb6ac59d7a389d5f56056073644e75acb5f6",
     "fp64": 1.4775e9,
     "fp32_store": 0.7236e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source

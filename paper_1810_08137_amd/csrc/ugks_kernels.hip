@@ -19,6 +19,10 @@
 // share one row segment and take one velocity quadrant each: within a quadrant the upwind
 // direction of both axes is uniform, so an x-face flux is evaluated once, by the lane of its
 // upwind cell, and handed to the downwind lane.
+// Two variants run through the same kernels: a gas with internal degrees of freedom, whose
+// second reduced distribution H takes velocity chunks of its own (its planes follow those of
+// G), and the Shakhov collision model, a separate instantiation of the moment and update
+// kernels (heat sums; equilibria times (1 + S)).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -1114,20 +1118,6 @@ __device__ __forceinline__ void load_e(const double (*st)[kWave], int col, int s
   }
 }
 
-// Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  A workgroup takes one segment of
-// kTileU cells of row j; its lanes hold the segment and two cells on each side.  Wavefront q
-// runs velocity quadrant q (signs su, sv): u nodes outer, v nodes inner.  Per velocity a lane
-// (cell i) forms
-//   its upwind reconstruction and slope term at its outgoing x and y faces,
-//   the flux through its outgoing x face, which the downwind lane takes over as its incoming
-//   x flux (x faces of the segment are each evaluated once),
-//   the flux through its outgoing y face, and the incoming y flux from the reconstruction of
-//   the upwind row's cell (i, j - sv), rebuilt from rows j - 2 sv .. j.
-// The equilibrium part of a face flux is GC En(un) Et(ut) P(un, ut): the Gaussian and cubic
-// of the u node are formed once per node, those of the v node follow the node by Gauss
-// recurrences.  Walls fold into the same form: the face leaving a wall carries only its
-// Maxwellian (P = 1, no free-transport part), the face reaching a wall only the first-order
-// free transport of the wall row.
 // Shakhov: S of one cell at fixed u as a cubic in v.  kqx, kqy = (1 - Pr)(lambda^2/rho) q;
 // S = (A + B v)(a2 v^2 + a1 v + a0) with A + B v = k (c . q), a2 v^2 + a1 v + a0 = 2 lambda |c|^2 - 4.
 __device__ __forceinline__ Cubic shakhov_in_v(double u, double kqx, double kqy, double lam,
@@ -1144,6 +1134,20 @@ __device__ __forceinline__ Cubic shakhov_in_v(double u, double kqx, double kqy, 
   return c;
 }
 
+// Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  A workgroup takes one segment of
+// kTileU cells of row j; its lanes hold the segment and two cells on each side.  Wavefront q
+// runs velocity quadrant q (signs su, sv): u nodes outer, v nodes inner.  Per velocity a lane
+// (cell i) forms
+//   its upwind reconstruction and slope term at its outgoing x and y faces,
+//   the flux through its outgoing x face, which the downwind lane takes over as its incoming
+//   x flux (x faces of the segment are each evaluated once),
+//   the flux through its outgoing y face, and the incoming y flux from the reconstruction of
+//   the upwind row's cell (i, j - sv), rebuilt from rows j - 2 sv .. j.
+// The equilibrium part of a face flux is GC En(un) Et(ut) P(un, ut): the Gaussian and cubic
+// of the u node are formed once per node, those of the v node follow the node by Gauss
+// recurrences.  Walls fold into the same form: the face leaving a wall carries only its
+// Maxwellian (P = 1, no free-transport part), the face reaching a wall only the first-order
+// free transport of the wall row.
 template <typename S, int SU, bool kShak>
 __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& st,
                                                 const double (*sk)[kWave],
