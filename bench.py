@@ -108,6 +108,13 @@ def valu_issue(avg_ms):
             "frac": rate / VALU_ISSUE_PEAK}
 
 
+def traffic_rate(traffic, avg_ms, copy):
+    if traffic is None:
+        return None
+    gbs = traffic / (avg_ms * 1e-3) / 1e9
+    return {"GBs": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy["GBs"]}
+
+
 def stream_copy(nbytes=1 << 30, reps=20):
     """Device-to-device copy bandwidth of this GPU: bytes read plus bytes written per second
     over `reps` copies of an `nbytes` buffer.  The same copy calibrates the byte counters."""
@@ -375,6 +382,9 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic("fp64"),
                      "algorithmic_bytes_per_launch": algo_bytes},
+        # the measured bytes of the same launches over the same duration, against the peak and
+        # against this box's device-copy rate
+        "traffic_rate": traffic_rate(measured_traffic("fp64"), kernels[dom]["avg_ms"], copy),
         "valu_issue": valu_issue(kernels["update"]["avg_ms"]),
         "stream_copy": copy,
         "step_hbm_frac": algo_bytes / (fp64["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
