@@ -39,6 +39,7 @@ struct ugks_ref {
   double dx, dy, dt, mu_ref;
   int collisionless;
   double *uk, *vm, *wk, *wm;    /* 1D nodes and trapezoid weights */
+  double *fu, *fv, *fw;         /* the same per velocity k*M + m: u_k, v_m, w_k w_m */
   double *f, *fnew, *W, *Wnew;
   double *sx, *sy;              /* limited slopes of f, per cell and velocity */
   double *Fx, *Fy;              /* macroscopic face fluxes, global frame */
@@ -439,6 +440,15 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
   s->wm = malloc(sizeof(double) * s->M);
   ugks_ref_nodes(s->K, c->umax, s->uk, s->wk);
   ugks_ref_nodes(s->M, c->vmax, s->vm, s->wm);
+  s->fu = malloc(sizeof(double) * s->NV);
+  s->fv = malloc(sizeof(double) * s->NV);
+  s->fw = malloc(sizeof(double) * s->NV);
+  for (int k = 0; k < s->K; ++k)
+    for (int m = 0; m < s->M; ++m) {
+      s->fu[k * s->M + m] = s->uk[k];
+      s->fv[k * s->M + m] = s->vm[m];
+      s->fw[k * s->M + m] = s->wk[k] * s->wm[m];
+    }
   s->f = malloc(sizeof(double) * nc * NV);
   s->fnew = malloc(sizeof(double) * nc * NV);
   s->sx = malloc(sizeof(double) * nc * NV);
@@ -481,6 +491,7 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
 void ugks_ref_destroy(ugks_ref* s) {
   if (!s) return;
   free(s->uk); free(s->wk); free(s->vm); free(s->wm);
+  free(s->fu); free(s->fv); free(s->fw);
   free(s->f); free(s->fnew); free(s->sx); free(s->sy); free(s->W); free(s->Wnew);
   free(s->Fx); free(s->Fy); free(s->Ffx); free(s->Ffy); free(s->Wg); free(s->fg);
   free(s->xi_in);
@@ -818,17 +829,7 @@ static int update(ugks_ref* s) {
       double tn = collision_time(s->mu_ref, pn), tn1 = collision_time(s->mu_ref, pn1);
       double kn = (double)dof / (2.0 * pn[3]), kn1 = (double)dof / (2.0 * pn1[3]);
       double qn[2] = {0.0, 0.0};
-      if (s->pr != 1.0) {
-        double* cu = malloc(sizeof(double) * 3 * (size_t)NG);
-        for (int k = 0; k < K; ++k)
-          for (int m = 0; m < M; ++m) {
-            cu[k * M + m] = s->uk[k];
-            cu[NG + k * M + m] = s->vm[m];
-            cu[2 * NG + k * M + m] = s->wk[k] * s->wm[m];
-          }
-        heat_flux(NG, cu, cu + NG, cu + 2 * NG, f, pn, qn);
-        free(cu);
-      }
+      if (s->pr != 1.0) heat_flux(NG, s->fu, s->fv, s->fw, f, pn, qn);
       for (int k = 0; k < K; ++k)
         for (int m = 0; m < M; ++m)
           for (int v = k * M + m; v < NV; v += NG) {  /* G, then H */
