@@ -126,3 +126,26 @@ def test_batch_mixing_internal_dof_is_bitwise_the_lone_run():
             s.close()
     for (fa, Wa), (fb, Wb) in zip(alone, batched):
         assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb)
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(1, 6, 1), (8, 1, 1), (1, 1, 0), (2, 2, 1)])
+def test_degenerate_meshes_with_internal_dof(nx, ny, bc):
+    case = _case(nx=nx, ny=ny, lx=0.5 * nx, ly=0.5 * ny, nu=8, nv=8, umax=4.0, vmax=4.0, kn=0.3,
+                 bc=bc, noise=0.03, seed=21, dof=2)
+    PR.run_and_compare(case, 15, label=f"degenerate dof=2 {nx}x{ny} bc={bc}")
+
+
+def test_velocity_grid_at_the_limit_with_internal_dof():
+    """nu = nv = 1024 with G and H: 2^21 planes."""
+    case = _case(nx=3, ny=2, lx=1.5, ly=1.0, nu=1024, nv=1024, umax=12.0, vmax=12.0, kn=0.1,
+                 bc=1, noise=0.02, seed=17, dof=1)
+    PR.run_and_compare(case, 2, label="1024x1024 velocities dof=1")
+
+
+def test_info_reports_internal_dof():
+    kn, kw = WL.solver_kwargs(WL.C1_DOF)
+    s = ugks.Solver(kn, **kw)
+    try:
+        assert s.info.internal_dof == 1
+    finally:
+        s.close()

@@ -139,3 +139,16 @@ def test_batch_refuses_mixed_collision_models():
         b.close()
         for s in solvers:
             s.close()
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(1, 6, 1), (8, 1, 1), (1, 1, 0), (2, 2, 1)])
+def test_degenerate_meshes_shakhov(nx, ny, bc):
+    case = _case(nx=nx, ny=ny, lx=0.5 * nx, ly=0.5 * ny, nu=8, nv=8, umax=4.0, vmax=4.0, kn=0.3,
+                 bc=bc, noise=0.03, seed=21, prandtl=2.0 / 3.0)
+    PR.run_and_compare(case, 15, label=f"degenerate Shakhov {nx}x{ny} bc={bc}")
+
+
+def test_velocity_grid_at_the_limit_shakhov():
+    case = _case(nx=3, ny=2, lx=1.5, ly=1.0, nu=1024, nv=1024, umax=12.0, vmax=12.0, kn=0.1,
+                 bc=1, noise=0.02, seed=17, prandtl=2.0 / 3.0)
+    PR.run_and_compare(case, 2, label="1024x1024 velocities Shakhov")
