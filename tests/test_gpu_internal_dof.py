@@ -149,3 +149,8 @@ def test_info_reports_internal_dof():
         assert s.info.internal_dof == 1
     finally:
         s.close()
+
+
+def test_c3_with_internal_dof_full_size_steps():
+    """200x50 x 101^2 on [-20, 20]^2 with G and H."""
+    PR.run_and_compare(dict(WL.C3, dof=1), 2, label="C3 dof=1 200x50 101^2")

@@ -152,3 +152,8 @@ def test_velocity_grid_at_the_limit_shakhov():
     case = _case(nx=3, ny=2, lx=1.5, ly=1.0, nu=1024, nv=1024, umax=12.0, vmax=12.0, kn=0.1,
                  bc=1, noise=0.02, seed=17, prandtl=2.0 / 3.0)
     PR.run_and_compare(case, 2, label="1024x1024 velocities Shakhov")
+
+
+def test_c3_shakhov_full_size_steps():
+    """200x50 x 101^2 on [-20, 20]^2: large discrete speeds in the heat flux sums."""
+    PR.run_and_compare(dict(WL.C3, prandtl=2.0 / 3.0), 2, label="C3 Shakhov 200x50 101^2")
