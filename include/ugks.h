@@ -134,7 +134,7 @@ typedef struct {
   int plane_stride; /* values between the velocity planes of f in device memory: f is
                        stored per velocity as (ny+4) x (nx+4) padded planes */
   int precision;
-  int internal_dof;
+  int internal_dof;  /* as created; f then holds G and H, 2 nu nv values per cell */
   double dx, dy, dt;
   double tau_ref;  /* collision time at rho = T = 1; +inf in the collisionless limit */
   int64_t steps;   /* steps enqueued so far */
