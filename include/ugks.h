@@ -139,6 +139,7 @@ typedef struct {
   double tau_ref;  /* collision time at rho = T = 1; +inf in the collisionless limit */
   int64_t steps;   /* steps enqueued so far */
   size_t device_bytes;
+  double prandtl;  /* 1: BGK; below 1: the Shakhov model with this Prandtl number */
 } ugks_info;
 
 /* Device bytes a handle of this shape needs (f twice, twice more with internal degrees of

@@ -616,6 +616,7 @@ int ugks_get_info(const ugks_handle* h, ugks_info* out) {
   out->plane_stride = h->P.PS;
   out->precision = h->prec;
   out->internal_dof = h->P.dof;
+  out->prandtl = h->P.shak ? 1.0 - h->P.pr_c : 1.0;
   out->dx = h->P.dx;
   out->dy = h->P.dy;
   out->dt = h->P.dt;

@@ -94,6 +94,16 @@ def _run(case, steps):
         s.close()
 
 
+def test_info_reports_the_collision_model():
+    for c, pr in ((WL.C1, 1.0), (WL.C1_SHAKHOV, 2.0 / 3.0)):
+        kn, kw = WL.solver_kwargs(c)
+        s = ugks.Solver(kn, **kw)
+        try:
+            assert abs(s.info.prandtl - pr) < 1e-15
+        finally:
+            s.close()
+
+
 def test_collisionless_shakhov_is_bgk_bit_for_bit():
     case = _case(nx=12, ny=8, lx=1.0, ly=1.0, nu=12, nv=12, umax=3.0, vmax=3.0,
                  kn=float("inf"), bc=0, noise=0.3, seed=5)
