@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--paper-sweep", action="store_true",
                     help="also time the paper's meshes M1-M4 at 29^2, 49^2 and 69^2 velocities")
     ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--wide-velocity", action="store_true",
+                    help="also time the wide velocity space case (200x50 cells, 101^2 "
+                         "velocities, its 500 steps)")
     ap.add_argument("--no-shakhov", action="store_true",
                     help="skip the Shakhov collision model (Prandtl number 2/3)")
     ap.add_argument("--no-internal-dof", action="store_true",
@@ -187,6 +190,26 @@ def internal_dof(WL, ugks, steps, warmup):
             "distribution_values_per_s": 2 * upd * steps / (ms * 1e-3),
             "update_kernel_GBs": 32.0 * upd / (upd_ms * 1e-3) / 1e9,
             "step_hbm_frac": 32.0 * upd / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "kernels": prof}
+
+
+def wide_velocity(WL, ugks, warmup):
+    """The wide velocity space case: 200x50 cells, 101^2 velocities on [-20, 20]^2, Kn 0.5,
+    inlet velocity noise, FP64, its 500 steps."""
+    case = WL.C3
+    kn, kw = WL.solver_kwargs(case, "fp64")
+    s = ugks.Solver(kn, **kw)
+    try:
+        ms, _ = time_solver(s, WL.C3_STEPS, warmup)
+        prof = kernel_profile(s, 50)
+        s.moments()
+    finally:
+        s.close()
+    upd = WL.updates(case)
+    return {"cells": [case["nx"], case["ny"]], "velocities": [case["nu"], case["nv"]],
+            "steps": WL.C3_STEPS, "ms_per_step": ms / WL.C3_STEPS,
+            "updates_per_s": upd * WL.C3_STEPS / (ms * 1e-3),
+            "update_kernel_GBs": 16.0 * upd / (prof["update"]["avg_ms"] * 1e-3) / 1e9,
             "kernels": prof}
 
 
@@ -404,6 +427,8 @@ def main():
         out["serving"] = serving(args, fp64["updates_per_s"])
     if args.paper_sweep:
         out["paper_sweep"] = paper_sweep(WL, ugks, args.sweep_steps)
+    if args.wide_velocity:
+        out["wide_velocity"] = wide_velocity(WL, ugks, args.warmup)
     if not args.no_shakhov:
         out["shakhov"] = shakhov(WL, ugks, min(args.steps, 500), args.warmup)
     if not args.no_internal_dof:
