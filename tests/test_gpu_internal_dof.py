@@ -154,3 +154,22 @@ def test_info_reports_internal_dof():
 def test_c3_with_internal_dof_full_size_steps():
     """200x50 x 101^2 on [-20, 20]^2 with G and H."""
     PR.run_and_compare(dict(WL.C3, dof=1), 2, label="C3 dof=1 200x50 101^2")
+
+
+def test_checkpoint_resume_with_internal_dof_is_bitwise():
+    """The state holds G and H; restoring it into a fresh solver resumes bit for bit."""
+    kn, kw = WL.solver_kwargs(WL.C1_DOF)
+    a, b = ugks.Solver(kn, **kw), ugks.Solver(kn, **dict(kw, seed=99))
+    try:
+        a.step(10)
+        f, W = a.state()
+        assert f.shape[-1] == 2 * 576
+        b.set_state(f, W)
+        a.step(15)
+        b.step(15)
+        fa, Wa = a.state()
+        fb, Wb = b.state()
+        assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb)
+    finally:
+        a.close()
+        b.close()

@@ -276,3 +276,21 @@ def test_transverse_speed_ratio_limit(V, flagged):
             assert np.all(np.isfinite(m))
     finally:
         a.close()
+
+
+def test_zero_steps_change_nothing():
+    """ugks_step(h, 0) and a zero-step batch enqueue no work: the state stays bitwise."""
+    kn, kw = WL.solver_kwargs(WL.C1)
+    a = ugks.Solver(kn, **kw)
+    b = ugks.Batch(1)
+    try:
+        a.step(3)
+        f0, W0 = a.state()
+        a.step(0)
+        b.step([a], 0)
+        f1, W1 = a.state()
+        assert np.array_equal(f0, f1) and np.array_equal(W0, W1)
+        assert a.info.steps == 3
+    finally:
+        b.close()
+        a.close()

@@ -167,3 +167,20 @@ def test_velocity_grid_at_the_limit_shakhov():
 def test_c3_shakhov_full_size_steps():
     """200x50 x 101^2 on [-20, 20]^2: large discrete speeds in the heat flux sums."""
     PR.run_and_compare(dict(WL.C3, prandtl=2.0 / 3.0), 2, label="C3 Shakhov 200x50 101^2")
+
+
+def test_checkpoint_resume_shakhov_is_bitwise():
+    kn, kw = WL.solver_kwargs(WL.C1_SHAKHOV)
+    a, b = ugks.Solver(kn, **kw), ugks.Solver(kn, **dict(kw, seed=99))
+    try:
+        a.step(10)
+        f, W = a.state()
+        b.set_state(f, W)
+        a.step(15)
+        b.step(15)
+        fa, Wa = a.state()
+        fb, Wb = b.state()
+        assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb)
+    finally:
+        a.close()
+        b.close()
