@@ -294,3 +294,43 @@ def test_zero_steps_change_nothing():
     finally:
         b.close()
         a.close()
+
+
+def test_paper_length_run_stays_valid_and_settles():
+    """10,000 steps (the length of the paper's runs) of the parity channel: the state stays
+    valid and the flow settles (the step-to-step change of W decays)."""
+    kn, kw = WL.solver_kwargs(WL.C1)
+    s = ugks.Solver(kn, **kw)
+    try:
+        changes = []
+        for _ in range(5):
+            s.step(1999)
+            _, Wa = s.state()
+            s.step(1)
+            _, Wb = s.state()
+            changes.append(float(np.max(np.abs(Wb - Wa))))
+        m = s.moments()                        # raises on an invalid state
+        assert s.info.steps == 10000
+    finally:
+        s.close()
+    print("[long run] max |W^{n+1} - W^n| every 2000 steps", changes, flush=True)
+    assert np.all(np.isfinite(m)) and m[..., 0].min() > 0 and m[..., 3].min() > 0
+    assert changes[-1] < 0.1 * changes[0]
+    assert np.max(m[..., 1]) > 1e-3            # a pressure-driven flow remains
+
+
+def test_periodic_box_conserves_over_10000_steps():
+    case = _case(nx=24, ny=16, lx=1.5, ly=1.0, nu=16, nv=16, umax=5.0, vmax=5.0, kn=0.05, bc=0,
+                 noise=0.05, seed=9)
+    kn, kw = WL.solver_kwargs(case)
+    s = ugks.Solver(kn, **kw)
+    try:
+        _, W0 = s.state()
+        s.step(10000)
+        _, W = s.state()
+    finally:
+        s.close()
+    tot0, tot = W0.sum(axis=(0, 1)), W.sum(axis=(0, 1))
+    scale = np.array([tot0[0], tot0[0], tot0[0], tot0[3]])
+    print("[long run] periodic conservation", (tot - tot0) / scale, flush=True)
+    assert np.all(np.abs(tot - tot0) <= 1e-12 * scale)
