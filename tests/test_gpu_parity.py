@@ -334,3 +334,9 @@ def test_periodic_box_conserves_over_10000_steps():
     scale = np.array([tot0[0], tot0[0], tot0[0], tot0[3]])
     print("[long run] periodic conservation", (tot - tot0) / scale, flush=True)
     assert np.all(np.abs(tot - tot0) <= 1e-12 * scale)
+
+
+def test_c1_parity_holds_over_2000_steps():
+    """Rounding differences do not accumulate: after 2,000 steps (the flow near its steady
+    state) the GPU still matches the oracle within the FP64 bar."""
+    PR.run_and_compare(WL.C1, 2000, label="C1 2000 steps")
