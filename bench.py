@@ -24,15 +24,13 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # HBM bytes per launch of the update kernel on this workload: rocprofv3 FETCH_SIZE and
 # WRITE_SIZE of that kernel, each scaled by what the same counter reads for a device copy of
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
-# (This source differs from the one counted only in comments and in the Shakhov update
-# kernel's occupancy attribute; the kernels measured here compile to the same instructions.)
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "f1326c0deb37c17c8f1b3774369ccb6ac59d7a389d5f56056073644e75acb5f6",
-    "fp64": 1.4775e9,
-    "fp32_store": 0.7236e9,
+    "source_sha256": "a4b15b74a4aee1ba24e4e3b4730adb706490466499846ad980f402d4e89cfb06",
+    "fp64": 1.4842e9,
+    "fp32_store": 0.7274e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
-    "valu_fp64": 1.279e8,
+    "valu_fp64": 1.280e8,
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
 # 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)

@@ -578,14 +578,17 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     struct Vals {
       double c, s, n;
     };
-    auto load = [&](int c) {
-      const __amdgpu_buffer_rsrc_t r =
-          plane_rsrc(line + (long long)(hv.first + c * hv.step) * P.PS, P);
+    // planes and weight rows are walked with running pointers: one add per node each
+    const long long pstep = (long long)hv.step * P.PS;
+    const UGKS_GLOBAL S* pcur = line + (long long)hv.first * P.PS;
+    const UGKS_GLOBAL double* wp = P.vmom + 5 * hv.first;
+    const int wstep = 5 * hv.step;
+    auto load_at = [&](const UGKS_GLOBAL S* p) {
+      const __amdgpu_buffer_rsrc_t r = plane_rsrc(p, P);
       return Vals{bload<S>(r, oc), bload<S>(r, oS), bload<S>(r, oN)};
     };
-    auto node = [&](const Vals& x, int c) {
+    auto node = [&](const Vals& x) {
       // w_m v_m^n, n = 0..4, with the weight 1/2 of a node at v = 0 (visited by both halves)
-      const UGKS_GLOBAL double* wp = P.vmom + 5 * (hv.first + c * hv.step);
       const double w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3], w4 = wp[4];
       const double fW = from_lower(x.c), fE = from_upper(x.c);
       const double hx = half_limited(fE - x.c, x.c - fW);
@@ -603,17 +606,20 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
       Y2 = fma(hy, w2, Y2);
       Y3 = fma(hy, w3, Y3);
       Y4 = fma(hy, w4, Y4);
+      wp += wstep;
     };
     // two value sets, each node's loads issued one node ahead
-    Vals va = load(0);
+    Vals va = load_at(pcur);
     int c = 0;
     for (; c + 1 < hv.count; c += 2) {
-      const Vals vb = load(c + 1);
-      node(va, c);
-      va = load(c + 2 < hv.count ? c + 2 : c + 1);
-      node(vb, c + 1);
+      pcur += pstep;
+      const Vals vb = load_at(pcur);
+      node(va);
+      if (c + 2 < hv.count) pcur += pstep;
+      va = load_at(pcur);
+      node(vb);
     }
-    if (c < hv.count) node(va, c);
+    if (c < hv.count) node(va);
     // moments of the x-face reconstruction (S), the y-face one (R) and of D
     const double ucx = u * two_idx, u2h = 0.5 * u * u, wuu = wu * u;
     if (hpart) {
@@ -1198,13 +1204,17 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
     struct Vals {
       double c, y, o, yy;
     };
-    auto load = [&](int c) {
-      const __amdgpu_buffer_rsrc_t r =
-          plane_rsrc(line + (long long)(hv.first + c * hv.step) * P.PS, P);
+    // planes (read and written) and v nodes are walked with running pointers
+    const long long pstep = (long long)hv.step * P.PS;
+    const UGKS_GLOBAL S* pcur = line + (long long)hv.first * P.PS;
+    UGKS_GLOBAL S* wcur = wline + (long long)hv.first * P.PS;
+    int mcur = hv.first;
+    auto load_at = [&](const UGKS_GLOBAL S* p) {
+      const __amdgpu_buffer_rsrc_t r = plane_rsrc(p, P);
       return Vals{bload<S>(r, oc), bload<S>(r, oY), bload<S>(r, oO), bload<S>(r, oYY)};
     };
     // the first node's stencil values, requested before the node's tables are formed
-    Vals va = load(0);
+    Vals va = load_at(pcur);
     // x face: cubic in v times GC En(u), with |u| folded in
     Cubic cx;
     {
@@ -1271,9 +1281,8 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
     double ei = st.ys[hf][2 * yi][lane], ri = st.ys[hf][2 * yi + 1][lane];
     double en = st.gs[hf][0][lane], rn = st.gs[hf][1][lane];
     double e1 = st.gs[hf][2][lane], r1 = st.gs[hf][3][lane];
-    auto node = [&](const Vals& x, int c) {
-      const int m = hv.first + c * hv.step;
-      const double vv = vnode[m];
+    auto node = [&](const Vals& x) {
+      const double vv = vnode[mcur];
       const double fc = x.c, fY = x.y, fO = x.o, fYY = x.yy;
       const double av = fabs(vv);
       const double avcy = av * two_idy;
@@ -1303,7 +1312,9 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
         g = fma(cu1, e1, cun * en);
       const double f1 = fma(Af, fc, fma(AdF, (Fxi - Fxo) + (Fyi - Fyo), g));
       // lanes outside the segment store past the plane's range, which the hardware drops
-      bstore(plane_rsrc(wline + (long long)m * P.PS, P), valid ? oc : kDropOffset, f1, S{});
+      bstore(plane_rsrc(wcur, P), valid ? oc : kDropOffset, f1, S{});
+      wcur += pstep;
+      mcur += hv.step;
       gauss_next(ex, rx, qx);
       gauss_next(eo, ro, qo);
       gauss_next(ei, ri, qi);
@@ -1313,12 +1324,14 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
     // two value sets, each node's loads issued one node ahead
     int c = 0;
     for (; c + 1 < hv.count; c += 2) {
-      const Vals vb = load(c + 1);
-      node(va, c);
-      va = load(c + 2 < hv.count ? c + 2 : c + 1);
-      node(vb, c + 1);
+      pcur += pstep;
+      const Vals vb = load_at(pcur);
+      node(va);
+      if (c + 2 < hv.count) pcur += pstep;
+      va = load_at(pcur);
+      node(vb);
     }
-    if (c < hv.count) node(va, c);
+    if (c < hv.count) node(va);
   }
 }
 
