@@ -47,18 +47,23 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle sample")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=48)
-    ap.add_argument("--serving-steps", type=int, default=100)
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-steps", type=int, default=500)
     ap.add_argument("--serving-chunks", type=int, default=4,
                     help="cap on the velocity chunks of the serving solvers (0: automatic)")
-    ap.add_argument("--serving-rates", default="0.8",
+    ap.add_argument("--serving-rates", default="0.5,0.8,1.0",
                     help="Poisson arrival rates as fractions of the saturation rate")
     ap.add_argument("--paper-sweep", action="store_true",
                     help="also time the paper's meshes M1-M4 at 29^2, 49^2 and 69^2 velocities")
     ap.add_argument("--sweep-steps", type=int, default=200)
-    ap.add_argument("--wide-velocity", action="store_true",
-                    help="also time the wide velocity space case (200x50 cells, 101^2 "
-                         "velocities, its 500 steps)")
+    ap.add_argument("--no-wide-velocity", action="store_true",
+                    help="skip the wide velocity space case (200x50 cells, 101^2 velocities, "
+                         "its 500 steps)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FP32-store accuracy runs (1000 steps of both forms)")
+    ap.add_argument("--serving-reserve-gib", type=float, default=8.0,
+                    help="device memory left free when the serving budget is set from the "
+                         "free HBM at server start")
     ap.add_argument("--no-shakhov", action="store_true",
                     help="skip the Shakhov collision model (Prandtl number 2/3)")
     ap.add_argument("--no-internal-dof", action="store_true",
@@ -251,6 +256,32 @@ def moment_errors(m, ref):
     return {"rho_rel": rel(0), "U_abs": ab(1), "V_abs": ab(2), "T_rel": rel(3)}
 
 
+def accuracy_fp32_store(WL, ugks):
+    """The FP32-store form against the FP64 form after exactly the precision workload's step
+    count (1,000 steps of the 400x100 x 40^2 channel), both from the same seeded state.  The
+    FP64 GPU path itself matches the FP64 oracle within 1e-12."""
+    steps = WL.C4_STEPS
+    res = {}
+    for prec in ("fp64", "fp32_store"):
+        kn, kw = WL.solver_kwargs(WL.C4, prec)
+        s = ugks.Solver(kn, **kw)
+        try:
+            s.step(steps)
+            res[prec] = s.moments()
+            assert s.info.steps == steps
+        finally:
+            s.close()
+    return dict(moment_errors(res["fp32_store"], res["fp64"]), steps=steps, against="fp64 gpu")
+
+
+def serving_budget(reserve_gib):
+    """Admission budget: the device's free HBM at server start minus a reserve."""
+    import torch
+
+    free, total = torch.cuda.mem_get_info()
+    return max(0, int(free - reserve_gib * (1 << 30))), free, total
+
+
 def serving(args, fp64_rate):
     """Continuous batching of independent channel solves: saturation throughput from a burst
     of requests, then Poisson arrivals at fractions of that rate for the latency figures."""
@@ -262,14 +293,17 @@ def serving(args, fp64_rate):
            "meshes": SV.MESHES, "velocity_grids": SV.VGRIDS}
     ex = SV.GpuExecutor(max_slots=n, velocity_chunks=args.serving_chunks)
     runs = []
+    budget, free, total = serving_budget(args.serving_reserve_gib)
+    out["admission"] = {"budget_bytes": budget, "free_bytes_at_start": free,
+                        "total_bytes": total, "reserve_bytes": int(args.serving_reserve_gib * (1 << 30))}
     try:
-        burst = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=steps)
+        burst = SV.Server(ex, budget_bytes=budget, max_slots=n, quantum=steps)
         sat = burst.run(SV.serving_requests(n, float("inf"), seed=4, steps=steps))
         sat_rate = sat["done"] / sat["makespan_s"]
         print(f"serving: saturation {sat['updates_per_s']:.4g} updates/s", file=sys.stderr,
               flush=True)
         for frac in [float(x) for x in args.serving_rates.split(",") if x]:
-            srv = SV.Server(ex, budget_bytes=64 << 30, max_slots=n, quantum=25)
+            srv = SV.Server(ex, budget_bytes=budget, max_slots=n, quantum=25)
             st = srv.run(SV.serving_requests(n, frac * sat_rate, seed=4, steps=steps))
             runs.append({"rate_fraction": frac, "rate_per_s": frac * sat_rate, "done": st["done"],
                          "failed": st["failed"], "p50_latency_s": st["p50_latency_s"],
@@ -328,10 +362,12 @@ def cpu_model():
     return "unknown"
 
 
-def time_oracle(O, WL, threads, budget_s, max_steps):
+def time_oracle(O, WL, case, threads, budget_s, max_steps):
+    """Updates/s of the FP64 oracle on `case`: one untimed step, then as many timed steps as
+    fit the budget (at most max_steps)."""
     O.set_threads(threads)
     used = O.get_threads()
-    o = O.Oracle(**WL.oracle_kwargs(WL.C2))
+    o = O.Oracle(**WL.oracle_kwargs(case))
     try:
         t0 = time.perf_counter()
         assert o.step(1) == 0
@@ -342,20 +378,31 @@ def time_oracle(O, WL, threads, budget_s, max_steps):
         dt = time.perf_counter() - t0
     finally:
         o.close()
-    return WL.updates(WL.C2) * n / dt, n, dt, used
+    return WL.updates(case) * n / dt, n, dt, used
 
 
 def cpu_baseline(WL, budget_s):
+    """The FP64 oracle on this host: the 400x100 x 40^2 channel (the headline), plus the
+    40x10 x 24^2 parity channel (its 100 steps) and the 200x50 x 101^2 wide-velocity channel
+    (up to 10 steps), each with OpenMP over rows on every core and on one thread."""
     from oracle import oracle as O
 
     threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or 10**9)
-    v, n, dt, used = time_oracle(O, WL, threads, budget_s, 10)
-    v1, n1, dt1, _ = time_oracle(O, WL, 1, budget_s, 3)
+    v, n, dt, used = time_oracle(O, WL, WL.C2, threads, budget_s, 10)
+    v1, n1, dt1, _ = time_oracle(O, WL, WL.C2, 1, budget_s, 3)
+    legs = {}
+    for name, case, steps, b1 in (("c1", WL.C1, WL.C1_STEPS, budget_s), ("c3", WL.C3, 10, budget_s)):
+        va, na, da, _ = time_oracle(O, WL, case, threads, budget_s, steps)
+        vb, nb, db, _ = time_oracle(O, WL, case, 1, b1, steps)
+        legs[name] = {"cells": [case["nx"], case["ny"]], "velocities": [case["nu"], case["nv"]],
+                      "all_cores": {"value": va, "steps": na, "seconds": da},
+                      "single_thread": {"value": vb, "steps": nb, "seconds": db}}
     return {"value": v, "unit": "cell-velocity updates/s", "cores": used, "kind": "oracle",
             "sample": f"400x100 cells x 40^2 velocities, FP64 oracle, {n} timed steps after 1 "
                       f"untimed step ({dt:.1f} s), OpenMP over rows with {used} threads "
                       f"on {os.cpu_count()} logical CPUs ({cpu_model()})",
-            "single_thread": {"value": v1, "steps": n1, "seconds": dt1}}
+            "single_thread": {"value": v1, "steps": n1, "seconds": dt1},
+            "legs": legs}
 
 
 def main():
@@ -392,7 +439,6 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": fp64["ms_per_step"],
         "higher_is_better": True,
-        "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
@@ -417,15 +463,15 @@ def main():
                              "speedup_vs_fp64": fp32["updates_per_s"] / fp64["updates_per_s"],
                              "step_hbm_frac": 8.0 * upd / (fp32["ms_per_step"] * 1e-3) / 1e9
                              / HBM_PEAK_GBS,
-                             "error_vs_fp64": dict(moment_errors(fp32["moments"], fp64["moments"]),
-                                                   steps=fp32["total_steps"]),
+                             "error_vs_fp64": (None if args.no_accuracy
+                                               else accuracy_fp32_store(WL, ugks)),
                              "update_kernel_traffic": measured_traffic("fp32_store"),
                              "kernels": fp32["kernels"]}
     if not args.no_serving:
         out["serving"] = serving(args, fp64["updates_per_s"])
     if args.paper_sweep:
         out["paper_sweep"] = paper_sweep(WL, ugks, args.sweep_steps)
-    if args.wide_velocity:
+    if not args.no_wide_velocity:
         out["wide_velocity"] = wide_velocity(WL, ugks, args.warmup)
     if not args.no_shakhov:
         out["shakhov"] = shakhov(WL, ugks, min(args.steps, 500), args.warmup)

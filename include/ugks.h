@@ -158,12 +158,18 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
 
 /* Enqueue n >= 0 time steps (Eqs. (2)-(4), steps S1-S8 at every interface) on the handle's
    stream and return without waiting.  Invalid states reached inside a step are flagged on
-   the device and reported by the next ugks_moments / ugks_get_state. */
+   the device and reported by the next ugks_moments / ugks_get_state.  If a kernel launch
+   fails (UGKS_E_DEVICE), the steps enqueued in full are counted and the handle is marked
+   failed: its state is unknown and every later call except ugks_destroy, ugks_last_error and
+   ugks_get_info returns UGKS_E_DEVICE. */
 int ugks_step(ugks_handle* h, int n);
 
 /* Wait for the stream, then write (rho, U, V, T) for every cell to host_out
-   (4*nx*ny doubles, caller-owned).  Returns UGKS_E_STATE (after writing) if any cell or
-   interface state was invalid since creation. */
+   (4*nx*ny doubles, caller-owned).  These are the primitive variables of the conservative
+   cell state W = (rho, rho U, rho V, rho E) that Eq. (4) advances; W is the velocity moment
+   sum of w psi f with psi = (1, u, v, |c|^2/2) (Sec. 2), and T = 1/lambda follows from
+   rho E = rho |U|^2/2 + (2 + internal_dof) rho T/4.  Returns UGKS_E_STATE (after writing)
+   if any cell or interface state was invalid since creation. */
 int ugks_moments(ugks_handle* h, double* host_out);
 
 /* Release the handle and the device memory it owns; NULL is accepted and ignored. */
@@ -176,14 +182,19 @@ const char* ugks_last_error(const ugks_handle* h);
 /* Shape, step and memory of a handle. */
 int ugks_get_info(const ugks_handle* h, ugks_info* out);
 
-/* Checkpoint / test hooks.  f: nx*ny*NF doubles, W: 4*nx*ny doubles, canonical layout,
-   caller-owned host memory; either may be NULL.  get waits for the stream; set replaces
-   the current state (in FP32-store mode f is rounded to FP32). */
+/* Checkpoint / test hooks.  The state of the method is the distribution f of every cell and
+   discrete velocity (Sec. 2, the f of Eq. (3)) together with the conservative variables W
+   of Eq. (4).  f: nx*ny*NF doubles, W: 4*nx*ny doubles, canonical layout, caller-owned host
+   memory; either may be NULL.  get waits for the stream; set replaces the current state
+   (in FP32-store mode f is rounded to FP32).  Errors: UGKS_E_INVAL (NULL handle),
+   UGKS_E_BUSY, UGKS_E_DEVICE (a copy failed), UGKS_E_STATE (get: an invalid state was
+   flagged; the buffers are still written). */
 int ugks_get_state(ugks_handle* h, double* f, double* W);
 int ugks_set_state(ugks_handle* h, const double* f, const double* W);
 
-/* Macroscopic face fluxes of the last step, integrated over the step and multiplied by the
-   face length, global frame: Fx[(j*(nx+1) + i)*4] through the left face of cell i in +x
+/* Macroscopic face fluxes of the last step (the interface fluxes F of Eq. (4), built by the
+   flux steps S1-S7 of Sec. 2.B), integrated over the step and multiplied by the face
+   length, global frame: Fx[(j*(nx+1) + i)*4] through the left face of cell i in +x
    (i = nx is the right face of the last column), Fy[(j*nx + i)*4] through the bottom face of
    row j in +y (j = ny is the top face).  Host buffers of 4*(nx+1)*ny and 4*nx*(ny+1)
    doubles; either may be NULL. */
@@ -212,7 +223,9 @@ int ugks_get_kernel_timing(ugks_handle* h, int kernel, double* total_ms, int64_t
  * handle's result is bitwise the one ugks_step would give it alone.  The plan is rebuilt and re-sent only when
  * the member list changes or a member was stepped outside the batch; a rebuild first waits for
  * the previous plan upload.  Errors: UGKS_E_INVAL (arguments), UGKS_E_BUSY (a handle in use),
- * UGKS_E_DEVICE (launch failure; the message is in ugks_batch_last_error). */
+ * UGKS_E_DEVICE (launch failure, or a member that had one; the message is in
+ * ugks_batch_last_error).  After a launch failure the steps enqueued in full count for every
+ * member and every member is marked failed, as with ugks_step. */
 typedef struct ugks_batch ugks_batch;
 int ugks_batch_create(void* stream, int max_instances, ugks_batch** out);
 int ugks_step_batch(ugks_batch* b, ugks_handle* const* hs, int count, int n);

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -52,6 +53,9 @@ struct ugks_handle {
   double tau_ref = 0.0;
   std::string err;
   std::atomic<int> busy{0};
+  // a launch failed part-way through a step: the device state is unknown (which f/W buffer
+  // is current cannot be trusted), so every later call except destroy returns UGKS_E_DEVICE
+  bool poisoned = false;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> pool;
@@ -66,7 +70,7 @@ struct ugks_handle {
 
 namespace {
 
-thread_local std::string g_create_error;
+thread_local char g_create_error[512] = "";
 
 constexpr size_t kAlign = 256;
 constexpr double kPiHost = 3.14159265358979323846;
@@ -79,7 +83,7 @@ int fail(ugks_handle* h, int code, const char* fmt, const char* detail = "") {
   if (h)
     h->err = buf;
   else
-    g_create_error = buf;
+    std::memcpy(g_create_error, buf, sizeof buf);
   return code;
 }
 
@@ -95,8 +99,13 @@ int hip_fail(ugks_handle* h, hipError_t e, const char* what) {
   if (h)
     h->err = buf;
   else
-    g_create_error = buf;
+    std::memcpy(g_create_error, buf, sizeof buf);
   return UGKS_E_DEVICE;
+}
+
+int poisoned_fail(ugks_handle* h) {
+  return fail(h, UGKS_E_DEVICE,
+              "a kernel launch failed part-way through a step; the state is unknown%s");
 }
 
 struct Busy {
@@ -112,9 +121,7 @@ struct Busy {
 };
 
 // Uniform nodes on [-a, a] with both ends, made exactly mirror-symmetric; trapezoid weights.
-void velocity_nodes(int n, double a, std::vector<double>& x, std::vector<double>& w) {
-  x.assign(n, 0.0);
-  w.assign(n, 0.0);
+void velocity_nodes(int n, double a, double* x, double* w) {
   const double h = 2.0 * a / (double)(n - 1);
   for (int k = 0; k < n; ++k) x[k] = -a + (double)k * h;
   for (int k = 0; k < n / 2; ++k) x[n - 1 - k] = -x[k];
@@ -310,6 +317,171 @@ int collect_timing(ugks_handle* h) {
   return UGKS_OK;
 }
 
+
+// Every check of ugks_create's arguments; false with a message.
+bool problem_ok(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const ugks_bc* bc,
+                const ugks_opts* opts, Shape& s, bool& shak, std::string& why) {
+  if (!shape_ok(mesh, vgrid, s, why)) return false;
+  why.clear();
+  if (!bc || !opts)
+    why = "bc and opts are required";
+  else if (!(kn > 0))
+    why = "kn must be > 0 (or +inf)";
+  else if (bc->kind != UGKS_BC_PERIODIC && bc->kind != UGKS_BC_CHANNEL)
+    why = "unknown boundary kind";
+  else if (bc->kind == UGKS_BC_CHANNEL &&
+           (!(bc->p_ratio > 0) || !(bc->T_in > 0) || !(bc->T_wall > 0) ||
+            !std::isfinite(bc->p_ratio) || !std::isfinite(bc->T_in) || !std::isfinite(bc->T_wall)))
+    why = "channel needs p_ratio, T_in, T_wall > 0";
+  else if (opts->precision != UGKS_FP64 && opts->precision != UGKS_FP32_STORE)
+    why = "unknown precision";
+  else if (opts->velocity_chunks < 0 || opts->velocity_chunks > 16)
+    why = "velocity_chunks must be in 0..16";
+  else if (!(opts->rho0 > 0) || !(opts->T0 > 0) || !(std::fabs(opts->noise) < 1.0))
+    why = "need rho0 > 0, T0 > 0, |noise| < 1";
+  else if (!(opts->dt_override > 0) && !(opts->cfl > 0 && std::isfinite(opts->cfl)))
+    why = "need cfl > 0 or dt_override > 0";
+  if (!why.empty()) return false;
+  return collision_of(opts, s, shak, why);
+}
+
+// Host copies of the velocity tables and the inlet noise.
+struct HostTables {
+  double uk[kMaxNodes], wk[kMaxNodes], vm[kMaxNodes], wm[kMaxNodes], vmom[5 * kMaxNodes];
+};
+
+// Seeded inlet noise of row j (output nx*ny + j of the generator).
+double inlet_noise(const ugks_opts* opts, const Shape& s, int j) {
+  return noise_unit(opts->seed, s.nc + (uint64_t)j);
+}
+
+// The kernels' constants for a problem (everything of KParams but the device pointers), and
+// the tables the device copies of which the pointers will address.
+void fill_constants(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const ugks_bc* bc,
+                    const ugks_opts* opts, const Shape& s, bool shak, int chunks, KParams& P,
+                    HostTables& T) {
+  P.nx = s.nx;
+  P.ny = s.ny;
+  P.K = s.K;
+  P.M = s.M;
+  P.NV = s.NV;
+  P.NC = s.NC;
+  P.dof = s.dof;
+  P.lam_c = 0.25 * (double)(2 + s.dof);
+  P.q_c = 0.5 * (double)(2 + s.dof);
+  P.a4_c = 4.0 / (double)(2 + s.dof);
+  P.shak = shak ? 1 : 0;
+  P.nslot = shak ? kSlotsShakhov : kSlots;
+  P.pr_c = shak ? 1.0 - opts->prandtl : 0.0;
+  P.Lx = s.Lx;
+  P.Ly = s.Ly;
+  P.gmax = chunks;
+  P.PS = (long long)s.PS;
+  P.bc = bc->kind;
+  P.collisionless = std::isinf(kn) ? 1 : 0;
+  P.inlet_fixed_u = bc->inlet_fixed_u ? 1 : 0;
+  P.dx = mesh->lx / s.nx;
+  P.dy = mesh->ly / s.ny;
+  P.dt = opts->dt_override > 0 ? opts->dt_override
+                               : opts->cfl / (vgrid->umax / P.dx + vgrid->vmax / P.dy);
+  P.inv_dx = 1.0 / P.dx;
+  P.inv_dy = 1.0 / P.dy;
+  P.area = P.dx * P.dy;
+  P.mu_ref = P.collisionless ? 0.0 : 5.0 * std::sqrt(kPiHost) * kn / 16.0;
+  const double p0 = 0.5 * opts->rho0 * opts->T0;
+  const double r = bc->kind == UGKS_BC_CHANNEL ? bc->p_ratio : 1.0;
+  P.p_in = 2.0 * r * p0 / (r + 1.0);
+  P.p_out = 2.0 * p0 / (r + 1.0);
+  P.T_in = bc->kind == UGKS_BC_CHANNEL ? bc->T_in : 1.0;
+  const double Tw = bc->kind == UGKS_BC_CHANNEL ? bc->T_wall : 1.0;
+  P.lam_w = 1.0 / Tw;
+  P.kap_w = (double)s.dof / (2.0 * P.lam_w);
+  P.U_in = bc->U_in;
+  P.U_noise = bc->U_noise;
+
+  const double* uk = T.uk;
+  const double* wk = T.wk;
+  const double* vm = T.vm;
+  const double* wm = T.wm;
+  velocity_nodes(s.K, vgrid->umax, T.uk, T.wk);
+  velocity_nodes(s.M, vgrid->vmax, T.vm, T.wm);
+  P.du = 2.0 * vgrid->umax / (double)(s.K - 1);
+  P.dv = 2.0 * vgrid->vmax / (double)(s.M - 1);
+  // diffuse-wall constants: moments of the unit-density wall Maxwellian over the velocities
+  // that leave each wall, in the wall's local frame (v, u)
+  P.wall_den_bot = P.wall_den_top = 0.0;
+  for (int q = 0; q < 4; ++q) P.wall_G_bot[q] = P.wall_G_top[q] = 0.0;
+  for (int k = 0; k < s.K; ++k)
+    for (int m = 0; m < s.M; ++m) {
+      const double u = uk[k], v = vm[m], w = wk[k] * wm[m];
+      const double gw = P.lam_w / kPiHost * std::exp(-P.lam_w * (u * u + v * v));
+      const double psi[4] = {1.0, v, u, 0.5 * (u * u + v * v)};
+      if (v > 0) {
+        P.wall_den_bot += w * v * gw;
+        for (int q = 0; q < 4; ++q) P.wall_G_bot[q] += w * v * psi[q] * gw;
+      } else if (v < 0) {
+        P.wall_den_top += w * v * gw;
+        for (int q = 0; q < 4; ++q) P.wall_G_top[q] += w * v * psi[q] * gw;
+      }
+    }
+  // the wall's H (kap_w times its G) carries energy: psi = (0, 0, 0, 1/2)
+  P.wall_G_bot[3] += 0.5 * P.kap_w * P.wall_den_bot;
+  P.wall_G_top[3] += 0.5 * P.kap_w * P.wall_den_top;
+  // moment-kernel weights w_m v_m^n; a node at v = 0 is visited by both halves of v
+  for (int m = 0; m < s.M; ++m) {
+    double w = wm[m] * (vm[m] == 0.0 ? 0.5 : 1.0);
+    for (int n = 0; n < 5; ++n) {
+      T.vmom[5 * (size_t)m + n] = w;
+      w *= vm[m];
+    }
+  }
+}
+
+// Point the constants at the device tables of a set of buffers.
+void bind_tables(KParams& P, const Buffers& B, const Shape& s) {
+  P.wk = gp(B.wk);
+  P.wm = gp(B.wk + s.K);
+  P.vmom = gp(B.wk + s.K + s.M);
+  P.uk = gp(B.uk);
+  P.vm = gp(B.vm);
+  P.xi_in = gp(B.xi_in);
+  P.flag = gp(B.flag);
+}
+
+// One solver as the kernels see it; f[0] and W[0] hold the state when its step counter is 0.
+void make_inst(const KParams& P, const Buffers& B, int prec, Inst& I) {
+  I = Inst{};
+  I.P = P;
+  I.f[0] = gp(B.f[0]);
+  I.f[1] = gp(B.f[1]);
+  I.W[0] = gp(B.W[0]);
+  I.W[1] = gp(B.W[1]);
+  I.gsplit = 1;
+  I.Wg = gp(B.Wg);
+  I.hs = gp(B.hs);
+  I.hsg = gp(B.hsg);
+  I.recx = gp(B.recx);
+  I.recy = gp(B.recy);
+  I.cur = 0;
+  I.fp32 = prec == UGKS_FP32_STORE ? 1 : 0;
+}
+
+struct Copy {
+  void* dst;
+  const void* src;
+  size_t n;
+};
+
+// Host-to-device copies of the velocity tables into a set of buffers; returns their number (5).
+int table_copies(const Buffers& B, const HostTables& T, const Shape& s, Copy* out) {
+  out[0] = {B.wk, T.wk, (size_t)s.K * 8};
+  out[1] = {B.wk + s.K, T.wm, (size_t)s.M * 8};
+  out[2] = {B.wk + s.K + s.M, T.vmom, (size_t)s.M * 5 * 8};
+  out[3] = {B.uk, T.uk, (size_t)s.K * 8};
+  out[4] = {B.vm, T.vm, (size_t)s.M * 8};
+  return 5;
+}
+
 }  // namespace
 
 extern "C" {
@@ -337,26 +509,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   *out = nullptr;
   Shape s;
   std::string why;
-  if (!shape_ok(mesh, vgrid, s, why)) return fail(nullptr, UGKS_E_INVAL, "%s", why.c_str());
-  if (!bc || !opts) return fail(nullptr, UGKS_E_INVAL, "bc and opts are required%s");
-  if (!(kn > 0)) return fail(nullptr, UGKS_E_INVAL, "kn must be > 0 (or +inf)%s");
-  if (bc->kind != UGKS_BC_PERIODIC && bc->kind != UGKS_BC_CHANNEL)
-    return fail(nullptr, UGKS_E_INVAL, "unknown boundary kind%s");
-  if (bc->kind == UGKS_BC_CHANNEL &&
-      (!(bc->p_ratio > 0) || !(bc->T_in > 0) || !(bc->T_wall > 0) || !std::isfinite(bc->p_ratio) ||
-       !std::isfinite(bc->T_in) || !std::isfinite(bc->T_wall)))
-    return fail(nullptr, UGKS_E_INVAL, "channel needs p_ratio, T_in, T_wall > 0%s");
-  if (opts->precision != UGKS_FP64 && opts->precision != UGKS_FP32_STORE)
-    return fail(nullptr, UGKS_E_INVAL, "unknown precision%s");
-  if (opts->velocity_chunks < 0 || opts->velocity_chunks > 16)
-    return fail(nullptr, UGKS_E_INVAL, "velocity_chunks must be in 0..16%s");
-  if (!(opts->rho0 > 0) || !(opts->T0 > 0) || !(std::fabs(opts->noise) < 1.0))
-    return fail(nullptr, UGKS_E_INVAL, "need rho0 > 0, T0 > 0, |noise| < 1%s");
-  if (!(opts->dt_override > 0) && !(opts->cfl > 0 && std::isfinite(opts->cfl)))
-    return fail(nullptr, UGKS_E_INVAL, "need cfl > 0 or dt_override > 0%s");
-
   bool shak = false;
-  if (!collision_of(opts, s, shak, why)) return fail(nullptr, UGKS_E_INVAL, "%s", why.c_str());
+  if (!problem_ok(mesh, vgrid, kn, bc, opts, s, shak, why))
+    return fail(nullptr, UGKS_E_INVAL, "%s", why.c_str());
   const int chunks = chunks_of(s, opts->velocity_chunks);
   const Layout L = layout_of(s, opts->precision, chunks, shak);
   if (opts->workspace && opts->workspace_bytes < L.total)
@@ -391,74 +546,19 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
 
   // ---- constants
   KParams& P = h->P;
-  P.nx = s.nx;
-  P.ny = s.ny;
-  P.K = s.K;
-  P.M = s.M;
-  P.NV = s.NV;
-  P.NC = s.NC;
-  P.dof = s.dof;
-  P.lam_c = 0.25 * (double)(2 + s.dof);
-  P.q_c = 0.5 * (double)(2 + s.dof);
-  P.a4_c = 4.0 / (double)(2 + s.dof);
-  P.shak = shak ? 1 : 0;
-  P.nslot = shak ? kSlotsShakhov : kSlots;
-  P.pr_c = shak ? 1.0 - opts->prandtl : 0.0;
-  P.Lx = s.Lx;
-  P.Ly = s.Ly;
-  P.gmax = chunks;
-  P.PS = (long long)s.PS;
-  P.bc = bc->kind;
-  P.collisionless = std::isinf(kn) ? 1 : 0;
-  P.inlet_fixed_u = bc->inlet_fixed_u ? 1 : 0;
-  P.dx = mesh->lx / s.nx;
-  P.dy = mesh->ly / s.ny;
-  P.dt = opts->dt_override > 0 ? opts->dt_override
-                               : opts->cfl / (vgrid->umax / P.dx + vgrid->vmax / P.dy);
-  P.inv_dx = 1.0 / P.dx;
-  P.inv_dy = 1.0 / P.dy;
-  P.area = P.dx * P.dy;
-  P.mu_ref = P.collisionless ? 0.0 : 5.0 * std::sqrt(kPiHost) * kn / 16.0;
+  std::unique_ptr<HostTables> tables(new (std::nothrow) HostTables);
+  if (!tables) {
+    if (h->owns_ws) (void)hipFree(h->ws);
+    delete h;
+    return fail(nullptr, UGKS_E_NOMEM, "host allocation failed%s");
+  }
+  HostTables& T = *tables;
+  fill_constants(mesh, vgrid, kn, bc, opts, s, shak, chunks, P, T);
+  std::vector<double> xi(s.ny);
+  for (int j = 0; j < s.ny; ++j) xi[j] = inlet_noise(opts, s, j);
   h->tau_ref = P.collisionless ? std::numeric_limits<double>::infinity() : 2.0 * P.mu_ref;
-  const double p0 = 0.5 * opts->rho0 * opts->T0;
-  const double r = bc->kind == UGKS_BC_CHANNEL ? bc->p_ratio : 1.0;
-  P.p_in = 2.0 * r * p0 / (r + 1.0);
-  P.p_out = 2.0 * p0 / (r + 1.0);
-  P.T_in = bc->kind == UGKS_BC_CHANNEL ? bc->T_in : 1.0;
-  const double Tw = bc->kind == UGKS_BC_CHANNEL ? bc->T_wall : 1.0;
-  P.lam_w = 1.0 / Tw;
-  P.kap_w = (double)s.dof / (2.0 * P.lam_w);
-  P.U_in = bc->U_in;
-  P.U_noise = bc->U_noise;
-
-  std::vector<double> uk, wk, vm, wm;
-  velocity_nodes(s.K, vgrid->umax, uk, wk);
-  velocity_nodes(s.M, vgrid->vmax, vm, wm);
-  P.du = 2.0 * vgrid->umax / (double)(s.K - 1);
-  P.dv = 2.0 * vgrid->vmax / (double)(s.M - 1);
-  // diffuse-wall constants: moments of the unit-density wall Maxwellian over the velocities
-  // that leave each wall, in the wall's local frame (v, u)
-  P.wall_den_bot = P.wall_den_top = 0.0;
-  for (int q = 0; q < 4; ++q) P.wall_G_bot[q] = P.wall_G_top[q] = 0.0;
-  for (int k = 0; k < s.K; ++k)
-    for (int m = 0; m < s.M; ++m) {
-      const double u = uk[k], v = vm[m], w = wk[k] * wm[m];
-      const double gw = P.lam_w / kPiHost * std::exp(-P.lam_w * (u * u + v * v));
-      const double psi[4] = {1.0, v, u, 0.5 * (u * u + v * v)};
-      if (v > 0) {
-        P.wall_den_bot += w * v * gw;
-        for (int q = 0; q < 4; ++q) P.wall_G_bot[q] += w * v * psi[q] * gw;
-      } else if (v < 0) {
-        P.wall_den_top += w * v * gw;
-        for (int q = 0; q < 4; ++q) P.wall_G_top[q] += w * v * psi[q] * gw;
-      }
-    }
-  // the wall's H (kap_w times its G) carries energy: psi = (0, 0, 0, 1/2)
-  P.wall_G_bot[3] += 0.5 * P.kap_w * P.wall_den_bot;
-  P.wall_G_top[3] += 0.5 * P.kap_w * P.wall_den_top;
-  std::vector<double> W0(4 * s.nc), xi(s.ny);
+  std::vector<double> W0(4 * s.nc);
   for (int j = 0; j < s.ny; ++j) {
-    xi[j] = noise_unit(opts->seed, s.nc + (uint64_t)j);
     for (int i = 0; i < s.nx; ++i) {
       const size_t c = (size_t)j * s.nx + i;
       const double rho = opts->rho0 * (1.0 + opts->noise * noise_unit(opts->seed, c));
@@ -469,52 +569,20 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     }
   }
   Buffers& B = h->B;
-  P.wk = gp(B.wk);
-  P.wm = gp(B.wk + s.K);
-  P.vmom = gp(B.wk + s.K + s.M);
-  // moment-kernel weights w_m v_m^n; a node at v = 0 is visited by both halves of v
-  std::vector<double> vmom(5 * (size_t)s.M);
-  for (int m = 0; m < s.M; ++m) {
-    double w = wm[m] * (vm[m] == 0.0 ? 0.5 : 1.0);
-    for (int n = 0; n < 5; ++n) {
-      vmom[5 * (size_t)m + n] = w;
-      w *= vm[m];
-    }
-  }
-  P.uk = gp(B.uk);
-  P.vm = gp(B.vm);
-  P.xi_in = gp(B.xi_in);
-  P.flag = gp(B.flag);
+  bind_tables(P, B, s);
   Inst& I = h->inst;
-  I.P = P;
-  I.f[0] = gp(B.f[0]);
-  I.f[1] = gp(B.f[1]);
-  I.W[0] = gp(B.W[0]);
-  I.W[1] = gp(B.W[1]);
-  I.gsplit = 1;
-  I.Wg = gp(B.Wg);
-  I.hs = gp(B.hs);
-  I.hsg = gp(B.hsg);
-  I.recx = gp(B.recx);
-  I.recy = gp(B.recy);
-  I.cur = 0;
-  I.fp32 = h->prec == UGKS_FP32_STORE ? 1 : 0;
+  make_inst(P, B, h->prec, I);
   std::vector<char> plan_host(plan_bytes(1));
   h->pt = build_plan(&I, 1, plan_host.data(), h->plan_dev, &h->pv);
 
-  struct Copy {
-    void* dst;
-    const void* src;
-    size_t n;
-  } copies[] = {
-      {B.wk, wk.data(), wk.size() * 8},     {B.wk + s.K, wm.data(), wm.size() * 8},
-      {B.wk + s.K + s.M, vmom.data(), vmom.size() * 8},
-      {B.uk, uk.data(), uk.size() * 8},     {B.vm, vm.data(), vm.size() * 8},
-      {B.xi_in, xi.data(), xi.size() * 8},
-      {B.W[0], W0.data(), W0.size() * 8},          {h->plan_dev, plan_host.data(), plan_host.size()},
-  };
+  Copy copies[8];
+  int nt = table_copies(B, T, s, copies);
+  copies[nt++] = {B.xi_in, xi.data(), xi.size() * 8};
+  copies[nt++] = {B.W[0], W0.data(), W0.size() * 8};
+  copies[nt++] = {h->plan_dev, plan_host.data(), plan_host.size()};
   int rc = UGKS_OK;
-  for (auto& cp : copies) {
+  for (int c = 0; c < nt; ++c) {
+    const Copy& cp = copies[c];
     e = hipMemcpyAsync(cp.dst, cp.src, cp.n, hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) {
       rc = hip_fail(nullptr, e, "hipMemcpyAsync of the tables");
@@ -551,10 +619,14 @@ int ugks_step(ugks_handle* h, int n) {
   if (n < 0) return fail(h, UGKS_E_INVAL, "n must be >= 0%s");
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  if (h->poisoned) return poisoned_fail(h);
   for (int s = 0; s < n; ++s) {
     h->pv.step = (int)(h->steps & 1);
     const int rc = enqueue_plan_step(h, h->pv, h->pt, h->inst.fp32, h->stream);
-    if (rc != UGKS_OK) return rc;
+    if (rc != UGKS_OK) {
+      h->poisoned = true;
+      return rc;
+    }
     h->steps += 1;
   }
   return UGKS_OK;
@@ -565,6 +637,7 @@ int ugks_moments(ugks_handle* h, double* host_out) {
   if (!host_out) return fail(h, UGKS_E_INVAL, "host_out is NULL%s");
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  if (h->poisoned) return poisoned_fail(h);
   const size_t nc = (size_t)h->P.nx * h->P.ny;
   std::vector<double> W(4 * nc);
   int flag = 0;
@@ -604,7 +677,7 @@ int ugks_destroy(ugks_handle* h) {
 }
 
 const char* ugks_last_error(const ugks_handle* h) {
-  return h ? h->err.c_str() : g_create_error.c_str();
+  return h ? h->err.c_str() : g_create_error;
 }
 
 int ugks_get_info(const ugks_handle* h, ugks_info* out) {
@@ -630,6 +703,7 @@ int ugks_get_state(ugks_handle* h, double* f, double* W) {
   if (!h) return UGKS_E_INVAL;
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  if (h->poisoned) return poisoned_fail(h);
   const size_t nc = (size_t)h->P.nx * h->P.ny, NV = (size_t)h->P.NV * h->P.NC;
   const size_t PS = (size_t)h->P.PS;
   hipError_t e = hipSuccess;
@@ -665,6 +739,7 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
   if (!h) return UGKS_E_INVAL;
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  if (h->poisoned) return poisoned_fail(h);
   const size_t nc = (size_t)h->P.nx * h->P.ny, NV = (size_t)h->P.NV * h->P.NC;
   const size_t PS = (size_t)h->P.PS;
   std::vector<char> raw;
@@ -695,6 +770,7 @@ int ugks_get_face_flux(ugks_handle* h, double* Fx, double* Fy) {
   if (!h) return UGKS_E_INVAL;
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  if (h->poisoned) return poisoned_fail(h);
   const size_t nfx = (size_t)h->P.ny * (h->P.nx + 1), nfy = (size_t)(h->P.ny + 1) * h->P.nx;
   std::vector<double> rx(Fx ? nfx * kRec : 0), ry(Fy ? nfy * kRec : 0);
   hipError_t e = hipSuccess;
@@ -785,6 +861,10 @@ int ugks_step_batch(ugks_batch* b, ugks_handle* const* hs, int count, int n) {
         b->err = "a handle appears twice in the batch";
         return UGKS_E_INVAL;
       }
+    if (hs[q]->poisoned) {
+      b->err = "a handle of the batch had a failed launch; its state is unknown";
+      return UGKS_E_DEVICE;
+    }
   }
   // claim every handle for the duration of the call
   int claimed = 0;
@@ -854,14 +934,18 @@ int ugks_step_batch(ugks_batch* b, ugks_handle* const* hs, int count, int n) {
     b->upload_pending = true;
   }
   int rc = UGKS_OK;
-  for (int s = 0; s < n && rc == UGKS_OK; ++s) {
-    b->pv.step = (int)((b->counter + s) & 1);
+  int done = 0;  // steps whose launches were all enqueued
+  for (; done < n; ++done) {
+    b->pv.step = (int)((b->counter + done) & 1);
     rc = enqueue_plan_step(nullptr, b->pv, b->pt, b->fp32, b->stream);
+    if (rc != UGKS_OK) break;
   }
-  if (rc == UGKS_OK) {
-    b->counter += n;
-    for (int q = 0; q < count; ++q) hs[q]->steps += n;
-  } else {
+  // the steps enqueued in full advance every member; a step that failed part-way leaves each
+  // member's state unknown, so the members are poisoned
+  b->counter += done;
+  for (int q = 0; q < count; ++q) hs[q]->steps += done;
+  if (rc != UGKS_OK) {
+    for (int q = 0; q < count; ++q) hs[q]->poisoned = true;
     b->err = g_create_error;
     b->members.clear();
     rc = UGKS_E_DEVICE;

@@ -45,6 +45,7 @@ C2_SHAKHOV = dict(C2, prandtl=2.0 / 3.0)
 # Precision form: C2 with f stored in FP32.
 C4 = dict(C2)
 C4_PRECISION = "fp32_store"
+C4_STEPS = 1000
 
 # The paper's own channel (L/W = 2, Kn 0.1, p_in/p_out = 1.2/0.8) on its meshes M1-M4 and
 # velocity grids 29^2, 49^2, 69^2 (Table 1); the velocity range is our reading.

@@ -172,3 +172,4 @@ def test_null_handles():
     assert L.ugks_create(ctypes.byref(mesh), ctypes.byref(vgrid), 0.1, ctypes.byref(bc),
                          ctypes.byref(opts), None) == ugks.UGKS_E_INVAL
     assert L.ugks_required_bytes(None, None, None, None) == ugks.UGKS_E_INVAL
+

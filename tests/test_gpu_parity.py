@@ -340,3 +340,42 @@ def test_c1_parity_holds_over_2000_steps():
     """Rounding differences do not accumulate: after 2,000 steps (the flow near its steady
     state) the GPU still matches the oracle within the FP64 bar."""
     PR.run_and_compare(WL.C1, 2000, label="C1 2000 steps")
+
+
+def test_hot_inlet_and_hot_walls():
+    """Inlet ghost at T_in = 1.2 and diffuse walls at T_wall = 1.3 for the gas without internal
+    degrees of freedom: the ghost density 2 p_in / T_in, the ghost and wall Maxwellians at their
+    own temperatures."""
+    PR.run_and_compare(dict(WL.C1, T_in=1.2, T_wall=1.3), 50, label="C1 T_in 1.2 T_wall 1.3")
+
+
+@pytest.mark.parametrize("nvel", [29, 69])
+def test_paper_mesh_m4(nvel):
+    """The paper's largest mesh M4 (160x80) at its smallest and largest velocity grids
+    (Table 1), compared in full after a few steps."""
+    PR.run_and_compare(WL.paper_mesh(160, 80, nvel), 3, label=f"paper M4 {nvel}^2")
+
+
+def test_paper_mesh_m3_69():
+    """M3 (120x60) at 69^2, the largest grid the paper ran on its smaller GPU."""
+    PR.run_and_compare(WL.paper_mesh(120, 60, 69), 5, label="paper M3 69^2")
+
+
+def test_fp32_store_c4_after_1000_steps_against_fp64():
+    """The precision workload's accuracy statement: after its 1,000 steps the FP32-store form
+    is within 1e-5 of the FP64 form (rho, T relative; U, V absolute), both from the same seeded
+    state; the FP64 form matches the oracle within 1e-12 in the tests above."""
+    steps = WL.C4_STEPS
+    m = {}
+    for prec in ("fp64", "fp32_store"):
+        kn, kw = WL.solver_kwargs(WL.C4, prec)
+        s = ugks.Solver(kn, **kw)
+        try:
+            s.step(steps)
+            m[prec] = s.moments()
+        finally:
+            s.close()
+    e = PR.errors(m["fp32_store"], m["fp64"])
+    print(f"[parity] C4 FP32-store vs FP64 after {steps} steps: {e}", flush=True)
+    PR.assert_within(e, PR.FP32_STORE_TOL, "C4 FP32-store 1000 steps")
+    assert max(e.values()) > 1e-12

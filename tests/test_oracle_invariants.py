@@ -211,6 +211,81 @@ def test_channel_inlet_with_seeded_velocity():
         assert abs(pin[2]) < 1e-16
 
 
+# Boundary temperatures away from 1 (Sec. 3.A fixes the inlet temperature; the walls are a
+# reading): with T_in = T_wall = 1 a slip of lambda for T in either place would pass unseen.
+HOT = dict(C1, T_in=1.2, T_wall=1.3)
+
+
+def test_inlet_ghost_holds_the_inlet_temperature_and_pressure():
+    """The inlet ghost state has T = T_in and rho = 2 p_in / T_in (p = rho T / 2), taken here
+    from W by the energy relation rho E = rho |U|^2/2 + rho T/2, and its f is the Maxwellian
+    rho/(pi T_in) exp(-|c - U|^2 / T_in) on the grid."""
+    o = O.Oracle(**HOT)
+    assert o.step(3) == 0
+    Wg, fg = o.ghost()
+    p_in = 2 * 2.0 * 0.5 / 3.0
+    uk, vm, _, _ = o.velocity_grid()
+    uu, vv = np.meshgrid(uk, vm, indexing="ij")
+    for j in range(o.ny):
+        rho, mx, my, E = Wg[0, j]
+        U, V = mx / rho, my / rho
+        T = (E - 0.5 * rho * (U * U + V * V)) / (0.5 * rho)
+        assert math.isclose(T, 1.2, rel_tol=1e-13)
+        assert math.isclose(rho, 2.0 * p_in / 1.2, rel_tol=1e-13)
+        g = rho / (math.pi * 1.2) * np.exp(-((uu - U) ** 2 + (vv - V) ** 2) / 1.2)
+        np.testing.assert_allclose(fg[0, j], g.ravel(), rtol=1e-13, atol=0)
+        # the ratio of two grid values depends on T_in alone, whatever rho is
+        r = fg[0, j][0] / fg[0, j][o.nv * (o.nu // 2) + o.nv // 2]
+        d = ((uk[0] - U) ** 2 + (vm[0] - V) ** 2) - ((uk[o.nu // 2] - U) ** 2 + (vm[o.nv // 2] - V) ** 2)
+        assert math.isclose(r, math.exp(-d / 1.2), rel_tol=1e-12)
+
+
+def test_outlet_ghost_keeps_the_last_column_temperature_at_a_hot_inlet():
+    """The outlet ghost copies (U, V, T) of the last column and fixes p_out, also when the
+    inlet and walls are not at the reference temperature."""
+    o = O.Oracle(**HOT)
+    assert o.step(6) == 0
+    _, W = o.state()
+    assert o.step(1) == 0
+    Wg, _ = o.ghost()
+    p_out = 2 * 0.5 / 3.0
+    for j in range(o.ny):
+        rho, mx, my, E = W[j, -1]
+        T_last = (E - 0.5 * (mx * mx + my * my) / rho) / (0.5 * rho)
+        rg, gx, gy, Eg = Wg[1, j]
+        Tg = (Eg - 0.5 * (gx * gx + gy * gy) / rg) / (0.5 * rg)
+        assert math.isclose(Tg, T_last, rel_tol=1e-13)
+        assert math.isclose(0.5 * rg * Tg, p_out, rel_tol=1e-13)
+
+
+@pytest.mark.parametrize("top", [False, True])
+def test_hot_wall_emits_its_own_maxwellian(top):
+    """Particles leaving a wall at T_wall = 1.3 carry rho_w exp(-|c|^2 / T_wall): the ratio of
+    the distribution flux per unit normal velocity at two leaving velocities is
+    exp(-(|c1|^2 - |c2|^2) / T_wall) whatever rho_w is, and the net mass flux through the wall
+    is zero."""
+    o = O.Oracle(**HOT)
+    assert o.step(4) == 0
+    _, Ffy = o.micro_flux()
+    uk, vm, wk, wm = o.velocity_grid()
+    uu, vv = np.meshgrid(uk, vm, indexing="ij")
+    u, v, w = uu.ravel(), vv.ravel(), np.outer(wk, wm).ravel()
+    face = Ffy[-1] if top else Ffy[0]
+    leave = (v < 0) if top else (v > 0)
+    idx = np.flatnonzero(leave)
+    a, b = idx[0], idx[len(idx) // 2]
+    expect = math.exp(-((u[a] ** 2 + v[a] ** 2) - (u[b] ** 2 + v[b] ** 2)) / 1.3)
+    for i in range(o.nx):
+        r = (face[i, a] / v[a]) / (face[i, b] / v[b])
+        assert math.isclose(r, expect, rel_tol=1e-12), (i, r, expect)
+    # one emitted density per face: flux / (v exp(-|c|^2/T_w)) is the same for every leaving c
+    dens = face[:, idx] / (v[idx] * np.exp(-(u[idx] ** 2 + v[idx] ** 2) / 1.3))
+    np.testing.assert_allclose(dens, dens[:, :1] * np.ones_like(dens), rtol=1e-12)
+    assert np.all(dens > 0)
+    net = (face * w).sum(axis=1)
+    assert np.max(np.abs(net)) < 1e-14 * np.max(np.abs(face * w).sum(axis=1))
+
+
 def test_wall_rows_reconstruct_without_y_slope():
     """Reading: next to a wall the y-slope of f is zero, so in the collisionless limit the
     flux through the face above the bottom wall row, for v > 0, is pure upwind transport of
