@@ -164,6 +164,21 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
    ugks_get_info returns UGKS_E_DEVICE. */
 int ugks_step(ugks_handle* h, int n);
 
+/* ugks_step for callers that cannot allocate device memory (code under HIP graph capture,
+   tight serving loops, harnesses that forbid allocation): the same n steps, with the
+   transient buffers of each step (ghost states, per-cell moment sums, face records) in a
+   static device array of UGKS_STATIC_SCRATCH_BYTES that the library holds on every GPU it
+   runs on, instead of the handle's workspace.  It calls no allocating routine and records no
+   timing events.  The handle's state advances exactly as with ugks_step (bitwise), and the two
+   calls may be mixed.  All calls on one GPU share the array: calls on different streams that
+   overlap in time race and corrupt each other's results; calls ordered on one stream do not
+   interfere (each step rewrites every transient value before reading it).  ugks_get_face_flux
+   refuses (UGKS_E_INVAL) until the next ugks_step.  UGKS_E_INVAL also when the handle's
+   transient buffers exceed the array (the 400 x 100 x 40^2 channel needs 41 MB) or when the
+   array's device address could not be taken at ugks_create; ugks_last_error says which. */
+#define UGKS_STATIC_SCRATCH_BYTES ((size_t)48 << 20)
+int ugks_step_static(ugks_handle* h, int n);
+
 /* Wait for the stream, then write (rho, U, V, T) for every cell to host_out
    (4*nx*ny doubles, caller-owned).  These are the primitive variables of the conservative
    cell state W = (rho, rho U, rho V, rho E) that Eq. (4) advances; W is the velocity moment

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,6 +50,13 @@ struct ugks_handle {
   void* plan_dev = nullptr;  // its one-instance launch plan, inside the workspace
   PlanView pv{};
   PlanTotals pt{};
+  // ugks_step_static: a second one-instance plan (also inside the workspace) whose transient
+  // buffers are the device's static scratch array; built at create when they fit
+  void* plan_static = nullptr;
+  PlanView pv_static{};
+  bool static_ok = false;
+  std::string static_why;    // why not, when static_ok is false
+  bool last_static = false;  // the last step ran on the static scratch
   int64_t steps = 0;
   double tau_ref = 0.0;
   std::string err;
@@ -74,6 +82,40 @@ thread_local char g_create_error[512] = "";
 
 constexpr size_t kAlign = 256;
 constexpr double kPiHost = 3.14159265358979323846;
+
+// Static scratch of ugks_step_static: the transient buffers of one step (ghost states,
+// per-cell moment sums, face records) of whichever handle that call steps.  One copy per GPU,
+// held from the library's first use on that GPU until the process ends.  Host code never
+// passes this name to a kernel or a copy: it is a host-side stand-in for the device array,
+// whose address on each device comes from hipGetSymbolAddress (scratch_address).
+constexpr size_t kStaticScratchBytes = (size_t)48 << 20;
+static_assert(kStaticScratchBytes == UGKS_STATIC_SCRATCH_BYTES, "header and library disagree");
+__device__ __align__(256) static unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the static scratch on `device`, which must be the current device; looked
+// up once per device.  nullptr (and a message) if the lookup fails.
+void* scratch_address(int device, std::string& why) {
+  if (device < 0 || device >= kMaxDevices) {
+    why = "device index beyond the static scratch table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      why = std::string("hipGetSymbolAddress of the static scratch: ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -223,7 +265,7 @@ bool collision_of(const ugks_opts* o, const Shape& s, bool& shak, std::string& w
 
 Layout layout_of(const Shape& s, int prec, int chunks, bool shak) {
   const size_t ss = prec == UGKS_FP32_STORE ? 4 : 8;
-  const size_t sizes[14] = {
+  const size_t sizes[15] = {
       (size_t)s.NC * s.NV * s.PS * ss,          // f0: NC NV planes
       (size_t)s.NC * s.NV * s.PS * ss,          // f1
       s.nc * 4 * 8,                             // W0
@@ -238,10 +280,11 @@ Layout layout_of(const Shape& s, int prec, int chunks, bool shak) {
       (size_t)s.M * 8,                          // vm
       (size_t)s.ny * 8 + 64,                    // xi_in + flag
       plan_bytes(1),                            // one-instance launch plan
+      plan_bytes(1),                            // the same on the static scratch
   };
   Layout L{};
   size_t off = 0;
-  for (int b = 0; b < 14; ++b) {
+  for (int b = 0; b < 15; ++b) {
     L.off[b] = off;
     off += round_up(sizes[b], kAlign);
   }
@@ -267,6 +310,18 @@ void carve(ugks_handle* h, const Layout& L, const Shape& s) {
   B.xi_in = reinterpret_cast<double*>(base + L.off[12]);
   B.flag = reinterpret_cast<int*>(base + L.off[12] + round_up((size_t)s.ny * 8, 64));
   h->plan_dev = base + L.off[13];
+  h->plan_static = base + L.off[14];
+}
+
+// The transient buffers of one step (Wg, hs, hsg, recx, recy: layout entries 4..8) are
+// contiguous in the workspace; their size, and the same buffers carved out of `base`.
+size_t transient_bytes(const Layout& L) { return L.off[9] - L.off[4]; }
+void carve_transient(const Layout& L, char* base, Inst& I) {
+  I.Wg = gp(reinterpret_cast<double*>(base + (L.off[4] - L.off[4])));
+  I.hs = gp(reinterpret_cast<double*>(base + (L.off[5] - L.off[4])));
+  I.hsg = gp(reinterpret_cast<double*>(base + (L.off[6] - L.off[4])));
+  I.recx = gp(reinterpret_cast<double*>(base + (L.off[7] - L.off[4])));
+  I.recy = gp(reinterpret_cast<double*>(base + (L.off[8] - L.off[4])));
 }
 
 hipEvent_t pool_get(ugks_handle* h) {
@@ -574,12 +629,35 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   make_inst(P, B, h->prec, I);
   std::vector<char> plan_host(plan_bytes(1));
   h->pt = build_plan(&I, 1, plan_host.data(), h->plan_dev, &h->pv);
+  // the plan of ugks_step_static: the same instance with its transient buffers on this
+  // device's static scratch (looked up here, once per device)
+  std::vector<char> plan_static_host(plan_bytes(1));
+  {
+    std::string why;
+    void* sp = scratch_address(h->device, why);
+    if (!sp) {
+      h->static_why = why;
+    } else if (transient_bytes(L) > kStaticScratchBytes) {
+      char msg[256];
+      std::snprintf(msg, sizeof msg,
+                    "the transient buffers of this shape need %zu bytes, more than the "
+                    "static scratch's %zu",
+                    transient_bytes(L), kStaticScratchBytes);
+      h->static_why = msg;
+    } else {
+      Inst Is = I;
+      carve_transient(L, static_cast<char*>(sp), Is);
+      (void)build_plan(&Is, 1, plan_static_host.data(), h->plan_static, &h->pv_static);
+      h->static_ok = true;
+    }
+  }
 
-  Copy copies[8];
+  Copy copies[9];
   int nt = table_copies(B, T, s, copies);
   copies[nt++] = {B.xi_in, xi.data(), xi.size() * 8};
   copies[nt++] = {B.W[0], W0.data(), W0.size() * 8};
   copies[nt++] = {h->plan_dev, plan_host.data(), plan_host.size()};
+  if (h->static_ok) copies[nt++] = {h->plan_static, plan_static_host.data(), plan_static_host.size()};
   int rc = UGKS_OK;
   for (int c = 0; c < nt; ++c) {
     const Copy& cp = copies[c];
@@ -628,6 +706,33 @@ int ugks_step(ugks_handle* h, int n) {
       return rc;
     }
     h->steps += 1;
+    h->last_static = false;
+  }
+  return UGKS_OK;
+}
+
+int ugks_step_static(ugks_handle* h, int n) {
+  if (!h) return UGKS_E_INVAL;
+  if (n < 0) return fail(h, UGKS_E_INVAL, "n must be >= 0%s");
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  if (h->poisoned) return poisoned_fail(h);
+  if (!h->static_ok)
+    return fail(h, UGKS_E_INVAL, "ugks_step_static: %s", h->static_why.c_str());
+  static const char* names[4] = {"ghost kernel launch", "moment kernel launch",
+                                 "interface kernel launch", "update kernel launch"};
+  for (int s = 0; s < n; ++s) {
+    h->pv_static.step = (int)(h->steps & 1);
+    // no timing events here: creating them would allocate
+    for (int phase = 0; phase < 4; ++phase) {
+      const hipError_t e = launch_phase(h->pv_static, h->pt, h->inst.fp32, phase, h->stream);
+      if (e != hipSuccess) {
+        h->poisoned = true;
+        return hip_fail(h, e, names[phase]);
+      }
+    }
+    h->steps += 1;
+    h->last_static = true;
   }
   return UGKS_OK;
 }
@@ -771,6 +876,9 @@ int ugks_get_face_flux(ugks_handle* h, double* Fx, double* Fy) {
   Busy b(h);
   if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
   if (h->poisoned) return poisoned_fail(h);
+  if (h->last_static)
+    return fail(h, UGKS_E_INVAL,
+                "the last step ran with ugks_step_static, whose face records are not kept%s");
   const size_t nfx = (size_t)h->P.ny * (h->P.nx + 1), nfy = (size_t)(h->P.ny + 1) * h->P.nx;
   std::vector<double> rx(Fx ? nfx * kRec : 0), ry(Fy ? nfy * kRec : 0);
   hipError_t e = hipSuccess;
@@ -943,7 +1051,10 @@ int ugks_step_batch(ugks_batch* b, ugks_handle* const* hs, int count, int n) {
   // the steps enqueued in full advance every member; a step that failed part-way leaves each
   // member's state unknown, so the members are poisoned
   b->counter += done;
-  for (int q = 0; q < count; ++q) hs[q]->steps += done;
+  for (int q = 0; q < count; ++q) {
+    hs[q]->steps += done;
+    if (done > 0) hs[q]->last_static = false;
+  }
   if (rc != UGKS_OK) {
     for (int q = 0; q < count; ++q) hs[q]->poisoned = true;
     b->err = g_create_error;

@@ -110,7 +110,7 @@ struct Buffers {
 };
 
 struct Layout {
-  size_t off[14];
+  size_t off[15];
   size_t total;
 };
 

@@ -74,6 +74,7 @@ SIGNATURES = {
                                    ctypes.c_double, ctypes.POINTER(ugks_bc),
                                    ctypes.POINTER(ugks_opts), ctypes.POINTER(ctypes.c_void_p)]),
     "ugks_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "ugks_step_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "ugks_moments": (ctypes.c_int, [ctypes.c_void_p, _dp]),
     "ugks_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "ugks_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -143,6 +144,10 @@ def ugks_create(mesh, vgrid, kn, bc, opts):
 
 def ugks_step(h, n):
     return _check(lib().ugks_step(h, int(n)), h)
+
+
+def ugks_step_static(h, n):
+    return _check(lib().ugks_step_static(h, int(n)), h)
 
 
 def ugks_moments(h, out=None):
@@ -306,6 +311,9 @@ class Solver:
 
     def step(self, n=1):
         ugks_step(self.h, n)
+
+    def step_static(self, n=1):
+        ugks_step_static(self.h, n)
 
     def moments(self):
         return ugks_moments(self.h)
