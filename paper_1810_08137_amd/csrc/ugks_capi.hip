@@ -277,7 +277,7 @@ Layout layout_of(const Shape& s, int prec, int chunks, bool shak) {
       (size_t)s.NC * (s.ny + 1) * s.nx * kRec * 8,  // recy
       (size_t)(s.K + 6 * s.M) * 8,              // wk, wm, vmom
       (size_t)s.K * 8,                          // uk
-      (size_t)s.M * 8,                          // vm
+      (size_t)(s.M + 2) * 8,                    // vm, padded with a zero on each side
       (size_t)s.ny * 8 + 64,                    // xi_in + flag
       plan_bytes(1),                            // one-instance launch plan
       plan_bytes(1),                            // the same on the static scratch
@@ -403,6 +403,7 @@ bool problem_ok(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
 // Host copies of the velocity tables and the inlet noise.
 struct HostTables {
   double uk[kMaxNodes], wk[kMaxNodes], vm[kMaxNodes], wm[kMaxNodes], vmom[5 * kMaxNodes];
+  double vm_padded[kMaxNodes + 2];  // zero, vm[0..M), zero: the device copy of the v nodes
 };
 
 // Seeded inlet noise of row j (output nx*ny + j of the generator).
@@ -460,6 +461,9 @@ void fill_constants(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, c
   const double* wm = T.wm;
   velocity_nodes(s.K, vgrid->umax, T.uk, T.wk);
   velocity_nodes(s.M, vgrid->vmax, T.vm, T.wm);
+  T.vm_padded[0] = 0.0;
+  for (int m = 0; m < s.M; ++m) T.vm_padded[m + 1] = T.vm[m];
+  T.vm_padded[s.M + 1] = 0.0;
   P.du = 2.0 * vgrid->umax / (double)(s.K - 1);
   P.dv = 2.0 * vgrid->vmax / (double)(s.M - 1);
   // diffuse-wall constants: moments of the unit-density wall Maxwellian over the velocities
@@ -498,7 +502,7 @@ void bind_tables(KParams& P, const Buffers& B, const Shape& s) {
   P.wm = gp(B.wk + s.K);
   P.vmom = gp(B.wk + s.K + s.M);
   P.uk = gp(B.uk);
-  P.vm = gp(B.vm);
+  P.vm = gp(B.vm + 1);
   P.xi_in = gp(B.xi_in);
   P.flag = gp(B.flag);
 }
@@ -533,7 +537,7 @@ int table_copies(const Buffers& B, const HostTables& T, const Shape& s, Copy* ou
   out[1] = {B.wk + s.K, T.wm, (size_t)s.M * 8};
   out[2] = {B.wk + s.K + s.M, T.vmom, (size_t)s.M * 5 * 8};
   out[3] = {B.uk, T.uk, (size_t)s.K * 8};
-  out[4] = {B.vm, T.vm, (size_t)s.M * 8};
+  out[4] = {B.vm, T.vm_padded, (size_t)(s.M + 2) * 8};
   return 5;
 }
 

@@ -84,7 +84,7 @@ struct KParams {
   double wall_G_bot[4], wall_G_top[4];  // sum of w v psi_local g_w over the same velocities
                                         // (energy: with the wall's H)
   const UGKS_GLOBAL double* uk;    // [K]
-  const UGKS_GLOBAL double* vm;    // [M]
+  const UGKS_GLOBAL double* vm;    // [M], with one zero before and after (vm[-1], vm[M])
   const UGKS_GLOBAL double* wk;    // [K] weights of the u nodes
   const UGKS_GLOBAL double* wm;    // [M] weights of the v nodes
   const UGKS_GLOBAL double* vmom;  // [M][5] w_m v_m^n (n = 0..4), halved at v_m = 0
@@ -104,7 +104,7 @@ struct Buffers {
   double* recy;     // [NC][ny+1][nx][32]
   double* wk;       // [K], followed by wm [M], then vmom [M][5]
   double* uk;       // [K]
-  double* vm;       // [M]
+  double* vm;       // [M + 2]: zero, the M nodes, zero
   double* xi_in;    // [ny]
   int* flag;
 };
@@ -127,8 +127,10 @@ struct Inst {
   UGKS_GLOBAL double* recy;
   int cur;   // f[(cur + step) & 1] and W[(cur + step) & 1] are read, the others written
   int fp32;  // storage type of f
-  int gsplit;  // velocity chunks per quadrant and reduced distribution (P.gmax; set by
-               // build_plan); a segment has NC gsplit workgroups, those of H after those of G
+  int gsplit;  // velocity chunks per quadrant and reduced distribution of the moment kernel
+               // (P.gmax; set by build_plan); a segment has NC gsplit workgroups, those of H
+               // after those of G
+  int usplit;  // the same for the update kernel (set by build_plan for the whole launch)
 };
 
 // A launch plan: instances plus, per kernel, the prefix sum of the workgroups each instance
@@ -148,7 +150,6 @@ struct PlanView {
 struct PlanTotals {
   int sums, upd, face, ghost;  // workgroups of each launch
   int red;                     // workgroups of the chunk-sum launch (0: not launched)
-  int max_m;                   // largest nv of the plan's instances
   int shak;                    // the instances use the Shakhov model (all or none)
 };
 

@@ -38,7 +38,6 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kQuads = 4;                     // wavefronts per workgroup, one per quadrant
 constexpr int kTileS = kWave - 2;             // cells per moment-kernel wavefront
 constexpr int kTileU = kWave - 2 * kHalo;     // cells per update-kernel wavefront
-constexpr int kStage = R_M5 + 1;              // record fields the update kernel stages in LDS
 constexpr unsigned kDropOffset = 0xFFFFFFF0u;  // beyond any plane (at most 2^31 bytes)
 
 // Quadrant q of a workgroup: sign of u and of v.  Around the cycle (+,+) (-,+) (-,-) (+,-)
@@ -99,6 +98,13 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, d
 template <typename S>
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
   return bload(r, off, S{});
+}
+// The same, left in the storage type (converted where it is used)
+__device__ __forceinline__ double bload_raw(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float bload_raw(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
 // index of cell (i, j) in a plane; i and j may lie in the halo
@@ -1053,26 +1059,34 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
 }
 
 // ------------------------------------------------------------------ update kernel
-// Staged face records: sx[field][f] holds x face i0 - 2 + f (the left face of lane f),
-// sy[0 / 1][field][l] the bottom / top face of lane l.
-struct Stage {
-  double sx[kStage][kWave + 1];
-  double sy[2][kStage][kWave];
-  // v-direction Gaussians (value, ratio) at the first node of each half of the v axis:
-  // g^n and g^{n+1} per half, the bottom and top faces per half, the x face per wavefront
-  double gs[2][4][kWave];
-  double ys[2][4][kWave];
-  double xs[kQuads][2][kWave];
-};
-// Once Eq. (4) is done the flux fields (R_FX..R_FX+3) are free: they then hold, per lane, the
-// cell's state for Eq. (3) (CellField n in row cell_row(n)).
+// A workgroup takes one segment of kTileU cells of two neighbouring rows, jb and jb + 1; its
+// lanes hold the segment and two cells on each side.  Wavefront q runs velocity quadrant q
+// (signs su, sv) over both rows: u nodes outer, v nodes inner.  The upwind row of the pair
+// (jb for sv > 0) comes first: the flux through the face between the two rows is evaluated
+// once, as that row's outgoing flux, and taken over in registers as the other row's incoming
+// flux.  Per velocity the wavefront loads five row segments of the plane (the pair, the two
+// rows upwind of it, the row downwind of it) instead of four per row.
+//
+// Rows: the pairs are (0, 1), (2, 3), ...; with ny odd the last pair is (ny - 2, ny - 1), of
+// which only row ny - 1 is written (row ny - 2 belongs to the pair before), and with ny = 1
+// the only pair is (-1, 0), of which only row 0 is written.  A row outside the mesh reads
+// zeros or halo values and writes nothing; the faces it touches are chosen so that no flux
+// that a written row takes from it depends on its values (see face_role).
+constexpr int kPair = 2;
+// Face record fields staged in LDS: R_GC .. R_M5 except R_VY (read once, for the Gauss starts).
+constexpr int kSF = R_M5 - R_GC;
+__host__ __device__ constexpr int sf(int R) { return R < R_VY ? R - R_GC : R - R_GC - 1; }
+// Per-cell state of Eq. (3) (CellField) for the two rows.
 enum CellField { C_LAMN, C_UN, C_VN, C_LAM1, C_U1, C_V1, C_AN, C_A1, C_AF, C_ADF, C_COUNT };
-__device__ __forceinline__ double* cell_row(Stage& st, int n) {
-  return n < 4 ? st.sy[0][R_FX + n] : (n < 8 ? st.sy[1][R_FX + n - 4] : st.sx[R_FX + n - 8]);
-}
-__device__ __forceinline__ const double* cell_row(const Stage& st, int n) {
-  return n < 4 ? st.sy[0][R_FX + n] : (n < 8 ? st.sy[1][R_FX + n - 4] : st.sx[R_FX + n - 8]);
-}
+struct PairStage {
+  double sx[kPair][kSF][kWave + 1];  // x face i0 - 2 + f of row jb + r (left face of lane f)
+  double sy[kPair + 1][kSF][kWave];  // y face row jb + r (bottom face of row jb + r), lane l
+  double cell[kPair][C_COUNT][kWave];
+  // Gauss starts (value, ratio) at the first node of v half h (0: v > 0, 1: v < 0)
+  double xs[2][kPair][2][kWave + 1];   // x faces
+  double ys[2][kPair + 1][2][kWave];   // y faces
+  double gs[2][kPair][2][2][kWave];    // g^n (0) and g^{n+1} (1) of each cell
+};
 
 // A Gaussian factor exp(-lam (x - c)^2) along the uniform nodes x0, x0 + h, x0 + 2h, ...:
 // e is its value at the current node and r the ratio to the next one; successive ratios
@@ -1110,25 +1124,23 @@ __device__ __forceinline__ Cubic cubic_in_un(const double* e, double ut) {
 __device__ __forceinline__ double horner(const Cubic& c, double x) {
   return fma(x, fma(x, fma(x, c.c3, c.c2), c.c1), c.c0);
 }
-// e0..e8 of a staged record for particles with normal velocity of sign s
-__device__ __forceinline__ void load_e(const double (*st)[kWave + 1], int col, int s, double* e) {
-#pragma unroll
-  for (int n = 0; n < 9; ++n) e[n] = st[R_E + n][col];
-  if (s < 0) {
-    e[1] = st[R_ER + 0][col];
-    e[4] = st[R_ER + 1][col];
-    e[5] = st[R_ER + 2][col];
-    e[7] = st[R_ER + 3][col];
-  }
+__device__ __forceinline__ Cubic scaled(Cubic c, double s) {
+  c.c0 *= s;
+  c.c1 *= s;
+  c.c2 *= s;
+  c.c3 *= s;
+  return c;
 }
-__device__ __forceinline__ void load_e(const double (*st)[kWave], int col, int s, double* e) {
+// e0..e8 of a staged record for particles with normal velocity of sign s
+template <int N>
+__device__ __forceinline__ void load_e(const double (*st)[N], int col, int s, double* e) {
 #pragma unroll
-  for (int n = 0; n < 9; ++n) e[n] = st[R_E + n][col];
+  for (int n = 0; n < 9; ++n) e[n] = st[sf(R_E + n)][col];
   if (s < 0) {
-    e[1] = st[R_ER + 0][col];
-    e[4] = st[R_ER + 1][col];
-    e[5] = st[R_ER + 2][col];
-    e[7] = st[R_ER + 3][col];
+    e[1] = st[sf(R_ER + 0)][col];
+    e[4] = st[sf(R_ER + 1)][col];
+    e[5] = st[sf(R_ER + 2)][col];
+    e[7] = st[sf(R_ER + 3)][col];
   }
 }
 
@@ -1148,57 +1160,104 @@ __device__ __forceinline__ Cubic shakhov_in_v(double u, double kqx, double kqy, 
   return c;
 }
 
-// Per cell: Eq. (4) for W, then Eq. (3) for every velocity.  A workgroup takes one segment of
-// kTileU cells of row j; its lanes hold the segment and two cells on each side.  Wavefront q
-// runs velocity quadrant q (signs su, sv): u nodes outer, v nodes inner.  Per velocity a lane
-// (cell i) forms
+// Role of y face F (between rows F - 1 and F) for particles moving with the sign sv of v.  A
+// channel wall emits its Maxwellian when the particles leave it (F = 0 with sv > 0, F = ny with
+// sv < 0): the flux is GC Et(u) E(v) alone, with no polynomial and no free transport, and takes
+// nothing from the row beyond the wall.  A wall the particles reach (the other two cases)
+// takes the first-order free transport of the wall row (its record has no polynomial and M5 = 0;
+// the wall row has no y slope).  Every other face is an interior face.
+enum FaceRole { F_INTERIOR = 0, F_EMIT = 1, F_ABSORB = 2 };
+__device__ __forceinline__ int face_role(const KParams& P, int F, int sv) {
+  if (P.bc != UGKS_BC_CHANNEL) return F_INTERIOR;
+  if ((F == 0 && sv > 0) || (F == P.ny && sv < 0)) return F_EMIT;
+  if ((F == P.ny && sv > 0) || (F == 0 && sv < 0)) return F_ABSORB;
+  return F_INTERIOR;
+}
+
+// The equilibrium part of a y face at tangential velocity u as a cubic in v, and its free
+// transport weights, for particles of v sign sv, by the face's role.
+__device__ __forceinline__ void y_face(const PairStage& st, int fr, int lane, int sv, int role,
+                                       double u, Cubic& c, double& m4, double& m5) {
+  const double(*r)[kWave] = st.sy[fr];
+  const double d = u - r[sf(R_UX)][lane];
+  const double Et = r[sf(R_GC)][lane] * exp(-r[sf(R_LAM)][lane] * d * d);
+  if (role == F_EMIT) {
+    c = Cubic{Et, 0.0, 0.0, 0.0};
+    m4 = m5 = 0.0;
+    return;
+  }
+  m4 = r[sf(R_M4)][lane];
+  if (role == F_ABSORB) {
+    c = Cubic{0.0, 0.0, 0.0, 0.0};
+    m5 = 0.0;
+    return;
+  }
+  double e[9];
+  load_e(r, lane, sv, e);
+  c = scaled(cubic_in_un(e, u), Et);
+  m5 = r[sf(R_M5)][lane];
+}
+
+// Per velocity quadrant (SU = sign of u, sv = sign of v) of a row pair: Eq. (3) for every
+// velocity of the quadrant's chunk of u nodes.  Per velocity and row a lane (cell i) forms
 //   its upwind reconstruction and slope term at its outgoing x and y faces,
 //   the flux through its outgoing x face, which the downwind lane takes over as its incoming
 //   x flux (x faces of the segment are each evaluated once),
-//   the flux through its outgoing y face, and the incoming y flux from the reconstruction of
-//   the upwind row's cell (i, j - sv), rebuilt from rows j - 2 sv .. j.
+//   the flux through its outgoing y face; the upwind row's is the other row's incoming flux,
+//   and the upwind row's incoming flux comes from the reconstruction of the cell below it
+//   (i, jb - 1) for sv > 0 (above, (i, jb + 2), for sv < 0).
 // The equilibrium part of a face flux is GC En(un) Et(ut) P(un, ut): the Gaussian and cubic
 // of the u node are formed once per node, those of the v node follow the node by Gauss
-// recurrences.  Walls fold into the same form: the face leaving a wall carries only its
-// Maxwellian (P = 1, no free-transport part), the face reaching a wall only the first-order
-// free transport of the wall row.
-template <typename S, int SU, bool kShak>
-__device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& st,
-                                                const double (*sk)[kWave],
-                                                const double* vnode, int q, int lane, int sv,
-                                                int j, int g, int G,
-                                                bool valid, bool ghost_lane,
-                                                const UGKS_GLOBAL S* fin, UGKS_GLOBAL S* fout,
-                                                int o) {
+// recurrences.
+// kAhead: nodes whose loads are in flight ahead of the node computed.  The 400 x 100 x 40^2
+// channel measured 2 (FP64) and 3 (FP32 storage) 2-3% faster than 1; the Shakhov variant
+// has no registers to spare beyond 1.
+template <typename S, int SU, bool kShak,
+          int kAhead = kShak ? 1 : (sizeof(S) == 8 ? 2 : 3)>
+__device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage& st,
+                                              const double (*sk)[4][kWave], int lane, int sv,
+                                              int jb, bool store0, int g, int G, bool valid,
+                                              bool ghost_lane, const UGKS_GLOBAL S* fin,
+                                              UGKS_GLOBAL S* fout, int i) {
   const bool chan = P.bc == UGKS_BC_CHANNEL;
-  const int xo = lane + (SU > 0 ? 1 : 0);        // staged x face the lane's particles leave by
-  const int yo = sv > 0 ? 1 : 0, yi = 1 - yo;    // y faces: outgoing, incoming
-  // own wall row: no y slope; the upwind row (i, j - sv) likewise
-  const bool my = !(chan && (j == 0 || j == P.ny - 1));
-  const int jy = j - sv;
-  const bool mY = !(chan && (jy == 0 || jy == P.ny - 1));
-  const bool gm = !ghost_lane;                   // ghost columns have zero slopes
-  const bool gmy = gm && my;
-  const bool wall_o = chan && (sv > 0 ? j == P.ny - 1 : j == 0);
-  const bool wall_i = chan && (sv > 0 ? j == 0 : j == P.ny - 1);
-  // byte offsets of this cell and of rows j - sv, j + sv, j - 2 sv inside a plane
+  const int r0 = sv > 0 ? 0 : 1, r1 = 1 - r0;     // rows of the pair, upwind first
+  const int j0 = jb + r0, j1 = jb + r1;           // their mesh rows
+  const int jB = j0 - sv;                         // the cell upwind of row j0
+  // y face rows of the stage: incoming face of j0, the face between the rows, outgoing of j1
+  const int fin_r = sv > 0 ? 0 : 2, fout_r = 2 - fin_r, fmid_r = 1;
+  const int role_in = face_role(P, jb + fin_r, sv);
+  const int role_mid = face_role(P, jb + fmid_r, sv);
+  const int role_out = face_role(P, jb + fout_r, sv);
+  auto no_wall = [&](int j) { return !(chan && (j == 0 || j == P.ny - 1)); };
+  const bool gm = !ghost_lane;  // ghost columns have zero slopes
+  const bool mB = no_wall(jB), m0 = gm && no_wall(j0), m1 = gm && no_wall(j1);
+  const bool st0 = valid && (r0 == 0 ? store0 : true);
+  const bool st1 = valid && (r1 == 0 ? store0 : true);
+  // byte offsets of the five rows j0 - 2 sv, j0 - sv, j0, j1 = j0 + sv, j1 + sv
   const unsigned bs = (unsigned)sizeof(S);
-  const unsigned oc = (unsigned)o * bs;
-  const unsigned oY = (unsigned)(o - sv * P.Lx) * bs;
-  const unsigned oO = (unsigned)(o + sv * P.Lx) * bs;
-  const unsigned oYY = (unsigned)(o - 2 * sv * P.Lx) * bs;
-  const double m4o = st.sy[yo][R_M4][lane], m5o = wall_o ? 0.0 : st.sy[yo][R_M5][lane];
-  const double m4i = wall_i ? 0.0 : st.sy[yi][R_M4][lane];
-  const double m5i = wall_i ? 0.0 : st.sy[yi][R_M5][lane];
-  const double Af = cell_row(st, C_AF)[lane], AdF = cell_row(st, C_ADF)[lane];
+  const int ic = i < P.nx + 1 ? i : P.nx + 1;
+  const int o0 = pidx(P, ic, j0);
+  const int L = sv * P.Lx;
+  const unsigned oA = (unsigned)(o0 - 2 * L) * bs, oB = (unsigned)(o0 - L) * bs;
+  const unsigned oC = (unsigned)o0 * bs, oD = (unsigned)(o0 + L) * bs;
+  const unsigned oE = (unsigned)(o0 + 2 * L) * bs;
+  const unsigned w0 = st0 ? oC : kDropOffset, w1 = st1 ? oD : kDropOffset;
+  const int xo = lane + (SU > 0 ? 1 : 0);  // staged x face the lane's particles leave by
+  const double Af0 = st.cell[r0][C_AF][lane], AdF0 = st.cell[r0][C_ADF][lane];
+  const double Af1 = st.cell[r1][C_AF][lane], AdF1 = st.cell[r1][C_ADF][lane];
   const Half hu = axis_half(P.K, SU, false), hv = axis_half(P.M, sv, false);
+  const int hf = sv > 0 ? 0 : 1;
   const double hstep = sv * P.dv;
   const double h2 = -2.0 * hstep * hstep;
-  const double qx = expm1(h2 * st.sx[R_LAM][xo]);
-  const double qo = expm1(h2 * st.sy[yo][R_LAM][lane]);
-  const double qi = expm1(h2 * st.sy[yi][R_LAM][lane]);
-  const double qn = expm1(h2 * cell_row(st, C_LAMN)[lane]);
-  const double q1 = expm1(h2 * cell_row(st, C_LAM1)[lane]);
+  const double qx0 = expm1(h2 * st.sx[r0][sf(R_LAM)][xo]);
+  const double qx1 = expm1(h2 * st.sx[r1][sf(R_LAM)][xo]);
+  const double qyi = expm1(h2 * st.sy[fin_r][sf(R_LAM)][lane]);
+  const double qym = expm1(h2 * st.sy[fmid_r][sf(R_LAM)][lane]);
+  const double qyo = expm1(h2 * st.sy[fout_r][sf(R_LAM)][lane]);
+  const double qn0 = expm1(h2 * st.cell[r0][C_LAMN][lane]);
+  const double q10 = expm1(h2 * st.cell[r0][C_LAM1][lane]);
+  const double qn1 = expm1(h2 * st.cell[r1][C_LAMN][lane]);
+  const double q11 = expm1(h2 * st.cell[r1][C_LAM1][lane]);
   const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
   int a0, a1;
   chunk_range(hu.count, g, G, a0, a1);
@@ -1207,148 +1266,192 @@ __device__ __forceinline__ void update_quadrant(const KParams& P, const Stage& s
     const double u = P.uk[k];
     const double au = fabs(u);
     const double ucx = u * two_idx;
-    const UGKS_GLOBAL S* line = plane_of(fin, P, k * P.M);
-    UGKS_GLOBAL S* wline = plane_of(fout, P, k * P.M);
     struct Vals {
-      double c, y, o, yy;
+      S A, B, C, D, E;  // rows j0 - 2 sv, j0 - sv, j0, j1, j1 + sv, in the storage type
     };
     // planes (read and written) and v nodes are walked with running pointers
     const long long pstep = (long long)hv.step * P.PS;
-    const UGKS_GLOBAL S* pcur = line + (long long)hv.first * P.PS;
-    UGKS_GLOBAL S* wcur = wline + (long long)hv.first * P.PS;
-    int mcur = hv.first;
-    auto load_at = [&](const UGKS_GLOBAL S* p) {
-      const __amdgpu_buffer_rsrc_t r = plane_rsrc(p, P);
-      return Vals{bload<S>(r, oc), bload<S>(r, oY), bload<S>(r, oO), bload<S>(r, oYY)};
+    const UGKS_GLOBAL S* pnext = plane_of(fin, P, k * P.M) + (long long)hv.first * P.PS;
+    UGKS_GLOBAL S* wcur = plane_of(fout, P, k * P.M) + (long long)hv.first * P.PS;
+    const UGKS_GLOBAL double* vp = P.vm + hv.first;
+    // loads run kAhead nodes ahead of the node computed; past the last node of the half they
+    // read its plane again
+    int nl = 0;
+    auto load_next = [&]() {
+      const __amdgpu_buffer_rsrc_t r = plane_rsrc(pnext, P);
+      const Vals v{bload_raw(r, oA, S{}), bload_raw(r, oB, S{}), bload_raw(r, oC, S{}),
+                   bload_raw(r, oD, S{}), bload_raw(r, oE, S{})};
+      if (++nl < hv.count) pnext += pstep;
+      return v;
     };
-    // the first node's stencil values, requested before the node's tables are formed
-    Vals va = load_at(pcur);
-    // x face: cubic in v times GC En(u), with |u| folded in
-    Cubic cx;
+    // the first nodes' stencil values, requested before the node's tables are formed
+    constexpr int NB = kAhead + 1;
+    Vals ring[NB];
+#pragma unroll
+    for (int d = 0; d < kAhead; ++d) ring[d] = load_next();
+    // x faces of both rows: cubic in v times GC En(u), with |u| folded in
+    Cubic cx0, cx1;
+    double m4x0, m5x0, m4x1, m5x1;
     {
       double e[9];
-      load_e(st.sx, xo, u > 0.0 ? 1 : -1, e);
-      const double d = u - st.sx[R_UX][xo];
-      const double En = st.sx[R_GC][xo] * exp(-st.sx[R_LAM][xo] * d * d) * au;
-      cx = cubic_in_ut(e, u);
-      cx.c0 *= En;
-      cx.c1 *= En;
-      cx.c2 *= En;
-      cx.c3 *= En;
+      const double(*x0)[kWave + 1] = st.sx[r0];
+      load_e(x0, xo, SU, e);
+      const double d = u - x0[sf(R_UX)][xo];
+      cx0 = scaled(cubic_in_ut(e, u), x0[sf(R_GC)][xo] * exp(-x0[sf(R_LAM)][xo] * d * d) * au);
+      m4x0 = x0[sf(R_M4)][xo] * au;
+      m5x0 = x0[sf(R_M5)][xo] * au;
     }
-    const double m4xu = st.sx[R_M4][xo] * au, m5xu = st.sx[R_M5][xo] * au;
-    // the node's exponentials are formed one group at a time: interleaving them all would
-    // need more registers than the v loop leaves free
+    __builtin_amdgcn_sched_barrier(0);
+    {
+      double e[9];
+      const double(*x1)[kWave + 1] = st.sx[r1];
+      load_e(x1, xo, SU, e);
+      const double d = u - x1[sf(R_UX)][xo];
+      cx1 = scaled(cubic_in_ut(e, u), x1[sf(R_GC)][xo] * exp(-x1[sf(R_LAM)][xo] * d * d) * au);
+      m4x1 = x1[sf(R_M4)][xo] * au;
+      m5x1 = x1[sf(R_M5)][xo] * au;
+    }
     __builtin_amdgcn_sched_barrier(0);
     // y faces: cubic in v at tangential u, times GC Et(u)
-    Cubic co, ci;
+    Cubic ci, cm, co;
+    double m4i, m5i, m4m, m5m, m4o, m5o;
+    y_face(st, fin_r, lane, sv, role_in, u, ci, m4i, m5i);
+    __builtin_amdgcn_sched_barrier(0);
+    y_face(st, fmid_r, lane, sv, role_mid, u, cm, m4m, m5m);
+    __builtin_amdgcn_sched_barrier(0);
+    y_face(st, fout_r, lane, sv, role_out, u, co, m4o, m5o);
+    __builtin_amdgcn_sched_barrier(0);
+    // g^n and g^{n+1} of both cells: u factors (with the Eq. (3) weights) times the v
+    // Gaussians' start values
+    double en0, rn0, e10, r10, en1, rn1, e11, r11;
     {
-      double e[9];
-      load_e(st.sy[yo], lane, sv, e);
-      const double d = u - st.sy[yo][R_UX][lane];
-      const double Et = wall_o ? 0.0 : st.sy[yo][R_GC][lane] * exp(-st.sy[yo][R_LAM][lane] * d * d);
-      co = cubic_in_un(e, u);
-      co.c0 *= Et;
-      co.c1 *= Et;
-      co.c2 *= Et;
-      co.c3 *= Et;
+      const double(*c0)[kWave] = st.cell[r0];
+      const double dn = u - c0[C_UN][lane], d1 = u - c0[C_U1][lane];
+      en0 = c0[C_AN][lane] * exp(-c0[C_LAMN][lane] * dn * dn) * st.gs[hf][r0][0][0][lane];
+      e10 = c0[C_A1][lane] * exp(-c0[C_LAM1][lane] * d1 * d1) * st.gs[hf][r0][1][0][lane];
+      rn0 = st.gs[hf][r0][0][1][lane];
+      r10 = st.gs[hf][r0][1][1][lane];
     }
     __builtin_amdgcn_sched_barrier(0);
     {
-      double e[9];
-      load_e(st.sy[yi], lane, sv, e);
-      const double d = u - st.sy[yi][R_UX][lane];
-      const double Et = st.sy[yi][R_GC][lane] * exp(-st.sy[yi][R_LAM][lane] * d * d);
-      ci = cubic_in_un(e, u);
-      ci.c0 = wall_i ? Et : ci.c0 * Et;
-      ci.c1 = wall_i ? 0.0 : ci.c1 * Et;
-      ci.c2 = wall_i ? 0.0 : ci.c2 * Et;
-      ci.c3 = wall_i ? 0.0 : ci.c3 * Et;
+      const double(*c1)[kWave] = st.cell[r1];
+      const double dn = u - c1[C_UN][lane], d1 = u - c1[C_U1][lane];
+      en1 = c1[C_AN][lane] * exp(-c1[C_LAMN][lane] * dn * dn) * st.gs[hf][r1][0][0][lane];
+      e11 = c1[C_A1][lane] * exp(-c1[C_LAM1][lane] * d1 * d1) * st.gs[hf][r1][1][0][lane];
+      rn1 = st.gs[hf][r1][0][1][lane];
+      r11 = st.gs[hf][r1][1][1][lane];
     }
-    __builtin_amdgcn_sched_barrier(0);
-    // g^n and g^{n+1}: u factors with the Eq. (3) weights
-    double cun, cu1;
-    {
-      const double dn = u - cell_row(st, C_UN)[lane], d1 = u - cell_row(st, C_U1)[lane];
-      cun = cell_row(st, C_AN)[lane] * exp(-cell_row(st, C_LAMN)[lane] * dn * dn);
-      cu1 = cell_row(st, C_A1)[lane] * exp(-cell_row(st, C_LAM1)[lane] * d1 * d1);
-    }
-    // Shakhov: the factors (1 + S) of g^n and g^{n+1} as cubics in v
-    Cubic sn3{}, s13{};
+    // Shakhov: the factors (1 + S) of g^n and g^{n+1} of both cells as cubics in v
+    Cubic sn0{}, s10{}, sn1{}, s11{};
     if constexpr (kShak) {
-      sn3 = shakhov_in_v(u, sk[0][lane], sk[1][lane], cell_row(st, C_LAMN)[lane],
-                         cell_row(st, C_UN)[lane], cell_row(st, C_VN)[lane]);
-      s13 = shakhov_in_v(u, sk[2][lane], sk[3][lane], cell_row(st, C_LAM1)[lane],
-                         cell_row(st, C_U1)[lane], cell_row(st, C_V1)[lane]);
+      const double(*c0)[kWave] = st.cell[r0];
+      const double(*c1)[kWave] = st.cell[r1];
+      sn0 = shakhov_in_v(u, sk[r0][0][lane], sk[r0][1][lane], c0[C_LAMN][lane], c0[C_UN][lane],
+                         c0[C_VN][lane]);
+      s10 = shakhov_in_v(u, sk[r0][2][lane], sk[r0][3][lane], c0[C_LAM1][lane], c0[C_U1][lane],
+                         c0[C_V1][lane]);
+      sn1 = shakhov_in_v(u, sk[r1][0][lane], sk[r1][1][lane], c1[C_LAMN][lane], c1[C_UN][lane],
+                         c1[C_VN][lane]);
+      s11 = shakhov_in_v(u, sk[r1][2][lane], sk[r1][3][lane], c1[C_LAM1][lane], c1[C_U1][lane],
+                         c1[C_V1][lane]);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // v-direction Gaussians at the first node of the half and their ratios
-    const int hf = sv > 0 ? 0 : 1;
-    double ex = st.xs[q][0][lane], rx = st.xs[q][1][lane];
-    double eo = st.ys[hf][2 * yo][lane], ro = st.ys[hf][2 * yo + 1][lane];
-    double ei = st.ys[hf][2 * yi][lane], ri = st.ys[hf][2 * yi + 1][lane];
-    double en = st.gs[hf][0][lane], rn = st.gs[hf][1][lane];
-    double e1 = st.gs[hf][2][lane], r1 = st.gs[hf][3][lane];
-    auto node = [&](const Vals& x) {
-      const double vv = vnode[mcur];
-      const double fc = x.c, fY = x.y, fO = x.o, fYY = x.yy;
+    // v-direction Gaussians of the faces at the first node of the half, and their ratios
+    double ex0 = st.xs[hf][r0][0][xo], rx0 = st.xs[hf][r0][1][xo];
+    double ex1 = st.xs[hf][r1][0][xo], rx1 = st.xs[hf][r1][1][xo];
+    double ei = st.ys[hf][fin_r][0][lane], ri = st.ys[hf][fin_r][1][lane];
+    double em = st.ys[hf][fmid_r][0][lane], rm = st.ys[hf][fmid_r][1][lane];
+    double eo = st.ys[hf][fout_r][0][lane], ro = st.ys[hf][fout_r][1][lane];
+    double vv = *vp;
+    auto node = [&](const Vals& raw) {
+      const struct {
+        double A, B, C, D, E;
+      } x{(double)raw.A, (double)raw.B, (double)raw.C, (double)raw.D, (double)raw.E};
+      const double vnext = vp[hv.step];  // the next node (read one ahead; past the end a pad)
       const double av = fabs(vv);
       const double avcy = av * two_idy;
-      // this cell: half-cell changes (x: signed; y: times sv)
-      const double fW = from_lower(fc), fE = from_upper(fc);
-      const double Hx = half_limited(fE - fc, fc - fW, gm);
-      const double Hy = half_limited(fO - fc, fc - fY, gmy);
-      const double D0 = fma(ucx, Hx, avcy * Hy);
-      const double fhx = SU > 0 ? fc + Hx : fc - Hx;
-      const double fhy = fc + Hy;
-      // upwind row's cell
-      const double fYw = from_lower(fY), fYe = from_upper(fY);
-      const double hxY = half_limited(fYe - fY, fY - fYw);
-      const double HyY = half_limited(fc - fY, fY - fYY, mY);
-      const double DY = fma(ucx, hxY, avcy * HyY);
-      const double fhY = fY + HyY;
-      // x: outgoing face of this lane, incoming from the upwind lane
-      const double Fxo = fma(ex, horner(cx, vv), fma(m4xu, fhx, -m5xu * D0));
-      const double Fxi = SU > 0 ? from_lower(Fxo) : from_upper(Fxo);
-      // y: outgoing and incoming faces
-      const double Fyo = av * fma(eo, horner(co, vv), fma(m4o, fhy, -m5o * D0));
-      const double Fyi = av * fma(ei, horner(ci, vv), fma(m4i, fhY, -m5i * DY));
-      double g;
-      if constexpr (kShak)
-        g = fma(cu1 * e1, 1.0 + horner(s13, vv), (cun * en) * (1.0 + horner(sn3, vv)));
-      else
-        g = fma(cu1, e1, cun * en);
-      const double f1 = fma(Af, fc, fma(AdF, (Fxi - Fxo) + (Fyi - Fyo), g));
-      // lanes outside the segment store past the plane's range, which the hardware drops
-      bstore(plane_rsrc(wcur, P), valid ? oc : kDropOffset, f1, S{});
+      // upwind neighbour of row j0: half-cell changes towards the pair (y) and in x
+      const double fBw = from_lower(x.B), fBe = from_upper(x.B);
+      const double HxB = half_limited(fBe - x.B, x.B - fBw);
+      const double HyB = half_limited(x.C - x.B, x.B - x.A, mB);
+      const double DB = fma(ucx, HxB, avcy * HyB);
+      const double fhB = x.B + HyB;
+      // row j0
+      const double fCw = from_lower(x.C), fCe = from_upper(x.C);
+      const double HxC = half_limited(fCe - x.C, x.C - fCw, gm);
+      const double HyC = half_limited(x.D - x.C, x.C - x.B, m0);
+      const double DC = fma(ucx, HxC, avcy * HyC);
+      const double fxC = SU > 0 ? x.C + HxC : x.C - HxC;
+      const double fhC = x.C + HyC;
+      // row j1
+      const double fDw = from_lower(x.D), fDe = from_upper(x.D);
+      const double HxD = half_limited(fDe - x.D, x.D - fDw, gm);
+      const double HyD = half_limited(x.E - x.D, x.D - x.C, m1);
+      const double DD = fma(ucx, HxD, avcy * HyD);
+      const double fxD = SU > 0 ? x.D + HxD : x.D - HxD;
+      const double fhD = x.D + HyD;
+      // x faces: outgoing of this lane, incoming from the upwind lane
+      const double Fxo0 = fma(ex0, horner(cx0, vv), fma(m4x0, fxC, -m5x0 * DC));
+      const double Fxo1 = fma(ex1, horner(cx1, vv), fma(m4x1, fxD, -m5x1 * DD));
+      const double Fxi0 = SU > 0 ? from_lower(Fxo0) : from_upper(Fxo0);
+      const double Fxi1 = SU > 0 ? from_lower(Fxo1) : from_upper(Fxo1);
+      // y faces: into row j0, between the rows, out of row j1
+      const double Fyi = av * fma(ei, horner(ci, vv), fma(m4i, fhB, -m5i * DB));
+      const double Fym = av * fma(em, horner(cm, vv), fma(m4m, fhC, -m5m * DC));
+      const double Fyo = av * fma(eo, horner(co, vv), fma(m4o, fhD, -m5o * DD));
+      double g0, g1;
+      if constexpr (kShak) {
+        g0 = fma(e10, 1.0 + horner(s10, vv), en0 * (1.0 + horner(sn0, vv)));
+        g1 = fma(e11, 1.0 + horner(s11, vv), en1 * (1.0 + horner(sn1, vv)));
+      } else {
+        g0 = fma(e10, 1.0, en0);
+        g1 = fma(e11, 1.0, en1);
+      }
+      const double f0 = fma(Af0, x.C, fma(AdF0, (Fxi0 - Fxo0) + (Fyi - Fym), g0));
+      const double f1 = fma(Af1, x.D, fma(AdF1, (Fxi1 - Fxo1) + (Fym - Fyo), g1));
+      // lanes and rows without a cell to write store past the plane's range (dropped)
+      const __amdgpu_buffer_rsrc_t wr = plane_rsrc(wcur, P);
+      bstore(wr, w0, f0, S{});
+      bstore(wr, w1, f1, S{});
       wcur += pstep;
-      mcur += hv.step;
-      gauss_next(ex, rx, qx);
-      gauss_next(eo, ro, qo);
-      gauss_next(ei, ri, qi);
-      gauss_next(en, rn, qn);
-      gauss_next(e1, r1, q1);
+      vp += hv.step;
+      vv = vnext;
+      gauss_next(ex0, rx0, qx0);
+      gauss_next(ex1, rx1, qx1);
+      gauss_next(ei, ri, qyi);
+      gauss_next(em, rm, qym);
+      gauss_next(eo, ro, qyo);
+      gauss_next(en0, rn0, qn0);
+      gauss_next(e10, r10, q10);
+      gauss_next(en1, rn1, qn1);
+      gauss_next(e11, r11, q11);
     };
-    // two value sets, each node's loads issued one node ahead
+    // NB value sets in a ring: slot s holds node c + s, loaded kAhead nodes earlier
     int c = 0;
-    for (; c + 1 < hv.count; c += 2) {
-      pcur += pstep;
-      const Vals vb = load_at(pcur);
-      node(va);
-      if (c + 2 < hv.count) pcur += pstep;
-      va = load_at(pcur);
-      node(vb);
+    for (; c + NB <= hv.count; c += NB) {
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+        ring[(s + kAhead) % NB] = load_next();
+        node(ring[s]);
+      }
     }
-    if (c < hv.count) node(va);
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      if (c + s < hv.count) {
+        ring[(s + kAhead) % NB] = load_next();
+        node(ring[s]);
+      }
+    }
   }
 }
 
 // The body of the update kernel; kShak: the Shakhov collision model.
 template <typename S, bool kShak>
-__device__ __forceinline__ void update_body(const PlanView& pv, double* vnode) {
-  __shared__ Stage st;
-  // Shakhov: (1 - Pr)(lambda^2/rho) q of each lane's cell at t^n and t^{n+1}
-  __shared__ double sk[kShak ? 4 : 1][kWave];
+__device__ __forceinline__ void update_body(const PlanView& pv) {
+  __shared__ PairStage st;
+  // Shakhov: (1 - Pr)(lambda^2/rho) q of each lane's cell at t^n and t^{n+1}, per row
+  __shared__ double sk_raw[kShak ? kPair * 4 * kWave : 1];
+  double(*sk)[4][kWave] = reinterpret_cast<double(*)[4][kWave]>(sk_raw);
   const int lane = threadIdx.x & (kWave - 1);
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -1356,9 +1459,12 @@ __device__ __forceinline__ void update_body(const PlanView& pv, double* vnode) {
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
   const int parity = (I->cur + pv.step) & 1;
-  const int G = I->gsplit;
-  int t, gg, j;
-  cell_block(b - first_block(pv.off_upd, ii), P.ny, (P.nx + kTileU - 1) / kTileU, t, gg, j);
+  const int G = I->usplit;
+  int t, gg, pb;
+  cell_block(b - first_block(pv.off_upd, ii), (P.ny + 1) / 2, (P.nx + kTileU - 1) / kTileU, t,
+             gg, pb);
+  const int jb = min(2 * pb, P.ny - 2);       // rows jb, jb + 1
+  const bool store0 = jb == 2 * pb && jb >= 0;  // row jb is this pair's to write
   // chunks G..2G-1 update H: its planes, its face records, its equilibria
   const bool hpart = gg >= G;
   const int g = hpart ? gg - G : gg;
@@ -1376,52 +1482,71 @@ __device__ __forceinline__ void update_body(const PlanView& pv, double* vnode) {
   const bool valid = lane >= kHalo && lane < kHalo + kTileU && i < P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
   const bool ghost_lane = chan && (i == -1 || i == P.nx);
-  const int o = pidx(P, i < P.nx + 1 ? i : P.nx + 1, j);
-  // stage the records of the segment's faces (x faces i0-2 .. i0+62, y faces below / above
-  // lanes 0..63; indices clamped into the mesh for lanes outside it)
-  for (int e = threadIdx.x; e < (kWave + 1) * kRec; e += blockDim.x) {
-    const int fc = e / kRec, fld = e - fc * kRec;
-    if (fld < kStage) {
-      const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
-      st.sx[fld][fc] = recx[((size_t)j * (P.nx + 1) + fi) * kRec + fld];
-    }
+  // stage the records of the pair's faces: x faces i0-2 .. i0+62 of both rows, y face rows
+  // jb .. jb+2 below / above lanes 0..63; indices clamped into the mesh for lanes and rows
+  // outside it
+  for (int e = threadIdx.x; e < kPair * (kWave + 1) * kSF; e += blockDim.x) {
+    const int r = e / ((kWave + 1) * kSF), rem = e - r * ((kWave + 1) * kSF);
+    const int fc = rem / kSF, s = rem - fc * kSF;
+    const int fld = s <= sf(R_UX) ? R_GC + s : R_GC + s + 1;  // skip R_VY
+    const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
+    const int row = clampi(jb + r, 0, P.ny - 1);
+    st.sx[r][s][fc] = recx[((size_t)row * (P.nx + 1) + fi) * kRec + fld];
   }
-  for (int e = threadIdx.x; e < 2 * kWave * kRec; e += blockDim.x) {
-    const int side = e / (kWave * kRec), r = e - side * (kWave * kRec);
-    const int fc = r / kRec, fld = r - fc * kRec;
-    if (fld < kStage) {
-      const int fi = clampi(i0 - kHalo + fc, 0, P.nx - 1);
-      st.sy[side][fld][fc] = recy[((size_t)(j + side) * P.nx + fi) * kRec + fld];
-    }
+  for (int e = threadIdx.x; e < (kPair + 1) * kWave * kSF; e += blockDim.x) {
+    const int r = e / (kWave * kSF), rem = e - r * (kWave * kSF);
+    const int fc = rem / kSF, s = rem - fc * kSF;
+    const int fld = s <= sf(R_UX) ? R_GC + s : R_GC + s + 1;  // skip R_VY
+    const int fi = clampi(i0 - kHalo + fc, 0, P.nx - 1);
+    const int row = clampi(jb + r, 0, P.ny);
+    st.sy[r][s][fc] = recy[((size_t)row * P.nx + fi) * kRec + fld];
   }
-  for (int e = threadIdx.x; e < P.M; e += blockDim.x) vnode[e] = P.vm[e];
   __syncthreads();
-  if (q == 0) {
-    // Eq. (4), and the cell's Maxwellians of W^n and W^{n+1} with the weights of Eq. (3)
-    // solved for f^{n+1}: f1 = Af f + AdF dF + (A1 g^{n+1} + An g^n)
-    const size_t cc = (size_t)j * P.nx + (valid ? i : 0);
+  const double hstep = P.dv;
+  // A start value below the normal range cannot be carried up to a peak that lies inside
+  // the half: such a state (speed ratio |V| lambda^(1/2) above about 26 across v) is flagged.
+  bool lost = false;
+  // Gauss start of exp(-lam (v - c)^2) at the first node of half h and its ratio to the next
+  auto start = [&](double lam, double c, int h, double* e, double* r, int col) {
+    const double v0 = P.vm[h == 0 ? P.M / 2 : P.M / 2 - 1];
+    const double hs = h == 0 ? hstep : -hstep;
+    const double d = v0 - c;
+    const double x = lam * d * d;
+    e[col] = exp(-x);
+    r[col] = exp(-lam * hs * (2.0 * d + hs));
+    lost = lost || (x > 700.0 && (h == 0 ? c > v0 : c < v0));
+  };
+  if (q < kPair) {
+    // Eq. (4) for row jb + q, and the cell's Maxwellians of W^n and W^{n+1} with the
+    // weights of Eq. (3) solved for f^{n+1}: f1 = Af f + AdF dF + (A1 g^{n+1} + An g^n)
+    const int r = q;
+    const int jr = clampi(jb + r, 0, P.ny - 1);
+    const bool mine = valid && (r == 0 ? store0 : true);
+    const int ci = valid ? i : 0;
+    const size_t cc = (size_t)jr * P.nx + ci;
     double Wn[4] = {1.0, 0.0, 0.0, 1.0}, W1[4];
+    const UGKS_GLOBAL double* fl = recx + ((size_t)jr * (P.nx + 1) + ci) * kRec + R_FX;
+    const UGKS_GLOBAL double* fb = recy + ((size_t)jr * P.nx + ci) * kRec + R_FX;
+    const UGKS_GLOBAL double* ft = fb + (size_t)P.nx * kRec;
     if (valid) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Wn[r] = W[4 * cc + r];
+      for (int k = 0; k < 4; ++k) Wn[k] = W[4 * cc + k];
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const double dW = (st.sx[R_FX + r][lane] - st.sx[R_FX + r][lane + 1] +
-                         st.sy[0][R_FX + r][lane] - st.sy[1][R_FX + r][lane]) /
-                        P.area;
-      W1[r] = valid ? Wn[r] + dW : Wn[r];
+    for (int k = 0; k < 4; ++k) {
+      const double dW = (fl[k] - fl[kRec + k] + fb[k] - ft[k]) / P.area;
+      W1[k] = valid ? Wn[k] + dW : Wn[k];
     }
     // every velocity chunk of the segment forms the same W^{n+1}; chunk 0 stores it
-    if (valid && gg == 0) {
+    if (mine && gg == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Wout[4 * cc + r] = W1[r];
+      for (int k = 0; k < 4; ++k) Wout[4 * cc + k] = W1[k];
     }
     Prim pn{}, p1{};
     double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
     if (!P.collisionless) {
       const bool ok = prim_of(Wn, pn, P.lam_c) && prim_of(W1, p1, P.lam_c);
-      if (!ok && valid) *P.flag = 1;
+      if (!ok && mine) *P.flag = 1;
       const double tn = collision_time(pn, P.mu_ref), t1 = collision_time(p1, P.mu_ref);
       const double hdt = 0.5 * P.dt;
       const double den = 1.0 / (1.0 + hdt / t1);
@@ -1436,77 +1561,71 @@ __device__ __forceinline__ void update_body(const PlanView& pv, double* vnode) {
     }
     if constexpr (kShak) {
       // heat flux of f^n about U^n from the cell's raw moments (moment kernel, chunk 0)
-      const UGKS_GLOBAL double* cm = I->hs + (size_t)kSlotCell * ((size_t)P.nx * P.ny) + cc;
       const size_t nc = (size_t)P.nx * P.ny;
+      const UGKS_GLOBAL double* cm = I->hs + (size_t)kSlotCell * nc + cc;
       double m[8];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) m[r] = valid ? cm[(size_t)r * nc] : 0.0;
+      for (int k = 0; k < 8; ++k) m[k] = valid ? cm[(size_t)k * nc] : 0.0;
       double qn[2];
       heat_flux(m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[3] + m[5], pn.U, pn.V, qn);
       const double kn = P.collisionless ? 0.0 : P.pr_c * pn.lam * pn.lam / pn.rho;
       const double k1 = P.collisionless ? 0.0 : P.pr_c * p1.lam * p1.lam / p1.rho;
-      sk[0][lane] = kn * qn[0];
-      sk[1][lane] = kn * qn[1];
-      sk[2][lane] = k1 * qn[0];
-      sk[3][lane] = k1 * qn[1];
+      sk[r][0][lane] = kn * qn[0];
+      sk[r][1][lane] = kn * qn[1];
+      sk[r][2][lane] = k1 * qn[0];
+      sk[r][3][lane] = k1 * qn[1];
     }
-    // every read of the flux fields by this wavefront is complete before they are reused
-    __builtin_amdgcn_wave_barrier();
     const double cell[C_COUNT] = {pn.lam, pn.U, pn.V, p1.lam, p1.U, p1.V, An, A1, Af, AdF};
 #pragma unroll
-    for (int n = 0; n < C_COUNT; ++n) cell_row(st, n)[lane] = cell[n];
+    for (int n = 0; n < C_COUNT; ++n) st.cell[r][n][lane] = cell[n];
+    // Gauss starts of g^n and g^{n+1} of this cell in both halves of v
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      start(pn.lam, pn.V, h, st.gs[h][r][0][0], st.gs[h][r][0][1], lane);
+      start(p1.lam, p1.V, h, st.gs[h][r][1][0], st.gs[h][r][1][1], lane);
+    }
+  } else {
+    // Gauss starts of the faces: wavefront 2 takes the x faces of row jb and the y face row
+    // jb, wavefront 3 those of row jb + 1 and the y face rows jb + 1, jb + 2
+    const int r = q - kPair;
+    const int jr = clampi(jb + r, 0, P.ny - 1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      for (int fc = lane; fc < kWave + 1; fc += kWave) {
+        const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
+        const double vy = recx[((size_t)jr * (P.nx + 1) + fi) * kRec + R_VY];
+        start(st.sx[r][sf(R_LAM)][fc], vy, h, st.xs[h][r][0], st.xs[h][r][1], fc);
+      }
+      for (int fr = r == 0 ? 0 : 1; fr < (r == 0 ? 1 : kPair + 1); ++fr) {
+        const int fi = clampi(i0 - kHalo + lane, 0, P.nx - 1);
+        const int row = clampi(jb + fr, 0, P.ny);
+        const double vy = recy[((size_t)row * P.nx + fi) * kRec + R_VY];
+        start(st.sy[fr][sf(R_LAM)][lane], vy, h, st.ys[h][fr][0], st.ys[h][fr][1], lane);
+      }
+    }
   }
+  if (lost && valid) *P.flag = 1;
   __syncthreads();
   const int sv = quad_sv(q);
-  {
-    // Gauss starts: wavefront q takes its x face and, for the half of v its sign selects,
-    // g^n and g^{n+1} (q = 0, 2) or the two y faces (q = 1, 3)
-    const int hf = sv > 0 ? 0 : 1;
-    const double hstep = sv * P.dv;
-    const double v0 = vnode[sv > 0 ? P.M / 2 : P.M / 2 - 1];
-    // A start value below the normal range cannot be carried up to a peak that lies inside
-    // the half: such a state (speed ratio |V| lambda^(1/2) above about 26 across v) is flagged.
-    bool lost = false;
-    auto start = [&](double lam, double c, double* e, double* r) {
-      const double d = v0 - c;
-      const double x = lam * d * d;
-      e[lane] = exp(-x);
-      r[lane] = exp(-lam * hstep * (2.0 * d + hstep));
-      lost = lost || (x > 700.0 && (sv > 0 ? c > v0 : c < v0));
-    };
-    const int xo = lane + (quad_su(q) > 0 ? 1 : 0);
-    start(st.sx[R_LAM][xo], st.sx[R_VY][xo], st.xs[q][0], st.xs[q][1]);
-    if (q == 0 || q == 2) {
-      start(cell_row(st, C_LAMN)[lane], cell_row(st, C_VN)[lane], st.gs[hf][0], st.gs[hf][1]);
-      start(cell_row(st, C_LAM1)[lane], cell_row(st, C_V1)[lane], st.gs[hf][2], st.gs[hf][3]);
-    } else {
-      start(st.sy[0][R_LAM][lane], st.sy[0][R_VY][lane], st.ys[hf][0], st.ys[hf][1]);
-      start(st.sy[1][R_LAM][lane], st.sy[1][R_VY][lane], st.ys[hf][2], st.ys[hf][3]);
-    }
-    if (lost && valid) *P.flag = 1;
-  }
-  __syncthreads();
   if (quad_su(q) > 0)
-    update_quadrant<S, 1, kShak>(P, st, sk, vnode, q, lane, sv, j, g, G, valid, ghost_lane,
-                                 fin, fout, o);
+    pair_quadrant<S, 1, kShak>(P, st, sk, lane, sv, jb, store0, g, G, valid, ghost_lane, fin,
+                               fout, i);
   else
-    update_quadrant<S, -1, kShak>(P, st, sk, vnode, q, lane, sv, j, g, G, valid, ghost_lane,
-                                  fin, fout, o);
+    pair_quadrant<S, -1, kShak>(P, st, sk, lane, sv, jb, store0, g, G, valid, ghost_lane, fin,
+                                fout, i);
 }
 
+// Two workgroups per CU: the LDS stage (73 KB) and the registers of two rows allow two.
 template <typename S>
-__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(2)))
 void update_kernel(PlanView pv) {
-  extern __shared__ double vnode[];  // the v nodes of the largest instance of the plan
-  update_body<S, false>(pv, vnode);
+  update_body<S, false>(pv);
 }
 
-// The Shakhov variant carries two more cubics per u node and still fits three waves per SIMD.
 template <typename S>
-__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(2)))
 void update_kernel_shakhov(PlanView pv) {
-  extern __shared__ double vnode[];
-  update_body<S, true>(pv, vnode);
+  update_body<S, true>(pv);
 }
 
 }  // namespace
@@ -1522,6 +1641,22 @@ int velocity_chunks(int nx, int ny, int K, int NC) {
   if (G > half) G = half;
   if (G > 16) G = 16;
   return G < 1 ? 1 : (int)G;
+}
+
+// Update workgroups that run at once: two per CU.
+constexpr long long kUpdateSlots = 256 * 2;
+
+// Velocity chunks per quadrant of the update kernel for `base` workgroups per chunk (all
+// instances of a launch): the fewest chunks whose workgroups fill every round of the slots
+// that they start to at least 85%, and at least one full round; at most 16.  The update
+// kernel adds nothing across chunks, so its chunks do not change any result.
+int update_chunks(long long base) {
+  for (int U = 1; U <= 16; ++U) {
+    const long long n = base * U;
+    const long long rounds = (n + kUpdateSlots - 1) / kUpdateSlots;
+    if (n >= kUpdateSlots && n * 100 >= 85 * rounds * kUpdateSlots) return U;
+  }
+  return 16;
 }
 
 size_t plan_bytes(int n) {
@@ -1541,7 +1676,17 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   // each instance keeps the velocity chunks it was created with, in any plan, so that its
   // sums are added in the same order whether it is stepped alone or in a batch
   Inst* img = reinterpret_cast<Inst*>(h);
-  for (int q = 0; q < n; ++q) img[q].gsplit = insts[q].P.gmax;
+  long long upd_base = 0;  // update workgroups of all instances with one chunk
+  for (int q = 0; q < n; ++q) {
+    const KParams& P = insts[q].P;
+    upd_base += (long long)((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * P.NC;
+  }
+  const int U = update_chunks(upd_base);
+  for (int q = 0; q < n; ++q) {
+    img[q].gsplit = insts[q].P.gmax;
+    const int half = insts[q].P.K / 2;  // nodes of the smaller half of the u axis
+    img[q].usplit = U < half ? U : (half < 1 ? 1 : half);
+  }
   for (int q = 0; q < n; ++q) {
     const KParams& P = insts[q].P;
     const int G = img[q].gsplit * P.NC;  // chunks of G, then those of H
@@ -1555,8 +1700,7 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
     if (G > 1) t.red += (int)(((long long)P.nslot * P.nx * P.ny + 255) / 256);
     t.shak = t.shak || P.shak;
     t.sums += ((P.nx + kTileS - 1) / kTileS) * P.ny * G;
-    t.upd += ((P.nx + kTileU - 1) / kTileU) * P.ny * G;
-    t.max_m = P.M > t.max_m ? P.M : t.max_m;
+    t.upd += ((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * img[q].usplit * P.NC;
     t.face += (nf + 255) / 256;
     if (P.bc == UGKS_BC_CHANNEL) {
       t.ghost += 2 * P.ny;
@@ -1624,17 +1768,16 @@ hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int p
       faces_kernel<<<(unsigned)t.face, 256, 0, s>>>(pv);
       break;
     default: {
-      const size_t lds = 8 * (size_t)t.max_m;
       if (t.shak) {
         if (fp32)
-          update_kernel_shakhov<float><<<(unsigned)t.upd, kWave * kQuads, lds, s>>>(pv);
+          update_kernel_shakhov<float><<<(unsigned)t.upd, kWave * kQuads, 0, s>>>(pv);
         else
-          update_kernel_shakhov<double><<<(unsigned)t.upd, kWave * kQuads, lds, s>>>(pv);
+          update_kernel_shakhov<double><<<(unsigned)t.upd, kWave * kQuads, 0, s>>>(pv);
       } else {
         if (fp32)
-          update_kernel<float><<<(unsigned)t.upd, kWave * kQuads, lds, s>>>(pv);
+          update_kernel<float><<<(unsigned)t.upd, kWave * kQuads, 0, s>>>(pv);
         else
-          update_kernel<double><<<(unsigned)t.upd, kWave * kQuads, lds, s>>>(pv);
+          update_kernel<double><<<(unsigned)t.upd, kWave * kQuads, 0, s>>>(pv);
       }
     }
   }
