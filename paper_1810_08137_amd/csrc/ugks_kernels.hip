@@ -131,6 +131,12 @@ __device__ __forceinline__ double dpp_shift(double x, int ctrl_lower) {
 }
 __device__ __forceinline__ double from_lower(double x) { return dpp_shift(x, 1); }
 __device__ __forceinline__ double from_upper(double x) { return dpp_shift(x, 0); }
+__device__ __forceinline__ float from_lower(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_upper(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x130, 0xf, 0xf, true));
+}
 
 // ------------------------------------------------------------------ pointwise physics
 // Reciprocal: the hardware estimate (relative error below 5e-8 on gfx950) refined by one
@@ -156,6 +162,21 @@ __device__ __forceinline__ double half_limited(double p, double q, bool keep) {
   const double r = pq * recip(p + q);
   return (pq > 0.0 && keep) ? r : 0.0;
 }
+// FP32 forms (the FP32-storage update): the hardware reciprocal is accurate to 1 ulp.
+__device__ __forceinline__ float half_limited(float p, float q) {
+  const float pq = p * q;
+  const float r = pq * __builtin_amdgcn_rcpf(p + q);
+  return pq > 0.0f ? r : 0.0f;
+}
+__device__ __forceinline__ float half_limited(float p, float q, bool keep) {
+  const float pq = p * q;
+  const float r = pq * __builtin_amdgcn_rcpf(p + q);
+  return (pq > 0.0f && keep) ? r : 0.0f;
+}
+__device__ __forceinline__ float exp_of(float x) { return expf(x); }
+__device__ __forceinline__ double exp_of(double x) { return exp(x); }
+__device__ __forceinline__ float expm1_of(float x) { return expm1f(x); }
+__device__ __forceinline__ double expm1_of(double x) { return expm1(x); }
 
 
 struct Prim {
@@ -590,7 +611,7 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     double F0 = 0, F1 = 0, F2 = 0, F3 = 0, X0 = 0, X1 = 0, X2 = 0, X3 = 0;
     double Y0 = 0, Y1 = 0, Y2 = 0, Y3 = 0, Y4 = 0;
     struct Vals {
-      double c, s, n;
+      S c, s, n;  // in the storage type
     };
     // planes and weight rows are walked with running pointers: one add per node each
     const long long pstep = (long long)hv.step * P.PS;
@@ -599,18 +620,20 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     const int wstep = 5 * hv.step;
     auto load_at = [&](const UGKS_GLOBAL S* p) {
       const __amdgpu_buffer_rsrc_t r = plane_rsrc(p, P);
-      return Vals{bload<S>(r, oc), bload<S>(r, oS), bload<S>(r, oN)};
+      return Vals{bload_raw(r, oc, S{}), bload_raw(r, oS, S{}), bload_raw(r, oN, S{})};
     };
     auto node = [&](const Vals& x) {
       // w_m v_m^n, n = 0..4, with the weight 1/2 of a node at v = 0 (visited by both halves)
       const double w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3], w4 = wp[4];
-      const double fW = from_lower(x.c), fE = from_upper(x.c);
+      // slopes in the storage type (FP32 storage: FP32 slopes), sums in FP64
+      const S fW = from_lower(x.c), fE = from_upper(x.c);
       const double hx = half_limited(fE - x.c, x.c - fW);
-      const double hy = my * half_limited(x.n - x.c, x.c - x.s);
-      F0 = fma(x.c, w0, F0);
-      F1 = fma(x.c, w1, F1);
-      F2 = fma(x.c, w2, F2);
-      F3 = fma(x.c, w3, F3);
+      const double hy = my * (double)half_limited(x.n - x.c, x.c - x.s);
+      const double fc = x.c;
+      F0 = fma(fc, w0, F0);
+      F1 = fma(fc, w1, F1);
+      F2 = fma(fc, w2, F2);
+      F3 = fma(fc, w3, F3);
       X0 = fma(hx, w0, X0);
       X1 = fma(hx, w1, X1);
       X2 = fma(hx, w2, X2);
@@ -1067,6 +1090,11 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
 // flux.  Per velocity the wavefront loads five row segments of the plane (the pair, the two
 // rows upwind of it, the row downwind of it) instead of four per row.
 //
+// Arithmetic: with f stored in FP64 every step is FP64.  With f stored in FP32 the
+// per-velocity work (slopes, reconstruction, face fluxes, Eq. (3)) runs in FP32 on FP32
+// copies of the face records and cell constants; Eq. (4), the interface scalars and the
+// velocity moments stay FP64.
+//
 // Rows: the pairs are (0, 1), (2, 3), ...; with ny odd the last pair is (ny - 2, ny - 1), of
 // which only row ny - 1 is written (row ny - 2 belongs to the pair before), and with ny = 1
 // the only pair is (-1, 0), of which only row 0 is written.  A row outside the mesh reads
@@ -1078,21 +1106,23 @@ constexpr int kSF = R_M5 - R_GC;
 __host__ __device__ constexpr int sf(int R) { return R < R_VY ? R - R_GC : R - R_GC - 1; }
 // Per-cell state of Eq. (3) (CellField) for the two rows.
 enum CellField { C_LAMN, C_UN, C_VN, C_LAM1, C_U1, C_V1, C_AN, C_A1, C_AF, C_ADF, C_COUNT };
+template <typename T>
 struct PairStage {
-  double sx[kPair][kSF][kWave + 1];  // x face i0 - 2 + f of row jb + r (left face of lane f)
-  double sy[kPair + 1][kSF][kWave];  // y face row jb + r (bottom face of row jb + r), lane l
-  double cell[kPair][C_COUNT][kWave];
+  T sx[kPair][kSF][kWave + 1];  // x face i0 - 2 + f of row jb + r (left face of lane f)
+  T sy[kPair + 1][kSF][kWave];  // y face row jb + r (bottom face of row jb + r), lane l
+  T cell[kPair][C_COUNT][kWave];
   // Gauss starts (value, ratio) at the first node of v half h (0: v > 0, 1: v < 0)
-  double xs[2][kPair][2][kWave + 1];   // x faces
-  double ys[2][kPair + 1][2][kWave];   // y faces
-  double gs[2][kPair][2][2][kWave];    // g^n (0) and g^{n+1} (1) of each cell
+  T xs[2][kPair][2][kWave + 1];   // x faces
+  T ys[2][kPair + 1][2][kWave];   // y faces
+  T gs[2][kPair][2][2][kWave];    // g^n (0) and g^{n+1} (1) of each cell
 };
 
 // A Gaussian factor exp(-lam (x - c)^2) along the uniform nodes x0, x0 + h, x0 + 2h, ...:
 // e is its value at the current node and r the ratio to the next one; successive ratios
 // differ by the factor exp(-2 lam h^2), applied as r + r (exp(-2 lam h^2) - 1) with the
 // second factor from expm1, so that it adds one rounding per node and no drift.
-__device__ __forceinline__ void gauss_next(double& e, double& r, double qm1) {
+template <typename T>
+__device__ __forceinline__ void gauss_next(T& e, T& r, T qm1) {
   e *= r;
   r = fma(r, qm1, r);
 }
@@ -1100,31 +1130,38 @@ __device__ __forceinline__ void gauss_next(double& e, double& r, double qm1) {
 // Cubic of the folded equilibrium polynomial P(un, ut) of a record (interface scalars) in
 // one velocity with the other fixed.  The e1, e4, e5, e7 of the side the particles come from
 // are passed in (pos: un > 0).
+template <typename T>
 struct Cubic {
-  double c0, c1, c2, c3;
+  T c0, c1, c2, c3;
 };
 // P as a cubic in the tangential velocity at fixed normal velocity un.
-__device__ __forceinline__ Cubic cubic_in_ut(const double* e, double un) {
-  Cubic c;
-  c.c0 = fma(un, fma(un, fma(un, 0.5 * e[7], e[4] + 0.5 * e[3]), e[1]), e[0]);
-  c.c1 = fma(un, fma(un, 0.5 * e[8], e[5]), e[2]);
-  c.c2 = fma(un, 0.5 * e[7], e[6] + 0.5 * e[3]);
-  c.c3 = 0.5 * e[8];
+template <typename T>
+__device__ __forceinline__ Cubic<T> cubic_in_ut(const T* e, T un) {
+  const T h = T(0.5);
+  Cubic<T> c;
+  c.c0 = fma(un, fma(un, fma(un, h * e[7], e[4] + h * e[3]), e[1]), e[0]);
+  c.c1 = fma(un, fma(un, h * e[8], e[5]), e[2]);
+  c.c2 = fma(un, h * e[7], e[6] + h * e[3]);
+  c.c3 = h * e[8];
   return c;
 }
 // P as a cubic in the normal velocity at fixed tangential velocity ut.
-__device__ __forceinline__ Cubic cubic_in_un(const double* e, double ut) {
-  Cubic c;
-  c.c0 = fma(ut, fma(ut, fma(ut, 0.5 * e[8], 0.5 * e[3] + e[6]), e[2]), e[0]);
-  c.c1 = fma(ut, fma(ut, 0.5 * e[7], e[5]), e[1]);
-  c.c2 = fma(ut, 0.5 * e[8], 0.5 * e[3] + e[4]);
-  c.c3 = 0.5 * e[7];
+template <typename T>
+__device__ __forceinline__ Cubic<T> cubic_in_un(const T* e, T ut) {
+  const T h = T(0.5);
+  Cubic<T> c;
+  c.c0 = fma(ut, fma(ut, fma(ut, h * e[8], h * e[3] + e[6]), e[2]), e[0]);
+  c.c1 = fma(ut, fma(ut, h * e[7], e[5]), e[1]);
+  c.c2 = fma(ut, h * e[8], h * e[3] + e[4]);
+  c.c3 = h * e[7];
   return c;
 }
-__device__ __forceinline__ double horner(const Cubic& c, double x) {
+template <typename T>
+__device__ __forceinline__ T horner(const Cubic<T>& c, T x) {
   return fma(x, fma(x, fma(x, c.c3, c.c2), c.c1), c.c0);
 }
-__device__ __forceinline__ Cubic scaled(Cubic c, double s) {
+template <typename T>
+__device__ __forceinline__ Cubic<T> scaled(Cubic<T> c, T s) {
   c.c0 *= s;
   c.c1 *= s;
   c.c2 *= s;
@@ -1132,8 +1169,8 @@ __device__ __forceinline__ Cubic scaled(Cubic c, double s) {
   return c;
 }
 // e0..e8 of a staged record for particles with normal velocity of sign s
-template <int N>
-__device__ __forceinline__ void load_e(const double (*st)[N], int col, int s, double* e) {
+template <typename T, int N>
+__device__ __forceinline__ void load_e(const T (*st)[N], int col, int s, T* e) {
 #pragma unroll
   for (int n = 0; n < 9; ++n) e[n] = st[sf(R_E + n)][col];
   if (s < 0) {
@@ -1146,13 +1183,13 @@ __device__ __forceinline__ void load_e(const double (*st)[N], int col, int s, do
 
 // Shakhov: S of one cell at fixed u as a cubic in v.  kqx, kqy = (1 - Pr)(lambda^2/rho) q;
 // S = (A + B v)(a2 v^2 + a1 v + a0) with A + B v = k (c . q), a2 v^2 + a1 v + a0 = 2 lambda |c|^2 - 4.
-__device__ __forceinline__ Cubic shakhov_in_v(double u, double kqx, double kqy, double lam,
-                                              double U, double V) {
-  const double du = u - U;
-  const double A = fma(du, kqx, -V * kqy), B = kqy;
-  const double a2 = 2.0 * lam, a1 = -4.0 * lam * V;
-  const double a0 = fma(2.0 * lam, fma(du, du, V * V), -4.0);
-  Cubic c;
+template <typename T>
+__device__ __forceinline__ Cubic<T> shakhov_in_v(T u, T kqx, T kqy, T lam, T U, T V) {
+  const T du = u - U;
+  const T A = fma(du, kqx, -V * kqy), B = kqy;
+  const T a2 = T(2) * lam, a1 = T(-4) * lam * V;
+  const T a0 = fma(T(2) * lam, fma(du, du, V * V), T(-4));
+  Cubic<T> c;
   c.c0 = A * a0;
   c.c1 = fma(A, a1, B * a0);
   c.c2 = fma(A, a2, B * a1);
@@ -1176,30 +1213,32 @@ __device__ __forceinline__ int face_role(const KParams& P, int F, int sv) {
 
 // The equilibrium part of a y face at tangential velocity u as a cubic in v, and its free
 // transport weights, for particles of v sign sv, by the face's role.
-__device__ __forceinline__ void y_face(const PairStage& st, int fr, int lane, int sv, int role,
-                                       double u, Cubic& c, double& m4, double& m5) {
-  const double(*r)[kWave] = st.sy[fr];
-  const double d = u - r[sf(R_UX)][lane];
-  const double Et = r[sf(R_GC)][lane] * exp(-r[sf(R_LAM)][lane] * d * d);
+template <typename T>
+__device__ __forceinline__ void y_face(const PairStage<T>& st, int fr, int lane, int sv, int role,
+                                       T u, Cubic<T>& c, T& m4, T& m5) {
+  const T(*r)[kWave] = st.sy[fr];
+  const T d = u - r[sf(R_UX)][lane];
+  const T Et = r[sf(R_GC)][lane] * exp_of(-r[sf(R_LAM)][lane] * d * d);
   if (role == F_EMIT) {
-    c = Cubic{Et, 0.0, 0.0, 0.0};
-    m4 = m5 = 0.0;
+    c = Cubic<T>{Et, T(0), T(0), T(0)};
+    m4 = m5 = T(0);
     return;
   }
   m4 = r[sf(R_M4)][lane];
   if (role == F_ABSORB) {
-    c = Cubic{0.0, 0.0, 0.0, 0.0};
-    m5 = 0.0;
+    c = Cubic<T>{T(0), T(0), T(0), T(0)};
+    m5 = T(0);
     return;
   }
-  double e[9];
+  T e[9];
   load_e(r, lane, sv, e);
   c = scaled(cubic_in_un(e, u), Et);
   m5 = r[sf(R_M5)][lane];
 }
 
 // Per velocity quadrant (SU = sign of u, sv = sign of v) of a row pair: Eq. (3) for every
-// velocity of the quadrant's chunk of u nodes.  Per velocity and row a lane (cell i) forms
+// velocity of the quadrant's chunk of u nodes, in the arithmetic type S of the storage.  Per
+// velocity and row a lane (cell i) forms
 //   its upwind reconstruction and slope term at its outgoing x and y faces,
 //   the flux through its outgoing x face, which the downwind lane takes over as its incoming
 //   x flux (x faces of the segment are each evaluated once),
@@ -1212,13 +1251,13 @@ __device__ __forceinline__ void y_face(const PairStage& st, int fr, int lane, in
 // kAhead: nodes whose loads are in flight ahead of the node computed.  The 400 x 100 x 40^2
 // channel measured 2 (FP64) and 3 (FP32 storage) 2-3% faster than 1; the Shakhov variant
 // has no registers to spare beyond 1.
-template <typename S, int SU, bool kShak,
-          int kAhead = kShak ? 1 : (sizeof(S) == 8 ? 2 : 3)>
-__device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage& st,
-                                              const double (*sk)[4][kWave], int lane, int sv,
+template <typename S, int SU, bool kShak, int kAhead = kShak ? 1 : (sizeof(S) == 8 ? 2 : 3)>
+__device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<S>& st,
+                                              const S (*sk)[4][kWave], int lane, int sv,
                                               int jb, bool store0, int g, int G, bool valid,
                                               bool ghost_lane, const UGKS_GLOBAL S* fin,
                                               UGKS_GLOBAL S* fout, int i) {
+  typedef S T;  // arithmetic type of the per-velocity work
   const bool chan = P.bc == UGKS_BC_CHANNEL;
   const int r0 = sv > 0 ? 0 : 1, r1 = 1 - r0;     // rows of the pair, upwind first
   const int j0 = jb + r0, j1 = jb + r1;           // their mesh rows
@@ -1243,31 +1282,31 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage&
   const unsigned oE = (unsigned)(o0 + 2 * L) * bs;
   const unsigned w0 = st0 ? oC : kDropOffset, w1 = st1 ? oD : kDropOffset;
   const int xo = lane + (SU > 0 ? 1 : 0);  // staged x face the lane's particles leave by
-  const double Af0 = st.cell[r0][C_AF][lane], AdF0 = st.cell[r0][C_ADF][lane];
-  const double Af1 = st.cell[r1][C_AF][lane], AdF1 = st.cell[r1][C_ADF][lane];
+  const T Af0 = st.cell[r0][C_AF][lane], AdF0 = st.cell[r0][C_ADF][lane];
+  const T Af1 = st.cell[r1][C_AF][lane], AdF1 = st.cell[r1][C_ADF][lane];
   const Half hu = axis_half(P.K, SU, false), hv = axis_half(P.M, sv, false);
   const int hf = sv > 0 ? 0 : 1;
-  const double hstep = sv * P.dv;
-  const double h2 = -2.0 * hstep * hstep;
-  const double qx0 = expm1(h2 * st.sx[r0][sf(R_LAM)][xo]);
-  const double qx1 = expm1(h2 * st.sx[r1][sf(R_LAM)][xo]);
-  const double qyi = expm1(h2 * st.sy[fin_r][sf(R_LAM)][lane]);
-  const double qym = expm1(h2 * st.sy[fmid_r][sf(R_LAM)][lane]);
-  const double qyo = expm1(h2 * st.sy[fout_r][sf(R_LAM)][lane]);
-  const double qn0 = expm1(h2 * st.cell[r0][C_LAMN][lane]);
-  const double q10 = expm1(h2 * st.cell[r0][C_LAM1][lane]);
-  const double qn1 = expm1(h2 * st.cell[r1][C_LAMN][lane]);
-  const double q11 = expm1(h2 * st.cell[r1][C_LAM1][lane]);
-  const double two_idx = 2.0 * P.inv_dx, two_idy = 2.0 * P.inv_dy;
+  const T hstep = T(sv * P.dv);
+  const T h2 = T(-2) * hstep * hstep;
+  const T qx0 = expm1_of(h2 * st.sx[r0][sf(R_LAM)][xo]);
+  const T qx1 = expm1_of(h2 * st.sx[r1][sf(R_LAM)][xo]);
+  const T qyi = expm1_of(h2 * st.sy[fin_r][sf(R_LAM)][lane]);
+  const T qym = expm1_of(h2 * st.sy[fmid_r][sf(R_LAM)][lane]);
+  const T qyo = expm1_of(h2 * st.sy[fout_r][sf(R_LAM)][lane]);
+  const T qn0 = expm1_of(h2 * st.cell[r0][C_LAMN][lane]);
+  const T q10 = expm1_of(h2 * st.cell[r0][C_LAM1][lane]);
+  const T qn1 = expm1_of(h2 * st.cell[r1][C_LAMN][lane]);
+  const T q11 = expm1_of(h2 * st.cell[r1][C_LAM1][lane]);
+  const T two_idx = T(2.0 * P.inv_dx), two_idy = T(2.0 * P.inv_dy);
   int a0, a1;
   chunk_range(hu.count, g, G, a0, a1);
   for (int a = a0; a < a1; ++a) {
     const int k = hu.first + a * hu.step;
-    const double u = P.uk[k];
-    const double au = fabs(u);
-    const double ucx = u * two_idx;
+    const T u = T(P.uk[k]);
+    const T au = fabs(u);
+    const T ucx = u * two_idx;
     struct Vals {
-      S A, B, C, D, E;  // rows j0 - 2 sv, j0 - sv, j0, j1, j1 + sv, in the storage type
+      S A, B, C, D, E;  // rows j0 - 2 sv, j0 - sv, j0, j1, j1 + sv
     };
     // planes (read and written) and v nodes are walked with running pointers
     const long long pstep = (long long)hv.step * P.PS;
@@ -1290,31 +1329,31 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage&
 #pragma unroll
     for (int d = 0; d < kAhead; ++d) ring[d] = load_next();
     // x faces of both rows: cubic in v times GC En(u), with |u| folded in
-    Cubic cx0, cx1;
-    double m4x0, m5x0, m4x1, m5x1;
+    Cubic<T> cx0, cx1;
+    T m4x0, m5x0, m4x1, m5x1;
     {
-      double e[9];
-      const double(*x0)[kWave + 1] = st.sx[r0];
+      T e[9];
+      const T(*x0)[kWave + 1] = st.sx[r0];
       load_e(x0, xo, SU, e);
-      const double d = u - x0[sf(R_UX)][xo];
-      cx0 = scaled(cubic_in_ut(e, u), x0[sf(R_GC)][xo] * exp(-x0[sf(R_LAM)][xo] * d * d) * au);
+      const T d = u - x0[sf(R_UX)][xo];
+      cx0 = scaled(cubic_in_ut(e, u), x0[sf(R_GC)][xo] * exp_of(-x0[sf(R_LAM)][xo] * d * d) * au);
       m4x0 = x0[sf(R_M4)][xo] * au;
       m5x0 = x0[sf(R_M5)][xo] * au;
     }
     __builtin_amdgcn_sched_barrier(0);
     {
-      double e[9];
-      const double(*x1)[kWave + 1] = st.sx[r1];
+      T e[9];
+      const T(*x1)[kWave + 1] = st.sx[r1];
       load_e(x1, xo, SU, e);
-      const double d = u - x1[sf(R_UX)][xo];
-      cx1 = scaled(cubic_in_ut(e, u), x1[sf(R_GC)][xo] * exp(-x1[sf(R_LAM)][xo] * d * d) * au);
+      const T d = u - x1[sf(R_UX)][xo];
+      cx1 = scaled(cubic_in_ut(e, u), x1[sf(R_GC)][xo] * exp_of(-x1[sf(R_LAM)][xo] * d * d) * au);
       m4x1 = x1[sf(R_M4)][xo] * au;
       m5x1 = x1[sf(R_M5)][xo] * au;
     }
     __builtin_amdgcn_sched_barrier(0);
     // y faces: cubic in v at tangential u, times GC Et(u)
-    Cubic ci, cm, co;
-    double m4i, m5i, m4m, m5m, m4o, m5o;
+    Cubic<T> ci, cm, co;
+    T m4i, m5i, m4m, m5m, m4o, m5o;
     y_face(st, fin_r, lane, sv, role_in, u, ci, m4i, m5i);
     __builtin_amdgcn_sched_barrier(0);
     y_face(st, fmid_r, lane, sv, role_mid, u, cm, m4m, m5m);
@@ -1323,29 +1362,29 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage&
     __builtin_amdgcn_sched_barrier(0);
     // g^n and g^{n+1} of both cells: u factors (with the Eq. (3) weights) times the v
     // Gaussians' start values
-    double en0, rn0, e10, r10, en1, rn1, e11, r11;
+    T en0, rn0, e10, r10, en1, rn1, e11, r11;
     {
-      const double(*c0)[kWave] = st.cell[r0];
-      const double dn = u - c0[C_UN][lane], d1 = u - c0[C_U1][lane];
-      en0 = c0[C_AN][lane] * exp(-c0[C_LAMN][lane] * dn * dn) * st.gs[hf][r0][0][0][lane];
-      e10 = c0[C_A1][lane] * exp(-c0[C_LAM1][lane] * d1 * d1) * st.gs[hf][r0][1][0][lane];
+      const T(*c0)[kWave] = st.cell[r0];
+      const T dn = u - c0[C_UN][lane], d1 = u - c0[C_U1][lane];
+      en0 = c0[C_AN][lane] * exp_of(-c0[C_LAMN][lane] * dn * dn) * st.gs[hf][r0][0][0][lane];
+      e10 = c0[C_A1][lane] * exp_of(-c0[C_LAM1][lane] * d1 * d1) * st.gs[hf][r0][1][0][lane];
       rn0 = st.gs[hf][r0][0][1][lane];
       r10 = st.gs[hf][r0][1][1][lane];
     }
     __builtin_amdgcn_sched_barrier(0);
     {
-      const double(*c1)[kWave] = st.cell[r1];
-      const double dn = u - c1[C_UN][lane], d1 = u - c1[C_U1][lane];
-      en1 = c1[C_AN][lane] * exp(-c1[C_LAMN][lane] * dn * dn) * st.gs[hf][r1][0][0][lane];
-      e11 = c1[C_A1][lane] * exp(-c1[C_LAM1][lane] * d1 * d1) * st.gs[hf][r1][1][0][lane];
+      const T(*c1)[kWave] = st.cell[r1];
+      const T dn = u - c1[C_UN][lane], d1 = u - c1[C_U1][lane];
+      en1 = c1[C_AN][lane] * exp_of(-c1[C_LAMN][lane] * dn * dn) * st.gs[hf][r1][0][0][lane];
+      e11 = c1[C_A1][lane] * exp_of(-c1[C_LAM1][lane] * d1 * d1) * st.gs[hf][r1][1][0][lane];
       rn1 = st.gs[hf][r1][0][1][lane];
       r11 = st.gs[hf][r1][1][1][lane];
     }
     // Shakhov: the factors (1 + S) of g^n and g^{n+1} of both cells as cubics in v
-    Cubic sn0{}, s10{}, sn1{}, s11{};
+    Cubic<T> sn0{}, s10{}, sn1{}, s11{};
     if constexpr (kShak) {
-      const double(*c0)[kWave] = st.cell[r0];
-      const double(*c1)[kWave] = st.cell[r1];
+      const T(*c0)[kWave] = st.cell[r0];
+      const T(*c1)[kWave] = st.cell[r1];
       sn0 = shakhov_in_v(u, sk[r0][0][lane], sk[r0][1][lane], c0[C_LAMN][lane], c0[C_UN][lane],
                          c0[C_VN][lane]);
       s10 = shakhov_in_v(u, sk[r0][2][lane], sk[r0][3][lane], c0[C_LAM1][lane], c0[C_U1][lane],
@@ -1357,58 +1396,55 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage&
     }
     __builtin_amdgcn_sched_barrier(0);
     // v-direction Gaussians of the faces at the first node of the half, and their ratios
-    double ex0 = st.xs[hf][r0][0][xo], rx0 = st.xs[hf][r0][1][xo];
-    double ex1 = st.xs[hf][r1][0][xo], rx1 = st.xs[hf][r1][1][xo];
-    double ei = st.ys[hf][fin_r][0][lane], ri = st.ys[hf][fin_r][1][lane];
-    double em = st.ys[hf][fmid_r][0][lane], rm = st.ys[hf][fmid_r][1][lane];
-    double eo = st.ys[hf][fout_r][0][lane], ro = st.ys[hf][fout_r][1][lane];
-    double vv = *vp;
-    auto node = [&](const Vals& raw) {
-      const struct {
-        double A, B, C, D, E;
-      } x{(double)raw.A, (double)raw.B, (double)raw.C, (double)raw.D, (double)raw.E};
-      const double vnext = vp[hv.step];  // the next node (read one ahead; past the end a pad)
-      const double av = fabs(vv);
-      const double avcy = av * two_idy;
+    T ex0 = st.xs[hf][r0][0][xo], rx0 = st.xs[hf][r0][1][xo];
+    T ex1 = st.xs[hf][r1][0][xo], rx1 = st.xs[hf][r1][1][xo];
+    T ei = st.ys[hf][fin_r][0][lane], ri = st.ys[hf][fin_r][1][lane];
+    T em = st.ys[hf][fmid_r][0][lane], rm = st.ys[hf][fmid_r][1][lane];
+    T eo = st.ys[hf][fout_r][0][lane], ro = st.ys[hf][fout_r][1][lane];
+    T vv = T(*vp);
+    auto node = [&](const Vals& x) {
+      const T vnext = T(vp[hv.step]);  // the next node (read one ahead; past the end a pad)
+      const T av = fabs(vv);
+      const T avcy = av * two_idy;
       // upwind neighbour of row j0: half-cell changes towards the pair (y) and in x
-      const double fBw = from_lower(x.B), fBe = from_upper(x.B);
-      const double HxB = half_limited(fBe - x.B, x.B - fBw);
-      const double HyB = half_limited(x.C - x.B, x.B - x.A, mB);
-      const double DB = fma(ucx, HxB, avcy * HyB);
-      const double fhB = x.B + HyB;
+      const T fBw = from_lower(x.B), fBe = from_upper(x.B);
+      const T HxB = half_limited(fBe - x.B, x.B - fBw);
+      const T HyB = half_limited(x.C - x.B, x.B - x.A, mB);
+      const T DB = fma(ucx, HxB, avcy * HyB);
+      const T fhB = x.B + HyB;
       // row j0
-      const double fCw = from_lower(x.C), fCe = from_upper(x.C);
-      const double HxC = half_limited(fCe - x.C, x.C - fCw, gm);
-      const double HyC = half_limited(x.D - x.C, x.C - x.B, m0);
-      const double DC = fma(ucx, HxC, avcy * HyC);
-      const double fxC = SU > 0 ? x.C + HxC : x.C - HxC;
-      const double fhC = x.C + HyC;
+      const T fCw = from_lower(x.C), fCe = from_upper(x.C);
+      const T HxC = half_limited(fCe - x.C, x.C - fCw, gm);
+      const T HyC = half_limited(x.D - x.C, x.C - x.B, m0);
+      const T DC = fma(ucx, HxC, avcy * HyC);
+      const T fxC = SU > 0 ? x.C + HxC : x.C - HxC;
+      const T fhC = x.C + HyC;
       // row j1
-      const double fDw = from_lower(x.D), fDe = from_upper(x.D);
-      const double HxD = half_limited(fDe - x.D, x.D - fDw, gm);
-      const double HyD = half_limited(x.E - x.D, x.D - x.C, m1);
-      const double DD = fma(ucx, HxD, avcy * HyD);
-      const double fxD = SU > 0 ? x.D + HxD : x.D - HxD;
-      const double fhD = x.D + HyD;
+      const T fDw = from_lower(x.D), fDe = from_upper(x.D);
+      const T HxD = half_limited(fDe - x.D, x.D - fDw, gm);
+      const T HyD = half_limited(x.E - x.D, x.D - x.C, m1);
+      const T DD = fma(ucx, HxD, avcy * HyD);
+      const T fxD = SU > 0 ? x.D + HxD : x.D - HxD;
+      const T fhD = x.D + HyD;
       // x faces: outgoing of this lane, incoming from the upwind lane
-      const double Fxo0 = fma(ex0, horner(cx0, vv), fma(m4x0, fxC, -m5x0 * DC));
-      const double Fxo1 = fma(ex1, horner(cx1, vv), fma(m4x1, fxD, -m5x1 * DD));
-      const double Fxi0 = SU > 0 ? from_lower(Fxo0) : from_upper(Fxo0);
-      const double Fxi1 = SU > 0 ? from_lower(Fxo1) : from_upper(Fxo1);
+      const T Fxo0 = fma(ex0, horner(cx0, vv), fma(m4x0, fxC, -m5x0 * DC));
+      const T Fxo1 = fma(ex1, horner(cx1, vv), fma(m4x1, fxD, -m5x1 * DD));
+      const T Fxi0 = SU > 0 ? from_lower(Fxo0) : from_upper(Fxo0);
+      const T Fxi1 = SU > 0 ? from_lower(Fxo1) : from_upper(Fxo1);
       // y faces: into row j0, between the rows, out of row j1
-      const double Fyi = av * fma(ei, horner(ci, vv), fma(m4i, fhB, -m5i * DB));
-      const double Fym = av * fma(em, horner(cm, vv), fma(m4m, fhC, -m5m * DC));
-      const double Fyo = av * fma(eo, horner(co, vv), fma(m4o, fhD, -m5o * DD));
-      double g0, g1;
+      const T Fyi = av * fma(ei, horner(ci, vv), fma(m4i, fhB, -m5i * DB));
+      const T Fym = av * fma(em, horner(cm, vv), fma(m4m, fhC, -m5m * DC));
+      const T Fyo = av * fma(eo, horner(co, vv), fma(m4o, fhD, -m5o * DD));
+      T g0, g1;
       if constexpr (kShak) {
-        g0 = fma(e10, 1.0 + horner(s10, vv), en0 * (1.0 + horner(sn0, vv)));
-        g1 = fma(e11, 1.0 + horner(s11, vv), en1 * (1.0 + horner(sn1, vv)));
+        g0 = fma(e10, T(1) + horner(s10, vv), en0 * (T(1) + horner(sn0, vv)));
+        g1 = fma(e11, T(1) + horner(s11, vv), en1 * (T(1) + horner(sn1, vv)));
       } else {
-        g0 = fma(e10, 1.0, en0);
-        g1 = fma(e11, 1.0, en1);
+        g0 = e10 + en0;
+        g1 = e11 + en1;
       }
-      const double f0 = fma(Af0, x.C, fma(AdF0, (Fxi0 - Fxo0) + (Fyi - Fym), g0));
-      const double f1 = fma(Af1, x.D, fma(AdF1, (Fxi1 - Fxo1) + (Fym - Fyo), g1));
+      const T f0 = fma(Af0, x.C, fma(AdF0, (Fxi0 - Fxo0) + (Fyi - Fym), g0));
+      const T f1 = fma(Af1, x.D, fma(AdF1, (Fxi1 - Fxo1) + (Fym - Fyo), g1));
       // lanes and rows without a cell to write store past the plane's range (dropped)
       const __amdgpu_buffer_rsrc_t wr = plane_rsrc(wcur, P);
       bstore(wr, w0, f0, S{});
@@ -1448,10 +1484,11 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage&
 // The body of the update kernel; kShak: the Shakhov collision model.
 template <typename S, bool kShak>
 __device__ __forceinline__ void update_body(const PlanView& pv) {
-  __shared__ PairStage st;
+  typedef S T;  // arithmetic type of the per-velocity work (and of the LDS stage)
+  __shared__ PairStage<T> st;
   // Shakhov: (1 - Pr)(lambda^2/rho) q of each lane's cell at t^n and t^{n+1}, per row
-  __shared__ double sk_raw[kShak ? kPair * 4 * kWave : 1];
-  double(*sk)[4][kWave] = reinterpret_cast<double(*)[4][kWave]>(sk_raw);
+  __shared__ T sk_raw[kShak ? kPair * 4 * kWave : 1];
+  T(*sk)[4][kWave] = reinterpret_cast<T(*)[4][kWave]>(sk_raw);
   const int lane = threadIdx.x & (kWave - 1);
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -1491,7 +1528,7 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     const int fld = s <= sf(R_UX) ? R_GC + s : R_GC + s + 1;  // skip R_VY
     const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
     const int row = clampi(jb + r, 0, P.ny - 1);
-    st.sx[r][s][fc] = recx[((size_t)row * (P.nx + 1) + fi) * kRec + fld];
+    st.sx[r][s][fc] = T(recx[((size_t)row * (P.nx + 1) + fi) * kRec + fld]);
   }
   for (int e = threadIdx.x; e < (kPair + 1) * kWave * kSF; e += blockDim.x) {
     const int r = e / (kWave * kSF), rem = e - r * (kWave * kSF);
@@ -1499,7 +1536,7 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     const int fld = s <= sf(R_UX) ? R_GC + s : R_GC + s + 1;  // skip R_VY
     const int fi = clampi(i0 - kHalo + fc, 0, P.nx - 1);
     const int row = clampi(jb + r, 0, P.ny);
-    st.sy[r][s][fc] = recy[((size_t)row * P.nx + fi) * kRec + fld];
+    st.sy[r][s][fc] = T(recy[((size_t)row * P.nx + fi) * kRec + fld]);
   }
   __syncthreads();
   const double hstep = P.dv;
@@ -1507,13 +1544,14 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   // the half: such a state (speed ratio |V| lambda^(1/2) above about 26 across v) is flagged.
   bool lost = false;
   // Gauss start of exp(-lam (v - c)^2) at the first node of half h and its ratio to the next
-  auto start = [&](double lam, double c, int h, double* e, double* r, int col) {
+  // (FP64, stored in the stage's type)
+  auto start = [&](double lam, double c, int h, T* e, T* r, int col) {
     const double v0 = P.vm[h == 0 ? P.M / 2 : P.M / 2 - 1];
     const double hs = h == 0 ? hstep : -hstep;
     const double d = v0 - c;
     const double x = lam * d * d;
-    e[col] = exp(-x);
-    r[col] = exp(-lam * hs * (2.0 * d + hs));
+    e[col] = T(exp(-x));
+    r[col] = T(exp(-lam * hs * (2.0 * d + hs)));
     lost = lost || (x > 700.0 && (h == 0 ? c > v0 : c < v0));
   };
   if (q < kPair) {
@@ -1570,14 +1608,14 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       heat_flux(m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[3] + m[5], pn.U, pn.V, qn);
       const double kn = P.collisionless ? 0.0 : P.pr_c * pn.lam * pn.lam / pn.rho;
       const double k1 = P.collisionless ? 0.0 : P.pr_c * p1.lam * p1.lam / p1.rho;
-      sk[r][0][lane] = kn * qn[0];
-      sk[r][1][lane] = kn * qn[1];
-      sk[r][2][lane] = k1 * qn[0];
-      sk[r][3][lane] = k1 * qn[1];
+      sk[r][0][lane] = T(kn * qn[0]);
+      sk[r][1][lane] = T(kn * qn[1]);
+      sk[r][2][lane] = T(k1 * qn[0]);
+      sk[r][3][lane] = T(k1 * qn[1]);
     }
     const double cell[C_COUNT] = {pn.lam, pn.U, pn.V, p1.lam, p1.U, p1.V, An, A1, Af, AdF};
 #pragma unroll
-    for (int n = 0; n < C_COUNT; ++n) st.cell[r][n][lane] = cell[n];
+    for (int n = 0; n < C_COUNT; ++n) st.cell[r][n][lane] = T(cell[n]);
     // Gauss starts of g^n and g^{n+1} of this cell in both halves of v
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -1586,21 +1624,21 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     }
   } else {
     // Gauss starts of the faces: wavefront 2 takes the x faces of row jb and the y face row
-    // jb, wavefront 3 those of row jb + 1 and the y face rows jb + 1, jb + 2
+    // jb, wavefront 3 those of row jb + 1 and the y face rows jb + 1, jb + 2 (FP64 records)
     const int r = q - kPair;
     const int jr = clampi(jb + r, 0, P.ny - 1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       for (int fc = lane; fc < kWave + 1; fc += kWave) {
         const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
-        const double vy = recx[((size_t)jr * (P.nx + 1) + fi) * kRec + R_VY];
-        start(st.sx[r][sf(R_LAM)][fc], vy, h, st.xs[h][r][0], st.xs[h][r][1], fc);
+        const UGKS_GLOBAL double* rec = recx + ((size_t)jr * (P.nx + 1) + fi) * kRec;
+        start(rec[R_LAM], rec[R_VY], h, st.xs[h][r][0], st.xs[h][r][1], fc);
       }
       for (int fr = r == 0 ? 0 : 1; fr < (r == 0 ? 1 : kPair + 1); ++fr) {
         const int fi = clampi(i0 - kHalo + lane, 0, P.nx - 1);
         const int row = clampi(jb + fr, 0, P.ny);
-        const double vy = recy[((size_t)row * P.nx + fi) * kRec + R_VY];
-        start(st.sy[fr][sf(R_LAM)][lane], vy, h, st.ys[h][fr][0], st.ys[h][fr][1], lane);
+        const UGKS_GLOBAL double* rec = recy + ((size_t)row * P.nx + fi) * kRec;
+        start(rec[R_LAM], rec[R_VY], h, st.ys[h][fr][0], st.ys[h][fr][1], lane);
       }
     }
   }
@@ -1615,9 +1653,13 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
                                 fout, i);
 }
 
-// Two workgroups per CU: the LDS stage (73 KB) and the registers of two rows allow two.
+// FP64: two workgroups per CU (the LDS stage takes 73 KB, the registers of two rows allow
+// two waves per SIMD).  FP32 storage: the stage takes 37 KB and the FP32 registers allow
+// four waves per SIMD.
+constexpr int kUpdateWaves64 = 2, kUpdateWaves32 = 4;
 template <typename S>
-__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(kWave* kQuads)
+__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? kUpdateWaves64 : kUpdateWaves32)))
 void update_kernel(PlanView pv) {
   update_body<S, false>(pv);
 }
@@ -1643,18 +1685,16 @@ int velocity_chunks(int nx, int ny, int K, int NC) {
   return G < 1 ? 1 : (int)G;
 }
 
-// Update workgroups that run at once: two per CU.
-constexpr long long kUpdateSlots = 256 * 2;
-
 // Velocity chunks per quadrant of the update kernel for `base` workgroups per chunk (all
-// instances of a launch): the fewest chunks whose workgroups fill every round of the slots
-// that they start to at least 85%, and at least one full round; at most 16.  The update
-// kernel adds nothing across chunks, so its chunks do not change any result.
-int update_chunks(long long base) {
+// instances of a launch) and `slots` workgroups that run at once: the fewest chunks whose
+// workgroups fill every round of the slots that they start to at least 85%, and at least one
+// full round; at most 16.  The update kernel adds nothing across chunks, so its chunks do not
+// change any result.
+int update_chunks(long long base, long long slots) {
   for (int U = 1; U <= 16; ++U) {
     const long long n = base * U;
-    const long long rounds = (n + kUpdateSlots - 1) / kUpdateSlots;
-    if (n >= kUpdateSlots && n * 100 >= 85 * rounds * kUpdateSlots) return U;
+    const long long rounds = (n + slots - 1) / slots;
+    if (n >= slots && n * 100 >= 85 * rounds * slots) return U;
   }
   return 16;
 }
@@ -1681,7 +1721,10 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
     const KParams& P = insts[q].P;
     upd_base += (long long)((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * P.NC;
   }
-  const int U = update_chunks(upd_base);
+  // update workgroups per CU at once: FP64 two, FP32 storage four (Shakhov two)
+  const bool shak = n > 0 && insts[0].P.shak;
+  const int per_cu = (n > 0 && insts[0].fp32 && !shak) ? kUpdateWaves32 : kUpdateWaves64;
+  const int U = update_chunks(upd_base, 256LL * per_cu);
   for (int q = 0; q < n; ++q) {
     img[q].gsplit = insts[q].P.gmax;
     const int half = insts[q].P.K / 2;  // nodes of the smaller half of the u axis
