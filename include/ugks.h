@@ -115,7 +115,14 @@ typedef struct {
                     S = (1 - Pr)(lambda^2/rho)(c . q)(2 lambda |c|^2 - 4), c = u - U and q the
                     heat flux; at an interface S comes from the reconstructed f and is held
                     over the step, in a cell from f^n for both time levels of Eq. (3).
-                    Requires internal_dof = 0; other values give UGKS_E_INVAL. */
+                    Requires internal_dof = 0; other values give UGKS_E_INVAL.
+   adaptive_dt      0: every step takes dt (above).  1: each step takes
+                    dt^n = cfl / max over cells of [(umax + |U|)/dx + (vmax + |V|)/dy] from
+                    the state W^n it starts from (a global max-reduction on the device): the
+                    fixed step at rest, smaller where the gas moves.  The paper fixes no time
+                    step; this bounds the Courant number of the fastest discrete velocity plus
+                    the local flow speed.  Needs dt_override = 0.  ugks_get_time reports the
+                    simulated time and the next step. */
 typedef struct {
   int precision;
   int velocity_chunks;
@@ -127,6 +134,7 @@ typedef struct {
   void* workspace;
   size_t workspace_bytes;
   double prandtl;
+  int adaptive_dt;
 } ugks_opts;
 
 typedef struct {
@@ -196,6 +204,11 @@ const char* ugks_last_error(const ugks_handle* h);
 
 /* Shape, step and memory of a handle. */
 int ugks_get_info(const ugks_handle* h, ugks_info* out);
+
+/* Simulated time (the sum of the steps taken, each the dt of Eq. (2)-(4) it integrated over)
+   and the dt the next step takes (fixed, or the adaptive step of the current state).  Waits
+   for the stream. */
+int ugks_get_time(ugks_handle* h, double* time, double* dt_next);
 
 /* Checkpoint / test hooks.  The state of the method is the distribution f of every cell and
    discrete velocity (Sec. 2, the f of Eq. (3)) together with the conservative variables W

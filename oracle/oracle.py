@@ -34,6 +34,7 @@ class RefCase(ctypes.Structure):
         ("dt_override", ctypes.c_double),
         ("dof", ctypes.c_int),
         ("prandtl", ctypes.c_double),
+        ("adaptive_dt", ctypes.c_int),
     ]
 
 
@@ -56,6 +57,11 @@ def lib():
         L.ugks_ref_get_micro_flux.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.ugks_ref_dt.restype = ctypes.c_double
         L.ugks_ref_dt.argtypes = [ctypes.c_void_p]
+        L.ugks_ref_time.restype = ctypes.c_double
+        L.ugks_ref_time.argtypes = [ctypes.c_void_p]
+        L.ugks_ref_adaptive_dt.restype = ctypes.c_double
+        L.ugks_ref_adaptive_dt.argtypes = [_dp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.ugks_ref_tau_ref.restype = ctypes.c_double
         L.ugks_ref_tau_ref.argtypes = [ctypes.c_void_p]
         L.ugks_ref_destroy.argtypes = [ctypes.c_void_p]
@@ -185,6 +191,12 @@ def shakhov(prim, q, prandtl, u, v):
     return float(lib().ugks_ref_shakhov(_ptr(p), _ptr(qq), float(prandtl), float(u), float(v)))
 
 
+def adaptive_dt(W, cfl, umax, vmax, dx, dy):
+    """The adaptive step of a state W[..., 4] (see ugks_ref_adaptive_dt)."""
+    w = np.ascontiguousarray(np.asarray(W, dtype=np.float64).reshape(-1, 4))
+    return float(lib().ugks_ref_adaptive_dt(_ptr(w), w.shape[0], cfl, umax, vmax, dx, dy))
+
+
 def set_threads(n):
     lib().ugks_ref_set_threads(int(n))
 
@@ -202,7 +214,7 @@ def mu_ref_of_kn(kn):
 CASE_DEFAULTS = dict(lx=1.0, ly=1.0, umax=5.0, vmax=5.0, kn=0.1, bc=1, inlet_fixed_u=0,
                      p_ratio=2.0, T_in=1.0, T_wall=1.0, U_in=0.0, U_noise=0.0, cfl=0.8,
                      rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, dof=0,
-                     prandtl=1.0)
+                     prandtl=1.0, adaptive_dt=0)
 
 
 class Oracle:
@@ -236,6 +248,10 @@ class Oracle:
     @property
     def dt(self):
         return float(lib().ugks_ref_dt(self._h))
+
+    @property
+    def time(self):
+        return float(lib().ugks_ref_time(self._h))
 
     @property
     def tau_ref(self):

@@ -36,7 +36,8 @@ struct ugks_ref {
   int K, M, NV;
   int NC, NF;                   /* reduced functions per velocity (1, or 2 with dof > 0); NC*NV */
   double pr;                    /* Prandtl number of the collision model (1: BGK) */
-  double dx, dy, dt, mu_ref;
+  double dx, dy, dt, mu_ref;     /* dt: the step the next ugks_ref_step takes */
+  double time;                  /* simulated time: the sum of the steps taken */
   int collisionless;
   double *uk, *vm, *wk, *wm;    /* 1D nodes and trapezoid weights */
   double *fu, *fv, *fw;         /* the same per velocity k*M + m: u_k, v_m, w_k w_m */
@@ -418,6 +419,7 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
   if (!(c->prandtl > 0.0) || c->prandtl > 1.0) return NULL;
   if (c->prandtl != 1.0 && c->dof != 0) return NULL;  /* Shakhov: gas without internal dof */
   if (c->bc == 1 && (!(c->p_ratio > 0) || !(c->T_in > 0) || !(c->T_wall > 0))) return NULL;
+  if (c->adaptive_dt != 0 && (c->adaptive_dt != 1 || c->dt_override > 0)) return NULL;
   ugks_ref* s = (ugks_ref*)calloc(1, sizeof(ugks_ref));
   s->c = *c;
   s->K = c->nu;
@@ -485,7 +487,27 @@ ugks_ref* ugks_ref_create(const ugks_ref_case* c) {
         }
     }
   }
+  if (c->adaptive_dt) s->dt = ugks_ref_adaptive_dt(s->W, (int)nc, c->cfl, c->umax, c->vmax,
+                                                   s->dx, s->dy);
   return s;
+}
+
+/* Reading (the paper fixes no time step): the adaptive step bounds the Courant number of the
+   fastest discrete velocity on each axis plus the local flow speed of the cell, so that the
+   grid of discrete velocities, centred on zero, still covers the flow's equilibrium; the
+   largest such rate over all cells (a global max-reduction over the state at the start of
+   the step) sets dt.  At rest it equals the fixed CFL step. */
+double ugks_ref_adaptive_dt(const double* W, int ncell, double cfl, double umax, double vmax,
+                            double dx, double dy) {
+  double rmax = 0.0;
+  for (int c = 0; c < ncell; ++c) {
+    const double rho = W[4 * c];
+    if (!(rho > 0.0)) return 0.0;
+    const double U = W[4 * c + 1] / rho, V = W[4 * c + 2] / rho;
+    const double r = (umax + fabs(U)) / dx + (vmax + fabs(V)) / dy;
+    if (r > rmax) rmax = r;
+  }
+  return cfl / rmax;
 }
 
 void ugks_ref_destroy(ugks_ref* s) {
@@ -499,6 +521,7 @@ void ugks_ref_destroy(ugks_ref* s) {
 }
 
 double ugks_ref_dt(const ugks_ref* s) { return s->dt; }
+double ugks_ref_time(const ugks_ref* s) { return s->time; }
 double ugks_ref_tau_ref(const ugks_ref* s) {
   double p[4] = {1.0, 0.0, 0.0, 1.0};
   return s->collisionless ? INFINITY : collision_time(s->mu_ref, p);
@@ -528,6 +551,8 @@ void ugks_ref_set_state(ugks_ref* s, const double* f, const double* W) {
   size_t nc = (size_t)s->c.nx * s->c.ny;
   if (f) memcpy(s->f, f, sizeof(double) * nc * s->NF);
   if (W) memcpy(s->W, W, sizeof(double) * nc * 4);
+  if (W && s->c.adaptive_dt)
+    s->dt = ugks_ref_adaptive_dt(s->W, (int)nc, s->c.cfl, s->c.umax, s->c.vmax, s->dx, s->dy);
 }
 void ugks_ref_get_face_flux(const ugks_ref* s, double* Fx, double* Fy) {
   if (Fx) memcpy(Fx, s->Fx, sizeof(double) * (size_t)(s->c.nx + 1) * s->c.ny * 4);
@@ -868,6 +893,10 @@ int ugks_ref_step(ugks_ref* s, int n) {
       double p[4];
       if (ugks_ref_prim(s->W + 4 * c, p, s->c.dof)) return -4;
     }
+    s->time += s->dt;
+    /* adaptive step: the next step's dt from the state it starts from */
+    if (s->c.adaptive_dt)
+      s->dt = ugks_ref_adaptive_dt(s->W, (int)nc, s->c.cfl, s->c.umax, s->c.vmax, s->dx, s->dy);
   }
   return 0;
 }

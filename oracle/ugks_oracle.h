@@ -55,6 +55,9 @@ typedef struct {
   int dof;                 /* internal degrees of freedom, 0..16 (0: the paper's gas) */
   double prandtl;          /* collision model: 1 BGK (the paper's), < 1 Shakhov with this
                               Prandtl number (dof = 0 only) */
+  int adaptive_dt;         /* 0: fixed step; 1: each step's dt from the state at its start,
+                              dt = cfl / max_cells[(umax + |U|)/dx + (vmax + |V|)/dy]
+                              (needs dt_override = 0) */
 } ugks_ref_case;
 
 typedef struct ugks_ref ugks_ref;
@@ -68,7 +71,12 @@ void ugks_ref_get_face_flux(const ugks_ref* s, double* Fx, double* Fy);
 void ugks_ref_get_ghost(const ugks_ref* s, double* Wg, double* fg);  /* [2][ny][4], [2][ny][NF] */
 /* per-velocity face fluxes of the last step: [ny][nx+1][NF] and [ny+1][nx][NF] */
 void ugks_ref_get_micro_flux(const ugks_ref* s, double* Ffx, double* Ffy);
-double ugks_ref_dt(const ugks_ref* s);
+double ugks_ref_dt(const ugks_ref* s);    /* the step the next ugks_ref_step takes */
+double ugks_ref_time(const ugks_ref* s);  /* simulated time: the sum of the steps taken */
+/* the adaptive step of a state W (ncell cells): cfl / max over cells of
+   (umax + |U|)/dx + (vmax + |V|)/dy; 0 if a cell has rho <= 0 */
+double ugks_ref_adaptive_dt(const double* W, int ncell, double cfl, double umax, double vmax,
+                            double dx, double dy);
 double ugks_ref_tau_ref(const ugks_ref* s);
 void ugks_ref_destroy(ugks_ref* s);
 void ugks_ref_set_threads(int n);

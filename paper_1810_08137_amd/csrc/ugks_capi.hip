@@ -278,7 +278,7 @@ Layout layout_of(const Shape& s, int prec, int chunks, bool shak) {
       (size_t)(s.K + 6 * s.M) * 8,              // wk, wm, vmom
       (size_t)s.K * 8,                          // uk
       (size_t)(s.M + 2) * 8,                    // vm, padded with a zero on each side
-      (size_t)s.ny * 8 + 64,                    // xi_in + flag
+      (size_t)s.ny * 8 + 128,                   // xi_in, flag, rmax[2], tsum
       plan_bytes(1),                            // one-instance launch plan
       plan_bytes(1),                            // the same on the static scratch
   };
@@ -309,6 +309,8 @@ void carve(ugks_handle* h, const Layout& L, const Shape& s) {
   B.vm = reinterpret_cast<double*>(base + L.off[11]);
   B.xi_in = reinterpret_cast<double*>(base + L.off[12]);
   B.flag = reinterpret_cast<int*>(base + L.off[12] + round_up((size_t)s.ny * 8, 64));
+  B.rmax = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(B.flag) + 64);
+  B.tsum = reinterpret_cast<double*>(reinterpret_cast<char*>(B.flag) + 80);
   h->plan_dev = base + L.off[13];
   h->plan_static = base + L.off[14];
 }
@@ -396,6 +398,8 @@ bool problem_ok(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     why = "need rho0 > 0, T0 > 0, |noise| < 1";
   else if (!(opts->dt_override > 0) && !(opts->cfl > 0 && std::isfinite(opts->cfl)))
     why = "need cfl > 0 or dt_override > 0";
+  else if (opts->adaptive_dt != 0 && (opts->adaptive_dt != 1 || opts->dt_override > 0))
+    why = "adaptive_dt must be 0 or 1, and 1 needs dt_override = 0";
   if (!why.empty()) return false;
   return collision_of(opts, s, shak, why);
 }
@@ -454,6 +458,10 @@ void fill_constants(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, c
   P.kap_w = (double)s.dof / (2.0 * P.lam_w);
   P.U_in = bc->U_in;
   P.U_noise = bc->U_noise;
+  P.adaptive = opts->adaptive_dt ? 1 : 0;
+  P.cfl = opts->cfl;
+  P.umax = vgrid->umax;
+  P.vmax = vgrid->vmax;
 
   const double* uk = T.uk;
   const double* wk = T.wk;
@@ -496,6 +504,20 @@ void fill_constants(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, c
   }
 }
 
+// The adaptive step's rate of a host state W (nx*ny cells): the largest
+// (umax + |U|)/dx + (vmax + |V|)/dy over the cells, as the bits the kernels keep.
+unsigned long long rate_bits(const KParams& P, const double* W, size_t nc) {
+  double r = 0.0;
+  for (size_t c = 0; c < nc; ++c) {
+    const double rho = W[4 * c], U = W[4 * c + 1] / rho, V = W[4 * c + 2] / rho;
+    const double x = (P.umax + std::fabs(U)) / P.dx + (P.vmax + std::fabs(V)) / P.dy;
+    if (x > r) r = x;
+  }
+  unsigned long long b;
+  std::memcpy(&b, &r, sizeof b);
+  return b;
+}
+
 // Point the constants at the device tables of a set of buffers.
 void bind_tables(KParams& P, const Buffers& B, const Shape& s) {
   P.wk = gp(B.wk);
@@ -505,6 +527,8 @@ void bind_tables(KParams& P, const Buffers& B, const Shape& s) {
   P.vm = gp(B.vm + 1);
   P.xi_in = gp(B.xi_in);
   P.flag = gp(B.flag);
+  P.rmax = gp(B.rmax);
+  P.tsum = gp(B.tsum);
 }
 
 // One solver as the kernels see it; f[0] and W[0] hold the state when its step counter is 0.
@@ -656,10 +680,13 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     }
   }
 
-  Copy copies[9];
+  Copy copies[10];
   int nt = table_copies(B, T, s, copies);
   copies[nt++] = {B.xi_in, xi.data(), xi.size() * 8};
   copies[nt++] = {B.W[0], W0.data(), W0.size() * 8};
+  // rmax[0] of the initial state (adaptive step), rmax[1] and the simulated time zero
+  const unsigned long long rmax_tsum[3] = {rate_bits(P, W0.data(), s.nc), 0ull, 0ull};
+  copies[nt++] = {B.rmax, rmax_tsum, sizeof rmax_tsum};
   copies[nt++] = {h->plan_dev, plan_host.data(), plan_host.size()};
   if (h->static_ok) copies[nt++] = {h->plan_static, plan_static_host.data(), plan_static_host.size()};
   int rc = UGKS_OK;
@@ -808,6 +835,22 @@ int ugks_get_info(const ugks_handle* h, ugks_info* out) {
   return UGKS_OK;
 }
 
+int ugks_get_time(ugks_handle* h, double* time, double* dt_next) {
+  if (!h || !time || !dt_next) return UGKS_E_INVAL;
+  Busy b(h);
+  if (!b.ok) return fail(h, UGKS_E_BUSY, "handle in use%s");
+  if (h->poisoned) return poisoned_fail(h);
+  unsigned long long rt[3];
+  hipError_t e = hipMemcpyAsync(rt, h->B.rmax, sizeof rt, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reading the time");
+  std::memcpy(time, &rt[2], sizeof(double));
+  double r;
+  std::memcpy(&r, &rt[h->steps & 1], sizeof r);
+  *dt_next = h->P.adaptive ? h->P.cfl / r : h->P.dt;
+  return UGKS_OK;
+}
+
 int ugks_get_state(ugks_handle* h, double* f, double* W) {
   if (!h) return UGKS_E_INVAL;
   Busy b(h);
@@ -870,6 +913,11 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
   }
   if (e == hipSuccess && W)
     e = hipMemcpyAsync(h->B.W[h->steps & 1], W, nc * 4 * 8, hipMemcpyHostToDevice, h->stream);
+  // the adaptive step of the next step follows the new W
+  const unsigned long long rb = W ? rate_bits(h->P, W, nc) : 0ull;
+  if (e == hipSuccess && W)
+    e = hipMemcpyAsync(h->B.rmax + (h->steps & 1), &rb, sizeof rb, hipMemcpyHostToDevice,
+                       h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "writing the state");
   return UGKS_OK;

@@ -90,6 +90,13 @@ struct KParams {
   const UGKS_GLOBAL double* vmom;  // [M][5] w_m v_m^n (n = 0..4), halved at v_m = 0
   const UGKS_GLOBAL double* xi_in;  // [ny] inlet noise
   UGKS_GLOBAL int* flag;           // device flag: set to 1 on an invalid state
+  // adaptive step: dt^n = cfl / rmax[n & 1], rmax the largest (umax + |U|)/dx + (vmax + |V|)/dy
+  // over the cells of W^n, kept as the bits of a non-negative double (ordered like the
+  // integers, so an integer atomic max is the max of the doubles)
+  int adaptive;
+  double cfl, umax, vmax;
+  UGKS_GLOBAL unsigned long long* rmax;  // [2]
+  UGKS_GLOBAL double* tsum;              // simulated time: the sum of the steps taken
 };
 
 // Device buffers carved out of one workspace.
@@ -107,6 +114,8 @@ struct Buffers {
   double* vm;       // [M + 2]: zero, the M nodes, zero
   double* xi_in;    // [ny]
   int* flag;
+  unsigned long long* rmax;  // [2] (adaptive step)
+  double* tsum;              // simulated time
 };
 
 struct Layout {

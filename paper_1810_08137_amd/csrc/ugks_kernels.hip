@@ -80,12 +80,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const UGKS_GLOBAL S
   return __builtin_amdgcn_make_buffer_rsrc((void*)plane, (short)0, __builtin_bit_cast(int, bytes),
                                            0x00020000);
 }
-__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
-}
-__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off, float) {
-  return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
-}
 // Stores through the same resources; an offset past the plane's range is dropped by the
 // hardware range check, so lanes without a cell to write need no branch.
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, double x, double) {
@@ -95,11 +89,7 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, d
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, double x, float) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)x), r, off, 0, 0);
 }
-template <typename S>
-__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned off) {
-  return bload(r, off, S{});
-}
-// The same, left in the storage type (converted where it is used)
+// Loads through the same resources, in the storage type (converted where they are used).
 __device__ __forceinline__ double bload_raw(__amdgpu_buffer_rsrc_t r, unsigned off, double) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
@@ -294,6 +284,13 @@ __device__ __forceinline__ void time_weights(double dt, double tau, double* Mt) 
   Mt[2] = 0.5 * dt * dt - tau * Mt[0];
 }
 
+// The step of the launch's step (parity = the f/W buffer it reads): fixed, or with the
+// adaptive step cfl / rmax of the state W^n it starts from.
+__device__ __forceinline__ double step_dt(const KParams& P, int parity) {
+  if (!P.adaptive) return P.dt;
+  return P.cfl / __longlong_as_double((long long)P.rmax[parity]);
+}
+
 // ------------------------------------------------------------------ addressing
 __device__ __forceinline__ int wrap(int i, int n) { return ((i % n) + n) % n; }
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
@@ -309,6 +306,11 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int h = 32; h >= 1; h >>= 1) x += __shfl_xor(x, h, kWave);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int h = 32; h >= 1; h >>= 1) x = fmax(x, __shfl_xor(x, h, kWave));
   return x;
 }
 
@@ -447,6 +449,8 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
   UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
   const int local = b - first_block(pv.off_ghost, ii);
   const int lane = threadIdx.x & (kWave - 1), tid = threadIdx.x;
+  // the update kernel of this step takes the max rate of W^{n+1} into the other slot
+  if (local == 0 && tid == 0) P.rmax[((I->cur + pv.step) & 1) ^ 1] = 0ull;
   if (P.bc != UGKS_BC_CHANNEL) {
     const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
     const long long e = (long long)local * kGhostThreads + tid;
@@ -834,7 +838,7 @@ __device__ __forceinline__ void fold_shakhov(UGKS_GLOBAL double* rec, const Prim
 }
 
 template <bool kXi>
-__device__ void interface_scalars(const KParams& P, const double* S, const double* WL,
+__device__ void interface_scalars(const KParams& P, double dt, const double* S, const double* WL,
                                   const double* WR, double dn, double len, double* F,
                                   UGKS_GLOBAL double* rec, UGKS_GLOBAL double* recH,
                                   double& U0, double& V0, double T3 = 0.0) {
@@ -843,7 +847,7 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
   const double* Q1 = S + 8;
   const double* Q2 = S + 12;
   if (P.collisionless) {
-    const double Mt4 = P.dt, Mt5 = 0.5 * P.dt * P.dt;
+    const double Mt4 = dt, Mt5 = 0.5 * dt * dt;
 #pragma unroll
     for (int q = 0; q < 4; ++q) F[q] = len * (Mt4 * Q1[q] - Mt5 * Q2[q]);
 #pragma unroll
@@ -869,7 +873,7 @@ __device__ void interface_scalars(const KParams& P, const double* S, const doubl
   }
   const double tau0 = collision_time(p0, P.mu_ref);
   double Mt[5];
-  time_weights(P.dt, tau0, Mt);
+  time_weights(dt, tau0, Mt);
   double swL[4], swR[4], aL[4], aR[4], b[4], A[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -958,6 +962,7 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   const UGKS_GLOBAL double* hs = I->hs;
   const UGKS_GLOBAL double* hsg = I->hsg;
   const UGKS_GLOBAL double* W = I->W[(I->cur + pv.step) & 1];
+  const double dt = step_dt(P, (I->cur + pv.step) & 1);
   const UGKS_GLOBAL double* Wg = I->Wg;
   UGKS_GLOBAL double* recx = I->recx;
   UGKS_GLOBAL double* recy = I->recy;
@@ -1007,9 +1012,9 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
     UGKS_GLOBAL double* rec = recx + (size_t)e * kRec;
     UGKS_GLOBAL double* recH = rec + (size_t)nfx * kRec;
     if (P.NC > 1)
-      interface_scalars<true>(P, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0);
+      interface_scalars<true>(P, dt, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0);
     else
-      interface_scalars<false>(P, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0, T3);
+      interface_scalars<false>(P, dt, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0, T3);
     for (int c = 0; c < P.NC; ++c) {
       UGKS_GLOBAL double* r = c ? recH : rec;
 #pragma unroll
@@ -1033,7 +1038,7 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
     const double den = top ? P.wall_den_top : P.wall_den_bot;
     const double* Gw = top ? P.wall_G_top : P.wall_G_bot;
     const double rho_w = -Q1[0] / den;
-    const double s = P.dx * P.dt;
+    const double s = P.dx * dt;
     double Fl[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) Fl[q] = s * (Q1[q] + rho_w * Gw[q]);
@@ -1067,9 +1072,9 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   const double wl[4] = {W[4 * cl], W[4 * cl + 2], W[4 * cl + 1], W[4 * cl + 3]};
   const double wr[4] = {W[4 * cr], W[4 * cr + 2], W[4 * cr + 1], W[4 * cr + 3]};
   if (P.NC > 1)
-    interface_scalars<true>(P, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0);
+    interface_scalars<true>(P, dt, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0);
   else
-    interface_scalars<false>(P, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0, T3);
+    interface_scalars<false>(P, dt, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0, T3);
   for (int c = 0; c < P.NC; ++c) {
     UGKS_GLOBAL double* r = c ? recH : rec;
     r[R_FX + 0] = F[0];
@@ -1580,13 +1585,25 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) Wout[4 * cc + k] = W1[k];
     }
+    if (P.adaptive && gg == 0) {
+      // the adaptive step of the next step: the largest rate over the cells of W^{n+1}
+      double rate = 0.0;
+      if (mine)
+        rate = (P.umax + fabs(W1[1] / W1[0])) / P.dx + (P.vmax + fabs(W1[2] / W1[0])) / P.dy;
+      rate = wave_max(rate);
+      if (lane == 0)
+        atomicMax((unsigned long long*)(P.rmax + (parity ^ 1)),
+                  (unsigned long long)__double_as_longlong(rate));
+    }
+    // the simulated time advances by this step's dt (one thread of the instance)
+    if (b == first_block(pv.off_upd, ii) && q == 0 && lane == 0) *P.tsum += step_dt(P, parity);
     Prim pn{}, p1{};
     double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
     if (!P.collisionless) {
       const bool ok = prim_of(Wn, pn, P.lam_c) && prim_of(W1, p1, P.lam_c);
       if (!ok && mine) *P.flag = 1;
       const double tn = collision_time(pn, P.mu_ref), t1 = collision_time(p1, P.mu_ref);
-      const double hdt = 0.5 * P.dt;
+      const double hdt = 0.5 * step_dt(P, parity);
       const double den = 1.0 / (1.0 + hdt / t1);
       Af = (1.0 - hdt / tn) * den;
       AdF = den / P.area;

@@ -51,7 +51,7 @@ class ugks_opts(ctypes.Structure):
                 ("noise", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("dt_override", ctypes.c_double), ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("prandtl", ctypes.c_double)]
+                ("prandtl", ctypes.c_double), ("adaptive_dt", ctypes.c_int)]
 
 
 class ugks_info(ctypes.Structure):
@@ -79,6 +79,7 @@ SIGNATURES = {
     "ugks_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "ugks_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "ugks_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ugks_info)]),
+    "ugks_get_time": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
     "ugks_get_state": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
     "ugks_set_state": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
     "ugks_get_face_flux": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
@@ -174,6 +175,13 @@ def ugks_get_info(h):
     return info
 
 
+def ugks_get_time(h):
+    t = ctypes.c_double(0)
+    dt = ctypes.c_double(0)
+    _check(lib().ugks_get_time(h, ctypes.byref(t), ctypes.byref(dt)), h)
+    return float(t.value), float(dt.value)
+
+
 def values_per_cell(info):
     """f values per cell: nu*nv, twice that (G then H) with internal degrees of freedom."""
     return info.nu * info.nv * (2 if info.internal_dof > 0 else 1)
@@ -246,7 +254,7 @@ def ugks_batch_last_error(b):
 def make_structs(nx, ny, lx, ly, nu, nv, umax, vmax, bc="channel", p_ratio=2.0, T_in=1.0,
                  T_wall=1.0, inlet_fixed_u=0, U_in=0.0, U_noise=0.0, precision="fp64", cfl=0.8,
                  rho0=1.0, T0=1.0, noise=0.01, seed=1, dt_override=0.0, velocity_chunks=0,
-                 dof=0, prandtl=1.0, **_):
+                 dof=0, prandtl=1.0, adaptive_dt=0, **_):
     mesh = ugks_mesh(int(nx), int(ny), float(lx), float(ly))
     vgrid = ugks_vgrid(int(nu), int(nv), float(umax), float(vmax), int(dof))
     kind = {"periodic": UGKS_BC_PERIODIC, "channel": UGKS_BC_CHANNEL}[bc] if isinstance(bc, str) else int(bc)
@@ -254,7 +262,7 @@ def make_structs(nx, ny, lx, ly, nu, nv, umax, vmax, bc="channel", p_ratio=2.0, 
                 float(U_in), float(U_noise))
     prec = {"fp64": UGKS_FP64, "fp32_store": UGKS_FP32_STORE}[precision] if isinstance(precision, str) else int(precision)
     o = ugks_opts(prec, int(velocity_chunks), float(cfl), float(rho0), float(T0), float(noise),
-                  int(seed), float(dt_override), None, None, 0, float(prandtl))
+                  int(seed), float(dt_override), None, None, 0, float(prandtl), int(adaptive_dt))
     return mesh, vgrid, b, o
 
 
@@ -326,6 +334,10 @@ class Solver:
 
     def face_flux(self):
         return ugks_get_face_flux(self.h)
+
+    def time(self):
+        """(simulated time, dt of the next step)"""
+        return ugks_get_time(self.h)
 
     def kernel_timing(self, on=None):
         if on is not None:

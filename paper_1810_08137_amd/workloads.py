@@ -62,7 +62,7 @@ def oracle_kwargs(case):
     """Fields accepted by the oracle's case struct."""
     keys = ("nx", "ny", "lx", "ly", "nu", "nv", "umax", "vmax", "kn", "bc", "inlet_fixed_u",
             "p_ratio", "T_in", "T_wall", "U_in", "U_noise", "cfl", "rho0", "T0", "noise", "seed",
-            "dt_override", "dof", "prandtl")
+            "dt_override", "dof", "prandtl", "adaptive_dt")
     return {k: case[k] for k in keys if k in case}
 
 
