@@ -156,6 +156,10 @@ typedef struct {
 int ugks_required_bytes(const ugks_mesh* mesh, const ugks_vgrid* vgrid, const ugks_opts* opts,
                         size_t* out_bytes);
 
+/* Debug option: with the environment variable UGKS_DEBUG_POISON=1 at ugks_create, every cell
+   value of the f and W buffers that the first step writes starts as NaN (their halo is left as
+   it is), so a step that fails to write a value it later reads leaves a NaN in the state. */
+
 /* Create a solver and initialise its state on the device.  kn is the Knudsen number on the
    y extent of the domain (Sec. 3.A defines Kn on the channel width); kn = +INFINITY selects
    the collisionless limit (tau = inf).  The collision time is tau = mu/p with the hard-sphere

@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <memory>
@@ -711,6 +712,10 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     if (e == hipSuccess) e = hipMemsetAsync(B.f[1], 0, fbytes, h->stream);
     if (e == hipSuccess)
       e = launch_init(h->pv, I.fp32, (long long)s.nc * (long long)s.NV * s.NC, h->stream);
+    // debug option: every cell value of the buffers the first step writes starts as NaN
+    const char* poison = std::getenv("UGKS_DEBUG_POISON");
+    if (e == hipSuccess && poison && poison[0] == '1')
+      e = launch_poison(h->pv, I.fp32, (long long)s.nc * (long long)s.NV * s.NC, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) rc = hip_fail(nullptr, e, "initial state");
   }

@@ -174,6 +174,8 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
 
 // Launchers (ugks_kernels.hip).  All enqueue on `s` and return the launch error.
 hipError_t launch_init(const PlanView& pv, int fp32, long long nvalues, hipStream_t s);
+// Debug: NaN into every cell value of the f and W buffers the next step writes.
+hipError_t launch_poison(const PlanView& pv, int fp32, long long nvalues, hipStream_t s);
 hipError_t launch_step(const PlanView& pv, const PlanTotals& t, int fp32, hipStream_t s,
                        hipEvent_t* ev /* 8 events or NULL */);
 hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int phase,

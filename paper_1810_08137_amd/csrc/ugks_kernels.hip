@@ -433,6 +433,29 @@ __global__ __launch_bounds__(256) void init_kernel(PlanView pv) {
   stv(plane_of(f, P, p), pidx(P, i, j), g);
 }
 
+// Debug: quiet NaN in every cell value of the f and W buffers the next step writes (the
+// halo is left as it is: the kernels read it, where a wall or ghost switch discards it).  A
+// step that failed to write one of these values would leave a NaN in the state.
+template <typename S>
+__global__ __launch_bounds__(256) void poison_kernel(PlanView pv) {
+  const Inst* __restrict__ I = inst_at(pv, 0);
+  const KParams P = I->P;
+  const int nxt = (I->cur + pv.step + 1) & 1;
+  UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[nxt]);
+  UGKS_GLOBAL double* W = I->W[nxt];
+  const long long nc = (long long)P.nx * P.ny;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nc * P.NV * P.NC) return;
+  const int p = (int)(e / nc);
+  const int c = (int)(e - (long long)p * nc);
+  const int j = c / P.nx, i = c - j * P.nx;
+  plane_of(f, P, p)[pidx(P, i, j)] = static_cast<S>(__builtin_nan(""));
+  if (p == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) W[4 * (size_t)c + q] = __builtin_nan("");
+  }
+}
+
 // Halo of the current f.  Channel: one workgroup per (side, row) writes the inlet (side 0)
 // or outlet (side 1) ghost Maxwellian into that row's ghost column of every plane (H:
 // dof/(2 lambda) times it) and sums its moments towards the domain (its slopes are zero); the
@@ -1784,6 +1807,15 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   view->ninst = n;
   view->step = 0;
   return t;
+}
+
+hipError_t launch_poison(const PlanView& pv, int fp32, long long nvalues, hipStream_t s) {
+  const unsigned blocks = (unsigned)((nvalues + 255) / 256);
+  if (fp32)
+    poison_kernel<float><<<blocks, 256, 0, s>>>(pv);
+  else
+    poison_kernel<double><<<blocks, 256, 0, s>>>(pv);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const PlanView& pv, int fp32, long long nvalues, hipStream_t s) {
