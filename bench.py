@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--serving-steps", type=int, default=500)
     ap.add_argument("--serving-chunks", type=int, default=4,
                     help="cap on the velocity chunks of the serving solvers (0: automatic)")
+    ap.add_argument("--serving-quantum", type=int, default=10,
+                    help="steps per serving batch: an arrival joins at the next batch")
     ap.add_argument("--serving-rates", default="0.5,0.8,1.0",
                     help="Poisson arrival rates as fractions of the saturation rate")
     ap.add_argument("--paper-sweep", action="store_true",
@@ -289,6 +291,7 @@ def serving(args, fp64_rate):
 
     n, steps = args.serving_requests, args.serving_steps
     out = {"requests": n, "steps_per_request": steps, "precision": "fp32_store",
+           "steps_per_batch": args.serving_quantum,
            "velocity_chunks_cap": args.serving_chunks or "automatic",
            "meshes": SV.MESHES, "velocity_grids": SV.VGRIDS}
     ex = SV.GpuExecutor(max_slots=n, velocity_chunks=args.serving_chunks)
@@ -297,13 +300,13 @@ def serving(args, fp64_rate):
     out["admission"] = {"budget_bytes": budget, "free_bytes_at_start": free,
                         "total_bytes": total, "reserve_bytes": int(args.serving_reserve_gib * (1 << 30))}
     try:
-        burst = SV.Server(ex, budget_bytes=budget, max_slots=n, quantum=steps)
+        burst = SV.Server(ex, budget_bytes=budget, max_slots=n, quantum=args.serving_quantum)
         sat = burst.run(SV.serving_requests(n, float("inf"), seed=4, steps=steps))
         sat_rate = sat["done"] / sat["makespan_s"]
         print(f"serving: saturation {sat['updates_per_s']:.4g} updates/s", file=sys.stderr,
               flush=True)
         for frac in [float(x) for x in args.serving_rates.split(",") if x]:
-            srv = SV.Server(ex, budget_bytes=budget, max_slots=n, quantum=25)
+            srv = SV.Server(ex, budget_bytes=budget, max_slots=n, quantum=args.serving_quantum)
             st = srv.run(SV.serving_requests(n, frac * sat_rate, seed=4, steps=steps))
             runs.append({"rate_fraction": frac, "rate_per_s": frac * sat_rate, "done": st["done"],
                          "failed": st["failed"], "p50_latency_s": st["p50_latency_s"],

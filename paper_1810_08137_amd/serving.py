@@ -139,14 +139,20 @@ class GpuExecutor:
 
 
 class Server:
-    """Continuous batching with FIFO admission by memory footprint."""
+    """Continuous batching with FIFO admission by memory footprint.
 
-    def __init__(self, executor, budget_bytes, max_slots=256, quantum=50,
+    ``quantum`` caps the steps of one batch: a request that arrives while a batch runs joins
+    the next one.  ``admit_per_round`` caps the solvers created between two batches, so that a
+    burst of arrivals is created while the first of them already run (creation overlaps the
+    device work instead of delaying it)."""
+
+    def __init__(self, executor, budget_bytes, max_slots=256, quantum=50, admit_per_round=16,
                  clock=time.perf_counter, sleep=time.sleep):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.max_slots = int(max_slots)
         self.quantum = int(quantum)
+        self.admit_per_round = max(1, int(admit_per_round))
         self.clock = clock
         self.sleep = sleep
         self.batches = 0
@@ -173,7 +179,8 @@ class Server:
             nonlocal used
             while pending and pending[0].arrival <= now():
                 queue.append(pending.pop(0))
-            while queue and len(active) < self.max_slots:
+            created = 0
+            while queue and len(active) < self.max_slots and created < self.admit_per_round:
                 r = queue[0]
                 need = self.ex.footprint(r)
                 if need > self.budget:
@@ -189,6 +196,7 @@ class Server:
                     r.status, r.error = "failed", str(e)
                     continue
                 used += need
+                created += 1
                 r.status, r.admitted = "running", now()
                 active.append([r, s, 0, need])
             self.max_resident = max(self.max_resident, len(active))

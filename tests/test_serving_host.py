@@ -157,3 +157,27 @@ def test_request_generator_shape_and_seed():
         assert r.case["nu"] in SV.VGRIDS and r.case["nu"] == r.case["nv"]
         assert 0.01 <= r.case["kn"] <= 1.0 and 1.5 <= r.case["p_ratio"] <= 3.0
         assert r.steps == 500 and r.precision == "fp32_store"
+
+
+def test_a_burst_is_created_in_rounds_while_the_first_requests_run():
+    """With admit_per_round = 3, a burst of 10 arrivals is created three at a time between
+    batches: the first batch runs with three members, later ones with more, every request
+    still gets exactly its steps, and admission stays in arrival order."""
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    sizes = []
+    step = ex.step
+
+    def counting_step(solvers, n):
+        sizes.append(len(solvers))
+        step(solvers, n)
+
+    ex.step = counting_step
+    reqs = small_requests(10, rate=float("inf"))
+    srv = SV.Server(ex, budget_bytes=10**9, max_slots=10, quantum=2, admit_per_round=3,
+                    clock=clock, sleep=clock.sleep)
+    stats = srv.run(reqs)
+    assert stats["done"] == 10
+    assert sizes[0] == 3 and max(sizes) > 3
+    assert ex.order == sorted(ex.order)
+    assert all(ex.steps_done[r.rid] == r.steps for r in reqs)
