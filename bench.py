@@ -26,11 +26,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "4c9a42ef8fd9e32207ecb5e9be6a34decdeadbcabe93a9a33304b50a9151221d",
-    "fp64": 1.4796e9,
-    "fp32_store": 0.7268e9,
+    "source_sha256": "fb28af6f68aafd568060465c00c29f550ea449847713a60daecac93fd274167a",
+    "fp64": 1.3578e9,
+    "fp32_store": 0.7222e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
-    "valu_fp64": 1.246e8,
+    "valu_fp64": 1.0687e8,
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
 # 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)
