@@ -160,6 +160,7 @@ struct PlanTotals {
   int sums, upd, face, ghost;  // workgroups of each launch
   int red;                     // workgroups of the chunk-sum launch (0: not launched)
   int shak;                    // the instances use the Shakhov model (all or none)
+  int upd_ch;                  // velocity chunks per update workgroup (1 or 2)
 };
 
 // Bytes of a device plan with n instances, and its host image (offsets into one buffer).

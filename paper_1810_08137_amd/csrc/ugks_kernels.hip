@@ -1510,7 +1510,7 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
 }
 
 // The body of the update kernel; kShak: the Shakhov collision model.
-template <typename S, bool kShak>
+template <typename S, bool kShak, int kCh>
 __device__ __forceinline__ void update_body(const PlanView& pv) {
   typedef S T;  // arithmetic type of the per-velocity work (and of the LDS stage)
   __shared__ PairStage<T> st;
@@ -1518,7 +1518,9 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   __shared__ T sk_raw[kShak ? kPair * 4 * kWave : 1];
   T(*sk)[4][kWave] = reinterpret_cast<T(*)[4][kWave]>(sk_raw);
   const int lane = threadIdx.x & (kWave - 1);
-  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // wavefront w: quadrant q, and c, which of the workgroup's kCh velocity chunks
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int q = w & 3, c = w >> 2;
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int ii = find_inst(pv.off_upd, pv.ninst, b);
   const Inst* __restrict__ I = inst_at(pv, ii);
@@ -1582,10 +1584,10 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     r[col] = T(exp(-lam * hs * (2.0 * d + hs)));
     lost = lost || (x > 700.0 && (h == 0 ? c > v0 : c < v0));
   };
-  if (q < kPair) {
-    // Eq. (4) for row jb + q, and the cell's Maxwellians of W^n and W^{n+1} with the
+  if (w < kPair) {
+    // Eq. (4) for row jb + w, and the cell's Maxwellians of W^n and W^{n+1} with the
     // weights of Eq. (3) solved for f^{n+1}: f1 = Af f + AdF dF + (A1 g^{n+1} + An g^n)
-    const int r = q;
+    const int r = w;
     const int jr = clampi(jb + r, 0, P.ny - 1);
     const bool mine = valid && (r == 0 ? store0 : true);
     const int ci = valid ? i : 0;
@@ -1619,7 +1621,7 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
                   (unsigned long long)__double_as_longlong(rate));
     }
     // the simulated time advances by this step's dt (one thread of the instance)
-    if (b == first_block(pv.off_upd, ii) && q == 0 && lane == 0) *P.tsum += step_dt(P, parity);
+    if (b == first_block(pv.off_upd, ii) && w == 0 && lane == 0) *P.tsum += step_dt(P, parity);
     Prim pn{}, p1{};
     double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
     if (!P.collisionless) {
@@ -1663,51 +1665,65 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       start(p1.lam, p1.V, h, st.gs[h][r][1][0], st.gs[h][r][1][1], lane);
     }
   } else {
-    // Gauss starts of the faces: wavefront 2 takes the x faces of row jb and the y face row
-    // jb, wavefront 3 those of row jb + 1 and the y face rows jb + 1, jb + 2 (FP64 records)
-    const int r = q - kPair;
-    const int jr = clampi(jb + r, 0, P.ny - 1);
+    // Gauss starts of the faces (FP64 records): wavefront 2 + r takes the x faces of row
+    // jb + r; the y face rows jb .. jb + 2 go one to a wavefront 4..6 with eight wavefronts,
+    // else row jb to wavefront 2 and rows jb + 1, jb + 2 to wavefront 3
+    const int r = w - kPair;
+    if (r < kPair) {
+      const int jr = clampi(jb + r, 0, P.ny - 1);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      for (int fc = lane; fc < kWave + 1; fc += kWave) {
-        const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
-        const UGKS_GLOBAL double* rec = recx + ((size_t)jr * (P.nx + 1) + fi) * kRec;
-        start(rec[R_LAM], rec[R_VY], h, st.xs[h][r][0], st.xs[h][r][1], fc);
+      for (int h = 0; h < 2; ++h) {
+        for (int fc = lane; fc < kWave + 1; fc += kWave) {
+          const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
+          const UGKS_GLOBAL double* rec = recx + ((size_t)jr * (P.nx + 1) + fi) * kRec;
+          start(rec[R_LAM], rec[R_VY], h, st.xs[h][r][0], st.xs[h][r][1], fc);
+        }
       }
-      for (int fr = r == 0 ? 0 : 1; fr < (r == 0 ? 1 : kPair + 1); ++fr) {
-        const int fi = clampi(i0 - kHalo + lane, 0, P.nx - 1);
-        const int row = clampi(jb + fr, 0, P.ny);
-        const UGKS_GLOBAL double* rec = recy + ((size_t)row * P.nx + fi) * kRec;
+    }
+    const int fr0 = kCh == 2 ? r - kPair : (r == 0 ? 0 : 1);
+    const int fr1 = kCh == 2 ? min(r - kPair + 1, kPair + 1) : (r == 0 ? 1 : kPair + 1);
+    for (int fr = max(fr0, 0); fr < fr1; ++fr) {
+      const int fi = clampi(i0 - kHalo + lane, 0, P.nx - 1);
+      const int row = clampi(jb + fr, 0, P.ny);
+      const UGKS_GLOBAL double* rec = recy + ((size_t)row * P.nx + fi) * kRec;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
         start(rec[R_LAM], rec[R_VY], h, st.ys[h][fr][0], st.ys[h][fr][1], lane);
-      }
     }
   }
   if (lost && valid) *P.flag = 1;
   __syncthreads();
+  // the workgroup's chunks kCh g .. kCh g + kCh - 1 of the quadrant's kCh G chunks
   const int sv = quad_sv(q);
   if (quad_su(q) > 0)
-    pair_quadrant<S, 1, kShak>(P, st, sk, lane, sv, jb, store0, g, G, valid, ghost_lane, fin,
-                               fout, i);
+    pair_quadrant<S, 1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G, valid,
+                               ghost_lane, fin, fout, i);
   else
-    pair_quadrant<S, -1, kShak>(P, st, sk, lane, sv, jb, store0, g, G, valid, ghost_lane, fin,
-                                fout, i);
+    pair_quadrant<S, -1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G, valid,
+                                ghost_lane, fin, fout, i);
 }
 
-// FP64: two workgroups per CU (the LDS stage takes 73 KB, the registers of two rows allow
-// two waves per SIMD).  FP32 storage: the stage takes 37 KB and the FP32 registers allow
-// four waves per SIMD.
-constexpr int kUpdateWaves64 = 2, kUpdateWaves32 = 4;
-template <typename S>
-__global__ __launch_bounds__(kWave* kQuads)
-__attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? kUpdateWaves64 : kUpdateWaves32)))
+// Velocity chunks per update workgroup, kCh (its wavefronts: four quadrants times kCh), which
+// share one stage, and the update waves per SIMD.  FP64: the registers of two rows allow two
+// waves per SIMD; with two chunks, one workgroup of eight waves per CU (its stage takes 73 KB),
+// and sharing the stage halves its cost per velocity node; one chunk serves meshes too small
+// to give every CU a workgroup of two.  FP32 storage: four waves per SIMD, four workgroups of
+// four waves per CU (37 KB each); the Shakhov form two waves per SIMD.
+template <typename S, bool kShak>
+constexpr int kUpdateWaves = sizeof(S) == 8 || kShak ? 2 : 4;
+
+template <typename S, int kCh>
+__global__ __launch_bounds__(kWave* kQuads* kCh)
+__attribute__((amdgpu_waves_per_eu(kUpdateWaves<S, false>)))
 void update_kernel(PlanView pv) {
-  update_body<S, false>(pv);
+  update_body<S, false, kCh>(pv);
 }
 
-template <typename S>
-__global__ __launch_bounds__(kWave* kQuads) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename S, int kCh>
+__global__ __launch_bounds__(kWave* kQuads* kCh)
+__attribute__((amdgpu_waves_per_eu(kUpdateWaves<S, true>)))
 void update_kernel_shakhov(PlanView pv) {
-  update_body<S, true>(pv);
+  update_body<S, true, kCh>(pv);
 }
 
 }  // namespace
@@ -1739,6 +1755,25 @@ int update_chunks(long long base, long long slots) {
   return 16;
 }
 
+// The same where that count is more than an instance's u nodes allow (small meshes): U, at
+// most `cap` (every chunk keeps a node of the smaller half, `half` nodes, with `per_wg` chunks
+// to a workgroup), that minimises rounds x (2 + nodes per chunk), the workgroup's fixed cost
+// counted as two nodes; of equal costs the most workgroups.
+int update_chunks_capped(long long base, long long slots, int cap, int per_wg, int half) {
+  int best = 1;
+  long long best_cost = -1;
+  for (int U = 1; U <= cap && U <= 16; ++U) {
+    const long long rounds = (base * U + slots - 1) / slots;
+    const long long chunks = (long long)per_wg * U;
+    const long long cost = rounds * (2 + (half + chunks - 1) / chunks);
+    if (best_cost < 0 || cost <= best_cost) {
+      best = U;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 size_t plan_bytes(int n) {
   const size_t inst = ((sizeof(Inst) * (size_t)n + 255) / 256) * 256;
   return inst + 6 * (((size_t)(n + 1) * sizeof(int) + 255) / 256) * 256;
@@ -1761,14 +1796,38 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
     const KParams& P = insts[q].P;
     upd_base += (long long)((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * P.NC;
   }
-  // update workgroups per CU at once: FP64 two, FP32 storage four (Shakhov two)
+  // velocity chunks per update workgroup (FP64 two, FP32 storage one) and the workgroups
+  // that run at once: 256 CUs x waves per CU / waves per workgroup
   const bool shak = n > 0 && insts[0].P.shak;
-  const int per_cu = (n > 0 && insts[0].fp32 && !shak) ? kUpdateWaves32 : kUpdateWaves64;
-  const int U = update_chunks(upd_base, 256LL * per_cu);
+  const bool f32 = n > 0 && insts[0].fp32;
+  const int waves = f32 ? (shak ? kUpdateWaves<float, true> : kUpdateWaves<float, false>)
+                        : kUpdateWaves<double, false>;
+  int per_wg = f32 ? 1 : 2;
+  // each workgroup's chunks take at least one u node each of the smaller half
+  auto cap_of = [&](const KParams& P, int ch) {
+    const int c = P.K / 2 / ch;
+    return c < 1 ? 1 : c;
+  };
+  auto choose = [&](int ch) {
+    const long long slots = 256LL * waves / ch;
+    const int U = update_chunks(upd_base, slots);
+    if (n == 1 && U > cap_of(insts[0].P, ch))
+      return update_chunks_capped(upd_base, slots, cap_of(insts[0].P, ch), ch,
+                                  insts[0].P.K / 2);
+    return U;
+  };
+  int U = choose(per_wg);
+  // a mesh that leaves more than half the CUs without a workgroup of two chunks takes one
+  // chunk per workgroup: twice the workgroups, on twice the CUs
+  if (per_wg == 2 && n == 1 && upd_base * U < 128) {  // U is within the cap here
+    per_wg = 1;
+    U = choose(1);
+  }
+  t.upd_ch = per_wg;
   for (int q = 0; q < n; ++q) {
     img[q].gsplit = insts[q].P.gmax;
-    const int half = insts[q].P.K / 2;  // nodes of the smaller half of the u axis
-    img[q].usplit = U < half ? U : (half < 1 ? 1 : half);
+    const int cap = cap_of(insts[q].P, per_wg);
+    img[q].usplit = U < cap ? U : cap;
   }
   for (int q = 0; q < n; ++q) {
     const KParams& P = insts[q].P;
@@ -1860,16 +1919,22 @@ hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int p
       faces_kernel<<<(unsigned)t.face, 256, 0, s>>>(pv);
       break;
     default: {
+      // FP32 storage runs one chunk per workgroup (build_plan never asks for two)
+      const unsigned nt = (unsigned)(kWave * kQuads * t.upd_ch);
       if (t.shak) {
         if (fp32)
-          update_kernel_shakhov<float><<<(unsigned)t.upd, kWave * kQuads, 0, s>>>(pv);
+          update_kernel_shakhov<float, 1><<<(unsigned)t.upd, nt, 0, s>>>(pv);
+        else if (t.upd_ch == 2)
+          update_kernel_shakhov<double, 2><<<(unsigned)t.upd, nt, 0, s>>>(pv);
         else
-          update_kernel_shakhov<double><<<(unsigned)t.upd, kWave * kQuads, 0, s>>>(pv);
+          update_kernel_shakhov<double, 1><<<(unsigned)t.upd, nt, 0, s>>>(pv);
       } else {
         if (fp32)
-          update_kernel<float><<<(unsigned)t.upd, kWave * kQuads, 0, s>>>(pv);
+          update_kernel<float, 1><<<(unsigned)t.upd, nt, 0, s>>>(pv);
+        else if (t.upd_ch == 2)
+          update_kernel<double, 2><<<(unsigned)t.upd, nt, 0, s>>>(pv);
         else
-          update_kernel<double><<<(unsigned)t.upd, kWave * kQuads, 0, s>>>(pv);
+          update_kernel<double, 1><<<(unsigned)t.upd, nt, 0, s>>>(pv);
       }
     }
   }
