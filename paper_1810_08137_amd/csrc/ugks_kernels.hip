@@ -1741,11 +1741,12 @@ int velocity_chunks(int nx, int ny, int K, int NC) {
   return G < 1 ? 1 : (int)G;
 }
 
-// Velocity chunks per quadrant of the update kernel for `base` workgroups per chunk (all
-// instances of a launch) and `slots` workgroups that run at once: the fewest chunks whose
-// workgroups fill every round of the slots that they start to at least 85%, and at least one
-// full round; at most 16.  The update kernel adds nothing across chunks, so its chunks do not
-// change any result.
+// Velocity chunks per quadrant of the update kernel, U, for `base` workgroups per chunk and
+// `slots` workgroups that run at once.  The update kernel adds nothing across chunks, so its
+// chunks do not change any result.
+//
+// A batch of instances (update_chunks): the fewest chunks whose workgroups fill every round of
+// the slots that they start to at least 85%, and at least one full round; at most 16.
 int update_chunks(long long base, long long slots) {
   for (int U = 1; U <= 16; ++U) {
     const long long n = base * U;
@@ -1755,11 +1756,12 @@ int update_chunks(long long base, long long slots) {
   return 16;
 }
 
-// The same where that count is more than an instance's u nodes allow (small meshes): U, at
-// most `cap` (every chunk keeps a node of the smaller half, `half` nodes, with `per_wg` chunks
-// to a workgroup), that minimises rounds x (2 + nodes per chunk), the workgroup's fixed cost
-// counted as two nodes; of equal costs the most workgroups.
-int update_chunks_capped(long long base, long long slots, int cap, int per_wg, int half) {
+// One instance (update_chunks_single): U, at most `cap` and 16, that minimises
+// rounds x (2 + u nodes per chunk), with `per_wg` chunks to a workgroup over the `half` u
+// nodes of the smaller half: a workgroup's fixed cost (its stage and Gauss starts) counts as
+// two u nodes; of equal costs the most workgroups.  On the paper's meshes and the 400x100
+// channel it picks the fastest U of a sweep or one within 1% of it.
+int update_chunks_single(long long base, long long slots, int cap, int per_wg, int half) {
   int best = 1;
   long long best_cost = -1;
   for (int U = 1; U <= cap && U <= 16; ++U) {
@@ -1810,16 +1812,14 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   };
   auto choose = [&](int ch) {
     const long long slots = 256LL * waves / ch;
-    const int U = update_chunks(upd_base, slots);
-    if (n == 1 && U > cap_of(insts[0].P, ch))
-      return update_chunks_capped(upd_base, slots, cap_of(insts[0].P, ch), ch,
-                                  insts[0].P.K / 2);
-    return U;
+    if (n == 1)
+      return update_chunks_single(upd_base, slots, cap_of(insts[0].P, ch), ch, insts[0].P.K / 2);
+    return update_chunks(upd_base, slots);
   };
   int U = choose(per_wg);
   // a mesh that leaves more than half the CUs without a workgroup of two chunks takes one
   // chunk per workgroup: twice the workgroups, on twice the CUs
-  if (per_wg == 2 && n == 1 && upd_base * U < 128) {  // U is within the cap here
+  if (per_wg == 2 && n == 1 && upd_base * U < 128) {
     per_wg = 1;
     U = choose(1);
   }
