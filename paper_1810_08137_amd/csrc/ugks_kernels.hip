@@ -672,18 +672,50 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
       Y4 = fma(hy, w4, Y4);
       wp += wstep;
     };
-    // two value sets, each node's loads issued one node ahead
-    Vals va = load_at(pcur);
-    int c = 0;
-    for (; c + 1 < hv.count; c += 2) {
-      pcur += pstep;
-      const Vals vb = load_at(pcur);
-      node(va);
-      if (c + 2 < hv.count) pcur += pstep;
-      va = load_at(pcur);
-      node(vb);
+    if constexpr (sizeof(S) == 8) {
+      // FP64: two value sets, each node's loads issued one node ahead (deeper prefetch costs
+      // this kernel its fourth wave per SIMD)
+      Vals va = load_at(pcur);
+      int c = 0;
+      for (; c + 1 < hv.count; c += 2) {
+        pcur += pstep;
+        const Vals vb = load_at(pcur);
+        node(va);
+        if (c + 2 < hv.count) pcur += pstep;
+        va = load_at(pcur);
+        node(vb);
+      }
+      if (c < hv.count) node(va);
+    } else {
+      // FP32 storage: a row load brings half the bytes, so each node's loads are issued four
+      // nodes ahead (kSA + 1 value sets in a ring); past the last node of the half the loads
+      // read its plane again
+      constexpr int kSA = 4, NB = kSA + 1;
+      int nl = 0;
+      auto load_next = [&]() {
+        const Vals v = load_at(pcur);
+        if (++nl < hv.count) pcur += pstep;
+        return v;
+      };
+      Vals ring[NB];
+#pragma unroll
+      for (int d = 0; d < kSA; ++d) ring[d] = load_next();
+      int c = 0;
+      for (; c + NB <= hv.count; c += NB) {
+#pragma unroll
+        for (int s = 0; s < NB; ++s) {
+          ring[(s + kSA) % NB] = load_next();
+          node(ring[s]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+        if (c + s < hv.count) {
+          ring[(s + kSA) % NB] = load_next();
+          node(ring[s]);
+        }
+      }
     }
-    if (c < hv.count) node(va);
     // moments of the x-face reconstruction (S), the y-face one (R) and of D
     const double ucx = u * two_idx, u2h = 0.5 * u * u, wuu = wu * u;
     if (hpart) {
