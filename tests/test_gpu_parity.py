@@ -64,6 +64,16 @@ def test_ragged_channels_with_zero_velocities(nx, ny, nu, nv):
     PR.run_and_compare(case, 30, label=f"channel {nx}x{ny} {nu}x{nv}")
 
 
+@pytest.mark.parametrize("nx", [60, 61, 62, 63, 121, 124])
+def test_channel_widths_at_segment_edges(nx):
+    """Channel widths at the row-segment edges of the two cell kernels (60 cells per update
+    segment, 62 per moment segment): the outlet ghost column then falls on a segment's last
+    lane, on the halo of the segment before the last, or next to a one-cell last segment."""
+    case = _case(nx=nx, ny=3, lx=nx / 10.0, ly=0.3, nu=8, nv=6, umax=4.0, vmax=4.0, kn=0.1,
+                 noise=0.02, seed=21 + nx)
+    PR.run_and_compare(case, 20, label=f"channel {nx}x3 8x6")
+
+
 @pytest.mark.parametrize("bc", [0, 1])
 def test_collisionless_limit(bc):
     case = _case(nx=12, ny=6, lx=2.0, ly=1.0, nu=10, nv=9, umax=3.0, vmax=3.0, kn=float("inf"),

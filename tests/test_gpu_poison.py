@@ -30,6 +30,9 @@ CASES = {
     "paper mesh 40x20 at 29^2 (velocity chunks)": (WL.paper_mesh(40, 20, 29), "fp64"),
     "internal dof": (WL.C1_DOF, "fp64"),
     "shakhov": (WL.C1_SHAKHOV, "fp32_store"),
+    "channel 61x5 (outlet column on a segment's halo)": (
+        _case(nx=61, ny=5, lx=6.1, ly=0.5, nu=10, nv=8, umax=4.0, vmax=4.0, kn=0.1, seed=64),
+        "fp64"),
     "periodic 19x9": (_case(nx=19, ny=9, lx=1.9, ly=1.0, nu=14, nv=14, umax=5.0, vmax=5.0,
                             kn=0.05, bc=0, seed=63), "fp64"),
 }
