@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-steps", type=int, default=500)
-    ap.add_argument("--serving-chunks", type=int, default=4,
+    ap.add_argument("--serving-chunks", type=int, default=1,
                     help="cap on the velocity chunks of the serving solvers (0: automatic)")
     ap.add_argument("--serving-quantum", type=int, default=10,
                     help="steps per serving batch: an arrival joins at the next batch")

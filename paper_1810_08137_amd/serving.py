@@ -74,11 +74,13 @@ class GpuExecutor:
     """Runs requests as UGKS solvers on the current GPU, stepped together: one batch per
     storage precision and collision model (BGK or Shakhov) present, all on one stream, so a
     step of the resident requests is one launch per phase and group.
-    ``velocity_chunks`` caps every solver's velocity chunks (0: automatic).  A batch of
-    resident requests fills the GPU by itself, so a small cap saves per-chunk setup; the
-    default 4 keeps the low-load latency of the automatic choice."""
+    ``velocity_chunks`` caps every solver's moment-kernel velocity chunks (0: automatic).  A
+    batch of resident requests fills the GPU by itself, so the default 1 saves the per-chunk
+    setup and the chunk-sum pass: on the 256-request serving workload it saturated 2.5% higher
+    than a cap of 4 and halved the p50 latency at 0.8 of that rate, for 10% more p50 latency
+    at half of it."""
 
-    def __init__(self, max_slots, velocity_chunks=4):
+    def __init__(self, max_slots, velocity_chunks=1):
         import torch
 
         from . import ugks
