@@ -26,9 +26,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "1c76682faa02c9b573eaeea7afcaea20d2eef6a5dd6c8e6604d73de540b2333c",
-    "fp64": 1.2934e9,
-    "fp32_store": 0.7215e9,
+    "source_sha256": "049a74e72c721dfad536daf90255999db19d709e9b90dc649d176b845532554f",
+    "fp64": 1.2939e9,
+    "fp32_store": 0.7214e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
     "valu_fp64": 1.0335e8,
 }
