@@ -273,7 +273,7 @@ Layout layout_of(const Shape& s, int prec, int chunks, bool shak) {
       s.nc * 4 * 8,                             // W1
       2 * (size_t)s.ny * 4 * 8,                 // Wg
       (size_t)s.NC * chunks * s.nc * (shak ? kSlotsShakhov : kSlots) * 8,  // hs: partial sums
-      2 * (size_t)s.ny * kGhostSums * 8,        // hsg
+      (size_t)s.NC * chunks * 2 * s.ny * kGhostSums * 8,  // hsg: parts of the ghost sums
       (size_t)s.NC * s.ny * (s.nx + 1) * kRec * 8,  // recx
       (size_t)s.NC * (s.ny + 1) * s.nx * kRec * 8,  // recy
       (size_t)(s.K + 6 * s.M) * 8,              // wk, wm, vmom
@@ -316,15 +316,16 @@ void carve(ugks_handle* h, const Layout& L, const Shape& s) {
   h->plan_static = base + L.off[14];
 }
 
-// The transient buffers of one step (Wg, hs, hsg, recx, recy: layout entries 4..8) are
-// contiguous in the workspace; their size, and the same buffers carved out of `base`.
-size_t transient_bytes(const Layout& L) { return L.off[9] - L.off[4]; }
+// The transient buffers of one step (hs, hsg, recx, recy: layout entries 5..8) are
+// contiguous in the workspace; their size, and the same buffers carved out of `base`.  The
+// ghost states Wg (entry 4) are not transient: the update kernel of a step writes those of
+// the next.
+size_t transient_bytes(const Layout& L) { return L.off[9] - L.off[5]; }
 void carve_transient(const Layout& L, char* base, Inst& I) {
-  I.Wg = gp(reinterpret_cast<double*>(base + (L.off[4] - L.off[4])));
-  I.hs = gp(reinterpret_cast<double*>(base + (L.off[5] - L.off[4])));
-  I.hsg = gp(reinterpret_cast<double*>(base + (L.off[6] - L.off[4])));
-  I.recx = gp(reinterpret_cast<double*>(base + (L.off[7] - L.off[4])));
-  I.recy = gp(reinterpret_cast<double*>(base + (L.off[8] - L.off[4])));
+  I.hs = gp(reinterpret_cast<double*>(base + (L.off[5] - L.off[5])));
+  I.hsg = gp(reinterpret_cast<double*>(base + (L.off[6] - L.off[5])));
+  I.recx = gp(reinterpret_cast<double*>(base + (L.off[7] - L.off[5])));
+  I.recy = gp(reinterpret_cast<double*>(base + (L.off[8] - L.off[5])));
 }
 
 hipEvent_t pool_get(ugks_handle* h) {
@@ -712,6 +713,7 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     if (e == hipSuccess) e = hipMemsetAsync(B.f[1], 0, fbytes, h->stream);
     if (e == hipSuccess)
       e = launch_init(h->pv, I.fp32, (long long)s.nc * (long long)s.NV * s.NC, h->stream);
+    if (e == hipSuccess) e = launch_ghost_fill(h->pv, h->pt, I.fp32, h->stream);
     // debug option: every cell value of the buffers the first step writes starts as NaN
     const char* poison = std::getenv("UGKS_DEBUG_POISON");
     if (e == hipSuccess && poison && poison[0] == '1')
@@ -923,6 +925,12 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W) {
   if (e == hipSuccess && W)
     e = hipMemcpyAsync(h->B.rmax + (h->steps & 1), &rb, sizeof rb, hipMemcpyHostToDevice,
                        h->stream);
+  // the ghost columns and ghost states of the new state (the host image's halo is zero)
+  if (e == hipSuccess) {
+    PlanView pv = h->pv;
+    pv.step = (int)(h->steps & 1);
+    e = launch_ghost_fill(pv, h->pt, h->inst.fp32, h->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "writing the state");
   return UGKS_OK;

@@ -161,6 +161,8 @@ struct PlanTotals {
   int red;                     // workgroups of the chunk-sum launch (0: not launched)
   int shak;                    // the instances use the Shakhov model (all or none)
   int upd_ch;                  // velocity chunks per update workgroup (1 or 2)
+  int periodic;                // some instance has a periodic halo (the ghost kernel runs)
+  int channel;                 // some instance is a channel (ghost columns from the update)
 };
 
 // Bytes of a device plan with n instances, and its host image (offsets into one buffer).
@@ -177,6 +179,10 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
 hipError_t launch_init(const PlanView& pv, int fp32, long long nvalues, hipStream_t s);
 // Debug: NaN into every cell value of the f and W buffers the next step writes.
 hipError_t launch_poison(const PlanView& pv, int fp32, long long nvalues, hipStream_t s);
+// Fill the channel ghost columns of the current f and the ghost states Wg from the current W
+// (after the initial state and after ugks_set_state; the update kernel writes those of the
+// next step in every step), with the update kernel's own arithmetic.
+hipError_t launch_ghost_fill(const PlanView& pv, const PlanTotals& t, int fp32, hipStream_t s);
 hipError_t launch_step(const PlanView& pv, const PlanTotals& t, int fp32, hipStream_t s,
                        hipEvent_t* ev /* 8 events or NULL */);
 hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int phase,

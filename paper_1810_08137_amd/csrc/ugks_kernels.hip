@@ -1,17 +1,20 @@
 // gfx950 kernels of the 2D UGKS time step.
 //
-// One step is four launches on one stream:
-//   ghost   the halo of every velocity plane: pressure inlet/outlet ghost columns of a channel
-//           (Sec. 3.A) with their moment sums, or the periodic images of a periodic box
+// One step is three launches on one stream (four in a periodic box):
+//   ghost   periodic box only: the periodic images into the halo of every velocity plane
 //   sums    per cell and velocity: limited slopes of f, the upwind reconstruction at the
-//           cell's outgoing faces and their velocity moments (S1 and the sums of S7); a
-//           solver that splits its velocities into chunks adds the chunks' partial sums in
-//           a second, small launch
+//           cell's outgoing faces and their velocity moments (S1 and the sums of S7); in a
+//           channel also the sums of the inlet and outlet ghost columns (Sec. 3.A); a solver
+//           that splits its velocities into chunks adds the chunks' partial sums in a second,
+//           small launch
 //   faces   per interface: add the two sides' sums, then the scalar part of the flux
 //           (S2-S5: Maxwellian moments, time weights, micro slopes, equilibrium flux) into a
 //           record of folded coefficients
 //   update  per cell and velocity: the distribution flux at the faces (S6, S8), then Eq. (4)
-//           for W and Eq. (3) for f
+//           for W and Eq. (3) for f; in a channel also the ghost states of the next step
+//           (from W^{n+1}) and their Maxwellians in the ghost columns of f^{n+1}
+// After the initial state and after a state is set, the update kernel's fill mode writes a
+// channel's ghost columns from the current W.
 // f is stored velocity-major: one plane per discrete velocity, a padded nx x ny array with
 // two halo columns and rows on each side (KParams).  A wavefront takes 64 consecutive cells
 // of one row at one velocity, so every load is one coalesced row segment and the x
@@ -450,64 +453,20 @@ __global__ __launch_bounds__(256) void poison_kernel(PlanView pv) {
   const int c = (int)(e - (long long)p * nc);
   const int j = c / P.nx, i = c - j * P.nx;
   plane_of(f, P, p)[pidx(P, i, j)] = static_cast<S>(__builtin_nan(""));
+  // a channel's ghost columns, which the update kernel writes into f^{n+1}
+  if (P.bc == UGKS_BC_CHANNEL && (i == 0 || i == P.nx - 1))
+    plane_of(f, P, p)[pidx(P, i == 0 ? -1 : P.nx, j)] = static_cast<S>(__builtin_nan(""));
   if (p == 0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) W[4 * (size_t)c + q] = __builtin_nan("");
   }
 }
 
-// Halo of the current f.  Channel: one workgroup per (side, row) writes the inlet (side 0)
-// or outlet (side 1) ghost Maxwellian into that row's ghost column of every plane (H:
-// dof/(2 lambda) times it) and sums its moments towards the domain (its slopes are zero); the
-// other halo values stay zero.  Periodic: one thread per halo value of every plane copies the
-// periodic image.
-constexpr int kGhostThreads = 256;
-template <typename S>
-__global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
-  __shared__ double part[kGhostThreads / kWave][kGhostSums];
-  const int b = blockIdx.x;
-  const int ii = find_inst(pv.off_ghost, pv.ninst, b);
-  const Inst* __restrict__ I = inst_at(pv, ii);
-  const KParams P = I->P;
-  UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
-  const int local = b - first_block(pv.off_ghost, ii);
-  const int lane = threadIdx.x & (kWave - 1), tid = threadIdx.x;
-  // the update kernel of this step takes the max rate of W^{n+1} into the other slot
-  if (local == 0 && tid == 0) P.rmax[((I->cur + pv.step) & 1) ^ 1] = 0ull;
-  if (P.bc != UGKS_BC_CHANNEL) {
-    const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
-    const long long e = (long long)local * kGhostThreads + tid;
-    if (e >= frame * P.NV * P.NC) return;
-    const int p = (int)(e / frame);
-    int r = (int)(e - (long long)p * frame);
-    // frame order: the 2 halo rows below, then ny rows of 4 halo columns, then 2 rows above
-    int i, j;
-    const int band = kHalo * P.Lx;
-    if (r < band) {
-      j = r / P.Lx - kHalo;
-      i = r % P.Lx - kHalo;
-    } else if (r < band + 2 * kHalo * P.ny) {
-      r -= band;
-      j = r / (2 * kHalo);
-      const int c = r % (2 * kHalo);
-      i = c < kHalo ? c - kHalo : P.nx + (c - kHalo);
-    } else {
-      r -= band + 2 * kHalo * P.ny;
-      j = P.ny + r / P.Lx;
-      i = r % P.Lx - kHalo;
-    }
-    UGKS_GLOBAL S* pl = plane_of(f, P, p);
-    const double x = ldv(pl, pidx(P, wrap(i, P.nx), wrap(j, P.ny)));
-    stv(pl, pidx(P, i, j), x);
-    return;
-  }
-  const UGKS_GLOBAL double* W = I->W[(I->cur + pv.step) & 1];
-  UGKS_GLOBAL double* Wg = I->Wg;
-  UGKS_GLOBAL double* hsg = I->hsg;
-  const int side = local / P.ny, j = local - side * P.ny;
-  const int col = side == 0 ? 0 : P.nx - 1;
-  Prim pc, pg;
-  const bool ok = prim_of(W + 4 * ((size_t)j * P.nx + col), pc, P.lam_c);
+// Ghost state of row j of a channel (Sec. 3.A) from the primitive state pc of the cell next
+// to it: the inlet (side 0) holds p_in and T_in (its velocity that of the cell, or the fixed
+// inlet profile), the outlet (side 1) p_out with the cell's velocity and temperature.
+__device__ __forceinline__ Prim ghost_prim(const KParams& P, int side, int j, const Prim& pc) {
+  Prim pg;
   if (side == 0) {
     const double T = P.T_in;
     pg.lam = 1.0 / T;
@@ -526,54 +485,54 @@ __global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
     pg.V = pc.V;
     pg.lam = pc.lam;
   }
-  if (!ok && tid == 0) *P.flag = 1;
-  UGKS_GLOBAL double* wg = Wg + 4 * ((size_t)side * P.ny + j);
-  if (tid == 0) {
-    wg[0] = pg.rho;
-    wg[1] = pg.rho * pg.U;
-    wg[2] = pg.rho * pg.V;
-    wg[3] = 0.5 * pg.rho * (pg.U * pg.U + pg.V * pg.V) + P.lam_c * pg.rho / pg.lam;
+  return pg;
+}
+
+// Ghost state W of a channel ghost cell, stored for the interface kernel.
+__device__ __forceinline__ void store_wg(UGKS_GLOBAL double* wg, const Prim& pg, double lam_c) {
+  wg[0] = pg.rho;
+  wg[1] = pg.rho * pg.U;
+  wg[2] = pg.rho * pg.V;
+  wg[3] = 0.5 * pg.rho * (pg.U * pg.U + pg.V * pg.V) + lam_c * pg.rho / pg.lam;
+}
+
+// Halo of the current f of a periodic box (a step's first launch): one thread per halo value
+// of every plane copies the periodic image.  A channel's halo is written by the update kernel
+// (its ghost columns; the rest stays zero).
+constexpr int kGhostThreads = 256;
+template <typename S>
+__global__ __launch_bounds__(kGhostThreads) void ghost_kernel(PlanView pv) {
+  const int b = blockIdx.x;
+  const int ii = find_inst(pv.off_ghost, pv.ninst, b);
+  const Inst* __restrict__ I = inst_at(pv, ii);
+  const KParams P = I->P;
+  UGKS_GLOBAL S* f = static_cast<UGKS_GLOBAL S*>(I->f[(I->cur + pv.step) & 1]);
+  const int local = b - first_block(pv.off_ghost, ii);
+  const int tid = threadIdx.x;
+  const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
+  const long long e = (long long)local * kGhostThreads + tid;
+  if (e >= frame * P.NV * P.NC) return;
+  const int p = (int)(e / frame);
+  int r = (int)(e - (long long)p * frame);
+  // frame order: the 2 halo rows below, then ny rows of 4 halo columns, then 2 rows above
+  int i, j;
+  const int band = kHalo * P.Lx;
+  if (r < band) {
+    j = r / P.Lx - kHalo;
+    i = r % P.Lx - kHalo;
+  } else if (r < band + 2 * kHalo * P.ny) {
+    r -= band;
+    j = r / (2 * kHalo);
+    const int c = r % (2 * kHalo);
+    i = c < kHalo ? c - kHalo : P.nx + (c - kHalo);
+  } else {
+    r -= band + 2 * kHalo * P.ny;
+    j = P.ny + r / P.Lx;
+    i = r % P.Lx - kHalo;
   }
-  const double coef = pg.rho * pg.lam / kPi;
-  const double kap = (double)P.dof / (2.0 * pg.lam);
-  const int at = pidx(P, side == 0 ? -1 : P.nx, j);
-  double acc[kGhostSums];
-#pragma unroll
-  for (int q = 0; q < kGhostSums; ++q) acc[q] = 0.0;
-  for (int p = tid; p < P.NV; p += kGhostThreads) {
-    const int k = p / P.M, m = p - k * P.M;
-    const double u = P.uk[k], vv = P.vm[m], w = P.wk[k] * P.wm[m];
-    const double du = u - pg.U, dv = vv - pg.V;
-    const double g = coef * exp(-pg.lam * (du * du + dv * dv));
-    const S gs = static_cast<S>(g);  // the value the cells will read
-    stv(plane_of(f, P, p), at, (double)gs);
-    const double up = u > 0.0 ? 1.0 : (u < 0.0 ? 0.0 : 0.5);
-    const double h = side == 0 ? up : 1.0 - up;
-    add_side(acc, w * h, u, vv, 0.5 * (u * u + vv * vv), (double)gs, 0.0, 0.0);
-    // for the Shakhov heat flux of the interface: sum of ut (un^2 + ut^2)/2 f
-    acc[16] = fma((w * h) * (double)gs, vv * (0.5 * (u * u + vv * vv)), acc[16]);
-    if (P.NC > 1) {
-      // H carries energy only: psi = (0, 0, 0, 1/2)
-      const S hg = static_cast<S>(kap * g);
-      stv(plane_of(f, P, P.NV + p), at, (double)hg);
-      const double x0 = 0.5 * (w * h) * (double)hg;
-      acc[3] += x0;
-      acc[11] = fma(x0, u, acc[11]);
-    }
-  }
-  const int w = tid >> 6;
-#pragma unroll
-  for (int q = 0; q < kGhostSums; ++q) {
-    const double t = wave_sum(acc[q]);
-    if (lane == q) part[w][q] = t;
-  }
-  __syncthreads();
-  if (tid < kGhostSums) {
-    double t = 0.0;
-#pragma unroll
-    for (int r = 0; r < kGhostThreads / kWave; ++r) t += part[r][tid];
-    hsg[((size_t)side * P.ny + j) * kGhostSums + tid] = t;
-  }
+  UGKS_GLOBAL S* pl = plane_of(f, P, p);
+  const double x = ldv(pl, pidx(P, wrap(i, P.nx), wrap(j, P.ny)));
+  stv(pl, pidx(P, i, j), x);
 }
 
 // Per cell: slopes and the outgoing moment sums of all four faces.  A workgroup takes one
@@ -609,6 +568,11 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   UGKS_GLOBAL double* hs = I->hs + (size_t)gg * P.nslot * ((size_t)P.nx * P.ny);
   const int i = t * kTileS - 1 + lane;
   const bool valid = lane >= 1 && lane <= kTileS && i < P.nx;
+  // channel ghost columns (i = -1, nx): their sums towards the domain are the ghost sums of
+  // the inlet and outlet faces (zero slopes); only the first and last segments hold them
+  const bool chan = P.bc == UGKS_BC_CHANNEL;
+  const bool ghost = chan && (i == -1 || i == P.nx);
+  const bool ghost_wave = chan && (t == 0 || (t + 1) * kTileS >= P.nx);
   const int o = pidx(P, i < P.nx + 1 ? i : P.nx + 1, j);
   const unsigned bs = (unsigned)sizeof(S);
   const unsigned oc = (unsigned)o * bs, oS = (unsigned)(o - P.Lx) * bs;
@@ -716,6 +680,10 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
         }
       }
     }
+    if (ghost_wave && ghost) {  // a ghost cell has zero slopes
+      X0 = X1 = X2 = X3 = 0.0;
+      Y0 = Y1 = Y2 = Y3 = Y4 = 0.0;
+    }
     // moments of the x-face reconstruction (S), the y-face one (R) and of D
     const double ucx = u * two_idx, u2h = 0.5 * u * u, wuu = wu * u;
     if (hpart) {
@@ -811,6 +779,15 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
   }
   __syncthreads();
   const size_t nc = (size_t)P.nx * P.ny;
+  // the inlet ghost's sums towards +x (waves 0 and 3), the outlet ghost's towards -x (waves
+  // 1 and 2): this chunk's part, added over the chunks by the interface kernel
+  if (ghost_wave && ghost && q == (i < 0 ? 0 : 2)) {
+    const int ox = q == 0 ? 3 : 2, side = i < 0 ? 0 : 1;
+    UGKS_GLOBAL double* gs = I->hsg + (((size_t)gg * 2 + side) * P.ny + j) * kGhostSums;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) gs[r] = ax[r] + red[ox][r][lane];
+    if constexpr (kR < kGhostSums) gs[kGhostSums - 1] = 0.0;  // no heat sum without Shakhov
+  }
   if (valid && (q == 0 || q == 2)) {
     const size_t cell = (size_t)j * P.nx + i;
     const int fy = q == 0 ? S_YP : S_YM, fx = q == 0 ? S_XP : S_XM;
@@ -844,10 +821,19 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(PlanView pv) {
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
   const size_t nc = (size_t)P.nx * P.ny;
-  const size_t e = (size_t)(b - first_block(pv.off_red, ii)) * blockDim.x + threadIdx.x;
-  if (e >= (size_t)P.nslot * nc) return;
-  UGKS_GLOBAL double* at = I->hs + e;
-  const size_t gstride = (size_t)P.nslot * nc;
+  size_t e = (size_t)(b - first_block(pv.off_red, ii)) * blockDim.x + threadIdx.x;
+  UGKS_GLOBAL double* at;
+  size_t gstride;
+  if (e < (size_t)P.nslot * nc) {
+    at = I->hs + e;
+    gstride = (size_t)P.nslot * nc;
+  } else {
+    // a channel's ghost sums (2 ny rows of kGhostSums per chunk)
+    e -= (size_t)P.nslot * nc;
+    gstride = 2 * (size_t)P.ny * kGhostSums;
+    if (P.bc != UGKS_BC_CHANNEL || e >= gstride) return;
+    at = I->hsg + e;
+  }
   double x = at[0];
   for (int g = 1; g < I->gsplit * P.NC; ++g) x += at[(size_t)g * gstride];
   at[0] = x;
@@ -1022,6 +1008,8 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   UGKS_GLOBAL double* recx = I->recx;
   UGKS_GLOBAL double* recy = I->recy;
   const long e = (long)(b - first_block(pv.off_face, ii)) * blockDim.x + threadIdx.x;
+  // the update kernel of this step takes the max rate of W^{n+1} into the other slot
+  if (e == 0) P.rmax[((I->cur + pv.step) & 1) ^ 1] = 0ull;
   const long nfx = (long)P.ny * (P.nx + 1);
   const long nfy = (long)(P.ny + 1) * P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
@@ -1030,34 +1018,22 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   double U0, V0, T3 = 0.0;
   if (e < nfx) {
     const int j = (int)(e / (P.nx + 1)), i = (int)(e % (P.nx + 1));
-    const UGKS_GLOBAL double *sL, *sR, *WL, *WR;
-    size_t stL = nc, stR = nc;
-    const UGKS_GLOBAL double *hL, *hR;  // the heat sums of the two sides (Shakhov)
-    if (i > 0 || !chan) {
-      const size_t cl = (size_t)j * P.nx + wrap(i - 1, P.nx);
-      sL = hs + 16 * S_XP * nc + cl;
-      hL = hs + (kSlotHeat + S_XP) * nc + cl;
-      WL = W + 4 * cl;
-    } else {
-      sL = hsg + (size_t)j * kGhostSums;
-      hL = sL + 16;
-      stL = 1;
-      WL = Wg + 4 * (size_t)j;
-    }
-    if (i < P.nx || !chan) {
-      const size_t cr = (size_t)j * P.nx + wrap(i, P.nx);
-      sR = hs + 16 * S_XM * nc + cr;
-      hR = hs + (kSlotHeat + S_XM) * nc + cr;
-      WR = W + 4 * cr;
-    } else {
-      sR = hsg + ((size_t)P.ny + j) * kGhostSums;
-      hR = sR + 16;
-      stR = 1;
-      WR = Wg + 4 * ((size_t)P.ny + j);
-    }
+    // a channel's ghost side: the ghost sums the moment kernel left (the chunk-sum kernel has
+    // added the parts of the velocity chunks into the first)
+    const bool gL = chan && i == 0, gR = chan && i == P.nx;
+    const size_t cl = (size_t)j * P.nx + wrap(i - 1, P.nx);
+    const size_t cr = (size_t)j * P.nx + wrap(i, P.nx);
+    const UGKS_GLOBAL double* sL = gL ? hsg + (size_t)j * kGhostSums : hs + 16 * S_XP * nc + cl;
+    const UGKS_GLOBAL double* sR =
+        gR ? hsg + ((size_t)P.ny + j) * kGhostSums : hs + 16 * S_XM * nc + cr;
+    const size_t stL = gL ? 1 : nc, stR = gR ? 1 : nc;
+    const UGKS_GLOBAL double* WL = gL ? Wg + 4 * (size_t)j : W + 4 * cl;
+    const UGKS_GLOBAL double* WR = gR ? Wg + 4 * ((size_t)P.ny + j) : W + 4 * cr;
 #pragma unroll
     for (int q = 0; q < 16; ++q) S[q] = sL[q * stL] + sR[q * stR];
-    if (P.shak) T3 = *hL + *hR;
+    if (P.shak)  // the heat sums of the two sides
+      T3 = (gL ? sL[16] : hs[(kSlotHeat + S_XP) * nc + cl]) +
+           (gR ? sR[16] : hs[(kSlotHeat + S_XM) * nc + cr]);
     double wl[4], wr[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1315,7 +1291,8 @@ template <typename S, int SU, bool kShak, int kAhead = kShak ? 1 : (sizeof(S) ==
 __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<S>& st,
                                               const S (*sk)[4][kWave], int lane, int sv,
                                               int jb, bool store0, int g, int G, bool valid,
-                                              bool ghost_lane, const UGKS_GLOBAL S* fin,
+                                              bool ghost_lane, bool ghost_w,
+                                              const UGKS_GLOBAL S* fin,
                                               UGKS_GLOBAL S* fout, int i) {
   typedef S T;  // arithmetic type of the per-velocity work
   const bool chan = P.bc == UGKS_BC_CHANNEL;
@@ -1330,8 +1307,9 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
   auto no_wall = [&](int j) { return !(chan && (j == 0 || j == P.ny - 1)); };
   const bool gm = !ghost_lane;  // ghost columns have zero slopes
   const bool mB = no_wall(jB), m0 = gm && no_wall(j0), m1 = gm && no_wall(j1);
-  const bool st0 = valid && (r0 == 0 ? store0 : true);
-  const bool st1 = valid && (r1 == 0 ? store0 : true);
+  // cells, and a channel's ghost columns (the ghost Maxwellian of the next step)
+  const bool st0 = (valid || ghost_w) && (r0 == 0 ? store0 : true);
+  const bool st1 = (valid || ghost_w) && (r1 == 0 ? store0 : true);
   // byte offsets of the five rows j0 - 2 sv, j0 - sv, j0, j1 = j0 + sv, j1 + sv
   const unsigned bs = (unsigned)sizeof(S);
   const int ic = i < P.nx + 1 ? i : P.nx + 1;
@@ -1541,8 +1519,74 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
   }
 }
 
+// Fill mode of the update kernel, quadrant wavefront: the ghost columns of the current f from
+// the ghost states of the current W (after the initial state and after a state is set).  It
+// forms the ghost lanes' g^{n+1} with the expressions and Gauss recurrences of the update loop,
+// where Eq. (3) with every other weight zero leaves f = g^{n+1}, so a state set from a
+// checkpoint steps on exactly as a running solver does.
+template <typename S, int SU>
+__device__ __forceinline__ void ghost_fill_quadrant(const KParams& P, const PairStage<S>& st,
+                                                    int lane, int sv, int jb, bool store0,
+                                                    int g, int G, bool ghost_w,
+                                                    UGKS_GLOBAL S* f, int i) {
+  typedef S T;
+  const int r0 = sv > 0 ? 0 : 1, r1 = 1 - r0;
+  const int j0 = jb + r0;
+  const bool st0 = ghost_w && (r0 == 0 ? store0 : true);
+  const bool st1 = ghost_w && (r1 == 0 ? store0 : true);
+  const unsigned bs = (unsigned)sizeof(S);
+  const int ic = i < P.nx + 1 ? i : P.nx + 1;
+  const int o0 = pidx(P, ic, j0);
+  const unsigned oC = (unsigned)o0 * bs, oD = (unsigned)(o0 + sv * P.Lx) * bs;
+  const unsigned w0 = st0 ? oC : kDropOffset, w1 = st1 ? oD : kDropOffset;
+  const Half hu = axis_half(P.K, SU, false), hv = axis_half(P.M, sv, false);
+  const int hf = sv > 0 ? 0 : 1;
+  const T hstep = T(sv * P.dv);
+  const T h2 = T(-2) * hstep * hstep;
+  const T qn0 = expm1_of(h2 * st.cell[r0][C_LAMN][lane]);
+  const T q10 = expm1_of(h2 * st.cell[r0][C_LAM1][lane]);
+  const T qn1 = expm1_of(h2 * st.cell[r1][C_LAMN][lane]);
+  const T q11 = expm1_of(h2 * st.cell[r1][C_LAM1][lane]);
+  const long long pstep = (long long)hv.step * P.PS;
+  int a0, a1;
+  chunk_range(hu.count, g, G, a0, a1);
+  for (int a = a0; a < a1; ++a) {
+    const int k = hu.first + a * hu.step;
+    const T u = T(P.uk[k]);
+    UGKS_GLOBAL S* wcur = plane_of(f, P, k * P.M) + (long long)hv.first * P.PS;
+    T en0, rn0, e10, r10, en1, rn1, e11, r11;
+    {
+      const T(*c0)[kWave] = st.cell[r0];
+      const T dn = u - c0[C_UN][lane], d1 = u - c0[C_U1][lane];
+      en0 = c0[C_AN][lane] * exp_of(-c0[C_LAMN][lane] * dn * dn) * st.gs[hf][r0][0][0][lane];
+      e10 = c0[C_A1][lane] * exp_of(-c0[C_LAM1][lane] * d1 * d1) * st.gs[hf][r0][1][0][lane];
+      rn0 = st.gs[hf][r0][0][1][lane];
+      r10 = st.gs[hf][r0][1][1][lane];
+    }
+    {
+      const T(*c1)[kWave] = st.cell[r1];
+      const T dn = u - c1[C_UN][lane], d1 = u - c1[C_U1][lane];
+      en1 = c1[C_AN][lane] * exp_of(-c1[C_LAMN][lane] * dn * dn) * st.gs[hf][r1][0][0][lane];
+      e11 = c1[C_A1][lane] * exp_of(-c1[C_LAM1][lane] * d1 * d1) * st.gs[hf][r1][1][0][lane];
+      rn1 = st.gs[hf][r1][0][1][lane];
+      r11 = st.gs[hf][r1][1][1][lane];
+    }
+    for (int c = 0; c < hv.count; ++c) {
+      const T g0 = e10 + en0, g1 = e11 + en1;
+      const __amdgpu_buffer_rsrc_t wr = plane_rsrc(wcur, P);
+      bstore(wr, w0, g0, S{});
+      bstore(wr, w1, g1, S{});
+      wcur += pstep;
+      gauss_next(en0, rn0, qn0);
+      gauss_next(e10, r10, q10);
+      gauss_next(en1, rn1, qn1);
+      gauss_next(e11, r11, q11);
+    }
+  }
+}
+
 // The body of the update kernel; kShak: the Shakhov collision model.
-template <typename S, bool kShak, int kCh>
+template <typename S, bool kShak, int kCh, bool kFill = false>
 __device__ __forceinline__ void update_body(const PlanView& pv) {
   typedef S T;  // arithmetic type of the per-velocity work (and of the LDS stage)
   __shared__ PairStage<T> st;
@@ -1569,7 +1613,8 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   const int g = hpart ? gg - G : gg;
   const long long hoff = hpart ? (long long)P.NV * P.PS : 0ll;
   const UGKS_GLOBAL S* fin = static_cast<const UGKS_GLOBAL S*>(I->f[parity]) + hoff;
-  UGKS_GLOBAL S* fout = static_cast<UGKS_GLOBAL S*>(I->f[parity ^ 1]) + hoff;
+  // fill mode writes the ghost columns of the current f
+  UGKS_GLOBAL S* fout = static_cast<UGKS_GLOBAL S*>(I->f[kFill ? parity : parity ^ 1]) + hoff;
   const UGKS_GLOBAL double* recx =
       I->recx + (hpart ? (size_t)P.ny * (P.nx + 1) * kRec : (size_t)0);
   const UGKS_GLOBAL double* recy =
@@ -1581,10 +1626,13 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   const bool valid = lane >= kHalo && lane < kHalo + kTileU && i < P.nx;
   const bool chan = P.bc == UGKS_BC_CHANNEL;
   const bool ghost_lane = chan && (i == -1 || i == P.nx);
+  // the ghost lane whose neighbouring cell is this segment's writes the ghost column (the
+  // outlet column can also be the right halo of the segment before the last)
+  const bool ghost_w = ghost_lane && (i < 0 || lane <= kHalo + kTileU);
   // stage the records of the pair's faces: x faces i0-2 .. i0+62 of both rows, y face rows
   // jb .. jb+2 below / above lanes 0..63; indices clamped into the mesh for lanes and rows
   // outside it
-  for (int e = threadIdx.x; e < kPair * (kWave + 1) * kSF; e += blockDim.x) {
+  for (int e = threadIdx.x; !kFill && e < kPair * (kWave + 1) * kSF; e += blockDim.x) {
     const int r = e / ((kWave + 1) * kSF), rem = e - r * ((kWave + 1) * kSF);
     const int fc = rem / kSF, s = rem - fc * kSF;
     const int fld = s <= sf(R_UX) ? R_GC + s : R_GC + s + 1;  // skip R_VY
@@ -1592,7 +1640,7 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     const int row = clampi(jb + r, 0, P.ny - 1);
     st.sx[r][s][fc] = T(recx[((size_t)row * (P.nx + 1) + fi) * kRec + fld]);
   }
-  for (int e = threadIdx.x; e < (kPair + 1) * kWave * kSF; e += blockDim.x) {
+  for (int e = threadIdx.x; !kFill && e < (kPair + 1) * kWave * kSF; e += blockDim.x) {
     const int r = e / (kWave * kSF), rem = e - r * (kWave * kSF);
     const int fc = rem / kSF, s = rem - fc * kSF;
     const int fld = s <= sf(R_UX) ? R_GC + s : R_GC + s + 1;  // skip R_VY
@@ -1634,15 +1682,19 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double dW = (fl[k] - fl[kRec + k] + fb[k] - ft[k]) / P.area;
-      W1[k] = valid ? Wn[k] + dW : Wn[k];
+      if constexpr (kFill) {  // the ghost states of the current W
+        W1[k] = Wn[k];
+      } else {
+        const double dW = (fl[k] - fl[kRec + k] + fb[k] - ft[k]) / P.area;
+        W1[k] = valid ? Wn[k] + dW : Wn[k];
+      }
     }
     // every velocity chunk of the segment forms the same W^{n+1}; chunk 0 stores it
-    if (mine && gg == 0) {
+    if (!kFill && mine && gg == 0) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) Wout[4 * cc + k] = W1[k];
     }
-    if (P.adaptive && gg == 0) {
+    if (!kFill && P.adaptive && gg == 0) {
       // the adaptive step of the next step: the largest rate over the cells of W^{n+1}
       double rate = 0.0;
       if (mine)
@@ -1653,7 +1705,8 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
                   (unsigned long long)__double_as_longlong(rate));
     }
     // the simulated time advances by this step's dt (one thread of the instance)
-    if (b == first_block(pv.off_upd, ii) && w == 0 && lane == 0) *P.tsum += step_dt(P, parity);
+    if (!kFill && b == first_block(pv.off_upd, ii) && w == 0 && lane == 0)
+      *P.tsum += step_dt(P, parity);
     Prim pn{}, p1{};
     double Af = 1.0, AdF = 1.0 / P.area, A1 = 0.0, An = 0.0;
     if (!P.collisionless) {
@@ -1671,6 +1724,32 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
         An *= (double)P.dof / (2.0 * pn.lam);
       }
     }
+    // A channel's ghost column (lane of cell -1 or nx) takes the ghost state of step n + 1,
+    // formed from W^{n+1} of the cell next to it (Sec. 3.A), as its g^{n+1} with weight one
+    // and every other Eq. (3) weight zero: the loop then writes the ghost Maxwellian of the
+    // next step into the ghost column of f^{n+1}.  The first velocity chunk stores its W.
+    // (both shifts run on every lane: a lane exchange inside a per-lane branch would read
+    // the lanes the branch switched off)
+    double Wc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double up = from_upper(W1[k]), dn = from_lower(W1[k]);
+      Wc[k] = i < 0 ? up : dn;
+    }
+    if (ghost_w) {
+      const int side = i < 0 ? 0 : 1;
+      Prim pc;
+      (void)prim_of(Wc, pc, P.lam_c);  // an invalid cell state is flagged by its own lane
+      p1 = ghost_prim(P, side, jr, pc);
+      pn = p1;
+      if (gg == 0 && (r == 0 ? store0 : true))
+        store_wg(I->Wg + 4 * ((size_t)side * P.ny + jr), p1, P.lam_c);
+      Af = 0.0;
+      AdF = 0.0;
+      An = 0.0;
+      A1 = p1.rho * p1.lam / kPi;
+      if (hpart) A1 *= (double)P.dof / (2.0 * p1.lam);
+    }
     if constexpr (kShak) {
       // heat flux of f^n about U^n from the cell's raw moments (moment kernel, chunk 0)
       const size_t nc = (size_t)P.nx * P.ny;
@@ -1680,8 +1759,9 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       for (int k = 0; k < 8; ++k) m[k] = valid ? cm[(size_t)k * nc] : 0.0;
       double qn[2];
       heat_flux(m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[3] + m[5], pn.U, pn.V, qn);
-      const double kn = P.collisionless ? 0.0 : P.pr_c * pn.lam * pn.lam / pn.rho;
-      const double k1 = P.collisionless ? 0.0 : P.pr_c * p1.lam * p1.lam / p1.rho;
+      // no Shakhov factor on a ghost Maxwellian
+      const double kn = P.collisionless || ghost_w ? 0.0 : P.pr_c * pn.lam * pn.lam / pn.rho;
+      const double k1 = P.collisionless || ghost_w ? 0.0 : P.pr_c * p1.lam * p1.lam / p1.rho;
       sk[r][0][lane] = T(kn * qn[0]);
       sk[r][1][lane] = T(kn * qn[1]);
       sk[r][2][lane] = T(k1 * qn[0]);
@@ -1696,7 +1776,7 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       start(pn.lam, pn.V, h, st.gs[h][r][0][0], st.gs[h][r][0][1], lane);
       start(p1.lam, p1.V, h, st.gs[h][r][1][0], st.gs[h][r][1][1], lane);
     }
-  } else {
+  } else if (!kFill) {
     // Gauss starts of the faces (FP64 records): wavefront 2 + r takes the x faces of row
     // jb + r; the y face rows jb .. jb + 2 go one to a wavefront 4..6 with eight wavefronts,
     // else row jb to wavefront 2 and rows jb + 1, jb + 2 to wavefront 3
@@ -1723,16 +1803,25 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
         start(rec[R_LAM], rec[R_VY], h, st.ys[h][fr][0], st.ys[h][fr][1], lane);
     }
   }
-  if (lost && valid) *P.flag = 1;
+  if (lost && (valid || ghost_w)) *P.flag = 1;
   __syncthreads();
   // the workgroup's chunks kCh g .. kCh g + kCh - 1 of the quadrant's kCh G chunks
   const int sv = quad_sv(q);
+  if constexpr (kFill) {
+    if (quad_su(q) > 0)
+      ghost_fill_quadrant<S, 1>(P, st, lane, sv, jb, store0, kCh * g + c, kCh * G, ghost_w,
+                                fout, i);
+    else
+      ghost_fill_quadrant<S, -1>(P, st, lane, sv, jb, store0, kCh * g + c, kCh * G, ghost_w,
+                                 fout, i);
+    return;
+  }
   if (quad_su(q) > 0)
     pair_quadrant<S, 1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G, valid,
-                               ghost_lane, fin, fout, i);
+                               ghost_lane, ghost_w, fin, fout, i);
   else
     pair_quadrant<S, -1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G, valid,
-                                ghost_lane, fin, fout, i);
+                                ghost_lane, ghost_w, fin, fout, i);
 }
 
 // Velocity chunks per update workgroup, kCh (its wavefronts: four quadrants times kCh), which
@@ -1756,6 +1845,15 @@ __global__ __launch_bounds__(kWave* kQuads* kCh)
 __attribute__((amdgpu_waves_per_eu(kUpdateWaves<S, true>)))
 void update_kernel_shakhov(PlanView pv) {
   update_body<S, true, kCh>(pv);
+}
+
+// The update kernel's fill mode (any collision model: a ghost Maxwellian carries no Shakhov
+// factor), launched with the workgroups of the update kernel.
+template <typename S, int kCh>
+__global__ __launch_bounds__(kWave* kQuads* kCh)
+__attribute__((amdgpu_waves_per_eu(kUpdateWaves<S, false>)))
+void ghost_fill_kernel(PlanView pv) {
+  update_body<S, false, kCh, true>(pv);
 }
 
 }  // namespace
@@ -1871,14 +1969,18 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
     off[3][q] = t.ghost;
     off[4][q] = t.red;
     off[5][q] = 0;
-    if (G > 1) t.red += (int)(((long long)P.nslot * P.nx * P.ny + 255) / 256);
+    if (G > 1)  // the per-cell sums, and a channel's ghost sums
+      t.red += (int)(((long long)P.nslot * P.nx * P.ny +
+                      (P.bc == UGKS_BC_CHANNEL ? 2LL * P.ny * kGhostSums : 0) + 255) /
+                     256);
     t.shak = t.shak || P.shak;
     t.sums += ((P.nx + kTileS - 1) / kTileS) * P.ny * G;
     t.upd += ((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * img[q].usplit * P.NC;
     t.face += (nf + 255) / 256;
     if (P.bc == UGKS_BC_CHANNEL) {
-      t.ghost += 2 * P.ny;
+      t.channel = 1;
     } else {
+      t.periodic = 1;
       const long long frame = (long long)P.Lx * P.Ly - (long long)P.nx * P.ny;
       t.ghost += (int)((frame * P.NV * P.NC + kGhostThreads - 1) / kGhostThreads);
     }
@@ -1919,11 +2021,23 @@ hipError_t launch_init(const PlanView& pv, int fp32, long long nvalues, hipStrea
 }
 
 // phase 0 ghosts, 1 moment sums, 2 interface scalars, 3 cell update
+hipError_t launch_ghost_fill(const PlanView& pv, const PlanTotals& t, int fp32, hipStream_t s) {
+  if (!t.channel) return hipSuccess;
+  const unsigned nt = (unsigned)(kWave * kQuads * t.upd_ch);
+  if (fp32)
+    ghost_fill_kernel<float, 1><<<(unsigned)t.upd, nt, 0, s>>>(pv);
+  else if (t.upd_ch == 2)
+    ghost_fill_kernel<double, 2><<<(unsigned)t.upd, nt, 0, s>>>(pv);
+  else
+    ghost_fill_kernel<double, 1><<<(unsigned)t.upd, nt, 0, s>>>(pv);
+  return hipGetLastError();
+}
+
 hipError_t launch_phase(const PlanView& pv, const PlanTotals& t, int fp32, int phase,
                         hipStream_t s) {
   switch (phase) {
     case 0:
-      if (t.ghost == 0) return hipSuccess;
+      if (t.ghost == 0) return hipSuccess;  // no periodic instance
       if (fp32)
         ghost_kernel<float><<<(unsigned)t.ghost, kGhostThreads, 0, s>>>(pv);
       else
