@@ -157,8 +157,9 @@ int ugks_required_bytes(const ugks_mesh* mesh, const ugks_vgrid* vgrid, const ug
                         size_t* out_bytes);
 
 /* Debug option: with the environment variable UGKS_DEBUG_POISON=1 at ugks_create, every cell
-   value of the f and W buffers that the first step writes starts as NaN (their halo is left as
-   it is), so a step that fails to write a value it later reads leaves a NaN in the state. */
+   value of the f and W buffers that the first step writes starts as NaN, and in a channel also
+   the inlet and outlet ghost columns of that f (the rest of its halo is left as it is), so a
+   step that fails to write a value it later reads leaves a NaN in the state. */
 
 /* Create a solver and initialise its state on the device.  kn is the Knudsen number on the
    y extent of the domain (Sec. 3.A defines Kn on the channel width); kn = +INFINITY selects
@@ -178,7 +179,7 @@ int ugks_step(ugks_handle* h, int n);
 
 /* ugks_step for callers that cannot allocate device memory (code under HIP graph capture,
    tight serving loops, harnesses that forbid allocation): the same n steps, with the
-   transient buffers of each step (ghost states, per-cell moment sums, face records) in a
+   transient buffers of each step (per-cell and ghost moment sums, face records) in a
    static device array of UGKS_STATIC_SCRATCH_BYTES that the library holds on every GPU it
    runs on, instead of the handle's workspace.  It calls no allocating routine and records no
    timing events.  The handle's state advances exactly as with ugks_step (bitwise), and the two

@@ -1,5 +1,6 @@
 """Every value a step reads was written by the step before it: with UGKS_DEBUG_POISON=1 the
-library starts the buffers the first step writes as NaN in every cell, so a value a step failed
+library starts the buffers the first step writes as NaN in every cell (and, in a channel, in
+the ghost columns, which the update kernel writes for the next step), so a value a step failed
 to write would surface as a NaN in the state, and the poisoned solver would differ from a
 plain one.  Cases cover the update kernel's row pairs (odd row counts, one row), velocity
 chunks, both storage precisions, internal degrees of freedom, the Shakhov model and periodic
