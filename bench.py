@@ -26,11 +26,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "049a74e72c721dfad536daf90255999db19d709e9b90dc649d176b845532554f",
-    "fp64": 1.2939e9,
-    "fp32_store": 0.7214e9,
+    "source_sha256": "4551e53a1c3ad9f3e19a198ae04f22d2c45bca706665f5b4ac579c471232aed0",
+    "fp64": 1.2921e9,
+    "fp32_store": 0.7301e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
-    "valu_fp64": 1.0335e8,
+    "valu_fp64": 1.0364e8,
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
 # 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)
