@@ -234,9 +234,10 @@ int ugks_set_state(ugks_handle* h, const double* f, const double* W);
 int ugks_get_face_flux(ugks_handle* h, double* Fx, double* Fy);
 
 /* Per-kernel timing with HIP events recorded on the handle's stream around every launch.
-   kernel: 0 boundary ghosts, 1 velocity moments, 2 interface scalars, 3 cell update.
-   Enabling resets the totals; get waits for the stream and returns the summed milliseconds
-   and the number of launches timed. */
+   kernel: 0 boundary ghosts, 1 velocity moments, 2 interface scalars, 3 cell update.  Kernel 0
+   runs only in a periodic box (a channel's update kernel writes the next step's ghost
+   columns), so a channel reports no launches of it.  Enabling resets the totals; get waits
+   for the stream and returns the summed milliseconds and the number of launches timed. */
 int ugks_set_kernel_timing(ugks_handle* h, int on);
 int ugks_get_kernel_timing(ugks_handle* h, int kernel, double* total_ms, int64_t* launches);
 

@@ -150,7 +150,7 @@ struct PlanView {
   const int* off_sums;   // one workgroup per (row segment, velocity chunk) of the moment kernel
   const int* off_upd;    // one workgroup per (row segment, velocity chunk) of the update kernel
   const int* off_face;   // 256 faces per workgroup
-  const int* off_ghost;  // channel: 2 ny workgroups; periodic: the halo frame of every plane
+  const int* off_ghost;  // periodic: the halo frame of every plane (a channel has none)
   const int* off_red;    // chunk-sum workgroups (instances with more than one chunk)
   int ninst;
   int step;              // steps enqueued since the plan's `cur` values were taken
