@@ -147,11 +147,25 @@ def test_runs_are_bitwise_deterministic():
         b.close()
 
 
-def test_checkpoint_resume_is_bitwise():
-    kn, kw = WL.solver_kwargs(WL.C1)
+RESUME_CASES = {
+    "C1 fp64": (WL.C1, "fp64", 10),
+    "C1 fp32 (odd step count)": (WL.C1, "fp32_store", 11),
+    "channel 121x5, three segments": (
+        _case(nx=121, ny=5, lx=12.1, ly=0.5, nu=10, nv=8, umax=4.0, vmax=4.0, kn=0.1, seed=71),
+        "fp64", 7),
+}
+
+
+@pytest.mark.parametrize("name", list(RESUME_CASES))
+def test_checkpoint_resume_is_bitwise(name):
+    """A state copied into a second solver steps on bitwise as the first: the channel ghost
+    columns a set state gets from the update kernel's fill mode equal those a running solver's
+    update kernel writes."""
+    case, precision, steps = RESUME_CASES[name]
+    kn, kw = WL.solver_kwargs(case, precision)
     a, b = ugks.Solver(kn, **kw), ugks.Solver(kn, **dict(kw, seed=99))
     try:
-        a.step(10)
+        a.step(steps)
         f, W = a.state()
         b.set_state(f, W)
         a.step(15)
