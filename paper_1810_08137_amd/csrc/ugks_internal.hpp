@@ -106,7 +106,7 @@ struct Buffers {
   double* Wg;       // [2][ny][4]
   double* hs;       // [NC gmax][nslot][nx*ny]: partial g of sum q of face side s of cell c at
                     // ((g nslot) + 16 s + q) nx ny + c; chunks of H after those of G
-  double* hsg;      // [2][ny][kGhostSums]
+  double* hsg;      // [NC G][2][ny][kGhostSums]: the chunks' parts, added into the first
   double* recx;     // [NC][ny][nx+1][32]: records of G, then of H
   double* recy;     // [NC][ny+1][nx][32]
   double* wk;       // [K], followed by wm [M], then vmom [M][5]

@@ -306,43 +306,10 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 }
 
 // ------------------------------------------------------------------ wave reductions
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int h = 32; h >= 1; h >>= 1) x += __shfl_xor(x, h, kWave);
-  return x;
-}
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int h = 32; h >= 1; h >>= 1) x = fmax(x, __shfl_xor(x, h, kWave));
   return x;
-}
-
-// 16 moment sums of one face side (S1 and S7): weight wt, normal/tangential velocity
-// (un, ut), reconstructed f, the tangential half-cell change ht (the tangential slope times
-// half the tangential spacing; its sums are scaled when written) and the slope term
-// D = u sigma_x + v sigma_y.
-__device__ __forceinline__ void add_side(double* a, double wt, double un, double ut, double c2h,
-                                         double fh, double ht, double D) {
-  const double x0 = wt * fh;
-  const double x1 = wt * ht;
-  const double x2 = x0 * un;
-  const double x3 = (wt * un) * D;
-  a[0] += x0;
-  a[1] = fma(x0, un, a[1]);
-  a[2] = fma(x0, ut, a[2]);
-  a[3] = fma(x0, c2h, a[3]);
-  a[4] += x1;
-  a[5] = fma(x1, un, a[5]);
-  a[6] = fma(x1, ut, a[6]);
-  a[7] = fma(x1, c2h, a[7]);
-  a[8] += x2;
-  a[9] = fma(x2, un, a[9]);
-  a[10] = fma(x2, ut, a[10]);
-  a[11] = fma(x2, c2h, a[11]);
-  a[12] += x3;
-  a[13] = fma(x3, un, a[13]);
-  a[14] = fma(x3, ut, a[14]);
-  a[15] = fma(x3, c2h, a[15]);
 }
 
 // Node range of one half of a velocity axis.  Half s = +1 takes the nodes with positive
@@ -1290,9 +1257,8 @@ __device__ __forceinline__ void y_face(const PairStage<T>& st, int fr, int lane,
 template <typename S, int SU, bool kShak, int kAhead = kShak ? 1 : (sizeof(S) == 8 ? 2 : 3)>
 __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<S>& st,
                                               const S (*sk)[4][kWave], int lane, int sv,
-                                              int jb, bool store0, int g, int G, bool valid,
-                                              bool ghost_lane, bool ghost_w,
-                                              const UGKS_GLOBAL S* fin,
+                                              int jb, bool store0, int g, int G, bool writes,
+                                              bool ghost_lane, const UGKS_GLOBAL S* fin,
                                               UGKS_GLOBAL S* fout, int i) {
   typedef S T;  // arithmetic type of the per-velocity work
   const bool chan = P.bc == UGKS_BC_CHANNEL;
@@ -1308,8 +1274,8 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
   const bool gm = !ghost_lane;  // ghost columns have zero slopes
   const bool mB = no_wall(jB), m0 = gm && no_wall(j0), m1 = gm && no_wall(j1);
   // cells, and a channel's ghost columns (the ghost Maxwellian of the next step)
-  const bool st0 = (valid || ghost_w) && (r0 == 0 ? store0 : true);
-  const bool st1 = (valid || ghost_w) && (r1 == 0 ? store0 : true);
+  const bool st0 = writes && (r0 == 0 ? store0 : true);
+  const bool st1 = writes && (r1 == 0 ? store0 : true);
   // byte offsets of the five rows j0 - 2 sv, j0 - sv, j0, j1 = j0 + sv, j1 + sv
   const unsigned bs = (unsigned)sizeof(S);
   const int ic = i < P.nx + 1 ? i : P.nx + 1;
@@ -1817,11 +1783,11 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     return;
   }
   if (quad_su(q) > 0)
-    pair_quadrant<S, 1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G, valid,
-                               ghost_lane, ghost_w, fin, fout, i);
+    pair_quadrant<S, 1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G,
+                               valid || ghost_w, ghost_lane, fin, fout, i);
   else
-    pair_quadrant<S, -1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G, valid,
-                                ghost_lane, ghost_w, fin, fout, i);
+    pair_quadrant<S, -1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G,
+                                valid || ghost_w, ghost_lane, fin, fout, i);
 }
 
 // Velocity chunks per update workgroup, kCh (its wavefronts: four quadrants times kCh), which
