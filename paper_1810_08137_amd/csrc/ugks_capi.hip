@@ -706,8 +706,9 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
     if (e != hipSuccess) rc = hip_fail(nullptr, e, "hipMemsetAsync of the state flag");
   }
   if (rc == UGKS_OK) {
-    // the halo rows and columns start at zero; a channel never writes the halo outside its
-    // ghost columns, whose values the kernels then read as zero
+    // the halo rows and columns start at zero; in a channel only the ghost columns are
+    // written (by the fill below, then by every step's update kernel), the rest is read as
+    // zero
     const size_t fbytes = (size_t)s.NC * s.NV * s.PS * h->ssize;
     e = hipMemsetAsync(B.f[0], 0, fbytes, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(B.f[1], 0, fbytes, h->stream);
