@@ -148,6 +148,11 @@ typedef struct {
   int64_t steps;   /* steps enqueued so far */
   size_t device_bytes;
   double prandtl;  /* 1: BGK; below 1: the Shakhov model with this Prandtl number */
+  /* How the solver's steps split its velocities when it runs alone (a serving batch keeps
+     the moment chunks and chooses the update chunks for the whole batch): */
+  int moment_chunks;  /* u-range chunks per quadrant of the moment kernel (fixed at create) */
+  int update_chunks;  /* u-range chunks per quadrant and update workgroup */
+  int update_chunks_per_workgroup;  /* 2: FP64 workgroups of eight wavefronts; 1: four */
 } ugks_info;
 
 /* Device bytes a handle of this shape needs (f twice, twice more with internal degrees of

@@ -58,6 +58,7 @@ struct ugks_handle {
   bool static_ok = false;
   std::string static_why;    // why not, when static_ok is false
   bool last_static = false;  // the last step ran on the static scratch
+  int moment_chunks = 1, update_chunks = 1, update_ch = 1;  // the plan's choices (ugks_info)
   int64_t steps = 0;
   double tau_ref = 0.0;
   std::string err;
@@ -659,6 +660,12 @@ int ugks_create(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, const
   make_inst(P, B, h->prec, I);
   std::vector<char> plan_host(plan_bytes(1));
   h->pt = build_plan(&I, 1, plan_host.data(), h->plan_dev, &h->pv);
+  {
+    const Inst* img = reinterpret_cast<const Inst*>(plan_host.data());
+    h->moment_chunks = img->gsplit;
+    h->update_chunks = img->usplit;
+    h->update_ch = h->pt.upd_ch;
+  }
   // the plan of ugks_step_static: the same instance with its transient buffers on this
   // device's static scratch (looked up here, once per device)
   std::vector<char> plan_static_host(plan_bytes(1));
@@ -840,6 +847,9 @@ int ugks_get_info(const ugks_handle* h, ugks_info* out) {
   out->tau_ref = h->tau_ref;
   out->steps = h->steps;
   out->device_bytes = h->ws_bytes;
+  out->moment_chunks = h->moment_chunks;
+  out->update_chunks = h->update_chunks;
+  out->update_chunks_per_workgroup = h->update_ch;
   return UGKS_OK;
 }
 

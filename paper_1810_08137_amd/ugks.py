@@ -59,7 +59,9 @@ class ugks_info(ctypes.Structure):
                 ("nv", ctypes.c_int), ("plane_stride", ctypes.c_int), ("precision", ctypes.c_int),
                 ("internal_dof", ctypes.c_int), ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
                 ("tau_ref", ctypes.c_double), ("steps", ctypes.c_int64),
-                ("device_bytes", ctypes.c_size_t), ("prandtl", ctypes.c_double)]
+                ("device_bytes", ctypes.c_size_t), ("prandtl", ctypes.c_double),
+                ("moment_chunks", ctypes.c_int), ("update_chunks", ctypes.c_int),
+                ("update_chunks_per_workgroup", ctypes.c_int)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
