@@ -18,10 +18,11 @@
 // f is stored velocity-major: one plane per discrete velocity, a padded nx x ny array with
 // two halo columns and rows on each side (KParams).  A wavefront takes 64 consecutive cells
 // of one row at one velocity, so every load is one coalesced row segment and the x
-// neighbours of a cell come from the neighbouring lanes.  The four wavefronts of a workgroup
-// share one row segment and take one velocity quadrant each: within a quadrant the upwind
-// direction of both axes is uniform, so an x-face flux is evaluated once, by the lane of its
-// upwind cell, and handed to the downwind lane.
+// neighbours of a cell come from the neighbouring lanes.  The wavefronts of a workgroup share
+// one row segment (the update kernel: the same segment of two rows) and take one velocity
+// quadrant each (the FP64 update kernel: two wavefronts per quadrant, one per velocity
+// chunk): within a quadrant the upwind direction of both axes is uniform, so an x-face flux
+// is evaluated once, by the lane of its upwind cell, and handed to the downwind lane.
 // Two variants run through the same kernels: a gas with internal degrees of freedom, whose
 // second reduced distribution H takes velocity chunks of its own (its planes follow those of
 // G), and the Shakhov collision model, a separate instantiation of the moment and update
@@ -1825,7 +1826,7 @@ void ghost_fill_kernel(PlanView pv) {
 }  // namespace
 
 // ================================================================== launchers
-// Update workgroups that fill the GPU once: 3 per CU (its LDS and registers allow 3).
+// Moment-kernel workgroups that a solver's velocity chunks aim for: 3 per CU.
 constexpr long long kFillWorkgroups = 256 * 3;
 
 int velocity_chunks(int nx, int ny, int K, int NC) {
