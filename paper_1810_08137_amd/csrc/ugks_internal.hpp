@@ -14,6 +14,10 @@ namespace ugks {
 // Device buffers are declared in the global address space, so that pointers the kernels read
 // from a launch plan still compile to global (scalar-base) loads rather than flat ones.
 #define UGKS_GLOBAL __attribute__((address_space(1)))
+// Tables that no kernel writes while another reads them (velocity nodes, weights), read at a
+// wavefront-uniform address through the constant address space: scalar loads, counted apart
+// from the vector loads of f, so waiting for a table value never waits for f loads in flight.
+#define UGKS_CONST __attribute__((address_space(4)))
 template <typename T>
 inline UGKS_GLOBAL T* gp(T* p) {
   return (UGKS_GLOBAL T*)p;

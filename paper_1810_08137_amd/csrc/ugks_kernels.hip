@@ -802,8 +802,18 @@ __global__ __launch_bounds__(256) void chunk_sum_kernel(PlanView pv) {
     if (P.bc != UGKS_BC_CHANNEL || e >= gstride) return;
     at = I->hsg + e;
   }
+  // the chunks are added in chunk order; their loads go out eight at a time (a load per
+  // loop trip would wait out one memory latency per chunk)
+  const int n = I->gsplit * P.NC;
   double x = at[0];
-  for (int g = 1; g < I->gsplit * P.NC; ++g) x += at[(size_t)g * gstride];
+  for (int g0 = 1; g0 < n; g0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = g0 + k < n ? at[(size_t)(g0 + k) * gstride] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (g0 + k < n) x += v[k];
+  }
   at[0] = x;
 }
 
@@ -1252,10 +1262,12 @@ __device__ __forceinline__ void y_face(const PairStage<T>& st, int fr, int lane,
 // The equilibrium part of a face flux is GC En(un) Et(ut) P(un, ut): the Gaussian and cubic
 // of the u node are formed once per node, those of the v node follow the node by Gauss
 // recurrences.
-// kAhead: nodes whose loads are in flight ahead of the node computed.  The 400 x 100 x 40^2
-// channel measured 2 (FP64) and 3 (FP32 storage) 2-3% faster than 1; the Shakhov variant
-// has no registers to spare beyond 1.
-template <typename S, int SU, bool kShak, int kAhead = kShak ? 1 : (sizeof(S) == 8 ? 2 : 3)>
+// kAhead: nodes whose loads are in flight ahead of the node computed.  On the
+// 400 x 100 x 40^2 channel 2 measured fastest in both storage types (3 ahead: FP64 1% slower,
+// FP32 storage 4% slower, its registers then spill); the Shakhov variant has no registers to
+// spare beyond 1.  The ring only works because nothing else in the loop is a vector load: the
+// next v node is a scalar load (UGKS_CONST), so waiting for it never waits for f loads.
+template <typename S, int SU, bool kShak, int kAhead = kShak ? 1 : 2>
 __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<S>& st,
                                               const S (*sk)[4][kWave], int lane, int sv,
                                               int jb, bool store0, int g, int G, bool writes,
@@ -1317,7 +1329,7 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
     const long long pstep = (long long)hv.step * P.PS;
     const UGKS_GLOBAL S* pnext = plane_of(fin, P, k * P.M) + (long long)hv.first * P.PS;
     UGKS_GLOBAL S* wcur = plane_of(fout, P, k * P.M) + (long long)hv.first * P.PS;
-    const UGKS_GLOBAL double* vp = P.vm + hv.first;
+    const UGKS_CONST double* vp = (const UGKS_CONST double*)(P.vm + hv.first);
     // loads run kAhead nodes ahead of the node computed; past the last node of the half they
     // read its plane again
     int nl = 0;
@@ -1598,22 +1610,55 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   const bool ghost_w = ghost_lane && (i < 0 || lane <= kHalo + kTileU);
   // stage the records of the pair's faces: x faces i0-2 .. i0+62 of both rows, y face rows
   // jb .. jb+2 below / above lanes 0..63; indices clamped into the mesh for lanes and rows
-  // outside it
-  for (int e = threadIdx.x; !kFill && e < kPair * (kWave + 1) * kSF; e += blockDim.x) {
-    const int r = e / ((kWave + 1) * kSF), rem = e - r * ((kWave + 1) * kSF);
-    const int fc = rem / kSF, s = rem - fc * kSF;
-    const int fld = s <= sf(R_UX) ? R_GC + s : R_GC + s + 1;  // skip R_VY
-    const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
-    const int row = clampi(jb + r, 0, P.ny - 1);
-    st.sx[r][s][fc] = T(recx[((size_t)row * (P.nx + 1) + fi) * kRec + fld]);
-  }
-  for (int e = threadIdx.x; !kFill && e < (kPair + 1) * kWave * kSF; e += blockDim.x) {
-    const int r = e / (kWave * kSF), rem = e - r * (kWave * kSF);
-    const int fc = rem / kSF, s = rem - fc * kSF;
-    const int fld = s <= sf(R_UX) ? R_GC + s : R_GC + s + 1;  // skip R_VY
-    const int fi = clampi(i0 - kHalo + fc, 0, P.nx - 1);
-    const int row = clampi(jb + r, 0, P.ny);
-    st.sy[r][s][fc] = T(recy[((size_t)row * P.nx + fi) * kRec + fld]);
+  // outside it.  Every thread issues all its record loads before it writes any to LDS: one
+  // trip of a load-then-store loop per value would wait out one memory latency per trip.
+  if constexpr (!kFill) {
+    constexpr int kThreads = kWave * kQuads * kCh;  // the launch's workgroup size
+    constexpr int kNX = kPair * (kWave + 1) * kSF, kNY = (kPair + 1) * kWave * kSF;
+    constexpr int kItX = (kNX + kThreads - 1) / kThreads;
+    constexpr int kItY = (kNY + kThreads - 1) / kThreads;
+    auto fld_of = [](int s) { return s <= sf(R_UX) ? R_GC + s : R_GC + s + 1; };  // skip R_VY
+    double vx[kItX], vy[kItY];
+#pragma unroll
+    for (int it = 0; it < kItX; ++it) {
+      const int e = threadIdx.x + it * kThreads;
+      if (e < kNX) {
+        const int r = e / ((kWave + 1) * kSF), rem = e - r * ((kWave + 1) * kSF);
+        const int fc = rem / kSF, s = rem - fc * kSF;
+        const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
+        const int row = clampi(jb + r, 0, P.ny - 1);
+        vx[it] = recx[((size_t)row * (P.nx + 1) + fi) * kRec + fld_of(s)];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kItY; ++it) {
+      const int e = threadIdx.x + it * kThreads;
+      if (e < kNY) {
+        const int r = e / (kWave * kSF), rem = e - r * (kWave * kSF);
+        const int fc = rem / kSF, s = rem - fc * kSF;
+        const int fi = clampi(i0 - kHalo + fc, 0, P.nx - 1);
+        const int row = clampi(jb + r, 0, P.ny);
+        vy[it] = recy[((size_t)row * P.nx + fi) * kRec + fld_of(s)];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kItX; ++it) {
+      const int e = threadIdx.x + it * kThreads;
+      if (e < kNX) {
+        const int r = e / ((kWave + 1) * kSF), rem = e - r * ((kWave + 1) * kSF);
+        const int fc = rem / kSF, s = rem - fc * kSF;
+        st.sx[r][s][fc] = T(vx[it]);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kItY; ++it) {
+      const int e = threadIdx.x + it * kThreads;
+      if (e < kNY) {
+        const int r = e / (kWave * kSF), rem = e - r * (kWave * kSF);
+        const int fc = rem / kSF, s = rem - fc * kSF;
+        st.sy[r][s][fc] = T(vy[it]);
+      }
+    }
   }
   __syncthreads();
   const double hstep = P.dv;
@@ -1750,13 +1795,12 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     const int r = w - kPair;
     if (r < kPair) {
       const int jr = clampi(jb + r, 0, P.ny - 1);
+      for (int fc = lane; fc < kWave + 1; fc += kWave) {
+        const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
+        const UGKS_GLOBAL double* rec = recx + ((size_t)jr * (P.nx + 1) + fi) * kRec;
+        const double lam = rec[R_LAM], vy = rec[R_VY];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        for (int fc = lane; fc < kWave + 1; fc += kWave) {
-          const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
-          const UGKS_GLOBAL double* rec = recx + ((size_t)jr * (P.nx + 1) + fi) * kRec;
-          start(rec[R_LAM], rec[R_VY], h, st.xs[h][r][0], st.xs[h][r][1], fc);
-        }
+        for (int h = 0; h < 2; ++h) start(lam, vy, h, st.xs[h][r][0], st.xs[h][r][1], fc);
       }
     }
     const int fr0 = kCh == 2 ? r - kPair : (r == 0 ? 0 : 1);
