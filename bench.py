@@ -26,11 +26,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "c7978eeeff715f096191ce51965634581166217567c2b45d1432ab6c0e6db04d",
-    "fp64": 1.3220e9,
-    "fp32_store": 0.7813e9,
+    "source_sha256": "0a721010a1077fc3f1ed2e53c25a186737c6d7ad9ac950635cf2a29005629bd7",
+    "fp64": 1.3213e9,
+    "fp32_store": 0.8044e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
-    "valu_fp64": 1.0337e8,
+    "valu_fp64": 1.0346e8,
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
 # 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)

@@ -575,7 +575,10 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     // planes and weight rows are walked with running pointers: one add per node each
     const long long pstep = (long long)hv.step * P.PS;
     const UGKS_GLOBAL S* pcur = line + (long long)hv.first * P.PS;
-    const UGKS_GLOBAL double* wp = P.vmom + 5 * hv.first;
+    const UGKS_CONST double* wp = (const UGKS_CONST double*)(P.vmom + 5 * hv.first);
+    // FP64: each node's weights are requested one node ahead, as scalar loads (one node
+    // beyond the last node of a half lies in the other half)
+    double w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3], w4 = wp[4];
     const int wstep = 5 * hv.step;
     auto load_at = [&](const UGKS_GLOBAL S* p) {
       const __amdgpu_buffer_rsrc_t r = plane_rsrc(p, P);
@@ -583,7 +586,21 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
     };
     auto node = [&](const Vals& x) {
       // w_m v_m^n, n = 0..4, with the weight 1/2 of a node at v = 0 (visited by both halves)
-      const double w0 = wp[0], w1 = wp[1], w2 = wp[2], w3 = wp[3], w4 = wp[4];
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0, n4 = 0.0;
+      if constexpr (sizeof(S) == 8) {
+        n0 = wp[wstep];
+        n1 = wp[wstep + 1];
+        n2 = wp[wstep + 2];
+        n3 = wp[wstep + 3];
+        n4 = wp[wstep + 4];
+      } else {  // FP32 storage: read at the node (holding the next node's weights would cost
+                // this kernel its fourth wave per SIMD)
+        w0 = wp[0];
+        w1 = wp[1];
+        w2 = wp[2];
+        w3 = wp[3];
+        w4 = wp[4];
+      }
       // slopes in the storage type (FP32 storage: FP32 slopes), sums in FP64
       const S fW = from_lower(x.c), fE = from_upper(x.c);
       const double hx = half_limited(fE - x.c, x.c - fW);
@@ -603,6 +620,13 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
       Y3 = fma(hy, w3, Y3);
       Y4 = fma(hy, w4, Y4);
       wp += wstep;
+      if constexpr (sizeof(S) == 8) {
+        w0 = n0;
+        w1 = n1;
+        w2 = n2;
+        w3 = n3;
+        w4 = n4;
+      }
     };
     if constexpr (sizeof(S) == 8) {
       // FP64: two value sets, each node's loads issued one node ahead (deeper prefetch costs
@@ -1608,6 +1632,30 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   // the ghost lane whose neighbouring cell is this segment's writes the ghost column (the
   // outlet column can also be the right halo of the segment before the last)
   const bool ghost_w = ghost_lane && (i < 0 || lane <= kHalo + kTileU);
+  // the Eq. (4) inputs of wavefronts 0 and 1 (row jb + w), requested before the stage so that
+  // their latency overlaps the stage's
+  double eWn[4] = {1.0, 0.0, 0.0, 1.0}, eF[4][4] = {};
+  if (w < kPair) {
+    const int jr = clampi(jb + w, 0, P.ny - 1);
+    const int ci = valid ? i : 0;
+    const size_t cc = (size_t)jr * P.nx + ci;
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) eWn[k] = W[4 * cc + k];
+    }
+    if constexpr (!kFill) {
+      const UGKS_GLOBAL double* fl = recx + ((size_t)jr * (P.nx + 1) + ci) * kRec + R_FX;
+      const UGKS_GLOBAL double* fb = recy + ((size_t)jr * P.nx + ci) * kRec + R_FX;
+      const UGKS_GLOBAL double* ft = fb + (size_t)P.nx * kRec;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        eF[0][k] = fl[k];
+        eF[1][k] = fl[kRec + k];
+        eF[2][k] = fb[k];
+        eF[3][k] = ft[k];
+      }
+    }
+  }
   // stage the records of the pair's faces: x faces i0-2 .. i0+62 of both rows, y face rows
   // jb .. jb+2 below / above lanes 0..63; indices clamped into the mesh for lanes and rows
   // outside it.  Every thread issues all its record loads before it writes any to LDS: one
@@ -1684,20 +1732,15 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     const bool mine = valid && (r == 0 ? store0 : true);
     const int ci = valid ? i : 0;
     const size_t cc = (size_t)jr * P.nx + ci;
-    double Wn[4] = {1.0, 0.0, 0.0, 1.0}, W1[4];
-    const UGKS_GLOBAL double* fl = recx + ((size_t)jr * (P.nx + 1) + ci) * kRec + R_FX;
-    const UGKS_GLOBAL double* fb = recy + ((size_t)jr * P.nx + ci) * kRec + R_FX;
-    const UGKS_GLOBAL double* ft = fb + (size_t)P.nx * kRec;
-    if (valid) {
+    double Wn[4], W1[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) Wn[k] = W[4 * cc + k];
-    }
+    for (int k = 0; k < 4; ++k) Wn[k] = eWn[k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if constexpr (kFill) {  // the ghost states of the current W
         W1[k] = Wn[k];
       } else {
-        const double dW = (fl[k] - fl[kRec + k] + fb[k] - ft[k]) / P.area;
+        const double dW = (eF[0][k] - eF[1][k] + eF[2][k] - eF[3][k]) / P.area;
         W1[k] = valid ? Wn[k] + dW : Wn[k];
       }
     }
