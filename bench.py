@@ -26,9 +26,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "0a721010a1077fc3f1ed2e53c25a186737c6d7ad9ac950635cf2a29005629bd7",
-    "fp64": 1.3213e9,
-    "fp32_store": 0.8044e9,
+    "source_sha256": "9eb811984c317b51b5a4f6eddd05f88638ff0a426ad002985abce8d6d74d074d",
+    "fp64": 1.3202e9,
+    "fp32_store": 0.8053e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
     "valu_fp64": 1.0346e8,
 }

@@ -643,10 +643,10 @@ __global__ __launch_bounds__(kWave* kQuads) void sums_kernel(PlanView pv) {
       }
       if (c < hv.count) node(va);
     } else {
-      // FP32 storage: a row load brings half the bytes, so each node's loads are issued four
-      // nodes ahead (kSA + 1 value sets in a ring); past the last node of the half the loads
-      // read its plane again
-      constexpr int kSA = 4, NB = kSA + 1;
+      // FP32 storage: a row load brings half the bytes, so each node's loads are issued six
+      // nodes ahead (kSA + 1 value sets in a ring; 3 and 4 ahead measured 6% and 2% slower at
+      // 400 x 100 x 40^2); past the last node of the half the loads read its plane again
+      constexpr int kSA = 6, NB = kSA + 1;
       int nl = 0;
       auto load_next = [&]() {
         const Vals v = load_at(pcur);
