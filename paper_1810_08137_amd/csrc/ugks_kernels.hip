@@ -1343,7 +1343,7 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
   chunk_range(hu.count, g, G, a0, a1);
   for (int a = a0; a < a1; ++a) {
     const int k = hu.first + a * hu.step;
-    const T u = T(P.uk[k]);
+    const T u = T(((const UGKS_CONST double*)P.uk)[k]);  // a scalar load
     const T au = fabs(u);
     const T ucx = u * two_idx;
     struct Vals {
@@ -1555,7 +1555,7 @@ __device__ __forceinline__ void ghost_fill_quadrant(const KParams& P, const Pair
   chunk_range(hu.count, g, G, a0, a1);
   for (int a = a0; a < a1; ++a) {
     const int k = hu.first + a * hu.step;
-    const T u = T(P.uk[k]);
+    const T u = T(((const UGKS_CONST double*)P.uk)[k]);  // a scalar load
     UGKS_GLOBAL S* wcur = plane_of(f, P, k * P.M) + (long long)hv.first * P.PS;
     T en0, rn0, e10, r10, en1, rn1, e11, r11;
     {
@@ -1716,7 +1716,7 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   // Gauss start of exp(-lam (v - c)^2) at the first node of half h and its ratio to the next
   // (FP64, stored in the stage's type)
   auto start = [&](double lam, double c, int h, T* e, T* r, int col) {
-    const double v0 = P.vm[h == 0 ? P.M / 2 : P.M / 2 - 1];
+    const double v0 = ((const UGKS_CONST double*)P.vm)[h == 0 ? P.M / 2 : P.M / 2 - 1];
     const double hs = h == 0 ? hstep : -hstep;
     const double d = v0 - c;
     const double x = lam * d * d;
