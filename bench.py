@@ -26,11 +26,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "1ae86c7d874621e6a35156e05c95443e05f0b6a2d6871a117eedac5eb76197f6",
-    "fp64": 1.3243e9,
-    "fp32_store": 0.8053e9,
+    "source_sha256": "8207e5d6646a4d6a1f0f701dec64bdce1ecc9339f9b2bcbaf076ece7671097cb",
+    "fp64": 1.3265e9,
+    "fp32_store": 0.8052e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
-    "valu_fp64": 1.0341e8,
+    "valu_fp64": 1.0379e8,
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
 # 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)

@@ -102,6 +102,9 @@ typedef struct {
                     and nu/2); n in 1..16: at most n (the automatic choice capped at n).
                     Solvers that are stepped in large batches gain from a small cap.  Results
                     depend on G only through the order in which velocity sums are added.
+                    The same cap bounds the update kernel's v-range chunks (more than one
+                    only on meshes too small to fill the GPU otherwise; they change only the
+                    rounding of the v-direction Gaussians, started at each chunk's first node).
    seed             xi_c is output c = j*nx + i of the SplitMix64 generator seeded with
                     `seed` (output k = mix(seed + (k+1) * 0x9E3779B97F4A7C15)), mapped to
                     [-1, 1) as 2 (z >> 11) 2^-53 - 1; the inlet noise xi_j uses output
@@ -153,6 +156,8 @@ typedef struct {
   int moment_chunks;  /* u-range chunks per quadrant of the moment kernel (fixed at create) */
   int update_chunks;  /* u-range chunks per quadrant and update workgroup */
   int update_chunks_per_workgroup;  /* 2: FP64 workgroups of eight wavefronts; 1: four */
+  int update_v_chunks; /* v-range chunks per half of the update kernel (fixed at create; more
+                          than 1 only on meshes too small to fill the GPU otherwise) */
 } ugks_info;
 
 /* Device bytes a handle of this shape needs (f twice, twice more with internal degrees of

@@ -439,6 +439,8 @@ void fill_constants(const ugks_mesh* mesh, const ugks_vgrid* vgrid, double kn, c
   P.Lx = s.Lx;
   P.Ly = s.Ly;
   P.gmax = chunks;
+  P.vsplit = update_vsplit(s.nx, s.ny, s.K, s.M, s.NC, opts->precision == UGKS_FP32_STORE ? 1 : 0,
+                           shak ? 1 : 0, opts->velocity_chunks);
   P.PS = (long long)s.PS;
   P.bc = bc->kind;
   P.collisionless = std::isinf(kn) ? 1 : 0;
@@ -850,6 +852,7 @@ int ugks_get_info(const ugks_handle* h, ugks_info* out) {
   out->moment_chunks = h->moment_chunks;
   out->update_chunks = h->update_chunks;
   out->update_chunks_per_workgroup = h->update_ch;
+  out->update_v_chunks = h->P.vsplit;
   return UGKS_OK;
 }
 

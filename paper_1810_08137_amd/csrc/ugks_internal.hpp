@@ -78,6 +78,9 @@ struct KParams {
   int Lx, Ly;       // padded row length and row count of a plane
   int bc, collisionless, inlet_fixed_u;
   int gmax;         // velocity chunks per quadrant the moment-sum buffer has room for
+  int vsplit;       // v-range chunks per half of the update kernel, fixed at create: each
+                    // chunk starts its Gauss recurrences at its own first node, so the count
+                    // decides the rounding and is kept in every launch plan
   long long PS;     // values per plane
   double dx, dy, dt, inv_dx, inv_dy, area, mu_ref;
   double du, dv;    // node spacing of the uniform u and v grids
@@ -175,6 +178,10 @@ size_t plan_bytes(int n);
 // when the instance runs alone (NC reduced distributions each take their own chunks), at
 // least one u node per chunk and at most 16 chunks.
 int velocity_chunks(int nx, int ny, int K, int NC);
+// v-range chunks per half of the update kernel for a solver: 1 unless its update workgroups,
+// with the u ranges split as far as they go, would leave more than half the GPU idle; then as
+// many as fill it, each chunk at least four v nodes of the smaller half, at most `cap` (> 0).
+int update_vsplit(int nx, int ny, int K, int M, int NC, int fp32, int shak, int cap);
 // Build the host image of a plan for `n` instances into `buf` (plan_bytes(n) bytes) and return
 // the totals; `dev` is the device address the image will be copied to.
 PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, PlanView* view);

@@ -1294,9 +1294,10 @@ __device__ __forceinline__ void y_face(const PairStage<T>& st, int fr, int lane,
 template <typename S, int SU, bool kShak, int kAhead = kShak ? 1 : 2>
 __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<S>& st,
                                               const S (*sk)[4][kWave], int lane, int sv,
-                                              int jb, bool store0, int g, int G, bool writes,
-                                              bool ghost_lane, const UGKS_GLOBAL S* fin,
-                                              UGKS_GLOBAL S* fout, int i) {
+                                              int jb, bool store0, int g, int G, int gv, int Gv,
+                                              bool writes, bool ghost_lane,
+                                              const UGKS_GLOBAL S* fin, UGKS_GLOBAL S* fout,
+                                              int i) {
   typedef S T;  // arithmetic type of the per-velocity work
   const bool chan = P.bc == UGKS_BC_CHANNEL;
   const int r0 = sv > 0 ? 0 : 1, r1 = 1 - r0;     // rows of the pair, upwind first
@@ -1341,6 +1342,10 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
   const T two_idx = T(2.0 * P.inv_dx), two_idy = T(2.0 * P.inv_dy);
   int a0, a1;
   chunk_range(hu.count, g, G, a0, a1);
+  // this workgroup's v nodes of the half: chunk gv of Gv, vn nodes from node vf
+  int c0, c1;
+  chunk_range(hv.count, gv, Gv, c0, c1);
+  const int vn = c1 - c0, vf = hv.first + c0 * hv.step;
   for (int a = a0; a < a1; ++a) {
     const int k = hu.first + a * hu.step;
     const T u = T(((const UGKS_CONST double*)P.uk)[k]);  // a scalar load
@@ -1351,17 +1356,17 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
     };
     // planes (read and written) and v nodes are walked with running pointers
     const long long pstep = (long long)hv.step * P.PS;
-    const UGKS_GLOBAL S* pnext = plane_of(fin, P, k * P.M) + (long long)hv.first * P.PS;
-    UGKS_GLOBAL S* wcur = plane_of(fout, P, k * P.M) + (long long)hv.first * P.PS;
-    const UGKS_CONST double* vp = (const UGKS_CONST double*)(P.vm + hv.first);
-    // loads run kAhead nodes ahead of the node computed; past the last node of the half they
+    const UGKS_GLOBAL S* pnext = plane_of(fin, P, k * P.M) + (long long)vf * P.PS;
+    UGKS_GLOBAL S* wcur = plane_of(fout, P, k * P.M) + (long long)vf * P.PS;
+    const UGKS_CONST double* vp = (const UGKS_CONST double*)(P.vm + vf);
+    // loads run kAhead nodes ahead of the node computed; past the last node of the chunk they
     // read its plane again
     int nl = 0;
     auto load_next = [&]() {
       const __amdgpu_buffer_rsrc_t r = plane_rsrc(pnext, P);
       const Vals v{bload_raw(r, oA, S{}), bload_raw(r, oB, S{}), bload_raw(r, oC, S{}),
                    bload_raw(r, oD, S{}), bload_raw(r, oE, S{})};
-      if (++nl < hv.count) pnext += pstep;
+      if (++nl < vn) pnext += pstep;
       return v;
     };
     // the first nodes' stencil values, requested before the node's tables are formed
@@ -1505,7 +1510,7 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
     };
     // NB value sets in a ring: slot s holds node c + s, loaded kAhead nodes earlier
     int c = 0;
-    for (; c + NB <= hv.count; c += NB) {
+    for (; c + NB <= vn; c += NB) {
 #pragma unroll
       for (int s = 0; s < NB; ++s) {
         ring[(s + kAhead) % NB] = load_next();
@@ -1514,7 +1519,7 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
     }
 #pragma unroll
     for (int s = 0; s < NB; ++s) {
-      if (c + s < hv.count) {
+      if (c + s < vn) {
         ring[(s + kAhead) % NB] = load_next();
         node(ring[s]);
       }
@@ -1530,7 +1535,7 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
 template <typename S, int SU>
 __device__ __forceinline__ void ghost_fill_quadrant(const KParams& P, const PairStage<S>& st,
                                                     int lane, int sv, int jb, bool store0,
-                                                    int g, int G, bool ghost_w,
+                                                    int g, int G, int gv, int Gv, bool ghost_w,
                                                     UGKS_GLOBAL S* f, int i) {
   typedef S T;
   const int r0 = sv > 0 ? 0 : 1, r1 = 1 - r0;
@@ -1553,10 +1558,13 @@ __device__ __forceinline__ void ghost_fill_quadrant(const KParams& P, const Pair
   const long long pstep = (long long)hv.step * P.PS;
   int a0, a1;
   chunk_range(hu.count, g, G, a0, a1);
+  int c0, c1;
+  chunk_range(hv.count, gv, Gv, c0, c1);
+  const int vn = c1 - c0, vf = hv.first + c0 * hv.step;
   for (int a = a0; a < a1; ++a) {
     const int k = hu.first + a * hu.step;
     const T u = T(((const UGKS_CONST double*)P.uk)[k]);  // a scalar load
-    UGKS_GLOBAL S* wcur = plane_of(f, P, k * P.M) + (long long)hv.first * P.PS;
+    UGKS_GLOBAL S* wcur = plane_of(f, P, k * P.M) + (long long)vf * P.PS;
     T en0, rn0, e10, r10, en1, rn1, e11, r11;
     {
       const T(*c0)[kWave] = st.cell[r0];
@@ -1574,7 +1582,7 @@ __device__ __forceinline__ void ghost_fill_quadrant(const KParams& P, const Pair
       rn1 = st.gs[hf][r1][0][1][lane];
       r11 = st.gs[hf][r1][1][1][lane];
     }
-    for (int c = 0; c < hv.count; ++c) {
+    for (int c = 0; c < vn; ++c) {
       const T g0 = e10 + en0, g1 = e11 + en1;
       const __amdgpu_buffer_rsrc_t wr = plane_rsrc(wcur, P);
       bstore(wr, w0, g0, S{});
@@ -1605,15 +1613,17 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   const Inst* __restrict__ I = inst_at(pv, ii);
   const KParams P = I->P;
   const int parity = (I->cur + pv.step) & 1;
-  const int G = I->usplit;
+  const int G = I->usplit, Gv = P.vsplit;
   int t, gg, pb;
   cell_block(b - first_block(pv.off_upd, ii), (P.ny + 1) / 2, (P.nx + kTileU - 1) / kTileU, t,
              gg, pb);
   const int jb = min(2 * pb, P.ny - 2);       // rows jb, jb + 1
   const bool store0 = jb == 2 * pb && jb >= 0;  // row jb is this pair's to write
-  // chunks G..2G-1 update H: its planes, its face records, its equilibria
-  const bool hpart = gg >= G;
-  const int g = hpart ? gg - G : gg;
+  // chunk gg: u chunk g of G fastest, then v chunk gv of Gv; chunks G Gv.. update H: its
+  // planes, its face records, its equilibria
+  const bool hpart = gg >= G * Gv;
+  const int g2 = hpart ? gg - G * Gv : gg;
+  const int g = g2 % G, gv = g2 / G;
   const long long hoff = hpart ? (long long)P.NV * P.PS : 0ll;
   const UGKS_GLOBAL S* fin = static_cast<const UGKS_GLOBAL S*>(I->f[parity]) + hoff;
   // fill mode writes the ghost columns of the current f
@@ -1715,8 +1725,17 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   bool lost = false;
   // Gauss start of exp(-lam (v - c)^2) at the first node of half h and its ratio to the next
   // (FP64, stored in the stage's type)
+  // the first v node of this workgroup's chunk in half h (h = 0: v >= 0, walked upwards)
+  int vfirst[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const Half hv = axis_half(P.M, h == 0 ? 1 : -1, false);
+    int c0, c1;
+    chunk_range(hv.count, gv, Gv, c0, c1);
+    vfirst[h] = hv.first + c0 * hv.step;
+  }
   auto start = [&](double lam, double c, int h, T* e, T* r, int col) {
-    const double v0 = ((const UGKS_CONST double*)P.vm)[h == 0 ? P.M / 2 : P.M / 2 - 1];
+    const double v0 = ((const UGKS_CONST double*)P.vm)[vfirst[h]];
     const double hs = h == 0 ? hstep : -hstep;
     const double d = v0 - c;
     const double x = lam * d * d;
@@ -1863,18 +1882,18 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   const int sv = quad_sv(q);
   if constexpr (kFill) {
     if (quad_su(q) > 0)
-      ghost_fill_quadrant<S, 1>(P, st, lane, sv, jb, store0, kCh * g + c, kCh * G, ghost_w,
-                                fout, i);
+      ghost_fill_quadrant<S, 1>(P, st, lane, sv, jb, store0, kCh * g + c, kCh * G, gv, Gv,
+                                ghost_w, fout, i);
     else
-      ghost_fill_quadrant<S, -1>(P, st, lane, sv, jb, store0, kCh * g + c, kCh * G, ghost_w,
-                                 fout, i);
+      ghost_fill_quadrant<S, -1>(P, st, lane, sv, jb, store0, kCh * g + c, kCh * G, gv, Gv,
+                                 ghost_w, fout, i);
     return;
   }
   if (quad_su(q) > 0)
-    pair_quadrant<S, 1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G,
+    pair_quadrant<S, 1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G, gv, Gv,
                                valid || ghost_w, ghost_lane, fin, fout, i);
   else
-    pair_quadrant<S, -1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G,
+    pair_quadrant<S, -1, kShak>(P, st, sk, lane, sv, jb, store0, kCh * g + c, kCh * G, gv, Gv,
                                 valid || ghost_w, ghost_lane, fin, fout, i);
 }
 
@@ -1941,23 +1960,39 @@ int update_chunks(long long base, long long slots) {
 }
 
 // One instance (update_chunks_single): U, at most `cap` and 16, that minimises
-// rounds x (2 + u nodes per chunk), with `per_wg` chunks to a workgroup over the `half` u
-// nodes of the smaller half: a workgroup's fixed cost (its stage and Gauss starts) counts as
-// two u nodes; of equal costs the most workgroups.  On the paper's meshes and the 400x100
-// channel it picks the fastest U of a sweep or one within 1% of it.
-int update_chunks_single(long long base, long long slots, int cap, int per_wg, int half) {
+// rounds x (2 + u nodes per chunk / vs), with `per_wg` chunks to a workgroup over the `half`
+// u nodes of the smaller half and the v range in `vs` chunks: a workgroup's fixed cost (its
+// stage and Gauss starts) counts as two u nodes of a whole v half; of equal costs the most
+// workgroups.  On the paper's meshes and the 400x100 channel it picks the fastest U of a
+// sweep or one within 1% of it.
+int update_chunks_single(long long base, long long slots, int cap, int per_wg, int half,
+                         int vs) {
   int best = 1;
   long long best_cost = -1;
   for (int U = 1; U <= cap && U <= 16; ++U) {
     const long long rounds = (base * U + slots - 1) / slots;
     const long long chunks = (long long)per_wg * U;
-    const long long cost = rounds * (2 + (half + chunks - 1) / chunks);
+    const long long cost = rounds * (2LL * vs + (half + chunks - 1) / chunks);
     if (best_cost < 0 || cost <= best_cost) {
       best = U;
       best_cost = cost;
     }
   }
   return best;
+}
+
+int update_vsplit(int nx, int ny, int K, int M, int NC, int fp32, int shak, int cap) {
+  const long long base = (long long)((nx + kTileU - 1) / kTileU) * ((ny + 1) / 2) * NC;
+  const int umax = std::max(1, std::min(K / 2, 16));
+  // four-wavefront workgroups that run at once: 256 CUs x update waves per SIMD
+  const long long slots = 256LL * (fp32 ? (shak ? kUpdateWaves<float, true>
+                                                 : kUpdateWaves<float, false>)
+                                         : kUpdateWaves<double, false>);
+  if (2 * base * umax >= slots) return 1;
+  int vs = (int)(slots / (base * umax));
+  vs = std::min(vs, (M / 2) / 4);
+  if (cap > 0) vs = std::min(vs, cap);
+  return std::max(vs, 1);
 }
 
 size_t plan_bytes(int n) {
@@ -1980,7 +2015,7 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   long long upd_base = 0;  // update workgroups of all instances with one chunk
   for (int q = 0; q < n; ++q) {
     const KParams& P = insts[q].P;
-    upd_base += (long long)((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * P.NC;
+    upd_base += (long long)((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * P.NC * P.vsplit;
   }
   // velocity chunks per update workgroup (FP64 two, FP32 storage one) and the workgroups
   // that run at once: 256 CUs x waves per CU / waves per workgroup
@@ -1997,7 +2032,8 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
   auto choose = [&](int ch) {
     const long long slots = 256LL * waves / ch;
     if (n == 1)
-      return update_chunks_single(upd_base, slots, cap_of(insts[0].P, ch), ch, insts[0].P.K / 2);
+      return update_chunks_single(upd_base, slots, cap_of(insts[0].P, ch), ch, insts[0].P.K / 2,
+                                  insts[0].P.vsplit);
     return update_chunks(upd_base, slots);
   };
   int U = choose(per_wg);
@@ -2029,7 +2065,7 @@ PlanTotals build_plan(const Inst* insts, int n, void* buf, const void* dev, Plan
                      256);
     t.shak = t.shak || P.shak;
     t.sums += ((P.nx + kTileS - 1) / kTileS) * P.ny * G;
-    t.upd += ((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * img[q].usplit * P.NC;
+    t.upd += ((P.nx + kTileU - 1) / kTileU) * ((P.ny + 1) / 2) * img[q].usplit * P.vsplit * P.NC;
     t.face += (nf + 255) / 256;
     if (P.bc == UGKS_BC_CHANNEL) {
       t.channel = 1;

@@ -61,7 +61,7 @@ class ugks_info(ctypes.Structure):
                 ("tau_ref", ctypes.c_double), ("steps", ctypes.c_int64),
                 ("device_bytes", ctypes.c_size_t), ("prandtl", ctypes.c_double),
                 ("moment_chunks", ctypes.c_int), ("update_chunks", ctypes.c_int),
-                ("update_chunks_per_workgroup", ctypes.c_int)]
+                ("update_chunks_per_workgroup", ctypes.c_int), ("update_v_chunks", ctypes.c_int)]
 
 
 _dp = ctypes.POINTER(ctypes.c_double)

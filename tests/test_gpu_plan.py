@@ -1,8 +1,10 @@
 """The velocity chunks a solver's launches use, as ugks_info reports them, against the rules
 the kernels document (restated here): the moment kernel's chunks fixed at create so that its
-workgroups fill the GPU about three times per CU, and the update kernel's chunk count U that
-minimises rounds x (2 + u nodes per chunk) for a solver alone, with FP64 workgroups of two
-chunks (eight wavefronts) unless that would leave more than half the CUs without one."""
+workgroups fill the GPU about three times per CU; the update kernel's v-range chunks, fixed at
+create, more than one only when its workgroups with every u range split would leave more than
+half the GPU idle; and its u-range chunk count U that minimises rounds x (2 + u nodes per
+chunk / v chunks) for a solver alone, with FP64 workgroups of two chunks (eight wavefronts)
+unless that would leave more than half the CUs without one."""
 import math
 
 import pytest
@@ -22,26 +24,39 @@ def moment_chunks(nx, ny, K, NC, cap=0):
     return cap if 0 < cap < G else G
 
 
-def _single(base, slots, cap, per_wg, half):
+def update_v_chunks(nx, ny, K, M, NC, fp32, shak, cap=0):
+    base = math.ceil(nx / SEG) * ((ny + 1) // 2) * NC
+    umax = max(1, min(K // 2, 16))
+    slots = CUS * ((2 if shak else 4) if fp32 else 2)
+    if 2 * base * umax >= slots:
+        return 1
+    vs = min(slots // (base * umax), (M // 2) // 4)
+    if cap > 0:
+        vs = min(vs, cap)
+    return max(vs, 1)
+
+
+def _single(base, slots, cap, per_wg, half, vs):
     best, best_cost = 1, None
     for U in range(1, min(cap, 16) + 1):
         rounds = -(-base * U // slots)
-        cost = rounds * (2 + -(-half // (per_wg * U)))
+        cost = rounds * (2 * vs + -(-half // (per_wg * U)))
         if best_cost is None or cost <= best_cost:
             best, best_cost = U, cost
     return best
 
 
-def update_chunks(nx, ny, K, NC, fp32, shak):
-    base = math.ceil(nx / SEG) * ((ny + 1) // 2) * NC
+def update_chunks(nx, ny, K, M, NC, fp32, shak):
+    vs = update_v_chunks(nx, ny, K, M, NC, fp32, shak)
+    base = math.ceil(nx / SEG) * ((ny + 1) // 2) * NC * vs
     waves = (2 if shak else 4) if fp32 else 2   # waves per SIMD of the update kernel
     per = 1 if fp32 else 2
     cap = lambda ch: max(1, K // 2 // ch)
-    U = _single(base, CUS * waves // per, cap(per), per, K // 2)
+    U = _single(base, CUS * waves // per, cap(per), per, K // 2, vs)
     if per == 2 and base * U < CUS // 2:
         per = 1
-        U = _single(base, CUS * waves, cap(1), 1, K // 2)
-    return U, per
+        U = _single(base, CUS * waves, cap(1), 1, K // 2, vs)
+    return U, per, vs
 
 
 CASES = {"C1": (WL.C1, "fp64"), "C2": (WL.C2, "fp64"), "C2 fp32": (WL.C2, "fp32_store"),
@@ -63,8 +78,10 @@ def test_solver_reports_the_documented_velocity_chunks(name):
         shak = 0.0 < case.get("prandtl", 1.0) < 1.0
         K = case["nu"]
         assert info.moment_chunks == moment_chunks(case["nx"], case["ny"], K, NC), name
-        U, per = update_chunks(case["nx"], case["ny"], K, NC, precision == "fp32_store", shak)
-        assert (info.update_chunks, info.update_chunks_per_workgroup) == (U, per), name
+        U, per, vs = update_chunks(case["nx"], case["ny"], K, case["nv"], NC,
+                                   precision == "fp32_store", shak)
+        assert (info.update_chunks, info.update_chunks_per_workgroup, info.update_v_chunks) == \
+            (U, per, vs), name
     finally:
         s.close()
 
@@ -74,5 +91,6 @@ def test_velocity_chunk_cap_is_kept():
     s = ugks.Solver(kn, velocity_chunks=3, **{k: v for k, v in kw.items() if k != "velocity_chunks"})
     try:
         assert s.info.moment_chunks == 3
+        assert s.info.update_v_chunks == 3  # the automatic choice there is 3, within the cap
     finally:
         s.close()
