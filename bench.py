@@ -26,9 +26,9 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "8207e5d6646a4d6a1f0f701dec64bdce1ecc9339f9b2bcbaf076ece7671097cb",
-    "fp64": 1.3265e9,
-    "fp32_store": 0.8052e9,
+    "source_sha256": "9284d224f1f7c4cab6b12f17bac0329c5d0a81632a9d1052813ad4df609fee91",
+    "fp64": 1.3281e9,
+    "fp32_store": 0.8056e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
     "valu_fp64": 1.0379e8,
 }

@@ -1441,7 +1441,7 @@ __device__ __forceinline__ void pair_quadrant(const KParams& P, const PairStage<
                          c1[C_V1][lane]);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // v-direction Gaussians of the faces at the first node of the half, and their ratios
+    // v-direction Gaussians of the faces at the first node of the chunk, and their ratios
     T ex0 = st.xs[hf][r0][0][xo], rx0 = st.xs[hf][r0][1][xo];
     T ex1 = st.xs[hf][r1][0][xo], rx1 = st.xs[hf][r1][1][xo];
     T ei = st.ys[hf][fin_r][0][lane], ri = st.ys[hf][fin_r][1][lane];
@@ -1720,11 +1720,10 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   }
   __syncthreads();
   const double hstep = P.dv;
-  // A start value below the normal range cannot be carried up to a peak that lies inside
-  // the half: such a state (speed ratio |V| lambda^(1/2) above about 26 across v) is flagged.
+  // A start value below the normal range cannot be carried up to a peak that lies beyond the
+  // chunk's first node: such a state (speed ratio |V| lambda^(1/2) above about 26 across v)
+  // is flagged.
   bool lost = false;
-  // Gauss start of exp(-lam (v - c)^2) at the first node of half h and its ratio to the next
-  // (FP64, stored in the stage's type)
   // the first v node of this workgroup's chunk in half h (h = 0: v >= 0, walked upwards)
   int vfirst[2];
 #pragma unroll
@@ -1734,6 +1733,8 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     chunk_range(hv.count, gv, Gv, c0, c1);
     vfirst[h] = hv.first + c0 * hv.step;
   }
+  // Gauss start of exp(-lam (v - c)^2) at that node and its ratio to the next (FP64, stored
+  // in the stage's type)
   auto start = [&](double lam, double c, int h, T* e, T* r, int col) {
     const double v0 = ((const UGKS_CONST double*)P.vm)[vfirst[h]];
     const double hs = h == 0 ? hstep : -hstep;
