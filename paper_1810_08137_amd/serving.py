@@ -7,7 +7,9 @@ f/W state resident on the GPU, and advances every resident request together: one
 while a batch is running is admitted (its solver created on a separate stream) before the
 server waits for that batch, so admission overlaps the device work.  A request leaves after
 its step count, with its moments copied to the host; its latency is arrival -> result on the
-host.  A request whose state turns invalid fails alone.
+host.  A request whose state turns invalid fails alone.  A request can be cancelled at any
+time (``Server.cancel``, or ``Request.cancel_at``): a queued one is dropped, a running one
+leaves at the end of the batch in flight, its solver released and its memory returned.
 
 ``Server`` is independent of the GPU: it drives any executor with ``footprint``, ``create``,
 ``step``, ``wait``, ``finish`` and ``release``.  ``GpuExecutor`` is the one that runs here.
@@ -28,7 +30,8 @@ class Request:
     steps: int
     arrival: float      # seconds after the start of the run
     precision: str = "fp32_store"
-    status: str = "queued"   # queued, running, done, failed, rejected
+    status: str = "queued"   # queued, running, done, failed, rejected, cancelled
+    cancel_at: float = None  # the client cancels the request at this time (run clock), if set
     admitted: float = None
     finished: float = None
     result: np.ndarray = field(default=None, repr=False)
@@ -160,6 +163,13 @@ class Server:
         self.batches = 0
         self.max_resident = 0
         self.host_s = {}
+        self._cancel = set()   # request ids cancelled through cancel()
+
+    def cancel(self, rid):
+        """Cancel request `rid` (safe to call from another thread while run() executes): a
+        queued request is dropped at the next admission round, a running one after the batch
+        in flight."""
+        self._cancel.add(rid)
 
     def run(self, requests):
         pending = sorted(requests, key=lambda r: r.arrival)
@@ -177,8 +187,19 @@ class Server:
             finally:
                 host[part] += self.clock() - s0
 
+        def cancelled(r):
+            return r.rid in self._cancel or (r.cancel_at is not None and now() >= r.cancel_at)
+
+        def drop_cancelled():
+            # requests not yet admitted leave at once; running ones leave between batches
+            for lst in (pending, queue):
+                for r in [r for r in lst if cancelled(r)]:
+                    lst.remove(r)
+                    r.status, r.finished = "cancelled", now()
+
         def admit():
             nonlocal used
+            drop_cancelled()
             while pending and pending[0].arrival <= now():
                 queue.append(pending.pop(0))
             created = 0
@@ -205,6 +226,13 @@ class Server:
 
         while pending or queue or active:
             admit()
+            # resident requests cancelled since the last batch (no batch is in flight here)
+            for entry in [e for e in active if cancelled(e[0])]:
+                r, s, _, need = entry
+                r.status, r.finished = "cancelled", now()
+                self.ex.release(s)
+                used -= need
+                active.remove(entry)
             if not active:
                 if pending:
                     self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
@@ -224,7 +252,11 @@ class Server:
                     continue
                 r, s, d, need = entry
                 entry[2] = d = d + q
-                if d >= r.steps:
+                if d < r.steps and cancelled(r):   # cancelled while the batch ran
+                    r.status, r.finished = "cancelled", now()
+                    self.ex.release(s)
+                    used -= need
+                elif d >= r.steps:
                     try:
                         r.result = timed("finish", self.ex.finish, s)
                         r.status = "done"
@@ -248,6 +280,7 @@ def summarize(requests, makespan):
         "done": len(done),
         "failed": sum(r.status == "failed" for r in requests),
         "rejected": sum(r.status == "rejected" for r in requests),
+        "cancelled": sum(r.status == "cancelled" for r in requests),
         "makespan_s": makespan,
         "p50_latency_s": float(np.percentile(lat, 50)) if done else None,
         "p99_latency_s": float(np.percentile(lat, 99)) if done else None,

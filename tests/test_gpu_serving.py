@@ -135,6 +135,37 @@ def test_request_loop_end_to_end():
             s.close()
 
 
+def test_cancelled_request_leaves_and_the_others_end_as_alone():
+    """A request cancelled while its batch runs is released after that batch; the requests
+    still resident keep stepping and end bitwise as they would alone."""
+    reqs = SV.serving_requests(6, rate=float("inf"), seed=13, steps=12, precision="fp32_store",
+                               meshes=[(50, 12), (100, 25)], vgrids=[24])
+    ex = SV.GpuExecutor(max_slots=8)
+    try:
+        srv = SV.Server(ex, budget_bytes=8 << 30, max_slots=8, quantum=4)
+        step = ex.step
+
+        def step_and_cancel(solvers, n):
+            step(solvers, n)
+            if srv.batches == 0:
+                srv.cancel(reqs[2].rid)
+
+        ex.step = step_and_cancel
+        stats = srv.run(reqs)
+    finally:
+        ex.close()
+    print("[serving] cancel run", stats, flush=True)
+    assert reqs[2].status == "cancelled" and reqs[2].result is None
+    assert stats["done"] == 5 and stats["cancelled"] == 1
+    for r in [r for r in reqs if r is not reqs[2]][:2]:
+        s = _solver(r.case, "fp32_store", velocity_chunks=ex.velocity_chunks)
+        try:
+            s.step(r.steps)
+            assert np.array_equal(s.moments(), r.result)
+        finally:
+            s.close()
+
+
 def test_request_loop_with_mixed_gases_and_collision_models():
     """BGK, Shakhov and internal-degree-of-freedom requests in one request loop: the executor
     steps one batch per collision model and every request ends as it would alone."""

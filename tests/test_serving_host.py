@@ -181,3 +181,56 @@ def test_a_burst_is_created_in_rounds_while_the_first_requests_run():
     assert sizes[0] == 3 and max(sizes) > 3
     assert ex.order == sorted(ex.order)
     assert all(ex.steps_done[r.rid] == r.steps for r in reqs)
+
+
+def test_cancelling_a_running_request_releases_it_after_the_batch_in_flight():
+    """A request cancelled while its batch runs leaves when that batch ends: its solver is
+    released and its memory returned, it keeps the steps it got, and the others finish."""
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    reqs = small_requests(4, rate=float("inf"), steps=9)
+    srv = SV.Server(ex, budget_bytes=10**9, max_slots=8, quantum=3, clock=clock,
+                    sleep=clock.sleep)
+    step = ex.step
+
+    def step_and_cancel(solvers, n):
+        step(solvers, n)
+        if srv.batches == 0:          # the client cancels request 1 during the first batch
+            srv.cancel(reqs[1].rid)
+
+    ex.step = step_and_cancel
+    stats = srv.run(reqs)
+    assert reqs[1].status == "cancelled" and reqs[1].result is None
+    assert ex.steps_done[reqs[1].rid] == 3
+    assert all(r.status == "done" and ex.steps_done[r.rid] == 9 for r in reqs if r is not reqs[1])
+    assert stats["done"] == 3 and stats["cancelled"] == 1
+    assert ex.resident == 0
+
+
+def test_cancelling_a_queued_request_never_starts_it():
+    """With one slot, a request cancelled while it waits in the queue is never created."""
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    reqs = small_requests(3, rate=float("inf"), steps=4)
+    reqs[2].cancel_at = 0.0
+    stats = SV.Server(ex, budget_bytes=10**9, max_slots=1, quantum=2, clock=clock,
+                      sleep=clock.sleep).run(reqs)
+    assert reqs[2].status == "cancelled" and reqs[2].rid not in ex.order
+    assert stats["done"] == 2 and stats["cancelled"] == 1
+    assert ex.resident == 0
+
+
+def test_cancelling_a_resident_request_between_batches():
+    """A request cancelled at a time that falls between two batches leaves before the next
+    batch: it is not stepped again."""
+    clock = Clock()
+    ex = FakeExecutor(clock, cost=1.0)
+    reqs = small_requests(2, rate=float("inf"), steps=10)
+    per_batch = 1.0 * 2 * sum(WL.updates(r.case) for r in reqs) / 1e6   # two steps a batch
+    reqs[0].cancel_at = 1.5 * per_batch                               # after the first batch
+    stats = SV.Server(ex, budget_bytes=10**9, max_slots=4, quantum=2, clock=clock,
+                      sleep=clock.sleep).run(reqs)
+    assert reqs[0].status == "cancelled"
+    assert ex.steps_done[reqs[0].rid] in (2, 4)   # the batch in flight at cancel_at completes
+    assert reqs[1].status == "done" and ex.steps_done[reqs[1].rid] == 10
+    assert stats["cancelled"] == 1 and ex.resident == 0
