@@ -26,11 +26,11 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 # known size.  Valid only for the kernel source whose SHA-256 is recorded; null otherwise.
 KERNEL_SOURCE = os.path.join(HERE, "paper_1810_08137_amd", "csrc", "ugks_kernels.hip")
 MEASURED_TRAFFIC = {
-    "source_sha256": "9284d224f1f7c4cab6b12f17bac0329c5d0a81632a9d1052813ad4df609fee91",
-    "fp64": 1.3281e9,
-    "fp32_store": 0.8056e9,
+    "source_sha256": "773f6f18f85a245156b2dd6e31ac14258f87b59cbaca21c43567c11b4c4e843b",
+    "fp64": 1.3076e9,
+    "fp32_store": 0.7002e9,
     # SQ_INSTS_VALU per launch of the update kernel (wave instructions), same source
-    "valu_fp64": 1.0379e8,
+    "valu_fp64": 1.0361e8,
 }
 # VALU issue ceiling: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4 cycles at
 # 2.4 GHz (FP64 FMA runs at this full rate on MI355X: 78.6 TFLOP/s)

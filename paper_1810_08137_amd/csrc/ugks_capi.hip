@@ -966,10 +966,11 @@ int ugks_get_face_flux(ugks_handle* h, double* Fx, double* Fy) {
     e = hipMemcpyAsync(ry.data(), h->B.recy, ry.size() * 8, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "reading the face records");
+  // the records are field-major: field f of face k at f nf + k
   for (size_t k = 0; Fx && k < nfx; ++k)
-    for (int q = 0; q < 4; ++q) Fx[4 * k + q] = rx[k * kRec + R_FX + q];
+    for (int q = 0; q < 4; ++q) Fx[4 * k + q] = rx[(R_FX + q) * nfx + k];
   for (size_t k = 0; Fy && k < nfy; ++k)
-    for (int q = 0; q < 4; ++q) Fy[4 * k + q] = ry[k * kRec + R_FX + q];
+    for (int q = 0; q < 4; ++q) Fy[4 * k + q] = ry[(R_FX + q) * nfy + k];
   return UGKS_OK;
 }
 

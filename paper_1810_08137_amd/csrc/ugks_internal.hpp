@@ -114,8 +114,8 @@ struct Buffers {
   double* hs;       // [NC gmax][nslot][nx*ny]: partial g of sum q of face side s of cell c at
                     // ((g nslot) + 16 s + q) nx ny + c; chunks of H after those of G
   double* hsg;      // [NC G][2][ny][kGhostSums]: the chunks' parts, added into the first
-  double* recx;     // [NC][ny][nx+1][32]: records of G, then of H
-  double* recy;     // [NC][ny+1][nx][32]
+  double* recx;     // [NC][32][ny (nx+1)]: records of G, then of H, field-major
+  double* recy;     // [NC][32][(ny+1) nx]
   double* wk;       // [K], followed by wm [M], then vmom [M][5]
   double* uk;       // [K]
   double* vm;       // [M + 2]: zero, the M nodes, zero

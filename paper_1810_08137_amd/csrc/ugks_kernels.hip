@@ -863,7 +863,18 @@ __device__ __forceinline__ void heat_flux(double m0, double mn, double mt, doubl
 // flux, S0 = k (c . q)(2 lambda |c|^2 - 4), k = (1 - Pr) lambda^2/rho, c = (un - U, ut - V);
 // expanded in the record's basis {1, un, ut, c2h, un^2, un ut, ut^2, un c2h, ut c2h} it adds
 // to every coefficient of both upwind sides.
-__device__ __forceinline__ void fold_shakhov(UGKS_GLOBAL double* rec, const Prim& p0,
+// Face records are stored field-major: field f of face e of a family of nf faces (the x faces,
+// or the y faces) at f nf + e, so that a wavefront's 64 neighbouring faces read or write one
+// field as one contiguous access.  RecRef is one face's record in that layout.
+struct RecRef {
+  UGKS_GLOBAL double* p;  // field 0 of the face
+  size_t nf;              // faces of the family: the stride between fields
+  __device__ __forceinline__ UGKS_GLOBAL double& operator[](int f) const {
+    return p[(size_t)f * nf];
+  }
+};
+
+__device__ __forceinline__ void fold_shakhov(RecRef rec, const Prim& p0,
                                              const double* q, double km) {
   const double lam = p0.lam, U = p0.U, V = p0.V;
   const double Q0 = q[0] * U + q[1] * V;
@@ -883,7 +894,7 @@ __device__ __forceinline__ void fold_shakhov(UGKS_GLOBAL double* rec, const Prim
 template <bool kXi>
 __device__ void interface_scalars(const KParams& P, double dt, const double* S, const double* WL,
                                   const double* WR, double dn, double len, double* F,
-                                  UGKS_GLOBAL double* rec, UGKS_GLOBAL double* recH,
+                                  RecRef rec, RecRef recH,
                                   double& U0, double& V0, double T3 = 0.0) {
   const double* W0 = S;
   const double* Wt = S + 4;
@@ -1042,14 +1053,14 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
       wl[q] = WL[q];
       wr[q] = WR[q];
     }
-    UGKS_GLOBAL double* rec = recx + (size_t)e * kRec;
-    UGKS_GLOBAL double* recH = rec + (size_t)nfx * kRec;
+    const RecRef rec{recx + e, (size_t)nfx};
+    const RecRef recH{recx + (size_t)nfx * kRec + e, (size_t)nfx};
     if (P.NC > 1)
       interface_scalars<true>(P, dt, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0);
     else
       interface_scalars<false>(P, dt, S, wl, wr, P.dx, P.dy, F, rec, recH, U0, V0, T3);
     for (int c = 0; c < P.NC; ++c) {
-      UGKS_GLOBAL double* r = c ? recH : rec;
+      const RecRef r = c ? recH : rec;
 #pragma unroll
       for (int q = 0; q < 4; ++q) r[R_FX + q] = F[q];
       r[R_UX] = U0;
@@ -1060,8 +1071,8 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   if (e >= nfx + nfy) return;
   const long e2 = e - nfx;
   const int j = (int)(e2 / P.nx), i = (int)(e2 % P.nx);
-  UGKS_GLOBAL double* rec = recy + (size_t)e2 * kRec;
-  UGKS_GLOBAL double* recH = rec + (size_t)nfy * kRec;
+  const RecRef rec{recy + e2, (size_t)nfy};
+  const RecRef recH{recy + (size_t)nfy * kRec + e2, (size_t)nfy};
   if (chan && (j == 0 || j == P.ny)) {
     // diffuse wall: sums of the wall-row cell towards the wall; local frame (v, u)
     const bool top = j == P.ny;
@@ -1077,7 +1088,7 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
     for (int q = 0; q < 4; ++q) Fl[q] = s * (Q1[q] + rho_w * Gw[q]);
     // H leaves the wall with kap_w times the Maxwellian of G
     for (int c = 0; c < P.NC; ++c) {
-      UGKS_GLOBAL double* r = c ? recH : rec;
+      const RecRef r = c ? recH : rec;
       r[R_FX + 0] = Fl[0];
       r[R_FX + 1] = Fl[2];
       r[R_FX + 2] = Fl[1];
@@ -1109,7 +1120,7 @@ __global__ __launch_bounds__(256) void faces_kernel(PlanView pv) {
   else
     interface_scalars<false>(P, dt, S, wl, wr, P.dy, P.dx, F, rec, recH, U0, V0, T3);
   for (int c = 0; c < P.NC; ++c) {
-    UGKS_GLOBAL double* r = c ? recH : rec;
+    const RecRef r = c ? recH : rec;
     r[R_FX + 0] = F[0];
     r[R_FX + 1] = F[2];
     r[R_FX + 2] = F[1];
@@ -1628,10 +1639,11 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
   const UGKS_GLOBAL S* fin = static_cast<const UGKS_GLOBAL S*>(I->f[parity]) + hoff;
   // fill mode writes the ghost columns of the current f
   UGKS_GLOBAL S* fout = static_cast<UGKS_GLOBAL S*>(I->f[kFill ? parity : parity ^ 1]) + hoff;
-  const UGKS_GLOBAL double* recx =
-      I->recx + (hpart ? (size_t)P.ny * (P.nx + 1) * kRec : (size_t)0);
-  const UGKS_GLOBAL double* recy =
-      I->recy + (hpart ? (size_t)(P.ny + 1) * P.nx * kRec : (size_t)0);
+  // face records, field-major (RecRef): field f of x face e at f nfx + e, of y face e at
+  // f nfy + e; the records of H follow those of G
+  const size_t nfx = (size_t)P.ny * (P.nx + 1), nfy = (size_t)(P.ny + 1) * P.nx;
+  const UGKS_GLOBAL double* recx = I->recx + (hpart ? nfx * kRec : (size_t)0);
+  const UGKS_GLOBAL double* recy = I->recy + (hpart ? nfy * kRec : (size_t)0);
   const UGKS_GLOBAL double* W = I->W[parity];
   UGKS_GLOBAL double* Wout = I->W[parity ^ 1];
   const int i0 = t * kTileU;
@@ -1654,15 +1666,15 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       for (int k = 0; k < 4; ++k) eWn[k] = W[4 * cc + k];
     }
     if constexpr (!kFill) {
-      const UGKS_GLOBAL double* fl = recx + ((size_t)jr * (P.nx + 1) + ci) * kRec + R_FX;
-      const UGKS_GLOBAL double* fb = recy + ((size_t)jr * P.nx + ci) * kRec + R_FX;
-      const UGKS_GLOBAL double* ft = fb + (size_t)P.nx * kRec;
+      // the fluxes through the cell's left and right x faces and its lower and upper y faces
+      const UGKS_GLOBAL double* fl = recx + (size_t)R_FX * nfx + (size_t)jr * (P.nx + 1) + ci;
+      const UGKS_GLOBAL double* fb = recy + (size_t)R_FX * nfy + (size_t)jr * P.nx + ci;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        eF[0][k] = fl[k];
-        eF[1][k] = fl[kRec + k];
-        eF[2][k] = fb[k];
-        eF[3][k] = ft[k];
+        eF[0][k] = fl[k * nfx];
+        eF[1][k] = fl[k * nfx + 1];
+        eF[2][k] = fb[k * nfy];
+        eF[3][k] = fb[k * nfy + P.nx];
       }
     }
   }
@@ -1682,10 +1694,10 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       const int e = threadIdx.x + it * kThreads;
       if (e < kNX) {
         const int r = e / ((kWave + 1) * kSF), rem = e - r * ((kWave + 1) * kSF);
-        const int fc = rem / kSF, s = rem - fc * kSF;
+        const int s = rem / (kWave + 1), fc = rem - s * (kWave + 1);  // faces fastest
         const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
         const int row = clampi(jb + r, 0, P.ny - 1);
-        vx[it] = recx[((size_t)row * (P.nx + 1) + fi) * kRec + fld_of(s)];
+        vx[it] = recx[(size_t)fld_of(s) * nfx + (size_t)row * (P.nx + 1) + fi];
       }
     }
 #pragma unroll
@@ -1693,10 +1705,10 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       const int e = threadIdx.x + it * kThreads;
       if (e < kNY) {
         const int r = e / (kWave * kSF), rem = e - r * (kWave * kSF);
-        const int fc = rem / kSF, s = rem - fc * kSF;
+        const int s = rem / kWave, fc = rem - s * kWave;  // faces fastest
         const int fi = clampi(i0 - kHalo + fc, 0, P.nx - 1);
         const int row = clampi(jb + r, 0, P.ny);
-        vy[it] = recy[((size_t)row * P.nx + fi) * kRec + fld_of(s)];
+        vy[it] = recy[(size_t)fld_of(s) * nfy + (size_t)row * P.nx + fi];
       }
     }
 #pragma unroll
@@ -1704,7 +1716,7 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       const int e = threadIdx.x + it * kThreads;
       if (e < kNX) {
         const int r = e / ((kWave + 1) * kSF), rem = e - r * ((kWave + 1) * kSF);
-        const int fc = rem / kSF, s = rem - fc * kSF;
+        const int s = rem / (kWave + 1), fc = rem - s * (kWave + 1);
         st.sx[r][s][fc] = T(vx[it]);
       }
     }
@@ -1713,7 +1725,7 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       const int e = threadIdx.x + it * kThreads;
       if (e < kNY) {
         const int r = e / (kWave * kSF), rem = e - r * (kWave * kSF);
-        const int fc = rem / kSF, s = rem - fc * kSF;
+        const int s = rem / kWave, fc = rem - s * kWave;
         st.sy[r][s][fc] = T(vy[it]);
       }
     }
@@ -1860,8 +1872,8 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
       const int jr = clampi(jb + r, 0, P.ny - 1);
       for (int fc = lane; fc < kWave + 1; fc += kWave) {
         const int fi = clampi(i0 - kHalo + fc, 0, P.nx);
-        const UGKS_GLOBAL double* rec = recx + ((size_t)jr * (P.nx + 1) + fi) * kRec;
-        const double lam = rec[R_LAM], vy = rec[R_VY];
+        const UGKS_GLOBAL double* rec = recx + (size_t)jr * (P.nx + 1) + fi;
+        const double lam = rec[(size_t)R_LAM * nfx], vy = rec[(size_t)R_VY * nfx];
 #pragma unroll
         for (int h = 0; h < 2; ++h) start(lam, vy, h, st.xs[h][r][0], st.xs[h][r][1], fc);
       }
@@ -1871,10 +1883,11 @@ __device__ __forceinline__ void update_body(const PlanView& pv) {
     for (int fr = max(fr0, 0); fr < fr1; ++fr) {
       const int fi = clampi(i0 - kHalo + lane, 0, P.nx - 1);
       const int row = clampi(jb + fr, 0, P.ny);
-      const UGKS_GLOBAL double* rec = recy + ((size_t)row * P.nx + fi) * kRec;
+      const UGKS_GLOBAL double* rec = recy + (size_t)row * P.nx + fi;
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        start(rec[R_LAM], rec[R_VY], h, st.ys[h][fr][0], st.ys[h][fr][1], lane);
+        start(rec[(size_t)R_LAM * nfy], rec[(size_t)R_VY * nfy], h, st.ys[h][fr][0],
+              st.ys[h][fr][1], lane);
     }
   }
   if (lost && (valid || ghost_w)) *P.flag = 1;
