@@ -416,7 +416,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU slab split is a design note, not part of this build)",
+              "(the library steps solvers on one device; the slab split across GPUs is not implemented)",
               file=sys.stderr)
         sys.exit(2)
     import torch
