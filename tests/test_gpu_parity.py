@@ -74,6 +74,25 @@ def test_channel_widths_at_segment_edges(nx):
     PR.run_and_compare(case, 20, label=f"channel {nx}x3 8x6")
 
 
+@pytest.mark.parametrize("bc,precision", [(1, "fp64"), (0, "fp64"), (1, "fp32_store")])
+def test_odd_row_count_with_unequal_v_chunks(bc, precision):
+    """Seven rows (the last row pair overlaps the one before it and writes only its upper row)
+    with each v half of 33 nodes split into four chunks of unequal length (17 nodes on the
+    v >= 0 side, 16 on the other), each chunk starting its Gauss recurrences at its own first
+    node."""
+    case = _case(nx=23, ny=7, lx=2.3, ly=0.7, nu=33, nv=33, umax=5.0, vmax=5.0, kn=0.1, bc=bc,
+                 noise=0.03, seed=31)
+    kn, kw = WL.solver_kwargs(case, precision)
+    s = ugks.Solver(kn, **kw)
+    try:
+        assert s.info.update_v_chunks == 4
+    finally:
+        s.close()
+    tol = PR.FP64_TOL if precision == "fp64" else PR.FP32_STORE_TOL
+    PR.run_and_compare(case, 20, precision=precision, tol=tol,
+                       label=f"23x7 33^2 bc={bc} {precision}, 4 v chunks")
+
+
 @pytest.mark.parametrize("bc", [0, 1])
 def test_collisionless_limit(bc):
     case = _case(nx=12, ny=6, lx=2.0, ly=1.0, nu=10, nv=9, umax=3.0, vmax=3.0, kn=float("inf"),
