@@ -74,14 +74,18 @@ def test_channel_widths_at_segment_edges(nx):
     PR.run_and_compare(case, 20, label=f"channel {nx}x3 8x6")
 
 
-@pytest.mark.parametrize("bc,precision", [(1, "fp64"), (0, "fp64"), (1, "fp32_store")])
-def test_odd_row_count_with_unequal_v_chunks(bc, precision):
+@pytest.mark.parametrize("bc,precision,extra", [(1, "fp64", {}), (0, "fp64", {}),
+                                                 (1, "fp32_store", {}),
+                                                 (1, "fp64", {"prandtl": 2.0 / 3.0}),
+                                                 (1, "fp64", {"dof": 1})])
+def test_odd_row_count_with_unequal_v_chunks(bc, precision, extra):
     """Seven rows (the last row pair overlaps the one before it and writes only its upper row)
     with each v half of 33 nodes split into four chunks of unequal length (17 nodes on the
     v >= 0 side, 16 on the other), each chunk starting its Gauss recurrences at its own first
-    node."""
+    node; also with the Shakhov model and with internal degrees of freedom (whose chunks of H
+    follow those of G)."""
     case = _case(nx=23, ny=7, lx=2.3, ly=0.7, nu=33, nv=33, umax=5.0, vmax=5.0, kn=0.1, bc=bc,
-                 noise=0.03, seed=31)
+                 noise=0.03, seed=31, **extra)
     kn, kw = WL.solver_kwargs(case, precision)
     s = ugks.Solver(kn, **kw)
     try:
@@ -90,7 +94,7 @@ def test_odd_row_count_with_unequal_v_chunks(bc, precision):
         s.close()
     tol = PR.FP64_TOL if precision == "fp64" else PR.FP32_STORE_TOL
     PR.run_and_compare(case, 20, precision=precision, tol=tol,
-                       label=f"23x7 33^2 bc={bc} {precision}, 4 v chunks")
+                       label=f"23x7 33^2 bc={bc} {precision} {extra}, 4 v chunks")
 
 
 @pytest.mark.parametrize("bc", [0, 1])
